@@ -1,0 +1,142 @@
+"""Seeded workloads with the shapes and distributions of the paper's experiments.
+
+The paper (§2.3) draws the anisotropy parameters at random, fixes the grid, and
+takes the right-hand side vector f ~ N(0, I).  The batches below keep that recipe
+with the sizes of the measured configurations:
+
+  single   -- one isotropic problem (eps = 1, theta = 0), n = 63, f from seed 0
+  aniso    -- B problems, eps = 10**U(-4, 0), theta = U(0, pi), f ~ N(0, I) per instance
+  uneven   -- 512 problems with n drawn from {63, 127, 255, 511, 1023} in the
+              proportions 40/25/20/10/5 percent, then eps, theta, f as in ``aniso``
+  helmholtz-- B problems with kappa = U(20, 80) and a Gaussian point source
+
+Every draw comes from ``numpy.random.default_rng(seed)`` in the order written
+here.  Vectors are FP64, laid out per instance as ``u[j, i]`` (i fastest) and
+packed back to back in instance order.
+"""
+import numpy as np
+
+__all__ = [
+    "Batch", "single_isotropic", "aniso_batch", "uneven_batch", "helmholtz_batch",
+    "random_batch", "meta_params", "pack", "unpack_vec", "offsets_of",
+]
+
+META_HIDDEN = 64
+
+
+class Batch:
+    """A batch of independent problems: sizes, parameters and right-hand sides."""
+
+    def __init__(self, n, eps=None, theta=None, kappa=None, f=None, op="q1"):
+        self.n = [int(k) for k in n]
+        self.B = len(self.n)
+        self.op = op
+        self.eps = None if eps is None else np.asarray(eps, dtype=np.float64)
+        self.theta = None if theta is None else np.asarray(theta, dtype=np.float64)
+        self.kappa = None if kappa is None else np.asarray(kappa, dtype=np.float64)
+        self.f = f
+
+    @property
+    def offsets(self):
+        return offsets_of(self.n)
+
+    @property
+    def points(self):
+        return int(sum(k * k for k in self.n))
+
+    def f_packed(self):
+        return pack(self.f)
+
+
+def offsets_of(ns):
+    off = np.zeros(len(ns) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([int(k) * int(k) for k in ns])
+    return off
+
+
+def pack(vecs):
+    """Concatenate per-instance [n, n] arrays into one flat vector."""
+    return np.concatenate([np.asarray(v, dtype=np.float64).ravel() for v in vecs])
+
+
+def unpack_vec(flat, ns):
+    off = offsets_of(ns)
+    return [np.asarray(flat[off[b]:off[b + 1]]).reshape(ns[b], ns[b]) for b in range(len(ns))]
+
+
+def single_isotropic(n=63, seed=0):
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((n, n))
+    return Batch([n], eps=[1.0], theta=[0.0], f=[f])
+
+
+def _draw_params_and_rhs(rng, ns):
+    B = len(ns)
+    eps = 10.0 ** rng.uniform(-4.0, 0.0, size=B)
+    theta = rng.uniform(0.0, np.pi, size=B)
+    f = [rng.standard_normal((k, k)) for k in ns]
+    return eps, theta, f
+
+
+def aniso_batch(B, n, seed):
+    rng = np.random.default_rng(seed)
+    ns = [n] * B
+    eps, theta, f = _draw_params_and_rhs(rng, ns)
+    return Batch(ns, eps=eps, theta=theta, f=f)
+
+
+def uneven_batch(seed=4, sizes=(63, 127, 255, 511, 1023), counts=(205, 128, 102, 51, 26)):
+    rng = np.random.default_rng(seed)
+    ns = []
+    for s, c in zip(sizes, counts):
+        ns += [s] * c
+    ns = list(rng.permutation(np.array(ns)))
+    eps, theta, f = _draw_params_and_rhs(rng, ns)
+    return Batch(ns, eps=eps, theta=theta, f=f)
+
+
+def random_batch(ns, seed, eps_range=(1e-4, 1.0)):
+    """Small test batches with arbitrary (possibly ragged) sizes."""
+    rng = np.random.default_rng(seed)
+    B = len(ns)
+    lo, hi = np.log10(eps_range[0]), np.log10(eps_range[1])
+    eps = 10.0 ** rng.uniform(lo, hi, size=B)
+    theta = rng.uniform(0.0, np.pi, size=B)
+    f = [rng.standard_normal((k, k)) for k in ns]
+    return Batch(ns, eps=eps, theta=theta, f=f)
+
+
+def helmholtz_batch(B=32, n=511, seed=5, sigma_cells=2.0):
+    rng = np.random.default_rng(seed)
+    kappa = rng.uniform(20.0, 80.0, size=B)
+    centres = rng.uniform(0.1, 0.9, size=(B, 2))
+    h = 1.0 / (n + 1)
+    x = np.arange(1, n + 1) * h
+    f = []
+    for b in range(B):
+        dx2 = (x[None, :] - centres[b, 0]) ** 2
+        dy2 = (x[:, None] - centres[b, 1]) ** 2
+        f.append(np.exp(-(dx2 + dy2) / (2.0 * (sigma_cells * h) ** 2)))
+    return Batch([n] * B, kappa=kappa, f=f, op="helmholtz")
+
+
+def meta_params(m=16, seed=0, beta0=0.99, last_std=0.01):
+    """Initial meta-network parameters, flat, in the layout
+    W1[64][2], b1[64], W2[64][64], b2[64], W3[m+1][64], b3[m+1].
+
+    Hidden layers: U(-1/sqrt(fan_in), 1/sqrt(fan_in)) for weights and biases.
+    Last layer: N(0, last_std^2) weights; biases 0 except the momentum output,
+    whose bias is log(beta0 / (1 - beta0)).
+    """
+    rng = np.random.default_rng(seed)
+    H = META_HIDDEN
+    k1 = 1.0 / np.sqrt(2.0)
+    k2 = 1.0 / np.sqrt(H)
+    W1 = rng.uniform(-k1, k1, size=(H, 2))
+    b1 = rng.uniform(-k1, k1, size=H)
+    W2 = rng.uniform(-k2, k2, size=(H, H))
+    b2 = rng.uniform(-k2, k2, size=H)
+    W3 = rng.normal(0.0, last_std, size=(m + 1, H))
+    b3 = np.zeros(m + 1)
+    b3[m] = np.log(beta0 / (1.0 - beta0))
+    return np.concatenate([a.ravel() for a in (W1, b1, W2, b2, W3, b3)])
