@@ -1,0 +1,206 @@
+/*
+ * rm.h -- C ABI of the MI355X (gfx950) long-step Richardson(m) library.
+ *
+ * What it computes (Wang, Liu, Cui, Shu, "Momentum-Accelerated Richardson(m) and
+ * Their Multilevel Neural Solvers", arXiv 2412.08076):
+ *   - the operator A of a batch of independent 2D problems: the bilinear (Q1) FEM
+ *     9-point stencil of -div(C grad u) = f with C = R(theta) diag(1, eps) R(theta)^T
+ *     (§2.3, eq. anisotropy-poisson), or the 5-point finite-difference Helmholtz
+ *     stencil (§3.2, eq. Helmholtz-Sponge-stencil), zero Dirichlet boundary;
+ *   - Richardson(m) and NAG-Richardson(m) (§2, eq. Richardson(m); Table 1) with
+ *     per-instance, per-inner-step weights omega_i and momentum alpha_i (§2.2,
+ *     the weight vector of the neural solver), the relative residual
+ *     ||f - A u|| / ||f|| after every outer iteration (§2.3 stopping rule);
+ *   - the reverse-mode derivative of a K-step unroll with respect to omega, alpha
+ *     and f, used to train the weight network (§2.2, Algorithm 1, loss L2);
+ *   - the weight network Meta(theta; mu) itself (§2.2-2.3): a fully connected
+ *     network from (log10 eps, theta) to the m weights and the momentum.
+ *
+ * Conventions shared by every call
+ *   - Every vector, weight array and gradient is a DEVICE pointer owned by the
+ *     caller.  Host pointers are marked "host".  The library owns only its
+ *     context, plans and internal scratch.
+ *   - A batch of B instances is packed back to back in instance order; instance
+ *     b has n_b x n_b interior unknowns stored row-major as u[j][i] with i (the
+ *     x index) fastest and y increasing with j; h = 1/(n_b + 1).  P_tot is the
+ *     sum of n_b^2.  Boundary values are never stored (they are zero).
+ *   - Weight arrays omega[B][m], alpha[B][m] are row-major; inner step s of a
+ *     solve uses index i = s mod m, so omega[b][0] is applied first (the order
+ *     T_m = (I - omega_m A) ... (I - omega_1 A) of eq. Chebyshev(m)T).  The
+ *     library never reorders weights.
+ *   - All work is enqueued on the stream given to rm_create.  Calls return as
+ *     soon as the work is enqueued, except where a call says it blocks.
+ *   - Errors: a non-zero rm_status is returned, nothing is thrown.  Argument
+ *     errors are detected on the host before anything is launched (RM_EINVAL).
+ *     RM_EHIP means a HIP runtime call failed; rm_last_error() describes it.
+ *   - A context and its plans may be used from one host thread at a time.
+ */
+#ifndef RM_H
+#define RM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RM_OK = 0,
+  RM_EINVAL = 1,       /* bad argument; nothing was launched                    */
+  RM_ENOMEM = 2,       /* device allocation failed                             */
+  RM_EHIP = 3,         /* a HIP runtime call failed                            */
+  RM_ENOTCONV = 4,     /* an instance hit its iteration or round cap           */
+  RM_EDIVERGED = 5,    /* an instance produced a non-finite or growing residual */
+  RM_EUNSUPPORTED = 6  /* valid request this build does not implement          */
+} rm_status;
+
+typedef enum { RM_Q1_ANISO = 0, RM_FD5_HELMHOLTZ = 1 } rm_op;
+
+/* Table 1 of the paper, last column.  RM_RICHARDSON ignores alpha. */
+typedef enum { RM_RICHARDSON = 0, RM_NAG = 1 } rm_method;
+
+typedef enum { RM_F32 = 0, RM_F64 = 1 } rm_dtype;
+
+typedef enum {
+  RM_UNROLL = 0,  /* exactly K inner steps from (x0, v = 0), optional checkpoints */
+  RM_TO_TOL = 1   /* FP32 sweeps inside FP64 iterative refinement, until tol      */
+} rm_mode;
+
+/* One problem instance (host).  op = RM_Q1_ANISO uses eps in (0, 1] and theta;
+ * op = RM_FD5_HELMHOLTZ uses kappa (constant wavenumber, no sponge layer). */
+typedef struct {
+  int32_t n;       /* interior nodes per direction, 1 <= n <= 16384 */
+  int32_t op;      /* rm_op */
+  double eps;
+  double theta;
+  double kappa;
+} rm_instance;
+
+typedef struct {
+  int32_t mode;        /* rm_mode                                                 */
+  int32_t dtype;       /* RM_UNROLL: precision of the sweeps (RM_F32 or RM_F64)   */
+  int32_t m;           /* inner steps per outer iteration, 1..64                  */
+  int32_t K;           /* RM_UNROLL: inner steps, a multiple of m                 */
+  int32_t ckpt_every;  /* RM_UNROLL: checkpoint spacing (divides K), 0 = none     */
+  int32_t max_outer;   /* RM_TO_TOL: outer iterations per refinement round, cap   */
+  int32_t max_rounds;  /* RM_TO_TOL: refinement rounds, cap                       */
+  int32_t check_every; /* RM_TO_TOL: outer iterations between host polls (>= 1)   */
+  double tol;          /* RM_TO_TOL: target ||b - A x|| / ||b|| (FP64)            */
+  double tol_inner;    /* RM_TO_TOL: inner relative residual that ends a round    */
+} rm_solve_opts;
+
+/* Per-instance results of RM_TO_TOL (host arrays of length B, any may be NULL). */
+typedef struct {
+  int32_t* outer_iters;  /* outer iterations summed over all rounds          */
+  int32_t* rounds;       /* refinement rounds used                           */
+  double* relres;        /* final ||b - A x|| / ||b|| computed in FP64       */
+  int32_t* status;       /* RM_OK, RM_ENOTCONV or RM_EDIVERGED per instance  */
+} rm_report;
+
+typedef struct rm_ctx rm_ctx;
+typedef struct rm_plan_s rm_plan_t;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the handle. */
+rm_status rm_create(rm_ctx** out, int32_t device, void* hip_stream);
+rm_status rm_destroy(rm_ctx* ctx);
+
+/* Build a plan for a batch (host array inst[B]).  Computes the stencil
+ * coefficients of every instance in FP64 (§2.3 / §3.2), the packed offsets and
+ * the tile table, and uploads them.  Rejects n < 1, n > 16384, eps outside
+ * (0, 1], non-finite parameters, unknown op. */
+rm_status rm_plan(rm_ctx* ctx, int32_t B, const rm_instance* inst, rm_plan_t** out);
+rm_status rm_plan_free(rm_plan_t* plan);
+
+/* Host queries: number of instances, P_tot, and the packed offsets
+ * (host array off[B + 1], off[0] = 0, off[B] = P_tot). */
+int32_t rm_plan_batch(const rm_plan_t* plan);
+int64_t rm_plan_points(const rm_plan_t* plan);
+rm_status rm_plan_offsets(const rm_plan_t* plan, int64_t* off);
+/* Host copy of the five stencil coefficients per instance (host coef[B][5]:
+ * centre, (+-1,0), (0,+-1), (1,1)/(-1,-1), (-1,1)/(1,-1)) and of the
+ * Gershgorin bound |centre| + sum |off-diagonal| (host gersh[B]). */
+rm_status rm_plan_coefficients(const rm_plan_t* plan, double* coef, double* gersh);
+
+/* y = A x for every instance (§2.3, §3.2).  x, y: device [P_tot] of `dtype`,
+ * must not overlap. */
+rm_status rm_apply_A(rm_ctx* ctx, const rm_plan_t* plan, int32_t dtype, const void* x, void* y);
+
+/* r = b - A x and, per instance, ||r||^2 and ||b||^2 accumulated in FP64, and the
+ * squared relative residual ||r||^2 / ||b||^2 (the per-instance loss of §2.2,
+ * eq. loss-fun-relative-res, squared).
+ * b, x: device [P_tot] of `dtype`; r: device [P_tot] of `dtype` or NULL (not
+ * stored); r2, b2: device double [B] or NULL; rel2: device float [B] or NULL. */
+rm_status rm_residual(rm_ctx* ctx, const rm_plan_t* plan, int32_t dtype, const void* b,
+                      const void* x, void* r, double* r2, double* b2, float* rel2);
+
+/* Batched Richardson(m) / NAG-Richardson(m) (Table 1, last column; §2.3 evaluation).
+ *
+ * RM_UNROLL (asynchronous): K inner steps from u = x (in), v = 0, in opts->dtype.
+ *   b, x: device [P_tot] of opts->dtype; x is overwritten with u_K.
+ *   ckpt: device [K / ckpt_every][2][P_tot] of opts->dtype or NULL; slot c
+ *         receives (u, v) before step c * ckpt_every (slot 0 = (x0, 0)).
+ *   hist: device double [K / m][B] or NULL; receives ||b - A u||^2 after every
+ *         outer iteration (squared, not divided by ||b||^2).
+ *   rep is ignored.
+ * RM_TO_TOL (blocks until every instance is done): FP64 iterative refinement
+ *   around FP32 inner solves A d = fl32(b - A x) started from d = 0, v = 0, each
+ *   run in whole outer iterations until its relative residual is <= tol_inner
+ *   or max_outer is reached; x += d in FP64; stop when ||b - A x|| / ||b|| <= tol.
+ *   b, x: device double [P_tot]; x holds the initial guess and receives the
+ *   result.  ckpt and hist must be NULL.  rep (host) receives per-instance
+ *   counts, final FP64 relative residuals and status; the call returns the
+ *   worst per-instance status.
+ * omega: device float [B][m]; alpha: device float [B][m] (ignored, may be NULL,
+ * for RM_RICHARDSON). */
+rm_status rm_solve(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, const rm_solve_opts* opts,
+                   const float* omega, const float* alpha, const void* b, void* x, void* ckpt,
+                   double* hist, rm_report* rep);
+
+/* Reverse mode through the K-step FP32 unroll that rm_solve(RM_UNROLL) performed
+ * with the same plan, method, opts, omega, alpha, b and its checkpoints ckpt
+ * (opts->ckpt_every > 0 required).  Forward states are recomputed one
+ * checkpoint segment at a time; A is symmetric, so the backward sweep applies
+ * the same stencil.
+ *   g_uK:  device float [P_tot], the seed dJ/du_K; or NULL for the loss mode
+ *          J = sum_b g_loss[b] * ||b - A u_K||^2 / ||b||^2.
+ *   g_loss: device float [B] (loss mode only; NULL = all ones).
+ *   d_omega, d_alpha: device float [B][m], overwritten with dJ/domega, dJ/dalpha.
+ *   d_b: device float [P_tot] or NULL, overwritten with dJ/db.
+ *   loss: device float [B] or NULL (loss mode: ||b - A u_K||^2 / ||b||^2).
+ * Asynchronous.  Dot products are accumulated per tile in FP64 and summed in a
+ * fixed order, so repeated calls give bitwise identical results. */
+rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
+                           const rm_solve_opts* opts, const float* omega, const float* alpha,
+                           const float* b, const void* ckpt, const float* g_uK,
+                           const float* g_loss, float* d_omega, float* d_alpha, float* d_b,
+                           float* loss);
+
+/* Meta network (§2.2-2.3).  params: device float [5457 for m = 16; in general
+ * 64*2 + 64 + 64*64 + 64 + (m+1)*64 + (m+1)], layout
+ *   W1[64][2], b1[64], W2[64][64], b2[64], W3[m+1][64], b3[m+1]  (out x in).
+ * Input of instance b is (log10 eps_b, theta_b) taken from the plan (Q1
+ * instances; Helmholtz instances use (0, kappa)).  Forward:
+ *   z = W3 tanh(W2 tanh(W1 x + b1) + b2) + b3,
+ *   omega[b][i] = exp(z_i) / G_b (G_b the Gershgorin bound), alpha[b][i] = 1/(1+exp(-z_m)).
+ * omega, alpha: device float [B][m] outputs. */
+rm_status rm_meta_forward(rm_ctx* ctx, const rm_plan_t* plan, int32_t m, const float* params,
+                          float* omega, float* alpha);
+/* Gradient of sum_b <d_omega_b, omega_b> + <d_alpha_b, alpha_b> with respect to
+ * params, summed over the batch in a fixed order.  d_params: device float
+ * [n_params], overwritten. */
+rm_status rm_meta_backward(rm_ctx* ctx, const rm_plan_t* plan, int32_t m, const float* params,
+                           const float* d_omega, const float* d_alpha, float* d_params);
+
+/* Number of meta-network parameters for a given m. */
+int32_t rm_meta_param_count(int32_t m);
+
+const char* rm_status_string(rm_status s);
+/* Text of the last error recorded on this thread (argument or HIP error). */
+const char* rm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RM_H */

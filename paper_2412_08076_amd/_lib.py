@@ -1,0 +1,79 @@
+"""ctypes view of librm.so (include/rm.h).  Loading fails loudly when the HIP
+library has not been built: there is no CPU fallback."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librm.so")
+
+RM_OK, RM_EINVAL, RM_ENOMEM, RM_EHIP, RM_ENOTCONV, RM_EDIVERGED, RM_EUNSUPPORTED = range(7)
+RM_Q1_ANISO, RM_FD5_HELMHOLTZ = 0, 1
+RM_RICHARDSON, RM_NAG = 0, 1
+RM_F32, RM_F64 = 0, 1
+RM_UNROLL, RM_TO_TOL = 0, 1
+
+# every symbol include/rm.h declares
+EXPORTS = [
+    "rm_create", "rm_destroy", "rm_plan", "rm_plan_free", "rm_plan_batch", "rm_plan_points",
+    "rm_plan_offsets", "rm_plan_coefficients", "rm_apply_A", "rm_residual", "rm_solve",
+    "rm_solve_adjoint", "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count",
+    "rm_status_string", "rm_last_error",
+]
+
+
+class rm_instance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("op", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("theta", ctypes.c_double), ("kappa", ctypes.c_double)]
+
+
+class rm_solve_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("dtype", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("ckpt_every", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("max_rounds", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("tol_inner", ctypes.c_double)]
+
+
+class rm_report(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.POINTER(ctypes.c_int32)), ("rounds", ctypes.POINTER(ctypes.c_int32)),
+                ("relres", ctypes.POINTER(ctypes.c_double)), ("status", ctypes.POINTER(ctypes.c_int32))]
+
+
+_lib = None
+
+
+def load():
+    """Load librm.so once and declare every signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2412_08076_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    st = ctypes.c_int32
+    sig = {
+        "rm_create": (st, [ctypes.POINTER(P), I32, P]),
+        "rm_destroy": (st, [P]),
+        "rm_plan": (st, [P, I32, ctypes.POINTER(rm_instance), ctypes.POINTER(P)]),
+        "rm_plan_free": (st, [P]),
+        "rm_plan_batch": (I32, [P]),
+        "rm_plan_points": (I64, [P]),
+        "rm_plan_offsets": (st, [P, ctypes.POINTER(I64)]),
+        "rm_plan_coefficients": (st, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
+        "rm_apply_A": (st, [P, P, I32, P, P]),
+        "rm_residual": (st, [P, P, I32, P, P, P, P, P, P]),
+        "rm_solve": (st, [P, P, I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P, P,
+                          ctypes.POINTER(rm_report)]),
+        "rm_solve_adjoint": (st, [P, P, I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P, P, P, P, P, P]),
+        "rm_meta_forward": (st, [P, P, I32, P, P, P]),
+        "rm_meta_backward": (st, [P, P, I32, P, P, P, P]),
+        "rm_meta_param_count": (I32, [I32]),
+        "rm_status_string": (ctypes.c_char_p, [st]),
+        "rm_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

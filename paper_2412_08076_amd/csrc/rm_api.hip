@@ -1,0 +1,656 @@
+// C-ABI of the long-step Richardson(m) library (declared in include/rm.h):
+// contexts, plans (stencil coefficients and tile tables), and the host drivers of
+// the unrolled solve, the FP64-refined solve to tolerance, the adjoint and the
+// meta network.  All arithmetic on vectors runs in the kernels of rm_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rm.h"
+#include "rm_internal.h"
+
+using rmk::Inst;
+using rmk::PlanDev;
+using rmk::Tile;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rm_status fail(rm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define RM_HIP(expr)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(RM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));                 \
+  } while (0)
+
+#define RM_TRY(expr)            \
+  do {                          \
+    rm_status s_ = (expr);      \
+    if (s_ != RM_OK) return s_; \
+  } while (0)
+
+// Growable device buffer owned by a plan.  Growing synchronises the stream first
+// so that no enqueued kernel still references the old allocation.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  rm_status ensure(size_t need, hipStream_t st) {
+    if (need <= bytes) return RM_OK;
+    if (ptr != nullptr) {
+      RM_HIP(hipStreamSynchronize(st));
+      RM_HIP(hipFree(ptr));
+      ptr = nullptr;
+      bytes = 0;
+    }
+    if (hipMalloc(&ptr, need) != hipSuccess) {
+      ptr = nullptr;
+      (void)hipGetLastError();
+      return fail(RM_ENOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed");
+    }
+    bytes = need;
+    return RM_OK;
+  }
+  void release() {
+    if (ptr != nullptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(ptr);
+  }
+};
+
+}  // namespace
+
+struct rm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int* host_flag = nullptr;  // pinned, polled by the refined solve
+};
+
+struct rm_plan_s {
+  rm_ctx* ctx = nullptr;
+  int B = 0;
+  int64_t P = 0;
+  std::vector<rm_instance> inst;
+  std::vector<int64_t> off;
+  std::vector<double> coef;   // [B][8]
+  std::vector<double> gersh;  // [B]
+  std::vector<Tile> tiles;
+  std::vector<Inst> insts;
+  // device copies
+  DevBuf d_tiles, d_inst, d_coef32, d_coef64, d_mu, d_gersh;
+  // scratch
+  DevBuf partial, red, flags, vecA, vecB, vecC, vecD, vecE, vecF, states, acc, meta;
+  PlanDev dev() const {
+    PlanDev p;
+    p.tiles = d_tiles.as<Tile>();
+    p.ntiles = (int)tiles.size();
+    p.inst = d_inst.as<Inst>();
+    p.B = B;
+    p.coef32 = d_coef32.as<float>();
+    p.coef64 = d_coef64.as<double>();
+    p.mu = d_mu.as<float>();
+    p.gersh = d_gersh.as<float>();
+    return p;
+  }
+  ~rm_plan_s() {
+    for (DevBuf* b : {&d_tiles, &d_inst, &d_coef32, &d_coef64, &d_mu, &d_gersh, &partial, &red, &flags, &vecA,
+                      &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta})
+      b->release();
+  }
+};
+
+namespace {
+
+constexpr int kMaxN = 16384;
+constexpr int kMaxM = 64;
+
+// Stencil coefficients of one instance (slots: centre, (+-1,0), (0,+-1),
+// (1,1)/(-1,-1), (-1,1)/(1,-1)).
+// Q1 (§2.3): C = R diag(1, eps) R^T = [[a, b], [b, c]]; exact element integrals of
+// bilinear shape functions on a square give the h-free row below.
+// Helmholtz (§3.2): (1/h^2) [0 -1 0; -1 4 - kappa^2 h^2 -1; 0 -1 0], h = 1/(n+1).
+void stencil_coefficients(const rm_instance& in, double out[8]) {
+  std::fill(out, out + 8, 0.0);
+  if (in.op == RM_Q1_ANISO) {
+    const double cs = std::cos(in.theta), sn = std::sin(in.theta), e = in.eps;
+    const double a = cs * cs + e * sn * sn;
+    const double b = (1.0 - e) * sn * cs;
+    const double c = sn * sn + e * cs * cs;
+    out[0] = 4.0 * (a + c) / 3.0;
+    out[1] = (c - 2.0 * a) / 3.0;
+    out[2] = (a - 2.0 * c) / 3.0;
+    out[3] = -(a + c) / 6.0 - 0.5 * b;
+    out[4] = -(a + c) / 6.0 + 0.5 * b;
+  } else {
+    const double h = 1.0 / (in.n + 1.0);
+    const double ih2 = 1.0 / (h * h);
+    out[0] = 4.0 * ih2 - in.kappa * in.kappa;
+    out[1] = -ih2;
+    out[2] = -ih2;
+  }
+}
+
+rm_status check_ctx_plan(rm_ctx* ctx, const rm_plan_t* plan) {
+  if (ctx == nullptr) return fail(RM_EINVAL, "null context");
+  if (plan == nullptr) return fail(RM_EINVAL, "null plan");
+  if (plan->ctx != ctx) return fail(RM_EINVAL, "plan belongs to another context");
+  return RM_OK;
+}
+
+rm_status last_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RM_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return RM_OK;
+}
+
+template <typename T>
+size_t vec_bytes(const rm_plan_t* p) {
+  return (size_t)std::max<int64_t>(p->P, 1) * sizeof(T);
+}
+
+// ---------------------------------------------------------------------------
+// unrolled solve: K inner steps from (x, 0)
+// ---------------------------------------------------------------------------
+template <typename T>
+rm_status solve_unroll(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_opts* o, const float* omega,
+                       const float* alpha, const T* b, T* x, T* ckpt, double* hist) {
+  hipStream_t st = ctx->stream;
+  const int64_t P = pl->P;
+  RM_TRY(pl->vecA.ensure(vec_bytes<T>(pl), st));
+  RM_TRY(pl->vecB.ensure(vec_bytes<T>(pl), st));
+  RM_TRY(pl->vecC.ensure(vec_bytes<T>(pl), st));
+  RM_TRY(pl->partial.ensure(pl->tiles.size() * 2 * sizeof(double), st));
+  T* v0 = pl->vecA.as<T>();
+  T* u1 = pl->vecB.as<T>();
+  T* v1 = pl->vecC.as<T>();
+  T* us[2] = {x, u1};
+  T* vs[2] = {v0, v1};
+  const PlanDev p = pl->dev();
+  if (sizeof(T) == 4) {
+    rmk::launch_fill_f32((float*)v0, 0.f, P, st);
+    rmk::launch_fill_f32((float*)v1, 0.f, P, st);
+  } else {
+    rmk::launch_fill_f64((double*)v0, 0.0, P, st);
+    rmk::launch_fill_f64((double*)v1, 0.0, P, st);
+  }
+  const int E = o->ckpt_every;
+  for (int s = 0; s < o->K; ++s) {
+    const int cur = s & 1, nxt = cur ^ 1;
+    if (ckpt != nullptr && E > 0 && s % E == 0) {
+      T* slot = ckpt + (int64_t)(s / E) * 2 * P;
+      RM_HIP(hipMemcpyAsync(slot, us[cur], P * sizeof(T), hipMemcpyDeviceToDevice, st));
+      RM_HIP(hipMemcpyAsync(slot + P, vs[cur], P * sizeof(T), hipMemcpyDeviceToDevice, st));
+    }
+    rmk::launch_step<T>(method, p, p.tiles, p.ntiles, omega, alpha, o->m, s % o->m, b, us[cur], vs[cur],
+                        us[nxt], vs[nxt], nullptr, st);
+    if (hist != nullptr && (s + 1) % o->m == 0) {
+      const int k = (s + 1) / o->m - 1;
+      rmk::launch_residual<T>(p, p.tiles, p.ntiles, b, us[nxt], nullptr, pl->partial.as<double>(), nullptr, st);
+      rmk::launch_reduce_partials(p, pl->partial.as<double>(), hist + (int64_t)k * pl->B, nullptr, 1, nullptr, st);
+    }
+  }
+  if (o->K & 1) RM_HIP(hipMemcpyAsync(x, u1, P * sizeof(T), hipMemcpyDeviceToDevice, st));
+  return last_launch();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 iterative refinement around FP32 inner solves (blocks)
+// ---------------------------------------------------------------------------
+rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_opts* o, const float* omega,
+                       const float* alpha, const double* b, double* x, rm_report* rep) {
+  hipStream_t st = ctx->stream;
+  const int B = pl->B;
+  const size_t fb = vec_bytes<float>(pl);
+  RM_TRY(pl->vecA.ensure(fb, st));  // r32
+  RM_TRY(pl->vecB.ensure(fb, st));  // d0
+  RM_TRY(pl->vecC.ensure(fb, st));  // v0
+  RM_TRY(pl->vecD.ensure(fb, st));  // d1
+  RM_TRY(pl->vecE.ensure(fb, st));  // v1
+  RM_TRY(pl->partial.ensure(pl->tiles.size() * 2 * sizeof(double), st));
+  RM_TRY(pl->red.ensure((size_t)B * 4 * sizeof(double), st));
+  RM_TRY(pl->flags.ensure(((size_t)B * 4 + 16) * sizeof(int), st));
+  float* r32 = pl->vecA.as<float>();
+  float* ds[2] = {pl->vecB.as<float>(), pl->vecD.as<float>()};
+  float* vs[2] = {pl->vecC.as<float>(), pl->vecE.as<float>()};
+  double* r2 = pl->red.as<double>();      // [B]  ||b - A x||^2 (FP64)
+  double* b2 = r2 + B;                    // [B]  ||b||^2
+  double* rhs2 = r2 + 2 * B;              // [B]  ||r_j||^2 of the current round
+  double* res2 = r2 + 3 * B;              // [B]  inner residual^2 after an outer iteration
+  int* active = pl->flags.as<int>();      // [B]
+  int* count = active + B;                // [B]
+  int* status = active + 2 * B;           // [B]
+  int* mask = active + 3 * B;             // [B]
+  int* n_active = active + 4 * B;         // [1]
+  double* partial = pl->partial.as<double>();
+  const PlanDev p = pl->dev();
+
+  std::vector<int> done(B, 0), st_h(B, RM_OK), dst_h(B, 0), rounds(B, 0), mask_h(B, 1), cnt_h(B, 0);
+  std::vector<long long> outer_tot(B, 0);
+  std::vector<double> r2_h(B), b2_h(B), relres(B, 0.0);
+  rmk::launch_fill_i32(status, 0, B, st);
+  RM_HIP(hipMemcpyAsync(mask, mask_h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+  const double tol_in2 = o->tol_inner * o->tol_inner;
+  for (int j = 0;; ++j) {
+    if (j > 0) rmk::launch_refine_update(p, x, ds[0], ds[1], count, o->m, mask, st);
+    rmk::launch_refine_residual(p, b, x, r32, ds[0], vs[0], partial, mask, st);
+    rmk::launch_reduce_partials(p, partial, r2, b2, 1, nullptr, st);
+    RM_HIP(hipMemcpyAsync(r2_h.data(), r2, B * sizeof(double), hipMemcpyDeviceToHost, st));
+    RM_HIP(hipMemcpyAsync(b2_h.data(), b2, B * sizeof(double), hipMemcpyDeviceToHost, st));
+    RM_HIP(hipMemcpyAsync(dst_h.data(), status, B * sizeof(int), hipMemcpyDeviceToHost, st));
+    RM_HIP(hipStreamSynchronize(st));
+    RM_TRY(last_launch());
+    int n_round = 0;
+    for (int bi = 0; bi < B; ++bi) {
+      if (done[bi]) {
+        mask_h[bi] = 0;
+        continue;
+      }
+      const double rho = b2_h[bi] > 0.0 ? std::sqrt(r2_h[bi] / b2_h[bi]) : std::sqrt(r2_h[bi]);
+      relres[bi] = rho;
+      if (!std::isfinite(rho) || dst_h[bi] == RM_EDIVERGED) {
+        done[bi] = 1;
+        st_h[bi] = RM_EDIVERGED;
+      } else if (rho <= o->tol || r2_h[bi] == 0.0) {
+        done[bi] = 1;
+        st_h[bi] = RM_OK;
+      } else if (j >= o->max_rounds) {
+        done[bi] = 1;
+        st_h[bi] = RM_ENOTCONV;
+      }
+      mask_h[bi] = done[bi] ? 0 : 1;
+      if (!done[bi]) {
+        ++n_round;
+        ++rounds[bi];
+      }
+    }
+    if (n_round == 0) break;
+    // inner solve A d = r32 on the instances of this round
+    RM_HIP(hipMemcpyAsync(mask, mask_h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+    RM_HIP(hipMemcpyAsync(active, mask, B * sizeof(int), hipMemcpyDeviceToDevice, st));
+    RM_HIP(hipMemcpyAsync(rhs2, r2, B * sizeof(double), hipMemcpyDeviceToDevice, st));
+    rmk::launch_fill_i32(count, 0, B, st);
+    int cur = 0;
+    for (int k = 1;; ++k) {
+      for (int i = 0; i < o->m; ++i) {
+        rmk::launch_step<float>(method, p, p.tiles, p.ntiles, omega, alpha, o->m, i, r32, ds[cur], vs[cur],
+                                ds[cur ^ 1], vs[cur ^ 1], active, st);
+        cur ^= 1;
+      }
+      rmk::launch_residual<float>(p, p.tiles, p.ntiles, r32, ds[cur], nullptr, partial, active, st);
+      rmk::launch_reduce_partials(p, partial, res2, nullptr, 1, nullptr, st);
+      rmk::launch_fill_i32(n_active, 0, 1, st);
+      rmk::launch_inner_flags(B, res2, rhs2, tol_in2, o->max_outer, active, count, status, n_active, st);
+      if (k % o->check_every == 0 || k >= o->max_outer) {
+        RM_HIP(hipMemcpyAsync(ctx->host_flag, n_active, sizeof(int), hipMemcpyDeviceToHost, st));
+        RM_HIP(hipStreamSynchronize(st));
+        if (*ctx->host_flag == 0) break;
+      }
+    }
+    RM_HIP(hipMemcpyAsync(cnt_h.data(), count, B * sizeof(int), hipMemcpyDeviceToHost, st));
+    RM_HIP(hipStreamSynchronize(st));
+    for (int bi = 0; bi < B; ++bi)
+      if (mask_h[bi]) outer_tot[bi] += cnt_h[bi];
+  }
+  rm_status worst = RM_OK;
+  for (int bi = 0; bi < B; ++bi) {
+    if (st_h[bi] == RM_EDIVERGED) worst = RM_EDIVERGED;
+    else if (st_h[bi] == RM_ENOTCONV && worst == RM_OK) worst = RM_ENOTCONV;
+  }
+  if (rep != nullptr) {
+    for (int bi = 0; bi < B; ++bi) {
+      if (rep->outer_iters) rep->outer_iters[bi] = (int32_t)std::min<long long>(outer_tot[bi], INT32_MAX);
+      if (rep->rounds) rep->rounds[bi] = rounds[bi];
+      if (rep->relres) rep->relres[bi] = relres[bi];
+      if (rep->status) rep->status[bi] = st_h[bi];
+    }
+  }
+  RM_TRY(last_launch());
+  if (worst != RM_OK) g_last_error = worst == RM_EDIVERGED ? "an instance diverged" : "an instance hit a cap";
+  return worst;
+}
+
+rm_status validate_weights(const rm_plan_t* pl, int method, const rm_solve_opts* o, const float* omega,
+                           const float* alpha) {
+  if (o == nullptr) return fail(RM_EINVAL, "null opts");
+  if (method != RM_RICHARDSON && method != RM_NAG) return fail(RM_EINVAL, "unknown method");
+  if (o->m < 1 || o->m > kMaxM) return fail(RM_EINVAL, "m must be in 1..64");
+  if (omega == nullptr) return fail(RM_EINVAL, "null omega");
+  if (method == RM_NAG && alpha == nullptr) return fail(RM_EINVAL, "NAG needs alpha");
+  (void)pl;
+  return RM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rm_status_string(rm_status s) {
+  switch (s) {
+    case RM_OK: return "ok";
+    case RM_EINVAL: return "invalid argument";
+    case RM_ENOMEM: return "out of device memory";
+    case RM_EHIP: return "HIP runtime error";
+    case RM_ENOTCONV: return "not converged within the caps";
+    case RM_EDIVERGED: return "diverged";
+    case RM_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* rm_last_error(void) { return g_last_error.c_str(); }
+
+rm_status rm_create(rm_ctx** out, int32_t device, void* hip_stream) {
+  if (out == nullptr) return fail(RM_EINVAL, "null output handle");
+  int ndev = 0;
+  RM_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(RM_EINVAL, "no such device");
+  RM_HIP(hipSetDevice(device));
+  rm_ctx* c = new rm_ctx;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipHostMalloc((void**)&c->host_flag, sizeof(int) * 16, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(RM_ENOMEM, "pinned host allocation failed");
+  }
+  *out = c;
+  return RM_OK;
+}
+
+rm_status rm_destroy(rm_ctx* ctx) {
+  if (ctx == nullptr) return RM_OK;
+  if (ctx->host_flag != nullptr) (void)hipHostFree(ctx->host_flag);
+  delete ctx;
+  return RM_OK;
+}
+
+rm_status rm_plan(rm_ctx* ctx, int32_t B, const rm_instance* inst, rm_plan_t** out) {
+  if (ctx == nullptr || out == nullptr) return fail(RM_EINVAL, "null context or output handle");
+  if (B < 1 || inst == nullptr) return fail(RM_EINVAL, "need B >= 1 instances");
+  for (int b = 0; b < B; ++b) {
+    const rm_instance& in = inst[b];
+    if (in.n < 1 || in.n > kMaxN) return fail(RM_EINVAL, "instance " + std::to_string(b) + ": n out of range");
+    if (in.op == RM_Q1_ANISO) {
+      if (!(in.eps > 0.0 && in.eps <= 1.0) || !std::isfinite(in.theta))
+        return fail(RM_EINVAL, "instance " + std::to_string(b) + ": eps must be in (0, 1], theta finite");
+    } else if (in.op == RM_FD5_HELMHOLTZ) {
+      if (!std::isfinite(in.kappa) || in.kappa < 0.0)
+        return fail(RM_EINVAL, "instance " + std::to_string(b) + ": kappa must be finite and >= 0");
+    } else {
+      return fail(RM_EINVAL, "instance " + std::to_string(b) + ": unknown op");
+    }
+  }
+  RM_HIP(hipSetDevice(ctx->device));
+  rm_plan_t* pl = new rm_plan_t;
+  pl->ctx = ctx;
+  pl->B = B;
+  pl->inst.assign(inst, inst + B);
+  pl->off.assign(B + 1, 0);
+  pl->coef.assign((size_t)B * 8, 0.0);
+  pl->gersh.assign(B, 0.0);
+  std::vector<float> coef32((size_t)B * 8, 0.f), mu((size_t)B * 2), g32(B);
+  pl->insts.resize(B);
+  for (int b = 0; b < B; ++b) {
+    const int n = inst[b].n;
+    pl->off[b + 1] = pl->off[b] + (int64_t)n * n;
+    double* c = &pl->coef[(size_t)b * 8];
+    stencil_coefficients(inst[b], c);
+    pl->gersh[b] = std::fabs(c[0]) + 2.0 * (std::fabs(c[1]) + std::fabs(c[2]) + std::fabs(c[3]) + std::fabs(c[4]));
+    for (int k = 0; k < 8; ++k) coef32[(size_t)b * 8 + k] = (float)c[k];
+    g32[b] = (float)pl->gersh[b];
+    if (inst[b].op == RM_Q1_ANISO) {
+      mu[2 * b] = (float)std::log10(inst[b].eps);
+      mu[2 * b + 1] = (float)inst[b].theta;
+    } else {
+      mu[2 * b] = 0.f;
+      mu[2 * b + 1] = (float)inst[b].kappa;
+    }
+    Inst& I = pl->insts[b];
+    I.off = pl->off[b];
+    I.n = n;
+    I.tile_begin = (int)pl->tiles.size();
+    for (int y0 = 0; y0 < n; y0 += rmk::TY)
+      for (int x0 = 0; x0 < n; x0 += rmk::TX) pl->tiles.push_back(Tile{b, x0, y0, (int)pl->tiles.size()});
+    I.tile_end = (int)pl->tiles.size();
+    I.pad = 0;
+  }
+  while (pl->tiles.size() % 8 != 0) pl->tiles.push_back(Tile{-1, 0, 0, (int)pl->tiles.size()});
+  pl->P = pl->off[B];
+  hipStream_t st = ctx->stream;
+  rm_status s = RM_OK;
+  auto up = [&](DevBuf& d, const void* src, size_t bytes) {
+    if (s != RM_OK) return;
+    s = d.ensure(bytes, st);
+    if (s != RM_OK) return;
+    if (hipMemcpy(d.ptr, src, bytes, hipMemcpyHostToDevice) != hipSuccess) s = fail(RM_EHIP, "plan upload failed");
+  };
+  up(pl->d_tiles, pl->tiles.data(), pl->tiles.size() * sizeof(Tile));
+  up(pl->d_inst, pl->insts.data(), pl->insts.size() * sizeof(Inst));
+  up(pl->d_coef32, coef32.data(), coef32.size() * sizeof(float));
+  up(pl->d_coef64, pl->coef.data(), pl->coef.size() * sizeof(double));
+  up(pl->d_mu, mu.data(), mu.size() * sizeof(float));
+  up(pl->d_gersh, g32.data(), g32.size() * sizeof(float));
+  if (s != RM_OK) {
+    delete pl;
+    return s;
+  }
+  *out = pl;
+  return RM_OK;
+}
+
+rm_status rm_plan_free(rm_plan_t* plan) {
+  if (plan == nullptr) return RM_OK;
+  if (plan->ctx != nullptr) (void)hipStreamSynchronize(plan->ctx->stream);
+  delete plan;
+  return RM_OK;
+}
+
+int32_t rm_plan_batch(const rm_plan_t* plan) { return plan == nullptr ? -1 : plan->B; }
+int64_t rm_plan_points(const rm_plan_t* plan) { return plan == nullptr ? -1 : plan->P; }
+
+rm_status rm_plan_offsets(const rm_plan_t* plan, int64_t* off) {
+  if (plan == nullptr || off == nullptr) return fail(RM_EINVAL, "null argument");
+  std::memcpy(off, plan->off.data(), plan->off.size() * sizeof(int64_t));
+  return RM_OK;
+}
+
+rm_status rm_plan_coefficients(const rm_plan_t* plan, double* coef, double* gersh) {
+  if (plan == nullptr) return fail(RM_EINVAL, "null plan");
+  for (int b = 0; b < plan->B; ++b) {
+    if (coef != nullptr)
+      for (int k = 0; k < 5; ++k) coef[b * 5 + k] = plan->coef[(size_t)b * 8 + k];
+    if (gersh != nullptr) gersh[b] = plan->gersh[b];
+  }
+  return RM_OK;
+}
+
+rm_status rm_apply_A(rm_ctx* ctx, const rm_plan_t* plan, int32_t dtype, const void* x, void* y) {
+  RM_TRY(check_ctx_plan(ctx, plan));
+  if (x == nullptr || y == nullptr) return fail(RM_EINVAL, "null vector");
+  if (x == y) return fail(RM_EINVAL, "x and y must not overlap");
+  const PlanDev p = plan->dev();
+  if (dtype == RM_F32)
+    rmk::launch_apply<float>(p, p.tiles, p.ntiles, (const float*)x, (float*)y, ctx->stream);
+  else if (dtype == RM_F64)
+    rmk::launch_apply<double>(p, p.tiles, p.ntiles, (const double*)x, (double*)y, ctx->stream);
+  else
+    return fail(RM_EINVAL, "unknown dtype");
+  return last_launch();
+}
+
+rm_status rm_residual(rm_ctx* ctx, const rm_plan_t* plan, int32_t dtype, const void* b, const void* x, void* r,
+                      double* r2, double* b2, float* rel2) {
+  RM_TRY(check_ctx_plan(ctx, plan));
+  if (b == nullptr || x == nullptr) return fail(RM_EINVAL, "null vector");
+  if (r != nullptr && r == x) return fail(RM_EINVAL, "r and x must not overlap");
+  rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
+  RM_TRY(pl->partial.ensure(pl->tiles.size() * 2 * sizeof(double), ctx->stream));
+  const PlanDev p = pl->dev();
+  double* part = pl->partial.as<double>();
+  if (dtype == RM_F32)
+    rmk::launch_residual<float>(p, p.tiles, p.ntiles, (const float*)b, (const float*)x, (float*)r, part, nullptr,
+                                ctx->stream);
+  else if (dtype == RM_F64)
+    rmk::launch_residual<double>(p, p.tiles, p.ntiles, (const double*)b, (const double*)x, (double*)r, part,
+                                 nullptr, ctx->stream);
+  else
+    return fail(RM_EINVAL, "unknown dtype");
+  if (r2 != nullptr || b2 != nullptr || rel2 != nullptr)
+    rmk::launch_reduce_partials(p, part, r2, b2, 1, rel2, ctx->stream);
+  return last_launch();
+}
+
+rm_status rm_solve(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, const rm_solve_opts* opts,
+                   const float* omega, const float* alpha, const void* b, void* x, void* ckpt, double* hist,
+                   rm_report* rep) {
+  RM_TRY(check_ctx_plan(ctx, plan));
+  RM_TRY(validate_weights(plan, method, opts, omega, alpha));
+  if (b == nullptr || x == nullptr) return fail(RM_EINVAL, "null b or x");
+  rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
+  const int m = opts->m;
+  if (opts->mode == RM_UNROLL) {
+    if (opts->K < 0 || opts->K % m != 0) return fail(RM_EINVAL, "K must be a non-negative multiple of m");
+    if (opts->ckpt_every < 0 || (opts->ckpt_every > 0 && opts->K % opts->ckpt_every != 0))
+      return fail(RM_EINVAL, "ckpt_every must divide K");
+    if (ckpt != nullptr && opts->ckpt_every == 0) return fail(RM_EINVAL, "ckpt given but ckpt_every = 0");
+    if (opts->dtype == RM_F32)
+      return solve_unroll<float>(ctx, pl, method, opts, omega, alpha, (const float*)b, (float*)x,
+                                 (float*)ckpt, hist);
+    if (opts->dtype == RM_F64)
+      return solve_unroll<double>(ctx, pl, method, opts, omega, alpha, (const double*)b, (double*)x,
+                                  (double*)ckpt, hist);
+    return fail(RM_EINVAL, "unknown dtype");
+  }
+  if (opts->mode == RM_TO_TOL) {
+    if (ckpt != nullptr || hist != nullptr) return fail(RM_EINVAL, "RM_TO_TOL takes no ckpt or hist");
+    if (!(opts->tol > 0.0) || !(opts->tol_inner > 0.0 && opts->tol_inner < 1.0))
+      return fail(RM_EINVAL, "need tol > 0 and 0 < tol_inner < 1");
+    if (opts->max_outer < 1 || opts->max_rounds < 1 || opts->check_every < 1)
+      return fail(RM_EINVAL, "max_outer, max_rounds and check_every must be >= 1");
+    return solve_to_tol(ctx, pl, method, opts, omega, alpha, (const double*)b, (double*)x, rep);
+  }
+  return fail(RM_EINVAL, "unknown mode");
+}
+
+rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, const rm_solve_opts* opts,
+                           const float* omega, const float* alpha, const float* b, const void* ckpt_v,
+                           const float* g_uK, const float* g_loss, float* d_omega, float* d_alpha, float* d_b,
+                           float* loss) {
+  RM_TRY(check_ctx_plan(ctx, plan));
+  RM_TRY(validate_weights(plan, method, opts, omega, alpha));
+  if (opts->mode != RM_UNROLL) return fail(RM_EINVAL, "the adjoint follows an RM_UNROLL solve");
+  if (opts->dtype != RM_F32) return fail(RM_EUNSUPPORTED, "the adjoint runs in FP32 only");
+  const int m = opts->m, K = opts->K, E = opts->ckpt_every;
+  if (K < 1 || K % m != 0) return fail(RM_EINVAL, "K must be a positive multiple of m");
+  if (E < 1 || K % E != 0) return fail(RM_EINVAL, "ckpt_every must be >= 1 and divide K");
+  if (b == nullptr || ckpt_v == nullptr || d_omega == nullptr || d_alpha == nullptr)
+    return fail(RM_EINVAL, "null b, ckpt, d_omega or d_alpha");
+  rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
+  hipStream_t st = ctx->stream;
+  const int B = pl->B;
+  const int64_t P = pl->P;
+  const float* ckpt = static_cast<const float*>(ckpt_v);
+  const size_t fbytes = vec_bytes<float>(pl);
+  RM_TRY(pl->states.ensure(fbytes * 2 * (size_t)(E + 1), st));
+  RM_TRY(pl->vecA.ensure(fbytes, st));  // ub0
+  RM_TRY(pl->vecB.ensure(fbytes, st));  // vb0
+  RM_TRY(pl->vecC.ensure(fbytes, st));  // ub1
+  RM_TRY(pl->vecD.ensure(fbytes, st));  // vb1
+  RM_TRY(pl->vecE.ensure(fbytes, st));  // r_K
+  RM_TRY(pl->partial.ensure(pl->tiles.size() * 2 * sizeof(double), st));
+  RM_TRY(pl->red.ensure((size_t)B * 4 * sizeof(double), st));
+  RM_TRY(pl->acc.ensure((size_t)B * m * 2 * sizeof(double), st));
+  float* S = pl->states.as<float>();  // slot t: (u, v) before step c*E + t, t = 1..E; slot 0 unused
+                                      // (the checkpoint itself serves as slot 0)
+  float* ubs[2] = {pl->vecA.as<float>(), pl->vecC.as<float>()};
+  float* vbs[2] = {pl->vecB.as<float>(), pl->vecD.as<float>()};
+  float* rK = pl->vecE.as<float>();
+  double* partial = pl->partial.as<double>();
+  double* r2b2 = pl->red.as<double>();
+  double* acc_w = pl->acc.as<double>();
+  double* acc_a = acc_w + (size_t)B * m;
+  const PlanDev p = pl->dev();
+  const int nseg = K / E;
+  auto su = [&](int c, int t) -> const float* { return t == 0 ? ckpt + (int64_t)c * 2 * P : S + (int64_t)t * 2 * P; };
+  auto sv = [&](int c, int t) -> const float* {
+    return t == 0 ? ckpt + (int64_t)c * 2 * P + P : S + (int64_t)t * 2 * P + P;
+  };
+  // forward recompute of segment c into slots 1..E-1; the last segment also
+  // produces slot E, the final state u_K
+  auto recompute = [&](int c) {
+    const int steps = c == nseg - 1 ? E : E - 1;
+    for (int t = 0; t < steps; ++t) {
+      float* uo = S + (int64_t)(t + 1) * 2 * P;
+      rmk::launch_step<float>(method, p, p.tiles, p.ntiles, omega, alpha, m, (c * E + t) % m, b, su(c, t), sv(c, t),
+                              uo, uo + P, nullptr, st);
+    }
+  };
+  rmk::launch_fill_f64(acc_w, 0.0, (int64_t)B * m * 2, st);
+  rmk::launch_fill_f32(vbs[0], 0.f, P, st);
+  // terminal values
+  recompute(nseg - 1);
+  const float* uK = S + (int64_t)E * 2 * P;
+  if (g_uK == nullptr) {
+    rmk::launch_residual<float>(p, p.tiles, p.ntiles, b, uK, rK, partial, nullptr, st);
+    rmk::launch_reduce_partials(p, partial, r2b2, r2b2 + 1, 2, nullptr, st);
+    rmk::launch_adj_terminal(p, b, rK, r2b2, g_loss, ubs[0], d_b, loss, st);
+  } else {
+    RM_HIP(hipMemcpyAsync(ubs[0], g_uK, P * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (d_b != nullptr) rmk::launch_fill_f32(d_b, 0.f, P, st);
+  }
+  int cur = 0;
+  for (int c = nseg - 1; c >= 0; --c) {
+    if (c != nseg - 1) recompute(c);
+    for (int t = E - 1; t >= 0; --t) {
+      const int i = (c * E + t) % m;
+      rmk::launch_adj_step(method, p, omega, alpha, m, i, b, su(c, t), sv(c, t), ubs[cur], vbs[cur],
+                           ubs[cur ^ 1], vbs[cur ^ 1], d_b, partial, st);
+      rmk::launch_adj_accumulate(p, partial, m, i, acc_w, acc_a, st);
+      cur ^= 1;
+    }
+  }
+  rmk::launch_f64_to_f32(acc_w, d_omega, (int64_t)B * m, st);
+  rmk::launch_f64_to_f32(acc_a, d_alpha, (int64_t)B * m, st);
+  return last_launch();
+}
+
+int32_t rm_meta_param_count(int32_t m) {
+  const int H = 64;
+  return H * 2 + H + H * H + H + (m + 1) * H + (m + 1);
+}
+
+rm_status rm_meta_forward(rm_ctx* ctx, const rm_plan_t* plan, int32_t m, const float* params, float* omega,
+                          float* alpha) {
+  RM_TRY(check_ctx_plan(ctx, plan));
+  if (m < 1 || m > kMaxM) return fail(RM_EINVAL, "m must be in 1..64");
+  if (params == nullptr || omega == nullptr || alpha == nullptr) return fail(RM_EINVAL, "null pointer");
+  rmk::launch_meta_forward(plan->dev(), m, params, omega, alpha, ctx->stream);
+  return last_launch();
+}
+
+rm_status rm_meta_backward(rm_ctx* ctx, const rm_plan_t* plan, int32_t m, const float* params,
+                           const float* d_omega, const float* d_alpha, float* d_params) {
+  RM_TRY(check_ctx_plan(ctx, plan));
+  if (m < 1 || m > kMaxM) return fail(RM_EINVAL, "m must be in 1..64");
+  if (params == nullptr || d_omega == nullptr || d_alpha == nullptr || d_params == nullptr)
+    return fail(RM_EINVAL, "null pointer");
+  rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
+  RM_TRY(pl->meta.ensure((size_t)pl->B * rm_meta_param_count(m) * sizeof(float), ctx->stream));
+  rmk::launch_meta_backward(pl->dev(), m, params, d_omega, d_alpha, pl->meta.as<float>(), d_params, ctx->stream);
+  return last_launch();
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal declarations shared by the kernels (rm_kernels.hip) and the C-ABI host
+// code (rm_api.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace rmk {
+
+// Output tile of the one-step kernels: TX columns (one wave64 wide) by TY rows,
+// computed by a workgroup of WG = 256 threads (4 waves, each thread owns one
+// column and TY/4 rows).
+constexpr int TX = 64;
+constexpr int WG = 256;
+constexpr int TY = 32;
+
+// One entry of a plan's tile table.  inst < 0 marks padding (the table length is
+// a multiple of 8 so that the XCD-aware block remap is a bijection).
+struct Tile {
+  int32_t inst, x0, y0, pad;
+};
+
+// Per-instance layout: packed offset, size, and the [tile_begin, tile_end) range
+// of its tiles in the full tile table.
+struct Inst {
+  int64_t off;
+  int32_t n;
+  int32_t tile_begin;
+  int32_t tile_end;
+  int32_t pad;
+};
+
+enum { M_RICH = 0, M_NAG = 1 };
+
+// Device-side view of a plan.
+struct PlanDev {
+  const Tile* tiles;    // full tile table (padded)
+  int32_t ntiles;       // padded length
+  const Inst* inst;     // [B]
+  int32_t B;
+  const float* coef32;  // [B][8], slots 0..4 used
+  const double* coef64; // [B][8]
+  const float* mu;      // [B][2]  (log10 eps, theta) or (0, kappa)
+  const float* gersh;   // [B]
+};
+
+// ---- launchers (all asynchronous on `st`) ---------------------------------
+// y = A x                                      (dtype float or double)
+template <typename T>
+void launch_apply(const PlanDev& p, const Tile* tiles, int ntiles, const T* x, T* y, hipStream_t st);
+// r = b - A x (r may be null) with per-tile partial sums of ||r||^2 and ||b||^2
+template <typename T>
+void launch_residual(const PlanDev& p, const Tile* tiles, int ntiles, const T* b, const T* x, T* r,
+                     double* partial2, const int* active, hipStream_t st);
+// one fused inner step of Richardson(m) (method M_RICH) or NAG-Richardson(m)
+template <typename T>
+void launch_step(int method, const PlanDev& p, const Tile* tiles, int ntiles, const float* omega,
+                 const float* alpha, int m, int i, const T* f, const T* u, const T* v, T* u_out,
+                 T* v_out, const int* active, hipStream_t st);
+// per-instance fixed-order sums of per-tile partials over the instance's tiles t:
+// out0[b*stride] = sum_t partial2[2t], out1[b*stride] = sum_t partial2[2t+1],
+// ratio[b] = out0 / out1 as float (any output may be null)
+void launch_reduce_partials(const PlanDev& p, const double* partial2, double* out0, double* out1,
+                            int stride, float* ratio, hipStream_t st);
+// FP64 refinement: r = b - A x, r32 = fl32(r), d = v = 0, partials of ||r||^2, ||b||^2
+void launch_refine_residual(const PlanDev& p, const double* b, const double* x, float* r32,
+                            float* d, float* v, double* partial2, const int* round_mask,
+                            hipStream_t st);
+// x += d for instances with round_mask[b] != 0; d is d0 or d1 depending on the parity of
+// outer_count[b] * m (the inner solve ping-pongs between two buffers)
+void launch_refine_update(const PlanDev& p, double* x, const float* d0, const float* d1,
+                          const int* outer_count, int m, const int* round_mask, hipStream_t st);
+// inner-solve bookkeeping after one outer iteration (one thread per instance)
+void launch_inner_flags(int B, const double* res2, const double* rhs2, double tol_in2, int cap,
+                        int* active, int* outer_count, int* status, int* n_active, hipStream_t st);
+void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st);
+void launch_fill_f32(float* p, float value, int64_t count, hipStream_t st);
+void launch_fill_f64(double* p, double value, int64_t count, hipStream_t st);
+// adjoint: terminal values of the squared-relative-residual loss
+void launch_adj_terminal(const PlanDev& p, const float* b, const float* rK, const double* r2b2,
+                         const float* g_loss, float* ub, float* fb, float* loss, hipStream_t st);
+// adjoint: one reverse step (see rm_solve_adjoint); partial2 gets <g, r_s>, <g + ut_bar, v>
+void launch_adj_step(int method, const PlanDev& p, const float* omega, const float* alpha, int m,
+                     int i, const float* f, const float* u, const float* v, const float* ub,
+                     const float* vb, float* ub_out, float* vb_out, float* fb, double* partial2,
+                     hipStream_t st);
+// acc[b*m + i] += per-instance sums of partial2 (two components to acc_w, acc_a)
+void launch_adj_accumulate(const PlanDev& p, const double* partial2, int m, int i, double* acc_w,
+                           double* acc_a, hipStream_t st);
+void launch_f64_to_f32(const double* src, float* dst, int64_t count, hipStream_t st);
+// meta network
+void launch_meta_forward(const PlanDev& p, int m, const float* params, float* omega, float* alpha,
+                         hipStream_t st);
+void launch_meta_backward(const PlanDev& p, int m, const float* params, const float* d_omega,
+                          const float* d_alpha, float* per_inst, float* d_params, hipStream_t st);
+
+}  // namespace rmk

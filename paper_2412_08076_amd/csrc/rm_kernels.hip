@@ -1,0 +1,735 @@
+// HIP kernels for gfx950 (CDNA4, wave64) of the long-step Richardson(m) hot path.
+//
+// Operators (arXiv 2412.08076): the Q1 9-point stencil of the anisotropic
+// diffusion problem (§2.3) and the 5-point Helmholtz stencil (§3.2), both held as
+// five per-instance coefficients: centre, (+-1,0), (0,+-1), (1,1)/(-1,-1) and
+// (-1,1)/(1,-1).  Schemes: Richardson(m) and NAG-Richardson(m) (Table 1).
+//
+// Work decomposition.  Every kernel here walks a plan's tile table: one
+// workgroup of 256 threads (4 waves) owns a 64 x 32 output tile of one instance,
+// one thread per column and 8 rows per thread.  The inputs of a tile plus a
+// one-point halo are staged in LDS; points outside the n x n interior read as 0
+// (homogeneous Dirichlet), so ragged tails and boundaries need no special code.
+// The block index is remapped so that consecutive tiles land on the same XCD
+// (hardware dispatch is round robin over the 8 XCDs), which keeps the halo rows
+// shared by neighbouring tiles in one L2.
+//
+// Reductions (residual norms, adjoint dot products) are formed per tile in FP64
+// with a fixed shuffle tree, then summed per instance in tile order by a second
+// kernel: results are bitwise reproducible run to run.
+//
+// All floating-point combinations are written as explicit fused multiply-adds
+// with contraction switched off, so the single-step, adjoint-recompute and any
+// other kernel that evaluates the same stencil produce identical bits.
+#include "rm_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace rmk {
+
+namespace {
+
+constexpr int LDS_W = TX + 2;
+constexpr int RPT = TY / (WG / TX);  // rows per thread
+constexpr int NWAVE = WG / 64;
+
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+  // nb is a multiple of 8: XCD k (blocks bid = k mod 8) gets the contiguous range
+  // [k * nb / 8, (k + 1) * nb / 8) of the tile table.
+  const int per = nb >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+// Weighted 9-point sum in a fixed order: C centre, W/E = x -+ 1, S/N = y -+ 1.
+template <typename T>
+__device__ __forceinline__ T stencil9(const T c[5], T C, T W, T E, T S, T N, T SW, T NE, T SE, T NW) {
+  T acc = c[0] * C;
+  acc = fmadd(c[1], W + E, acc);
+  acc = fmadd(c[2], S + N, acc);
+  acc = fmadd(c[3], SW + NE, acc);
+  acc = fmadd(c[4], SE + NW, acc);
+  return acc;
+}
+
+// Stencil at LDS position (lx, ly) of a (TY+2) x LDS_W tile.
+template <typename T>
+__device__ __forceinline__ T stencil_lds(const T* s, int lx, int ly, const T c[5]) {
+  const T* rs = s + (ly - 1) * LDS_W + lx;
+  const T* rc = s + ly * LDS_W + lx;
+  const T* rn = s + (ly + 1) * LDS_W + lx;
+  return stencil9(c, rc[0], rc[-1], rc[1], rs[0], rn[0], rs[-1], rn[1], rs[1], rn[-1]);
+}
+
+// Fill the one-point halo ring of the LDS tile with val(gx, gy), or 0 outside the
+// n x n interior.
+template <typename T, typename F>
+__device__ __forceinline__ void stage_halo(T* s, int x0, int y0, int n, F&& val) {
+  constexpr int NH = 2 * LDS_W + 2 * TY;
+  for (int h = threadIdx.x; h < NH; h += WG) {
+    int hx, hy;
+    if (h < LDS_W) {
+      hx = h; hy = 0;
+    } else if (h < 2 * LDS_W) {
+      hx = h - LDS_W; hy = TY + 1;
+    } else if (h < 2 * LDS_W + TY) {
+      hx = 0; hy = 1 + (h - 2 * LDS_W);
+    } else {
+      hx = TX + 1; hy = 1 + (h - 2 * LDS_W - TY);
+    }
+    const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+    const bool in = (gx >= 0) && (gx < n) && (gy >= 0) && (gy < n);
+    s[hy * LDS_W + hx] = in ? val(gx, gy) : T(0);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_coef(const PlanDev& p, int b, T c[5]);
+template <>
+__device__ __forceinline__ void load_coef<float>(const PlanDev& p, int b, float c[5]) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) c[k] = p.coef32[b * 8 + k];
+}
+template <>
+__device__ __forceinline__ void load_coef<double>(const PlanDev& p, int b, double c[5]) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) c[k] = p.coef64[b * 8 + k];
+}
+
+// Sum over the workgroup (fixed order); the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double x, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = x;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NWAVE; ++k) r += sh[k];
+  }
+  return r;
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// y = A x  /  r = b - A x with per-tile ||r||^2, ||b||^2
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>  // MODE 0: y = A x; MODE 1: residual (+ partials)
+__global__ __launch_bounds__(WG) void k_apply(PlanDev p, const Tile* tiles, const T* __restrict__ b,
+                                              const T* __restrict__ x, T* __restrict__ y,
+                                              double* __restrict__ partial2,
+                                              const int* __restrict__ active) {
+  __shared__ T s[(TY + 2) * LDS_W];
+  __shared__ double sh[NWAVE];
+  const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+  if (tl.inst < 0) return;
+  if (active != nullptr && active[tl.inst] == 0) return;
+  const Inst in = p.inst[tl.inst];
+  const int n = in.n;
+  T c[5];
+  load_coef<T>(p, tl.inst, c);
+  const T* xi = x + in.off;
+  const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+  const int gx = tl.x0 + tx;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
+    const bool in_ = gx < n && gy < n;
+    s[(ly + 1) * LDS_W + tx + 1] = in_ ? xi[gy * n + gx] : T(0);
+  }
+  stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return xi[Y * n + X]; });
+  __syncthreads();
+  double r2 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
+    if (gx < n && gy < n) {
+      const T ax = stencil_lds(s, tx + 1, ly + 1, c);
+      const int64_t idx = in.off + (int64_t)gy * n + gx;
+      if (MODE == 0) {
+        y[idx] = ax;
+      } else {
+        const T bv = b[idx];
+        const T r = bv - ax;
+        if (y != nullptr) y[idx] = r;
+        r2 += (double)r * (double)r;
+        b2 += (double)bv * (double)bv;
+      }
+    }
+  }
+  if (MODE == 1 && partial2 != nullptr) {
+    const double t0 = block_sum(r2, sh);
+    __syncthreads();
+    const double t1 = block_sum(b2, sh);
+    if (threadIdx.x == 0) {
+      partial2[2 * tl.pad + 0] = t0;
+      partial2[2 * tl.pad + 1] = t1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One fused inner step (Table 1, last column):
+//   NAG:        u~ = u + a_i v; r = f - A u~; v' = a_i v + w_i r; u' = u + v'
+//   Richardson: r = f - A u;    v' = w_i r;    u' = u + v'
+// ---------------------------------------------------------------------------
+template <typename T, int METHOD>
+__global__ __launch_bounds__(WG) void k_step(PlanDev p, const Tile* tiles, const float* __restrict__ omega,
+                                             const float* __restrict__ alpha, int m, int i,
+                                             const T* __restrict__ f, const T* __restrict__ u,
+                                             const T* __restrict__ v, T* __restrict__ u_out,
+                                             T* __restrict__ v_out, const int* __restrict__ active) {
+  __shared__ T s[(TY + 2) * LDS_W];
+  const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+  if (tl.inst < 0) return;
+  if (active != nullptr && active[tl.inst] == 0) return;
+  const Inst in = p.inst[tl.inst];
+  const int n = in.n;
+  T c[5];
+  load_coef<T>(p, tl.inst, c);
+  const T w = (T)omega[tl.inst * m + i];
+  const T a = METHOD == M_NAG ? (T)alpha[tl.inst * m + i] : T(0);
+  const T* ui = u + in.off;
+  const T* vi = v + in.off;
+  const T* fi = f + in.off;
+  const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+  const int gx = tl.x0 + tx;
+  T ru[RPT], rv[RPT], rf[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
+    const bool in_ = gx < n && gy < n;
+    const int idx = gy * n + gx;
+    ru[k] = in_ ? ui[idx] : T(0);
+    rv[k] = (METHOD == M_NAG && in_) ? vi[idx] : T(0);
+    rf[k] = in_ ? fi[idx] : T(0);
+    s[(ly + 1) * LDS_W + tx + 1] = METHOD == M_NAG ? fmadd(a, rv[k], ru[k]) : ru[k];
+  }
+  if (METHOD == M_NAG)
+    stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return fmadd(a, vi[Y * n + X], ui[Y * n + X]); });
+  else
+    stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return ui[Y * n + X]; });
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
+    if (gx < n && gy < n) {
+      const T r = rf[k] - stencil_lds(s, tx + 1, ly + 1, c);
+      const T vn = METHOD == M_NAG ? fmadd(a, rv[k], w * r) : w * r;
+      const int64_t idx = in.off + (int64_t)gy * n + gx;
+      u_out[idx] = ru[k] + vn;
+      if (METHOD == M_NAG) v_out[idx] = vn;
+    }
+  }
+}
+
+// Per-instance fixed-order sum of per-tile partials: one wave per instance.
+__global__ __launch_bounds__(64) void k_reduce_partials(PlanDev p, const double* __restrict__ partial2,
+                                                        double* __restrict__ out0, double* __restrict__ out1,
+                                                        int stride, float* __restrict__ ratio) {
+  const int b = blockIdx.x;
+  const Inst in = p.inst[b];
+  double s0 = 0.0, s1 = 0.0;
+  for (int t = in.tile_begin + (int)threadIdx.x; t < in.tile_end; t += 64) {
+    s0 += partial2[2 * t];
+    s1 += partial2[2 * t + 1];
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if (threadIdx.x == 0) {
+    if (out0 != nullptr) out0[b * stride] = s0;
+    if (out1 != nullptr) out1[b * stride] = s1;
+    if (ratio != nullptr) ratio[b] = (float)(s0 / s1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 iterative refinement
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_refine_residual(PlanDev p, const double* __restrict__ b,
+                                                        const double* __restrict__ x, float* __restrict__ r32,
+                                                        float* __restrict__ d, float* __restrict__ v,
+                                                        double* __restrict__ partial2,
+                                                        const int* __restrict__ mask) {
+  __shared__ double s[(TY + 2) * LDS_W];
+  __shared__ double sh[NWAVE];
+  const Tile tl = p.tiles[xcd_remap(blockIdx.x, gridDim.x)];
+  if (tl.inst < 0) return;
+  if (mask != nullptr && mask[tl.inst] == 0) return;
+  const Inst in = p.inst[tl.inst];
+  const int n = in.n;
+  double c[5];
+  load_coef<double>(p, tl.inst, c);
+  const double* xi = x + in.off;
+  const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+  const int gx = tl.x0 + tx;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
+    s[(ly + 1) * LDS_W + tx + 1] = (gx < n && gy < n) ? xi[gy * n + gx] : 0.0;
+  }
+  stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return xi[Y * n + X]; });
+  __syncthreads();
+  double r2 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
+    if (gx < n && gy < n) {
+      const int64_t idx = in.off + (int64_t)gy * n + gx;
+      const double bv = b[idx];
+      const double r = bv - stencil_lds(s, tx + 1, ly + 1, c);
+      r32[idx] = (float)r;
+      d[idx] = 0.0f;
+      v[idx] = 0.0f;
+      r2 += r * r;
+      b2 += bv * bv;
+    }
+  }
+  const double t0 = block_sum(r2, sh);
+  __syncthreads();
+  const double t1 = block_sum(b2, sh);
+  if (threadIdx.x == 0) {
+    partial2[2 * tl.pad + 0] = t0;
+    partial2[2 * tl.pad + 1] = t1;
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_refine_update(PlanDev p, double* __restrict__ x,
+                                                      const float* __restrict__ d0,
+                                                      const float* __restrict__ d1,
+                                                      const int* __restrict__ outer_count, int m,
+                                                      const int* __restrict__ mask) {
+  const Tile tl = p.tiles[xcd_remap(blockIdx.x, gridDim.x)];
+  if (tl.inst < 0) return;
+  if (mask[tl.inst] == 0) return;
+  const Inst in = p.inst[tl.inst];
+  const int n = in.n;
+  const float* d = (((int64_t)outer_count[tl.inst] * m) & 1) ? d1 : d0;
+  const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+  const int gx = tl.x0 + tx;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int gy = tl.y0 + ty0 + 4 * k;
+    if (gx < n && gy < n) {
+      const int64_t idx = in.off + (int64_t)gy * n + gx;
+      x[idx] = x[idx] + (double)d[idx];
+    }
+  }
+}
+
+// After one outer iteration of an inner solve: stop instances whose relative
+// residual reached tol_in (or that hit the cap, or went non-finite / grew
+// beyond 1e12 times the right-hand side), count the rest.
+__global__ void k_inner_flags(int B, const double* __restrict__ res2, const double* __restrict__ rhs2,
+                              double tol_in2, int cap, int* __restrict__ active, int* __restrict__ outer_count,
+                              int* __restrict__ status, int* __restrict__ n_active) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B || active[b] == 0) return;
+  const int cnt = outer_count[b] + 1;
+  outer_count[b] = cnt;
+  const double r2 = res2[b];
+  const double f2 = rhs2[b];
+  int keep = 1;
+  if (!(r2 <= 1e12 * f2)) {  // NaN, Inf or growth
+    status[b] = 5;           // RM_EDIVERGED
+    keep = 0;
+  } else if (r2 <= tol_in2 * f2) {
+    keep = 0;
+  } else if (cnt >= cap) {
+    keep = 0;
+  }
+  active[b] = keep;
+  if (keep) atomicAdd(n_active, 1);
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, T value, int64_t count) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
+       k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = value;
+}
+
+__global__ void k_f64_to_f32(const double* __restrict__ s, float* __restrict__ d, int64_t count) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
+       k += (int64_t)gridDim.x * blockDim.x)
+    d[k] = (float)s[k];
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the K-step unroll
+// ---------------------------------------------------------------------------
+// Terminal values for J = sum_b g_b ||r_K||^2 / ||b||^2 with r_K = b - A u_K:
+//   ub = -2 g_b / ||b||^2 A r_K,  fb = g_b (2 r_K - 2 L_b b) / ||b||^2.
+__global__ __launch_bounds__(WG) void k_adj_terminal(PlanDev p, const float* __restrict__ f,
+                                                     const float* __restrict__ rK,
+                                                     const double* __restrict__ r2b2,
+                                                     const float* __restrict__ g_loss,
+                                                     float* __restrict__ ub, float* __restrict__ fb,
+                                                     float* __restrict__ loss) {
+  __shared__ float s[(TY + 2) * LDS_W];
+  const Tile tl = p.tiles[xcd_remap(blockIdx.x, gridDim.x)];
+  if (tl.inst < 0) return;
+  const int bi = tl.inst;
+  const Inst in = p.inst[bi];
+  const int n = in.n;
+  float c[5];
+  load_coef<float>(p, bi, c);
+  const double r2 = r2b2[2 * bi], b2 = r2b2[2 * bi + 1];
+  const double L = r2 / b2;
+  const double g = g_loss != nullptr ? (double)g_loss[bi] : 1.0;
+  if (loss != nullptr && tl.pad == in.tile_begin && threadIdx.x == 0) loss[bi] = (float)L;
+  const float su = (float)(-2.0 * g / b2);
+  const float sr = (float)(2.0 * g / b2);
+  const float sb = (float)(-2.0 * g * L / b2);
+  const float* ri = rK + in.off;
+  const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+  const int gx = tl.x0 + tx;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
+    s[(ly + 1) * LDS_W + tx + 1] = (gx < n && gy < n) ? ri[gy * n + gx] : 0.0f;
+  }
+  stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return ri[Y * n + X]; });
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
+    if (gx < n && gy < n) {
+      const int64_t idx = in.off + (int64_t)gy * n + gx;
+      ub[idx] = su * stencil_lds(s, tx + 1, ly + 1, c);
+      if (fb != nullptr) fb[idx] = fmadd(sr, s[(ly + 1) * LDS_W + tx + 1], sb * f[idx]);
+    }
+  }
+}
+
+// Reverse of one forward step s (weight index i), from the forward state
+// (u, v) = (u_{s-1}, v_{s-1}) and the adjoints (ub, vb) of (u_s, v_s):
+//   g = vb + ub;  r_s = f - A(u + a v);  wbar += <g, r_s>;  rb = w g;  fb += rb;
+//   ut_bar = -A rb;  abar += <g + ut_bar, v>;  ub' = ub + ut_bar;  vb' = a (g + ut_bar).
+template <int METHOD>
+__global__ __launch_bounds__(WG) void k_adj_step(PlanDev p, const float* __restrict__ omega,
+                                                 const float* __restrict__ alpha, int m, int i,
+                                                 const float* __restrict__ f, const float* __restrict__ u,
+                                                 const float* __restrict__ v, const float* __restrict__ ub,
+                                                 const float* __restrict__ vb, float* __restrict__ ub_out,
+                                                 float* __restrict__ vb_out, float* __restrict__ fb,
+                                                 double* __restrict__ partial2) {
+  __shared__ float su[(TY + 2) * LDS_W];
+  __shared__ float sg[(TY + 2) * LDS_W];
+  __shared__ double sh[NWAVE];
+  const Tile tl = p.tiles[xcd_remap(blockIdx.x, gridDim.x)];
+  if (tl.inst < 0) return;
+  const int bi = tl.inst;
+  const Inst in = p.inst[bi];
+  const int n = in.n;
+  float c[5];
+  load_coef<float>(p, bi, c);
+  const float w = omega[bi * m + i];
+  const float a = METHOD == M_NAG ? alpha[bi * m + i] : 0.0f;
+  const float* ui = u + in.off;
+  const float* vi = v + in.off;
+  const float* ubi = ub + in.off;
+  const float* vbi = vb + in.off;
+  const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+  const int gx = tl.x0 + tx;
+  float rv[RPT], rg[RPT], rub[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
+    const bool in_ = gx < n && gy < n;
+    const int idx = gy * n + gx;
+    const float uu = in_ ? ui[idx] : 0.0f;
+    rv[k] = (METHOD == M_NAG && in_) ? vi[idx] : 0.0f;
+    rub[k] = in_ ? ubi[idx] : 0.0f;
+    const float vbb = (METHOD == M_NAG && in_) ? vbi[idx] : 0.0f;
+    rg[k] = vbb + rub[k];
+    su[(ly + 1) * LDS_W + tx + 1] = METHOD == M_NAG ? fmadd(a, rv[k], uu) : uu;
+    sg[(ly + 1) * LDS_W + tx + 1] = rg[k];
+  }
+  if (METHOD == M_NAG) {
+    stage_halo(su, tl.x0, tl.y0, n, [&](int X, int Y) { return fmadd(a, vi[Y * n + X], ui[Y * n + X]); });
+    stage_halo(sg, tl.x0, tl.y0, n, [&](int X, int Y) { return vbi[Y * n + X] + ubi[Y * n + X]; });
+  } else {
+    stage_halo(su, tl.x0, tl.y0, n, [&](int X, int Y) { return ui[Y * n + X]; });
+    stage_halo(sg, tl.x0, tl.y0, n, [&](int X, int Y) { return ubi[Y * n + X]; });
+  }
+  __syncthreads();
+  double pw = 0.0, pa = 0.0;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
+    if (gx < n && gy < n) {
+      const int64_t idx = in.off + (int64_t)gy * n + gx;
+      const float r = f[idx] - stencil_lds(su, tx + 1, ly + 1, c);
+      const float g = rg[k];
+      const float utb = -(w * stencil_lds(sg, tx + 1, ly + 1, c));
+      const float gu = g + utb;
+      pw += (double)g * (double)r;
+      pa += (double)gu * (double)rv[k];
+      ub_out[idx] = rub[k] + utb;
+      if (METHOD == M_NAG) vb_out[idx] = a * gu;
+      if (fb != nullptr) fb[idx] = fmadd(w, g, fb[idx]);
+    }
+  }
+  const double t0 = block_sum(pw, sh);
+  __syncthreads();
+  const double t1 = block_sum(pa, sh);
+  if (threadIdx.x == 0) {
+    partial2[2 * tl.pad + 0] = t0;
+    partial2[2 * tl.pad + 1] = t1;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_adj_accumulate(PlanDev p, const double* __restrict__ partial2, int m,
+                                                       int i, double* __restrict__ acc_w,
+                                                       double* __restrict__ acc_a) {
+  const int b = blockIdx.x;
+  const Inst in = p.inst[b];
+  double s0 = 0.0, s1 = 0.0;
+  for (int t = in.tile_begin + (int)threadIdx.x; t < in.tile_end; t += 64) {
+    s0 += partial2[2 * t];
+    s1 += partial2[2 * t + 1];
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if (threadIdx.x == 0) {
+    acc_w[b * m + i] += s0;
+    acc_a[b * m + i] += s1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Meta network: (log10 eps, theta) -> tanh 64 -> tanh 64 -> m + 1, head
+// omega_i = exp(z_i) / G, alpha_i = sigmoid(z_m).  One wave per instance.
+// ---------------------------------------------------------------------------
+constexpr int MH = 64;
+
+struct MetaPtrs {
+  const float *W1, *b1, *W2, *b2, *W3, *b3;
+};
+__device__ __forceinline__ MetaPtrs meta_ptrs(const float* P, int m) {
+  MetaPtrs q;
+  q.W1 = P;
+  q.b1 = q.W1 + MH * 2;
+  q.W2 = q.b1 + MH;
+  q.b2 = q.W2 + MH * MH;
+  q.W3 = q.b2 + MH;
+  q.b3 = q.W3 + (m + 1) * MH;
+  return q;
+}
+
+__global__ __launch_bounds__(64) void k_meta_forward(PlanDev p, int m, const float* __restrict__ P,
+                                                     float* __restrict__ omega, float* __restrict__ alpha) {
+  __shared__ float h1s[MH], h2s[MH];
+  const int b = blockIdx.x, j = threadIdx.x;
+  const MetaPtrs q = meta_ptrs(P, m);
+  const float x0 = p.mu[2 * b], x1 = p.mu[2 * b + 1];
+  const float h1 = tanhf(fmadd(q.W1[2 * j + 1], x1, fmadd(q.W1[2 * j], x0, q.b1[j])));
+  h1s[j] = h1;
+  __syncthreads();
+  float acc = q.b2[j];
+  for (int k = 0; k < MH; ++k) acc = fmadd(q.W2[j * MH + k], h1s[k], acc);
+  h2s[j] = tanhf(acc);
+  __syncthreads();
+  const float G = p.gersh[b];
+  for (int o = j; o <= m; o += 64) {
+    float z = q.b3[o];
+    for (int k = 0; k < MH; ++k) z = fmadd(q.W3[o * MH + k], h2s[k], z);
+    if (o < m) {
+      omega[b * m + o] = expf(z) / G;
+    } else {
+      const float beta = 1.0f / (1.0f + expf(-z));
+      for (int t = 0; t < m; ++t) alpha[b * m + t] = beta;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_meta_backward(PlanDev p, int m, const float* __restrict__ P,
+                                                      const float* __restrict__ d_omega,
+                                                      const float* __restrict__ d_alpha,
+                                                      float* __restrict__ per_inst, int np) {
+  __shared__ float h1s[MH], h2s[MH], dzs[65], da2s[MH];
+  const int b = blockIdx.x, j = threadIdx.x;
+  const MetaPtrs q = meta_ptrs(P, m);
+  const float x0 = p.mu[2 * b], x1 = p.mu[2 * b + 1];
+  const float h1 = tanhf(fmadd(q.W1[2 * j + 1], x1, fmadd(q.W1[2 * j], x0, q.b1[j])));
+  h1s[j] = h1;
+  __syncthreads();
+  float acc = q.b2[j];
+  for (int k = 0; k < MH; ++k) acc = fmadd(q.W2[j * MH + k], h1s[k], acc);
+  const float h2 = tanhf(acc);
+  h2s[j] = h2;
+  __syncthreads();
+  const float G = p.gersh[b];
+  for (int o = j; o <= m; o += 64) {
+    float z = q.b3[o];
+    for (int k = 0; k < MH; ++k) z = fmadd(q.W3[o * MH + k], h2s[k], z);
+    if (o < m) {
+      dzs[o] = d_omega[b * m + o] * (expf(z) / G);
+    } else {
+      const float beta = 1.0f / (1.0f + expf(-z));
+      float s = 0.0f;
+      for (int t = 0; t < m; ++t) s += d_alpha[b * m + t];
+      dzs[m] = s * beta * (1.0f - beta);
+    }
+  }
+  __syncthreads();
+  float* g = per_inst + (int64_t)b * np;
+  float* gW1 = g;
+  float* gb1 = gW1 + MH * 2;
+  float* gW2 = gb1 + MH;
+  float* gb2 = gW2 + MH * MH;
+  float* gW3 = gb2 + MH;
+  float* gb3 = gW3 + (m + 1) * MH;
+  for (int o = 0; o <= m; ++o) gW3[o * MH + j] = dzs[o] * h2s[j];
+  for (int o = j; o <= m; o += 64) gb3[o] = dzs[o];
+  float dh2 = 0.0f;
+  for (int o = 0; o <= m; ++o) dh2 = fmadd(dzs[o], q.W3[o * MH + j], dh2);
+  const float da2 = dh2 * (1.0f - h2 * h2);
+  da2s[j] = da2;
+  __syncthreads();
+  for (int jj = 0; jj < MH; ++jj) gW2[jj * MH + j] = da2s[jj] * h1s[j];
+  gb2[j] = da2;
+  float dh1 = 0.0f;
+  for (int jj = 0; jj < MH; ++jj) dh1 = fmadd(da2s[jj], q.W2[jj * MH + j], dh1);
+  const float da1 = dh1 * (1.0f - h1 * h1);
+  gW1[2 * j] = da1 * x0;
+  gW1[2 * j + 1] = da1 * x1;
+  gb1[j] = da1;
+}
+
+__global__ void k_meta_reduce(int B, int np, const float* __restrict__ per_inst, float* __restrict__ d_params) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= np) return;
+  double acc = 0.0;
+  for (int b = 0; b < B; ++b) acc += (double)per_inst[(int64_t)b * np + k];
+  d_params[k] = (float)acc;
+}
+
+inline int fill_grid(int64_t count) {
+  int64_t g = (count + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_apply(const PlanDev& p, const Tile* tiles, int ntiles, const T* x, T* y, hipStream_t st) {
+  hipLaunchKernelGGL((k_apply<T, 0>), dim3(ntiles), dim3(WG), 0, st, p, tiles, (const T*)nullptr, x, y,
+                     (double*)nullptr, (const int*)nullptr);
+}
+template <typename T>
+void launch_residual(const PlanDev& p, const Tile* tiles, int ntiles, const T* b, const T* x, T* r,
+                     double* partial2, const int* active, hipStream_t st) {
+  hipLaunchKernelGGL((k_apply<T, 1>), dim3(ntiles), dim3(WG), 0, st, p, tiles, b, x, r, partial2, active);
+}
+template <typename T>
+void launch_step(int method, const PlanDev& p, const Tile* tiles, int ntiles, const float* omega,
+                 const float* alpha, int m, int i, const T* f, const T* u, const T* v, T* u_out, T* v_out,
+                 const int* active, hipStream_t st) {
+  if (method == M_NAG)
+    hipLaunchKernelGGL((k_step<T, M_NAG>), dim3(ntiles), dim3(WG), 0, st, p, tiles, omega, alpha, m, i, f, u,
+                       v, u_out, v_out, active);
+  else
+    hipLaunchKernelGGL((k_step<T, M_RICH>), dim3(ntiles), dim3(WG), 0, st, p, tiles, omega, alpha, m, i, f,
+                       u, v, u_out, v_out, active);
+}
+
+template void launch_apply<float>(const PlanDev&, const Tile*, int, const float*, float*, hipStream_t);
+template void launch_apply<double>(const PlanDev&, const Tile*, int, const double*, double*, hipStream_t);
+template void launch_residual<float>(const PlanDev&, const Tile*, int, const float*, const float*, float*,
+                                     double*, const int*, hipStream_t);
+template void launch_residual<double>(const PlanDev&, const Tile*, int, const double*, const double*,
+                                      double*, double*, const int*, hipStream_t);
+template void launch_step<float>(int, const PlanDev&, const Tile*, int, const float*, const float*, int, int,
+                                 const float*, const float*, const float*, float*, float*, const int*,
+                                 hipStream_t);
+template void launch_step<double>(int, const PlanDev&, const Tile*, int, const float*, const float*, int, int,
+                                  const double*, const double*, const double*, double*, double*, const int*,
+                                  hipStream_t);
+
+void launch_reduce_partials(const PlanDev& p, const double* partial2, double* out0, double* out1, int stride,
+                            float* ratio, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(p.B), dim3(64), 0, st, p, partial2, out0, out1, stride, ratio);
+}
+
+void launch_refine_residual(const PlanDev& p, const double* b, const double* x, float* r32, float* d, float* v,
+                            double* partial2, const int* round_mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_residual, dim3(p.ntiles), dim3(WG), 0, st, p, b, x, r32, d, v, partial2,
+                     round_mask);
+}
+
+void launch_refine_update(const PlanDev& p, double* x, const float* d0, const float* d1, const int* outer_count,
+                          int m, const int* round_mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_update, dim3(p.ntiles), dim3(WG), 0, st, p, x, d0, d1, outer_count, m,
+                     round_mask);
+}
+
+void launch_inner_flags(int B, const double* res2, const double* rhs2, double tol_in2, int cap, int* active,
+                        int* outer_count, int* status, int* n_active, hipStream_t st) {
+  hipLaunchKernelGGL(k_inner_flags, dim3((B + 255) / 256), dim3(256), 0, st, B, res2, rhs2, tol_in2, cap,
+                     active, outer_count, status, n_active);
+}
+
+void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_fill<int>, dim3(fill_grid(count)), dim3(256), 0, st, p, value, count);
+}
+void launch_fill_f32(float* p, float value, int64_t count, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_fill<float>, dim3(fill_grid(count)), dim3(256), 0, st, p, value, count);
+}
+void launch_fill_f64(double* p, double value, int64_t count, hipStream_t st) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_fill<double>, dim3(fill_grid(count)), dim3(256), 0, st, p, value, count);
+}
+void launch_f64_to_f32(const double* src, float* dst, int64_t count, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_f64_to_f32, dim3(fill_grid(count)), dim3(256), 0, st, src, dst, count);
+}
+
+void launch_adj_terminal(const PlanDev& p, const float* b, const float* rK, const double* r2b2,
+                         const float* g_loss, float* ub, float* fb, float* loss, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_terminal, dim3(p.ntiles), dim3(WG), 0, st, p, b, rK, r2b2, g_loss, ub, fb, loss);
+}
+
+void launch_adj_step(int method, const PlanDev& p, const float* omega, const float* alpha, int m, int i,
+                     const float* f, const float* u, const float* v, const float* ub, const float* vb,
+                     float* ub_out, float* vb_out, float* fb, double* partial2, hipStream_t st) {
+  if (method == M_NAG)
+    hipLaunchKernelGGL(k_adj_step<M_NAG>, dim3(p.ntiles), dim3(WG), 0, st, p, omega, alpha, m, i, f, u, v, ub,
+                       vb, ub_out, vb_out, fb, partial2);
+  else
+    hipLaunchKernelGGL(k_adj_step<M_RICH>, dim3(p.ntiles), dim3(WG), 0, st, p, omega, alpha, m, i, f, u, v,
+                       ub, vb, ub_out, vb_out, fb, partial2);
+}
+
+void launch_adj_accumulate(const PlanDev& p, const double* partial2, int m, int i, double* acc_w,
+                           double* acc_a, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_accumulate, dim3(p.B), dim3(64), 0, st, p, partial2, m, i, acc_w, acc_a);
+}
+
+void launch_meta_forward(const PlanDev& p, int m, const float* params, float* omega, float* alpha,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_meta_forward, dim3(p.B), dim3(64), 0, st, p, m, params, omega, alpha);
+}
+
+void launch_meta_backward(const PlanDev& p, int m, const float* params, const float* d_omega,
+                          const float* d_alpha, float* per_inst, float* d_params, hipStream_t st) {
+  const int np = MH * 2 + MH + MH * MH + MH + (m + 1) * MH + (m + 1);
+  hipLaunchKernelGGL(k_meta_backward, dim3(p.B), dim3(64), 0, st, p, m, params, d_omega, d_alpha, per_inst,
+                     np);
+  hipLaunchKernelGGL(k_meta_reduce, dim3((np + 255) / 256), dim3(256), 0, st, p.B, np, per_inst, d_params);
+}
+
+}  // namespace rmk

@@ -1,0 +1,215 @@
+"""Python binding of librm.so: argument marshalling only.
+
+Each function has the name of the C entry point it calls (include/rm.h) and takes
+torch CUDA (HIP) tensors for the device pointers.  Shapes, dtypes, devices and
+contiguity are checked here; every computation happens in the HIP kernels.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (RM_EDIVERGED, RM_ENOTCONV, RM_F32, RM_F64, RM_FD5_HELMHOLTZ, RM_NAG, RM_OK,
+                   RM_Q1_ANISO, RM_RICHARDSON, RM_TO_TOL, RM_UNROLL)
+
+__all__ = [
+    "RMError", "Context", "Plan", "rm_apply_A", "rm_residual", "rm_solve", "rm_solve_adjoint",
+    "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count", "solve_opts",
+    "RM_Q1_ANISO", "RM_FD5_HELMHOLTZ", "RM_RICHARDSON", "RM_NAG", "RM_F32", "RM_F64",
+    "RM_UNROLL", "RM_TO_TOL", "RM_OK", "RM_ENOTCONV", "RM_EDIVERGED",
+]
+
+
+class RMError(RuntimeError):
+    def __init__(self, status, where):
+        lib = _lib.load()
+        msg = lib.rm_last_error().decode()
+        super().__init__(f"{where}: {lib.rm_status_string(status).decode()} ({msg})")
+        self.status = status
+
+
+def _check(status, where):
+    if status != RM_OK:
+        raise RMError(status, where)
+
+
+_DT = {torch.float32: RM_F32, torch.float64: RM_F64}
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """rm_create / rm_destroy; enqueues on the given (default: current) torch stream."""
+
+    def __init__(self, device=0, stream=None):
+        self.lib = _lib.load()
+        dev = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        self.stream = stream
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(self.lib.rm_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream)), "rm_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.rm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """rm_plan: a batch of instances.  ``n`` list of sizes; Q1 instances take eps and
+    theta, Helmholtz instances take kappa."""
+
+    def __init__(self, ctx, n, eps=None, theta=None, kappa=None, op=RM_Q1_ANISO):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        B = len(n)
+        arr = (_lib.rm_instance * B)()
+        for b in range(B):
+            arr[b].n = int(n[b])
+            arr[b].op = op
+            arr[b].eps = float(eps[b]) if eps is not None else 1.0
+            arr[b].theta = float(theta[b]) if theta is not None else 0.0
+            arr[b].kappa = float(kappa[b]) if kappa is not None else 0.0
+        h = ctypes.c_void_p()
+        _check(self.lib.rm_plan(ctx.handle, B, arr, ctypes.byref(h)), "rm_plan")
+        self.handle = h
+        self.B = B
+        self.n = [int(k) for k in n]
+        self.P = int(self.lib.rm_plan_points(h))
+        off = (ctypes.c_int64 * (B + 1))()
+        _check(self.lib.rm_plan_offsets(h, off), "rm_plan_offsets")
+        self.offsets = np.frombuffer(off, dtype=np.int64).copy()
+
+    def coefficients(self):
+        c = (ctypes.c_double * (5 * self.B))()
+        g = (ctypes.c_double * self.B)()
+        _check(self.lib.rm_plan_coefficients(self.handle, c, g), "rm_plan_coefficients")
+        return np.frombuffer(c).reshape(self.B, 5).copy(), np.frombuffer(g).copy()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.rm_plan_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_opts(mode=RM_UNROLL, dtype=RM_F32, m=16, K=0, ckpt_every=0, max_outer=100000, max_rounds=8,
+               check_every=4, tol=1e-10, tol_inner=1e-4):
+    o = _lib.rm_solve_opts()
+    o.mode, o.dtype, o.m, o.K, o.ckpt_every = mode, dtype, m, K, ckpt_every
+    o.max_outer, o.max_rounds, o.check_every = max_outer, max_rounds, check_every
+    o.tol, o.tol_inner = tol, tol_inner
+    return o
+
+
+def rm_apply_A(ctx, plan, x, y):
+    dt = _DT[x.dtype]
+    _check(ctx.lib.rm_apply_A(ctx.handle, plan.handle, dt, _ptr(x, x.dtype, plan.P, "x"),
+                              _ptr(y, x.dtype, plan.P, "y")), "rm_apply_A")
+    return y
+
+
+def rm_residual(ctx, plan, b, x, r=None, r2=None, b2=None, rel2=None):
+    dt = _DT[b.dtype]
+    _check(ctx.lib.rm_residual(ctx.handle, plan.handle, dt, _ptr(b, b.dtype, plan.P, "b"),
+                               _ptr(x, b.dtype, plan.P, "x"), _ptr(r, b.dtype, plan.P, "r"),
+                               _ptr(r2, torch.float64, plan.B, "r2"), _ptr(b2, torch.float64, plan.B, "b2"),
+                               _ptr(rel2, torch.float32, plan.B, "rel2")), "rm_residual")
+
+
+def rm_solve(ctx, plan, method, opts, omega, alpha, b, x, ckpt=None, hist=None):
+    """UNROLL: returns None (asynchronous).  TO_TOL: blocks and returns a dict of
+    per-instance numpy arrays (outer_iters, rounds, relres, status) plus 'status'."""
+    m = opts.m
+    om = _ptr(omega, torch.float32, plan.B * m, "omega")
+    al = _ptr(alpha, torch.float32, plan.B * m, "alpha") if alpha is not None else None
+    if opts.mode == RM_UNROLL:
+        vdt = torch.float32 if opts.dtype == RM_F32 else torch.float64
+        ck = None
+        if ckpt is not None:
+            ck = _ptr(ckpt, vdt, (opts.K // opts.ckpt_every) * 2 * plan.P, "ckpt")
+        hs = _ptr(hist, torch.float64, (opts.K // m) * plan.B, "hist") if hist is not None else None
+        st = ctx.lib.rm_solve(ctx.handle, plan.handle, method, ctypes.byref(opts), om, al,
+                              _ptr(b, vdt, plan.P, "b"), _ptr(x, vdt, plan.P, "x"), ck, hs, None)
+        _check(st, "rm_solve")
+        return None
+    B = plan.B
+    outer = (ctypes.c_int32 * B)()
+    rounds = (ctypes.c_int32 * B)()
+    relres = (ctypes.c_double * B)()
+    status = (ctypes.c_int32 * B)()
+    rep = _lib.rm_report(outer, rounds, relres, status)
+    st = ctx.lib.rm_solve(ctx.handle, plan.handle, method, ctypes.byref(opts), om, al,
+                          _ptr(b, torch.float64, plan.P, "b"), _ptr(x, torch.float64, plan.P, "x"),
+                          None, None, ctypes.byref(rep))
+    if st not in (RM_OK, RM_ENOTCONV, RM_EDIVERGED):
+        _check(st, "rm_solve")
+    return {
+        "status": st,
+        "outer_iters": np.frombuffer(outer, dtype=np.int32).copy(),
+        "rounds": np.frombuffer(rounds, dtype=np.int32).copy(),
+        "relres": np.frombuffer(relres, dtype=np.float64).copy(),
+        "inst_status": np.frombuffer(status, dtype=np.int32).copy(),
+    }
+
+
+def rm_solve_adjoint(ctx, plan, method, opts, omega, alpha, b, ckpt, d_omega, d_alpha, g_uK=None,
+                     g_loss=None, d_b=None, loss=None):
+    m = opts.m
+    P, B = plan.P, plan.B
+    st = ctx.lib.rm_solve_adjoint(
+        ctx.handle, plan.handle, method, ctypes.byref(opts),
+        _ptr(omega, torch.float32, B * m, "omega"),
+        _ptr(alpha, torch.float32, B * m, "alpha") if alpha is not None else None,
+        _ptr(b, torch.float32, P, "b"),
+        _ptr(ckpt, torch.float32, (opts.K // opts.ckpt_every) * 2 * P, "ckpt"),
+        _ptr(g_uK, torch.float32, P, "g_uK"), _ptr(g_loss, torch.float32, B, "g_loss"),
+        _ptr(d_omega, torch.float32, B * m, "d_omega"), _ptr(d_alpha, torch.float32, B * m, "d_alpha"),
+        _ptr(d_b, torch.float32, P, "d_b"), _ptr(loss, torch.float32, B, "loss"))
+    _check(st, "rm_solve_adjoint")
+
+
+def rm_meta_param_count(m):
+    return int(_lib.load().rm_meta_param_count(m))
+
+
+def rm_meta_forward(ctx, plan, m, params, omega, alpha):
+    _check(ctx.lib.rm_meta_forward(ctx.handle, plan.handle, m,
+                                   _ptr(params, torch.float32, rm_meta_param_count(m), "params"),
+                                   _ptr(omega, torch.float32, plan.B * m, "omega"),
+                                   _ptr(alpha, torch.float32, plan.B * m, "alpha")), "rm_meta_forward")
+
+
+def rm_meta_backward(ctx, plan, m, params, d_omega, d_alpha, d_params):
+    npar = rm_meta_param_count(m)
+    _check(ctx.lib.rm_meta_backward(ctx.handle, plan.handle, m, _ptr(params, torch.float32, npar, "params"),
+                                    _ptr(d_omega, torch.float32, plan.B * m, "d_omega"),
+                                    _ptr(d_alpha, torch.float32, plan.B * m, "d_alpha"),
+                                    _ptr(d_params, torch.float32, npar, "d_params")), "rm_meta_backward")
