@@ -122,6 +122,27 @@ rm_status rm_plan_offsets(const rm_plan_t* plan, int64_t* off);
  * Gershgorin bound |centre| + sum |off-diagonal| (host gersh[B]). */
 rm_status rm_plan_coefficients(const rm_plan_t* plan, double* coef, double* gersh);
 
+/* Kernel configuration of the FP32 sweeps.  Instances are grouped by size n;
+ * every size class runs a temporal-blocked kernel that advances T inner steps
+ * per launch on extended tiles of shape index `shape` (0..4: 64x64, 64x128,
+ * 96x96, 128x64, 160x96 points) with a halo of T + 1 points.  rm_plan picks a
+ * configuration per class from a cost model; rm_tune measures.
+ * rm_plan_set_kernel: set (shape, T) for the class of size n (n <= 0: all
+ * classes); shape = -1 switches the whole plan to one launch per inner step.
+ * RM_EINVAL if the halo does not fit the shape or no instance has size n. */
+rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t T);
+rm_status rm_plan_get_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, int32_t* T);
+
+/* Autotuner: for every size class, time each valid (shape, T) on this plan's
+ * data (16 inner steps of `method` with the given device weights and right-hand
+ * side, best of 3) and keep the fastest.  cache_path (host string, may be NULL)
+ * names a JSON file of choices keyed by "<gfx arch> n=<n> B=<class size>
+ * m=<m> method=<method>": classes found there are not timed again, new results
+ * are written back.  *us_per_step (may be NULL) receives the summed per-step
+ * time of the chosen configurations in microseconds.  Blocks. */
+rm_status rm_tune(rm_ctx* ctx, rm_plan_t* plan, int32_t method, int32_t m, const float* omega,
+                  const float* alpha, const float* b, const char* cache_path, double* us_per_step);
+
 /* y = A x for every instance (§2.3, §3.2).  x, y: device [P_tot] of `dtype`,
  * must not overlap. */
 rm_status rm_apply_A(rm_ctx* ctx, const rm_plan_t* plan, int32_t dtype, const void* x, void* y);

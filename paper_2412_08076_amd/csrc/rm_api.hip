@@ -94,6 +94,20 @@ struct rm_plan_s {
   DevBuf d_tiles, d_inst, d_coef32, d_coef64, d_mu, d_gersh;
   // scratch
   DevBuf partial, red, flags, vecA, vecB, vecC, vecD, vecE, vecF, states, acc, meta;
+  // FP32 sweeps: temporal-blocked kernels, one configuration per size class
+  struct ClassExec {
+    int n = 0;
+    int shape = 0;  // index into rmk::kBlockShapes
+    int T = 1;      // steps per launch
+    std::vector<int> insts;
+    DevBuf tiles;
+    int ntiles = 0;
+  };
+  bool use_block = true;
+  bool exec_dirty = true;
+  std::vector<ClassExec> classes;
+  DevBuf d_ranges;  // int [B][2]: slot range of each instance over all class tables
+  int nslots = 0;
   PlanDev dev() const {
     PlanDev p;
     p.tiles = d_tiles.as<Tile>();
@@ -108,8 +122,9 @@ struct rm_plan_s {
   }
   ~rm_plan_s() {
     for (DevBuf* b : {&d_tiles, &d_inst, &d_coef32, &d_coef64, &d_mu, &d_gersh, &partial, &red, &flags, &vecA,
-                      &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta})
+                      &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges})
       b->release();
+    for (auto& c : classes) c.tiles.release();
   }
 };
 
@@ -163,6 +178,149 @@ size_t vec_bytes(const rm_plan_t* p) {
 }
 
 // ---------------------------------------------------------------------------
+// temporal-blocked execution plan
+// ---------------------------------------------------------------------------
+// Extended tile of a class: shape s, halo h = T + 1 (one ring more than the T
+// steps need, so the residual of the final iterate can be formed in the same
+// launch).  Owned region W x H = (EW - 2h) x (EH - 2h).
+bool class_geometry(int shape, int T, int& W, int& H, int& h) {
+  const rmk::BlockShape& bs = rmk::kBlockShapes[shape];
+  h = T + 1;
+  W = bs.cw - 2 * h;
+  H = bs.ns * bs.r - 2 * h;
+  return W >= 1 && H >= 1;
+}
+
+// Cost model used before any tuning: the larger of an arithmetic bound
+// (redundant halo work included) and an HBM bound (load u, v, f on the extended
+// tile, store u, v on the owned one, once per T steps), per inner step.
+double model_cost(int n, int shape, int T) {
+  int W, H, h;
+  if (!class_geometry(shape, T, W, H, h)) return 1e300;
+  const rmk::BlockShape& bs = rmk::kBlockShapes[shape];
+  const double tiles = (double)((n + W - 1) / W) * (double)((n + H - 1) / H);
+  const double ext = tiles * bs.cw * (double)(bs.ns * bs.r);
+  const double own = (double)n * n;
+  const double compute = ext / 1.2e12;
+  const double memory = (12.0 * ext + 8.0 * own) / T / 5.0e12;
+  return std::max(compute, memory) + 4e-6 / T / 256.0;
+}
+
+void default_class_config(int n, int& shape, int& T) {
+  double best = 1e301;
+  shape = 0;
+  T = 1;
+  for (int s = 0; s < rmk::kNumBlockShapes; ++s)
+    for (int t : rmk::kBlockTs) {
+      const double c = model_cost(n, s, t);
+      if (c < best * 0.999) {
+        best = c;
+        shape = s;
+        T = t;
+      }
+    }
+}
+
+void init_classes(rm_plan_t* pl) {
+  pl->classes.clear();
+  std::vector<int> sizes;
+  for (const auto& in : pl->inst) sizes.push_back(in.n);
+  std::sort(sizes.begin(), sizes.end());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  for (int n : sizes) {
+    rm_plan_s::ClassExec c;
+    c.n = n;
+    default_class_config(n, c.shape, c.T);
+    for (int b = 0; b < pl->B; ++b)
+      if (pl->inst[b].n == n) c.insts.push_back(b);
+    pl->classes.push_back(std::move(c));
+  }
+  pl->exec_dirty = true;
+}
+
+rm_status build_exec(rm_plan_t* pl, hipStream_t st) {
+  if (!pl->exec_dirty) return RM_OK;
+  std::vector<int> ranges((size_t)pl->B * 2, 0);
+  int slot = 0;
+  for (auto& c : pl->classes) {
+    int W, H, h;
+    if (!class_geometry(c.shape, c.T, W, H, h)) return fail(RM_EINVAL, "invalid kernel shape for this T");
+    std::vector<Tile> t;
+    for (int b : c.insts) {
+      const int n = pl->inst[b].n;
+      ranges[2 * b] = slot;
+      for (int oy = 0; oy < n; oy += H)
+        for (int ox = 0; ox < n; ox += W) t.push_back(Tile{b, ox - h, oy - h, slot++});
+      ranges[2 * b + 1] = slot;
+    }
+    while (t.size() % 8 != 0) t.push_back(Tile{-1, 0, 0, slot++});
+    c.ntiles = (int)t.size();
+    RM_TRY(c.tiles.ensure(t.size() * sizeof(Tile), st));
+    RM_HIP(hipStreamSynchronize(st));
+    RM_HIP(hipMemcpy(c.tiles.ptr, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  }
+  pl->nslots = slot;
+  RM_TRY(pl->d_ranges.ensure(ranges.size() * sizeof(int), st));
+  RM_HIP(hipMemcpy(pl->d_ranges.ptr, ranges.data(), ranges.size() * sizeof(int), hipMemcpyHostToDevice));
+  pl->exec_dirty = false;
+  return RM_OK;
+}
+
+size_t partial_slots(const rm_plan_t* pl) { return std::max<size_t>(pl->tiles.size(), (size_t)pl->nslots); }
+
+// Advance `nsteps` FP32 inner steps (global step indices s0 ..) on the pingpong
+// pair (us, vs), starting from set `cur`; `cur` ends on the set holding the
+// result and `flips` counts the swaps.  When res_partial is given, the residual
+// ||f - A u||^2 of the final iterate is left per tile in res_partial and
+// *res_ranges tells the reduction which slots belong to which instance.
+// `only_class` >= 0 restricts the launches to one size class (autotuning).
+rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int nsteps, const float* omega,
+                const float* alpha, const float* f, float* const us[2], float* const vs[2], int& cur, int& flips,
+                const int* active, double* res_partial, const int** res_ranges, int only_class = -1) {
+  const PlanDev p = pl->dev();
+  if (!pl->use_block) {
+    for (int k = 0; k < nsteps; ++k) {
+      rmk::launch_step<float>(method, p, p.tiles, p.ntiles, omega, alpha, m, (s0 + k) % m, f, us[cur], vs[cur],
+                              us[cur ^ 1], vs[cur ^ 1], active, st);
+      cur ^= 1;
+      ++flips;
+    }
+    if (res_partial != nullptr) {
+      rmk::launch_residual<float>(p, p.tiles, p.ntiles, f, us[cur], nullptr, res_partial, active, st);
+      *res_ranges = nullptr;
+    }
+    return RM_OK;
+  }
+  RM_TRY(build_exec(pl, st));
+  int done = 0;
+  while (done < nsteps) {
+    // chunk: the largest supported T not above the remaining steps and the
+    // smallest class T (every class advances by the same number of steps)
+    int tmax = 8;
+    for (size_t ci = 0; ci < pl->classes.size(); ++ci)
+      if (only_class < 0 || (int)ci == only_class) tmax = std::min(tmax, pl->classes[ci].T);
+    int t = 1;
+    for (int cand : rmk::kBlockTs)
+      if (cand <= tmax && cand <= nsteps - done) t = cand;
+    const bool last = done + t == nsteps;
+    for (size_t ci = 0; ci < pl->classes.size(); ++ci) {
+      if (only_class >= 0 && (int)ci != only_class) continue;
+      auto& c = pl->classes[ci];
+      const int h = c.T + 1;
+      if (!rmk::launch_block(c.shape, t, method, p, c.tiles.as<Tile>(), c.ntiles, h, omega, alpha, m, s0 + done, f,
+                             us[cur], vs[cur], us[cur ^ 1], vs[cur ^ 1], active,
+                             last ? res_partial : nullptr, st))
+        return fail(RM_EUNSUPPORTED, "block kernel configuration not built");
+    }
+    cur ^= 1;
+    ++flips;
+    done += t;
+  }
+  if (res_partial != nullptr) *res_ranges = pl->d_ranges.as<int>();
+  return RM_OK;
+}
+
+// ---------------------------------------------------------------------------
 // unrolled solve: K inner steps from (x, 0)
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -188,6 +346,36 @@ rm_status solve_unroll(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     rmk::launch_fill_f64((double*)v1, 0.0, P, st);
   }
   const int E = o->ckpt_every;
+  if (sizeof(T) == 4) {
+    // FP32: temporal-blocked sweeps between checkpoint and history boundaries
+    RM_TRY(build_exec(pl, st));
+    RM_TRY(pl->partial.ensure(partial_slots(pl) * 2 * sizeof(double), st));
+    float* fu[2] = {(float*)us[0], (float*)us[1]};
+    float* fv[2] = {(float*)vs[0], (float*)vs[1]};
+    int cur = 0, flips = 0;
+    for (int s = 0; s < o->K;) {
+      if (ckpt != nullptr && E > 0 && s % E == 0) {
+        T* slot = ckpt + (int64_t)(s / E) * 2 * P;
+        RM_HIP(hipMemcpyAsync(slot, us[cur], P * sizeof(T), hipMemcpyDeviceToDevice, st));
+        RM_HIP(hipMemcpyAsync(slot + P, vs[cur], P * sizeof(T), hipMemcpyDeviceToDevice, st));
+      }
+      int next = (s / o->m + 1) * o->m;
+      if (ckpt != nullptr && E > 0) next = std::min(next, (s / E + 1) * E);
+      next = std::min(next, o->K);
+      const bool want_hist = hist != nullptr && next % o->m == 0;
+      const int* ranges = nullptr;
+      RM_TRY(sweep(pl, st, method, o->m, s, next - s, omega, alpha, (const float*)b, fu, fv, cur, flips, nullptr,
+                   want_hist ? pl->partial.as<double>() : nullptr, &ranges));
+      if (want_hist) {
+        const int k = next / o->m - 1;
+        rmk::launch_reduce_partials(p, pl->partial.as<double>(), hist + (int64_t)k * pl->B, nullptr, 1, nullptr, st,
+                                    ranges);
+      }
+      s = next;
+    }
+    if (cur == 1) RM_HIP(hipMemcpyAsync(x, u1, P * sizeof(T), hipMemcpyDeviceToDevice, st));
+    return last_launch();
+  }
   for (int s = 0; s < o->K; ++s) {
     const int cur = s & 1, nxt = cur ^ 1;
     if (ckpt != nullptr && E > 0 && s % E == 0) {
@@ -220,9 +408,10 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   RM_TRY(pl->vecC.ensure(fb, st));  // v0
   RM_TRY(pl->vecD.ensure(fb, st));  // d1
   RM_TRY(pl->vecE.ensure(fb, st));  // v1
-  RM_TRY(pl->partial.ensure(pl->tiles.size() * 2 * sizeof(double), st));
-  RM_TRY(pl->red.ensure((size_t)B * 4 * sizeof(double), st));
-  RM_TRY(pl->flags.ensure(((size_t)B * 4 + 16) * sizeof(int), st));
+  RM_TRY(build_exec(pl, st));
+  RM_TRY(pl->partial.ensure(partial_slots(pl) * 2 * sizeof(double), st));
+  RM_TRY(pl->red.ensure((size_t)B * 6 * sizeof(double), st));
+  RM_TRY(pl->flags.ensure(((size_t)B * 5 + 16) * sizeof(int), st));
   float* r32 = pl->vecA.as<float>();
   float* ds[2] = {pl->vecB.as<float>(), pl->vecD.as<float>()};
   float* vs[2] = {pl->vecC.as<float>(), pl->vecE.as<float>()};
@@ -230,22 +419,28 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   double* b2 = r2 + B;                    // [B]  ||b||^2
   double* rhs2 = r2 + 2 * B;              // [B]  ||r_j||^2 of the current round
   double* res2 = r2 + 3 * B;              // [B]  inner residual^2 after an outer iteration
+  double* target2 = r2 + 4 * B;           // [B]  inner residual^2 that ends the round
+  double* best2 = r2 + 5 * B;             // [B]  smallest inner residual^2 so far (stagnation)
   int* active = pl->flags.as<int>();      // [B]
   int* count = active + B;                // [B]
   int* status = active + 2 * B;           // [B]
   int* mask = active + 3 * B;             // [B]
-  int* n_active = active + 4 * B;         // [1]
+  int* since = active + 4 * B;            // [B]  outer iterations since the last 10 % gain
+  int* n_active = active + 5 * B;         // [1]
   double* partial = pl->partial.as<double>();
   const PlanDev p = pl->dev();
 
   std::vector<int> done(B, 0), st_h(B, RM_OK), dst_h(B, 0), rounds(B, 0), mask_h(B, 1), cnt_h(B, 0);
   std::vector<long long> outer_tot(B, 0);
-  std::vector<double> r2_h(B), b2_h(B), relres(B, 0.0);
+  std::vector<double> r2_h(B), b2_h(B), relres(B, 0.0), prev_rho(B, 0.0), target2_h(B, 0.0);
+  std::vector<int> strikes(B, 0);
+  // stagnation window in outer iterations: at least 256 inner steps
+  const int stall = std::max(16, (256 + o->m - 1) / o->m);
   rmk::launch_fill_i32(status, 0, B, st);
   RM_HIP(hipMemcpyAsync(mask, mask_h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
-  const double tol_in2 = o->tol_inner * o->tol_inner;
+  int flips_per_outer = 0;
   for (int j = 0;; ++j) {
-    if (j > 0) rmk::launch_refine_update(p, x, ds[0], ds[1], count, o->m, mask, st);
+    if (j > 0) rmk::launch_refine_update(p, x, ds[0], ds[1], count, flips_per_outer, mask, st);
     rmk::launch_refine_residual(p, b, x, r32, ds[0], vs[0], partial, mask, st);
     rmk::launch_reduce_partials(p, partial, r2, b2, 1, nullptr, st);
     RM_HIP(hipMemcpyAsync(r2_h.data(), r2, B * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -270,11 +465,18 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
       } else if (j >= o->max_rounds) {
         done[bi] = 1;
         st_h[bi] = RM_ENOTCONV;
+      } else if (j > 0 && rho > 0.5 * prev_rho[bi] && ++strikes[bi] >= 2) {
+        done[bi] = 1;  // two rounds without halving the residual: give up
+        st_h[bi] = RM_ENOTCONV;
       }
+      prev_rho[bi] = rho;
       mask_h[bi] = done[bi] ? 0 : 1;
       if (!done[bi]) {
         ++n_round;
         ++rounds[bi];
+        // inner target: tol_inner, relaxed in the last round to what reaching tol needs
+        const double tau = std::max(o->tol_inner, 0.5 * o->tol / rho);
+        target2_h[bi] = tau * tau * r2_h[bi];
       }
     }
     if (n_round == 0) break;
@@ -282,18 +484,20 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     RM_HIP(hipMemcpyAsync(mask, mask_h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
     RM_HIP(hipMemcpyAsync(active, mask, B * sizeof(int), hipMemcpyDeviceToDevice, st));
     RM_HIP(hipMemcpyAsync(rhs2, r2, B * sizeof(double), hipMemcpyDeviceToDevice, st));
+    RM_HIP(hipMemcpyAsync(best2, r2, B * sizeof(double), hipMemcpyDeviceToDevice, st));
+    RM_HIP(hipMemcpyAsync(target2, target2_h.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
     rmk::launch_fill_i32(count, 0, B, st);
+    rmk::launch_fill_i32(since, 0, B, st);
     int cur = 0;
     for (int k = 1;; ++k) {
-      for (int i = 0; i < o->m; ++i) {
-        rmk::launch_step<float>(method, p, p.tiles, p.ntiles, omega, alpha, o->m, i, r32, ds[cur], vs[cur],
-                                ds[cur ^ 1], vs[cur ^ 1], active, st);
-        cur ^= 1;
-      }
-      rmk::launch_residual<float>(p, p.tiles, p.ntiles, r32, ds[cur], nullptr, partial, active, st);
-      rmk::launch_reduce_partials(p, partial, res2, nullptr, 1, nullptr, st);
+      int flips = 0;
+      const int* ranges = nullptr;
+      RM_TRY(sweep(pl, st, method, o->m, 0, o->m, omega, alpha, r32, ds, vs, cur, flips, active, partial, &ranges));
+      flips_per_outer = flips;
+      rmk::launch_reduce_partials(p, partial, res2, nullptr, 1, nullptr, st, ranges);
       rmk::launch_fill_i32(n_active, 0, 1, st);
-      rmk::launch_inner_flags(B, res2, rhs2, tol_in2, o->max_outer, active, count, status, n_active, st);
+      rmk::launch_inner_flags(B, res2, rhs2, target2, best2, since, stall, o->max_outer, active, count, status,
+                              n_active, st);
       if (k % o->check_every == 0 || k >= o->max_outer) {
         RM_HIP(hipMemcpyAsync(ctx->host_flag, n_active, sizeof(int), hipMemcpyDeviceToHost, st));
         RM_HIP(hipStreamSynchronize(st));
@@ -332,6 +536,16 @@ rm_status validate_weights(const rm_plan_t* pl, int method, const rm_solve_opts*
   if (method == RM_NAG && alpha == nullptr) return fail(RM_EINVAL, "NAG needs alpha");
   (void)pl;
   return RM_OK;
+}
+
+}  // namespace
+
+namespace {
+
+std::string tune_key(const char* arch, const rm_plan_s::ClassExec& c, int m, int method) {
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s n=%d B=%zu m=%d method=%d", arch, c.n, c.insts.size(), m, method);
+  return buf;
 }
 
 }  // namespace
@@ -429,6 +643,7 @@ rm_status rm_plan(rm_ctx* ctx, int32_t B, const rm_instance* inst, rm_plan_t** o
   }
   while (pl->tiles.size() % 8 != 0) pl->tiles.push_back(Tile{-1, 0, 0, (int)pl->tiles.size()});
   pl->P = pl->off[B];
+  init_classes(pl);
   hipStream_t st = ctx->stream;
   rm_status s = RM_OK;
   auto up = [&](DevBuf& d, const void* src, size_t bytes) {
@@ -624,6 +839,165 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   }
   rmk::launch_f64_to_f32(acc_w, d_omega, (int64_t)B * m, st);
   rmk::launch_f64_to_f32(acc_a, d_alpha, (int64_t)B * m, st);
+  return last_launch();
+}
+
+rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t T) {
+  if (plan == nullptr) return fail(RM_EINVAL, "null plan");
+  if (shape == -1) {
+    plan->use_block = false;
+    return RM_OK;
+  }
+  if (shape < 0 || shape >= rmk::kNumBlockShapes) return fail(RM_EINVAL, "unknown kernel shape");
+  if (T != 1 && T != 2 && T != 4 && T != 8) return fail(RM_EINVAL, "T must be 1, 2, 4 or 8");
+  int W, H, h;
+  if (!class_geometry(shape, T, W, H, h)) return fail(RM_EINVAL, "halo T + 1 does not fit this shape");
+  bool hit = false;
+  for (auto& c : plan->classes)
+    if (n <= 0 || c.n == n) {
+      c.shape = shape;
+      c.T = T;
+      hit = true;
+    }
+  if (!hit) return fail(RM_EINVAL, "no instance of that size in the plan");
+  plan->use_block = true;
+  plan->exec_dirty = true;
+  return RM_OK;
+}
+
+rm_status rm_plan_get_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, int32_t* T) {
+  if (plan == nullptr || shape == nullptr || T == nullptr) return fail(RM_EINVAL, "null argument");
+  if (!plan->use_block) {
+    *shape = -1;
+    *T = 1;
+    return RM_OK;
+  }
+  for (const auto& c : plan->classes)
+    if (c.n == n) {
+      *shape = c.shape;
+      *T = c.T;
+      return RM_OK;
+    }
+  return fail(RM_EINVAL, "no instance of that size in the plan");
+}
+
+rm_status rm_tune(rm_ctx* ctx, rm_plan_t* plan, int32_t method, int32_t m, const float* omega, const float* alpha,
+                  const float* b, const char* cache_path, double* us_per_step) {
+  RM_TRY(check_ctx_plan(ctx, plan));
+  if (method != RM_RICHARDSON && method != RM_NAG) return fail(RM_EINVAL, "unknown method");
+  if (m < 1 || m > kMaxM) return fail(RM_EINVAL, "m must be in 1..64");
+  if (omega == nullptr || b == nullptr || (method == RM_NAG && alpha == nullptr))
+    return fail(RM_EINVAL, "null omega, alpha or b");
+  hipStream_t st = ctx->stream;
+  hipDeviceProp_t prop;
+  RM_HIP(hipGetDeviceProperties(&prop, ctx->device));
+  char arch[64];
+  std::snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+  for (char* q = arch; *q; ++q)
+    if (*q == ':') *q = 0;
+  // cached choices
+  std::vector<std::pair<std::string, std::string>> cache;
+  if (cache_path != nullptr) {
+    if (FILE* fh = std::fopen(cache_path, "r")) {
+      char line[512];
+      while (std::fgets(line, sizeof line, fh)) {
+        char key[300];
+        int sh, T;
+        double us;
+        if (std::sscanf(line, " \"%299[^\"]\": [%d, %d, %lf]", key, &sh, &T, &us) == 4) {
+          char val[64];
+          std::snprintf(val, sizeof val, "[%d, %d, %.3f]", sh, T, us);
+          cache.emplace_back(key, val);
+        }
+      }
+      std::fclose(fh);
+    }
+  }
+  const size_t fb = vec_bytes<float>(plan);
+  RM_TRY(plan->vecA.ensure(fb, st));
+  RM_TRY(plan->vecB.ensure(fb, st));
+  RM_TRY(plan->vecC.ensure(fb, st));
+  RM_TRY(plan->vecD.ensure(fb, st));
+  float* us_[2] = {plan->vecA.as<float>(), plan->vecB.as<float>()};
+  float* vs_[2] = {plan->vecC.as<float>(), plan->vecD.as<float>()};
+  for (int k = 0; k < 2; ++k) {
+    rmk::launch_fill_f32(us_[k], 0.f, plan->P, st);
+    rmk::launch_fill_f32(vs_[k], 0.f, plan->P, st);
+  }
+  plan->use_block = true;
+  hipEvent_t e0, e1;
+  RM_HIP(hipEventCreate(&e0));
+  RM_HIP(hipEventCreate(&e1));
+  double total_us = 0.0;
+  const int steps = 16, reps = 3;
+  for (size_t ci = 0; ci < plan->classes.size(); ++ci) {
+    auto& c = plan->classes[ci];
+    const std::string key = tune_key(arch, c, m, method);
+    bool found = false;
+    for (auto& kv : cache)
+      if (kv.first == key) {
+        int sh, T;
+        double us;
+        if (std::sscanf(kv.second.c_str(), "[%d, %d, %lf]", &sh, &T, &us) == 3) {
+          int W, H, h;
+          if (sh >= 0 && sh < rmk::kNumBlockShapes && class_geometry(sh, T, W, H, h)) {
+            c.shape = sh;
+            c.T = T;
+            total_us += us;
+            found = true;
+          }
+        }
+      }
+    if (found) continue;
+    double best = 1e300;
+    int best_s = c.shape, best_T = c.T;
+    for (int sh = 0; sh < rmk::kNumBlockShapes; ++sh)
+      for (int T : rmk::kBlockTs) {
+        int W, H, h;
+        if (!class_geometry(sh, T, W, H, h)) continue;
+        c.shape = sh;
+        c.T = T;
+        plan->exec_dirty = true;
+        double t_best = 1e300;
+        for (int r = 0; r < reps + 1; ++r) {
+          int cur = 0, flips = 0;
+          RM_HIP(hipEventRecord(e0, st));
+          RM_TRY(sweep(plan, st, method, m, 0, steps, omega, alpha, b, us_, vs_, cur, flips, nullptr, nullptr,
+                       nullptr, (int)ci));
+          RM_HIP(hipEventRecord(e1, st));
+          RM_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          RM_HIP(hipEventElapsedTime(&ms, e0, e1));
+          if (r > 0) t_best = std::min(t_best, (double)ms * 1e3 / steps);
+        }
+        if (t_best < best) {
+          best = t_best;
+          best_s = sh;
+          best_T = T;
+        }
+      }
+    c.shape = best_s;
+    c.T = best_T;
+    total_us += best;
+    char val[64];
+    std::snprintf(val, sizeof val, "[%d, %d, %.3f]", best_s, best_T, best);
+    cache.emplace_back(key, val);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  plan->exec_dirty = true;
+  RM_TRY(build_exec(plan, st));
+  if (cache_path != nullptr) {
+    if (FILE* fh = std::fopen(cache_path, "w")) {
+      std::fprintf(fh, "{\n");
+      for (size_t k = 0; k < cache.size(); ++k)
+        std::fprintf(fh, "  \"%s\": %s%s\n", cache[k].first.c_str(), cache[k].second.c_str(),
+                     k + 1 < cache.size() ? "," : "");
+      std::fprintf(fh, "}\n");
+      std::fclose(fh);
+    }
+  }
+  if (us_per_step != nullptr) *us_per_step = total_us;
   return last_launch();
 }
 

@@ -59,20 +59,22 @@ void launch_step(int method, const PlanDev& p, const Tile* tiles, int ntiles, co
                  T* v_out, const int* active, hipStream_t st);
 // per-instance fixed-order sums of per-tile partials over the instance's tiles t:
 // out0[b*stride] = sum_t partial2[2t], out1[b*stride] = sum_t partial2[2t+1],
-// ratio[b] = out0 / out1 as float (any output may be null)
+// ratio[b] = out0 / out1 as float (any output may be null).  The tiles of instance b are
+// [ranges[2b], ranges[2b+1]) when ranges is given, else its range in the plan's tile table.
 void launch_reduce_partials(const PlanDev& p, const double* partial2, double* out0, double* out1,
-                            int stride, float* ratio, hipStream_t st);
+                            int stride, float* ratio, hipStream_t st, const int* ranges = nullptr);
 // FP64 refinement: r = b - A x, r32 = fl32(r), d = v = 0, partials of ||r||^2, ||b||^2
 void launch_refine_residual(const PlanDev& p, const double* b, const double* x, float* r32,
                             float* d, float* v, double* partial2, const int* round_mask,
                             hipStream_t st);
 // x += d for instances with round_mask[b] != 0; d is d0 or d1 depending on the parity of
-// outer_count[b] * m (the inner solve ping-pongs between two buffers)
+// outer_count[b] * flips (the inner solve swaps its two buffers `flips` times per outer iteration)
 void launch_refine_update(const PlanDev& p, double* x, const float* d0, const float* d1,
-                          const int* outer_count, int m, const int* round_mask, hipStream_t st);
+                          const int* outer_count, int flips, const int* round_mask, hipStream_t st);
 // inner-solve bookkeeping after one outer iteration (one thread per instance)
-void launch_inner_flags(int B, const double* res2, const double* rhs2, double tol_in2, int cap,
-                        int* active, int* outer_count, int* status, int* n_active, hipStream_t st);
+void launch_inner_flags(int B, const double* res2, const double* rhs2, const double* target2,
+                        double* best2, int* since, int stall, int cap, int* active, int* outer_count,
+                        int* status, int* n_active, hipStream_t st);
 void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st);
 void launch_fill_f32(float* p, float value, int64_t count, hipStream_t st);
 void launch_fill_f64(double* p, double value, int64_t count, hipStream_t st);
@@ -93,5 +95,21 @@ void launch_meta_forward(const PlanDev& p, int m, const float* params, float* om
                          hipStream_t st);
 void launch_meta_backward(const PlanDev& p, int m, const float* params, const float* d_omega,
                           const float* d_alpha, float* per_inst, float* d_params, hipStream_t st);
+
+// ---- temporal-blocked steps (rm_block.hip) ---------------------------------
+// Extended-tile shapes: CW columns by NS strips of R rows, CW * NS threads.
+struct BlockShape {
+  int cw, ns, r;
+};
+constexpr int kNumBlockShapes = 5;
+extern const BlockShape kBlockShapes[kNumBlockShapes];
+constexpr int kBlockTs[4] = {1, 2, 4, 8};
+// T fused steps (s0 .. s0 + T - 1) over a tile table of extended tiles inset by h
+// (h >= T; h >= T + 1 when partial2 is given, which then receives ||f - A u||^2 of
+// the final u per tile).  Returns false for an unsupported (shape, T).
+bool launch_block(int shape, int T, int method, const PlanDev& p, const Tile* tiles, int ntiles, int h,
+                  const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,
+                  const float* v, float* u_out, float* v_out, const int* active, double* partial2,
+                  hipStream_t st);
 
 }  // namespace rmk

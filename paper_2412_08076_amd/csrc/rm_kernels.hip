@@ -233,12 +233,15 @@ __global__ __launch_bounds__(WG) void k_step(PlanDev p, const Tile* tiles, const
 
 // Per-instance fixed-order sum of per-tile partials: one wave per instance.
 __global__ __launch_bounds__(64) void k_reduce_partials(PlanDev p, const double* __restrict__ partial2,
+                                                        const int* __restrict__ ranges,
                                                         double* __restrict__ out0, double* __restrict__ out1,
                                                         int stride, float* __restrict__ ratio) {
   const int b = blockIdx.x;
   const Inst in = p.inst[b];
+  const int t0 = ranges != nullptr ? ranges[2 * b] : in.tile_begin;
+  const int t1 = ranges != nullptr ? ranges[2 * b + 1] : in.tile_end;
   double s0 = 0.0, s1 = 0.0;
-  for (int t = in.tile_begin + (int)threadIdx.x; t < in.tile_end; t += 64) {
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += 64) {
     s0 += partial2[2 * t];
     s1 += partial2[2 * t + 1];
   }
@@ -305,14 +308,14 @@ __global__ __launch_bounds__(WG) void k_refine_residual(PlanDev p, const double*
 __global__ __launch_bounds__(WG) void k_refine_update(PlanDev p, double* __restrict__ x,
                                                       const float* __restrict__ d0,
                                                       const float* __restrict__ d1,
-                                                      const int* __restrict__ outer_count, int m,
+                                                      const int* __restrict__ outer_count, int flips,
                                                       const int* __restrict__ mask) {
   const Tile tl = p.tiles[xcd_remap(blockIdx.x, gridDim.x)];
   if (tl.inst < 0) return;
   if (mask[tl.inst] == 0) return;
   const Inst in = p.inst[tl.inst];
   const int n = in.n;
-  const float* d = (((int64_t)outer_count[tl.inst] * m) & 1) ? d1 : d0;
+  const float* d = (((int64_t)outer_count[tl.inst] * flips) & 1) ? d1 : d0;
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = tl.x0 + tx;
 #pragma unroll
@@ -325,26 +328,32 @@ __global__ __launch_bounds__(WG) void k_refine_update(PlanDev p, double* __restr
   }
 }
 
-// After one outer iteration of an inner solve: stop instances whose relative
-// residual reached tol_in (or that hit the cap, or went non-finite / grew
-// beyond 1e12 times the right-hand side), count the rest.
+// After one outer iteration of an inner solve: stop instances whose residual
+// reached their target (or that hit the cap, stagnated -- no 10 % reduction of
+// the residual within `stall` outer iterations -- or went non-finite / grew
+// beyond 1e6 times the right-hand side), count the rest.
 __global__ void k_inner_flags(int B, const double* __restrict__ res2, const double* __restrict__ rhs2,
-                              double tol_in2, int cap, int* __restrict__ active, int* __restrict__ outer_count,
-                              int* __restrict__ status, int* __restrict__ n_active) {
+                              const double* __restrict__ target2, double* __restrict__ best2,
+                              int* __restrict__ since, int stall, int cap, int* __restrict__ active,
+                              int* __restrict__ outer_count, int* __restrict__ status, int* __restrict__ n_active) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B || active[b] == 0) return;
   const int cnt = outer_count[b] + 1;
   outer_count[b] = cnt;
   const double r2 = res2[b];
-  const double f2 = rhs2[b];
   int keep = 1;
-  if (!(r2 <= 1e12 * f2)) {  // NaN, Inf or growth
-    status[b] = 5;           // RM_EDIVERGED
+  if (!(r2 <= 1e12 * rhs2[b])) {  // NaN, Inf or growth
+    status[b] = 5;                // RM_EDIVERGED
     keep = 0;
-  } else if (r2 <= tol_in2 * f2) {
+  } else if (r2 <= target2[b] || cnt >= cap) {
     keep = 0;
-  } else if (cnt >= cap) {
+  } else if (r2 < 0.81 * best2[b]) {
+    best2[b] = r2;
+    since[b] = 0;
+  } else if (since[b] + 1 >= stall) {
     keep = 0;
+  } else {
+    since[b] = since[b] + 1;
   }
   active[b] = keep;
   if (keep) atomicAdd(n_active, 1);
@@ -662,8 +671,8 @@ template void launch_step<double>(int, const PlanDev&, const Tile*, int, const f
                                   hipStream_t);
 
 void launch_reduce_partials(const PlanDev& p, const double* partial2, double* out0, double* out1, int stride,
-                            float* ratio, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3(p.B), dim3(64), 0, st, p, partial2, out0, out1, stride, ratio);
+                            float* ratio, hipStream_t st, const int* ranges) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(p.B), dim3(64), 0, st, p, partial2, ranges, out0, out1, stride, ratio);
 }
 
 void launch_refine_residual(const PlanDev& p, const double* b, const double* x, float* r32, float* d, float* v,
@@ -678,10 +687,11 @@ void launch_refine_update(const PlanDev& p, double* x, const float* d0, const fl
                      round_mask);
 }
 
-void launch_inner_flags(int B, const double* res2, const double* rhs2, double tol_in2, int cap, int* active,
-                        int* outer_count, int* status, int* n_active, hipStream_t st) {
-  hipLaunchKernelGGL(k_inner_flags, dim3((B + 255) / 256), dim3(256), 0, st, B, res2, rhs2, tol_in2, cap,
-                     active, outer_count, status, n_active);
+void launch_inner_flags(int B, const double* res2, const double* rhs2, const double* target2, double* best2,
+                        int* since, int stall, int cap, int* active, int* outer_count, int* status, int* n_active,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_inner_flags, dim3((B + 255) / 256), dim3(256), 0, st, B, res2, rhs2, target2, best2, since,
+                     stall, cap, active, outer_count, status, n_active);
 }
 
 void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st) {

@@ -14,7 +14,7 @@ from ._lib import (RM_EDIVERGED, RM_ENOTCONV, RM_F32, RM_F64, RM_FD5_HELMHOLTZ, 
                    RM_Q1_ANISO, RM_RICHARDSON, RM_TO_TOL, RM_UNROLL)
 
 __all__ = [
-    "RMError", "Context", "Plan", "rm_apply_A", "rm_residual", "rm_solve", "rm_solve_adjoint",
+    "RMError", "Context", "Plan", "rm_tune", "rm_apply_A", "rm_residual", "rm_solve", "rm_solve_adjoint",
     "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count", "solve_opts",
     "RM_Q1_ANISO", "RM_FD5_HELMHOLTZ", "RM_RICHARDSON", "RM_NAG", "RM_F32", "RM_F64",
     "RM_UNROLL", "RM_TO_TOL", "RM_OK", "RM_ENOTCONV", "RM_EDIVERGED",
@@ -102,6 +102,15 @@ class Plan:
         _check(self.lib.rm_plan_offsets(h, off), "rm_plan_offsets")
         self.offsets = np.frombuffer(off, dtype=np.int64).copy()
 
+    def set_kernel(self, shape, T, n=0):
+        """rm_plan_set_kernel: (shape, T) for the size class n (n <= 0: all); shape -1 = one-step kernel."""
+        _check(self.lib.rm_plan_set_kernel(self.handle, n, shape, T), "rm_plan_set_kernel")
+
+    def get_kernel(self, n):
+        sh, T = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.rm_plan_get_kernel(self.handle, n, ctypes.byref(sh), ctypes.byref(T)), "rm_plan_get_kernel")
+        return sh.value, T.value
+
     def coefficients(self):
         c = (ctypes.c_double * (5 * self.B))()
         g = (ctypes.c_double * self.B)()
@@ -121,12 +130,22 @@ class Plan:
 
 
 def solve_opts(mode=RM_UNROLL, dtype=RM_F32, m=16, K=0, ckpt_every=0, max_outer=100000, max_rounds=8,
-               check_every=4, tol=1e-10, tol_inner=1e-4):
+               check_every=4, tol=1e-10, tol_inner=1e-3):
     o = _lib.rm_solve_opts()
     o.mode, o.dtype, o.m, o.K, o.ckpt_every = mode, dtype, m, K, ckpt_every
     o.max_outer, o.max_rounds, o.check_every = max_outer, max_rounds, check_every
     o.tol, o.tol_inner = tol, tol_inner
     return o
+
+
+def rm_tune(ctx, plan, method, m, omega, alpha, b, cache_path=None):
+    """Autotune every size class of the plan on its data; returns the summed us per step."""
+    us = ctypes.c_double()
+    _check(ctx.lib.rm_tune(ctx.handle, plan.handle, method, m, _ptr(omega, torch.float32, plan.B * m, "omega"),
+                           _ptr(alpha, torch.float32, plan.B * m, "alpha") if alpha is not None else None,
+                           _ptr(b, torch.float32, plan.P, "b"),
+                           cache_path.encode() if cache_path else None, ctypes.byref(us)), "rm_tune")
+    return us.value
 
 
 def rm_apply_A(ctx, plan, x, y):

@@ -1,0 +1,138 @@
+"""Temporal-blocked FP32 sweeps: bitwise equal to one launch per inner step (the LDS
+race / halo detector), for every kernel shape and steps-per-launch T, on ragged
+sizes; autotuner choices and cache."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import problem
+from synthetic import random_batch
+from tests.gpu_helpers import dev, host, need_gpu, oracle_coef, plan_for, say
+
+pytestmark = pytest.mark.gpu
+
+NS = [1, 3, 17, 40, 63, 64, 65, 97, 130, 200]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    need_gpu()
+    from paper_2412_08076_amd import rm
+    return rm.Context(0)
+
+
+def _weights(batch, m, seed):
+    rng = np.random.default_rng(seed)
+    G = np.array([problem.gershgorin(oracle_coef(batch, b)) for b in range(batch.B)])
+    om = (rng.uniform(0.5, 1.0, (batch.B, m)) / G[:, None]).astype(np.float32)
+    al = rng.uniform(0.8, 0.97, (batch.B, m)).astype(np.float32)
+    return dev(om, torch.float32), dev(al, torch.float32)
+
+
+def _unroll(ctx, plan, method, om, al, f, m, K, hist=False, ckpt_every=0):
+    from paper_2412_08076_amd import rm
+    x = torch.zeros(plan.P, dtype=torch.float32, device="cuda")
+    h = torch.zeros(K // m * plan.B, dtype=torch.float64, device="cuda") if hist else None
+    ck = torch.zeros(K // ckpt_every * 2 * plan.P, dtype=torch.float32, device="cuda") if ckpt_every else None
+    opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=K, ckpt_every=ckpt_every)
+    rm.rm_solve(ctx, plan, method, opts, om, al, f, x, ckpt=ck, hist=h)
+    return host(x), (host(h) if hist else None), (host(ck) if ckpt_every else None)
+
+
+@pytest.mark.parametrize("method_name", ["nag", "richardson"])
+def test_blocked_equals_one_step_bitwise(ctx, method_name):
+    from paper_2412_08076_amd import rm
+    method = rm.RM_NAG if method_name == "nag" else rm.RM_RICHARDSON
+    batch = random_batch(NS, seed=5)
+    plan = plan_for(ctx, batch)
+    m, K = 16, 48
+    om, al = _weights(batch, m, 1)
+    f = dev(batch.f_packed(), torch.float32)
+    plan.set_kernel(-1, 1)
+    ref, ref_h, _ = _unroll(ctx, plan, method, om, al, f, m, K, hist=True)
+    for shape in range(5):
+        for T in (1, 2, 4, 8):
+            try:
+                plan.set_kernel(shape, T)
+            except rm.RMError:
+                continue  # halo T + 1 does not fit this shape
+            say("blocked vs one-step", method_name, "shape", shape, "T", T)
+            got, got_h, _ = _unroll(ctx, plan, method, om, al, f, m, K, hist=True)
+            assert np.array_equal(got, ref), (shape, T, np.max(np.abs(got - ref)))
+            # the per-tile residual sums differ only in summation order
+            assert np.allclose(got_h, ref_h, rtol=1e-12, atol=0), (shape, T)
+
+
+def test_blocked_checkpoints_and_mixed_classes(ctx):
+    """Different (shape, T) per size class in one plan; checkpoints at a spacing that
+    is not a multiple of T; the adjoint's recompute agrees with the forward."""
+    from paper_2412_08076_amd import rm
+    ns = [63, 63, 127, 255, 31]
+    batch = random_batch(ns, seed=9)
+    plan = plan_for(ctx, batch)
+    m, K, E = 8, 24, 6
+    om, al = _weights(batch, m, 2)
+    f = dev(batch.f_packed(), torch.float32)
+    plan.set_kernel(-1, 1)
+    ref, _, ref_ck = _unroll(ctx, plan, rm.RM_NAG, om, al, f, m, K, ckpt_every=E)
+    plan.set_kernel(0, 2, n=63)
+    plan.set_kernel(2, 4, n=127)
+    plan.set_kernel(4, 8, n=255)
+    plan.set_kernel(3, 1, n=31)
+    say("mixed classes", [plan.get_kernel(k) for k in (31, 63, 127, 255)])
+    got, _, got_ck = _unroll(ctx, plan, rm.RM_NAG, om, al, f, m, K, ckpt_every=E)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(got_ck, ref_ck)
+
+
+def test_refined_solve_blocked_matches_one_step(ctx):
+    from paper_2412_08076_amd import rm
+    ns = [33, 64, 100]
+    batch = random_batch(ns, seed=13, eps_range=(1e-2, 1.0))
+    plan = plan_for(ctx, batch)
+    m = 16
+    om, al = _weights(batch, m, 3)
+    b = dev(batch.f_packed())
+    reps = []
+    for cfg in ((-1, 1), (2, 4), (4, 8)):
+        plan.set_kernel(*cfg)
+        x = torch.zeros(plan.P, dtype=torch.float64, device="cuda")
+        opts = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=1e-10, tol_inner=1e-3, max_outer=20000, max_rounds=10)
+        rep = rm.rm_solve(ctx, plan, rm.RM_NAG, opts, om, al, b, x)
+        say("refined", cfg, rep["outer_iters"], rep["rounds"])
+        assert rep["status"] == rm.RM_OK and np.all(rep["relres"] <= 1e-10)
+        reps.append((rep, host(x)))
+    for rep, x in reps[1:]:
+        assert np.array_equal(rep["outer_iters"], reps[0][0]["outer_iters"])
+        assert np.array_equal(x, reps[0][1])
+
+
+def test_autotune_and_cache(ctx, tmp_path):
+    from paper_2412_08076_amd import rm
+    ns = [63, 255, 255]
+    batch = random_batch(ns, seed=17)
+    plan = plan_for(ctx, batch)
+    m = 16
+    om, al = _weights(batch, m, 4)
+    f = dev(batch.f_packed(), torch.float32)
+    cache = str(tmp_path / "tune.json")
+    us = rm.rm_tune(ctx, plan, rm.RM_NAG, m, om, al, f, cache_path=cache)
+    say("tuned", us, [plan.get_kernel(k) for k in (63, 255)])
+    assert us > 0
+    table = json.load(open(cache))
+    assert len(table) == 2 and all(len(v) == 3 for v in table.values())
+    # a second plan reads the cache (no timing) and lands on the same choices
+    plan2 = plan_for(ctx, batch)
+    us2 = rm.rm_tune(ctx, plan2, rm.RM_NAG, m, om, al, f, cache_path=cache)
+    assert abs(us2 - us) < 1e-2
+    for k in (63, 255):
+        assert plan2.get_kernel(k) == plan.get_kernel(k)
+    # tuned plan still computes the same iterates as the one-step kernel
+    ref_plan = plan_for(ctx, batch)
+    ref_plan.set_kernel(-1, 1)
+    a, _, _ = _unroll(ctx, plan, rm.RM_NAG, om, al, f, m, 32)
+    r, _, _ = _unroll(ctx, ref_plan, rm.RM_NAG, om, al, f, m, 32)
+    assert np.array_equal(a, r)
