@@ -124,16 +124,21 @@ rm_status rm_plan_coefficients(const rm_plan_t* plan, double* coef, double* gers
 
 /* Kernel configuration of the FP32 sweeps.  Instances are grouped by size n;
  * every size class runs a temporal-blocked kernel that advances T inner steps
- * per launch on extended tiles of shape index `shape` (0..4: 64x64, 64x128,
- * 96x96, 128x64, 160x96 points) with a halo of T + 1 points.  rm_plan picks a
- * configuration per class from a cost model; rm_tune measures.
- * rm_plan_set_kernel: set (shape, T) for the class of size n (n <= 0: all
- * classes); shape = -1 switches the whole plan to one launch per inner step.
- * RM_EINVAL if the halo does not fit the shape or no instance has size n. */
-rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t T);
-rm_status rm_plan_get_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, int32_t* T);
+ * per launch on extended tiles of cw x 8R points (cw a multiple of 8) with a
+ * halo of T + 1 points, using 8 cw threads per workgroup.  Kernel variant
+ * `shape` fixes R and the largest cw: 0: R = 8, cw <= 64; 1: R = 16, cw <= 64;
+ * 2: R = 8, cw <= 128; 3: R = 13, cw <= 104; 4: R = 16, cw <= 128;
+ * 5: R = 12, cw <= 96.  rm_plan
+ * picks a configuration per class from a cost model; rm_tune measures.
+ * rm_plan_set_kernel: set (shape, T, cw) for the class of size n (n <= 0: all
+ * classes; cw <= 0: the width the cost model prefers); shape = -1 switches the
+ * whole plan to one launch per inner step.  RM_EINVAL if the halo or width does
+ * not fit the variant or no instance has size n. */
+rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t T, int32_t cw);
+rm_status rm_plan_get_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, int32_t* T,
+                             int32_t* cw);
 
-/* Autotuner: for every size class, time each valid (shape, T) on this plan's
+/* Autotuner: for every size class, time each valid (shape, T, cw) on this plan's
  * data (16 inner steps of `method` with the given device weights and right-hand
  * side, best of 3) and keep the fastest.  cache_path (host string, may be NULL)
  * names a JSON file of choices keyed by "<gfx arch> n=<n> B=<class size>

@@ -61,8 +61,8 @@ def load():
         "rm_plan_points": (I64, [P]),
         "rm_plan_offsets": (st, [P, ctypes.POINTER(I64)]),
         "rm_plan_coefficients": (st, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
-        "rm_plan_set_kernel": (st, [P, I32, I32, I32]),
-        "rm_plan_get_kernel": (st, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "rm_plan_set_kernel": (st, [P, I32, I32, I32, I32]),
+        "rm_plan_get_kernel": (st, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "rm_tune": (st, [P, P, I32, I32, P, P, P, ctypes.c_char_p, ctypes.POINTER(D)]),
         "rm_apply_A": (st, [P, P, I32, P, P]),
         "rm_residual": (st, [P, P, I32, P, P, P, P, P, P]),

@@ -97,8 +97,9 @@ struct rm_plan_s {
   // FP32 sweeps: temporal-blocked kernels, one configuration per size class
   struct ClassExec {
     int n = 0;
-    int shape = 0;  // index into rmk::kBlockShapes
+    int shape = 0;  // kernel variant, index into rmk::kBlockVariants
     int T = 1;      // steps per launch
+    int cw = 64;    // extended tile width (multiple of 8)
     std::vector<int> insts;
     DevBuf tiles;
     int ntiles = 0;
@@ -180,45 +181,67 @@ size_t vec_bytes(const rm_plan_t* p) {
 // ---------------------------------------------------------------------------
 // temporal-blocked execution plan
 // ---------------------------------------------------------------------------
-// Extended tile of a class: shape s, halo h = T + 1 (one ring more than the T
-// steps need, so the residual of the final iterate can be formed in the same
-// launch).  Owned region W x H = (EW - 2h) x (EH - 2h).
-bool class_geometry(int shape, int T, int& W, int& H, int& h) {
-  const rmk::BlockShape& bs = rmk::kBlockShapes[shape];
+// Extended tile of a class: kernel variant v (strips of R rows, extended height
+// 8R), width cw, halo h = T + 1 (one ring more than the T steps need, so the
+// residual of the final iterate can be formed in the same launch).  Owned
+// region W x H = (cw - 2h) x (8R - 2h).
+bool class_geometry(int v, int T, int cw, int& W, int& H, int& h) {
+  if (v < 0 || v >= rmk::kNumBlockVariants) return false;
+  const rmk::BlockVariant& bv = rmk::kBlockVariants[v];
   h = T + 1;
-  W = bs.cw - 2 * h;
-  H = bs.ns * bs.r - 2 * h;
-  return W >= 1 && H >= 1;
+  W = cw - 2 * h;
+  H = 8 * bv.r - 2 * h;
+  return cw >= 8 && cw % 8 == 0 && cw + 2 <= bv.lw && W >= 1 && H >= 1;
 }
 
 // Cost model used before any tuning: the larger of an arithmetic bound
 // (redundant halo work included) and an HBM bound (load u, v, f on the extended
 // tile, store u, v on the owned one, once per T steps), per inner step.
-double model_cost(int n, int shape, int T) {
+double model_cost(int n, int v, int T, int cw) {
   int W, H, h;
-  if (!class_geometry(shape, T, W, H, h)) return 1e300;
-  const rmk::BlockShape& bs = rmk::kBlockShapes[shape];
+  if (!class_geometry(v, T, cw, W, H, h)) return 1e300;
   const double tiles = (double)((n + W - 1) / W) * (double)((n + H - 1) / H);
-  const double ext = tiles * bs.cw * (double)(bs.ns * bs.r);
+  const double ext = tiles * cw * (double)(8 * rmk::kBlockVariants[v].r);
   const double own = (double)n * n;
-  const double compute = ext / 1.2e12;
+  const double compute = ext / 1.6e12;
   const double memory = (12.0 * ext + 8.0 * own) / T / 5.0e12;
   return std::max(compute, memory) + 4e-6 / T / 256.0;
 }
 
-void default_class_config(int n, int& shape, int& T) {
+// Tile widths worth trying for (n, v, T): the narrowest width that covers n with
+// k tiles across, for the few smallest feasible k.
+std::vector<int> candidate_widths(int n, int v, int T) {
+  std::vector<int> out;
+  const int h = T + 1;
+  const int lw = rmk::kBlockVariants[v].lw;
+  for (int k = 1; k <= 64 && (int)out.size() < 4; ++k) {
+    const int own = (n + k - 1) / k;
+    const int cw = ((own + 2 * h + 7) / 8) * 8;
+    int W, H, hh;
+    if (cw + 2 > lw) continue;
+    if (!class_geometry(v, T, cw, W, H, hh)) continue;
+    if (std::find(out.begin(), out.end(), cw) == out.end()) out.push_back(cw);
+    if (own <= 8) break;
+  }
+  return out;
+}
+
+void default_class_config(int n, int& shape, int& T, int& cw) {
   double best = 1e301;
   shape = 0;
   T = 1;
-  for (int s = 0; s < rmk::kNumBlockShapes; ++s)
-    for (int t : rmk::kBlockTs) {
-      const double c = model_cost(n, s, t);
-      if (c < best * 0.999) {
-        best = c;
-        shape = s;
-        T = t;
+  cw = 64;
+  for (int v = 0; v < rmk::kNumBlockVariants; ++v)
+    for (int t : rmk::kBlockTs)
+      for (int w : candidate_widths(n, v, t)) {
+        const double c = model_cost(n, v, t, w);
+        if (c < best * 0.999) {
+          best = c;
+          shape = v;
+          T = t;
+          cw = w;
+        }
       }
-    }
 }
 
 void init_classes(rm_plan_t* pl) {
@@ -230,7 +253,7 @@ void init_classes(rm_plan_t* pl) {
   for (int n : sizes) {
     rm_plan_s::ClassExec c;
     c.n = n;
-    default_class_config(n, c.shape, c.T);
+    default_class_config(n, c.shape, c.T, c.cw);
     for (int b = 0; b < pl->B; ++b)
       if (pl->inst[b].n == n) c.insts.push_back(b);
     pl->classes.push_back(std::move(c));
@@ -244,7 +267,7 @@ rm_status build_exec(rm_plan_t* pl, hipStream_t st) {
   int slot = 0;
   for (auto& c : pl->classes) {
     int W, H, h;
-    if (!class_geometry(c.shape, c.T, W, H, h)) return fail(RM_EINVAL, "invalid kernel shape for this T");
+    if (!class_geometry(c.shape, c.T, c.cw, W, H, h)) return fail(RM_EINVAL, "invalid kernel shape for this T");
     std::vector<Tile> t;
     for (int b : c.insts) {
       const int n = pl->inst[b].n;
@@ -307,7 +330,7 @@ rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int ns
       if (only_class >= 0 && (int)ci != only_class) continue;
       auto& c = pl->classes[ci];
       const int h = c.T + 1;
-      if (!rmk::launch_block(c.shape, t, method, p, c.tiles.as<Tile>(), c.ntiles, h, omega, alpha, m, s0 + done, f,
+      if (!rmk::launch_block(c.shape, t, c.cw, method, p, c.tiles.as<Tile>(), c.ntiles, h, omega, alpha, m, s0 + done, f,
                              us[cur], vs[cur], us[cur ^ 1], vs[cur ^ 1], active,
                              last ? res_partial : nullptr, st))
         return fail(RM_EUNSUPPORTED, "block kernel configuration not built");
@@ -842,40 +865,55 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   return last_launch();
 }
 
-rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t T) {
+rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t T, int32_t cw) {
   if (plan == nullptr) return fail(RM_EINVAL, "null plan");
   if (shape == -1) {
     plan->use_block = false;
     return RM_OK;
   }
-  if (shape < 0 || shape >= rmk::kNumBlockShapes) return fail(RM_EINVAL, "unknown kernel shape");
+  if (shape < 0 || shape >= rmk::kNumBlockVariants) return fail(RM_EINVAL, "unknown kernel variant");
   if (T != 1 && T != 2 && T != 4 && T != 8) return fail(RM_EINVAL, "T must be 1, 2, 4 or 8");
-  int W, H, h;
-  if (!class_geometry(shape, T, W, H, h)) return fail(RM_EINVAL, "halo T + 1 does not fit this shape");
   bool hit = false;
-  for (auto& c : plan->classes)
-    if (n <= 0 || c.n == n) {
-      c.shape = shape;
-      c.T = T;
-      hit = true;
+  for (auto& c : plan->classes) {
+    if (n > 0 && c.n != n) continue;
+    int w = cw;
+    if (w <= 0) {
+      double best = 1e301;
+      for (int cand : candidate_widths(c.n, shape, T)) {
+        const double cost = model_cost(c.n, shape, T, cand);
+        if (cost < best) {
+          best = cost;
+          w = cand;
+        }
+      }
     }
+    int W, H, h;
+    if (!class_geometry(shape, T, w, W, H, h))
+      return fail(RM_EINVAL, "tile width / halo T + 1 does not fit this kernel variant");
+    c.shape = shape;
+    c.T = T;
+    c.cw = w;
+    hit = true;
+  }
   if (!hit) return fail(RM_EINVAL, "no instance of that size in the plan");
   plan->use_block = true;
   plan->exec_dirty = true;
   return RM_OK;
 }
 
-rm_status rm_plan_get_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, int32_t* T) {
-  if (plan == nullptr || shape == nullptr || T == nullptr) return fail(RM_EINVAL, "null argument");
+rm_status rm_plan_get_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, int32_t* T, int32_t* cw) {
+  if (plan == nullptr || shape == nullptr || T == nullptr || cw == nullptr) return fail(RM_EINVAL, "null argument");
   if (!plan->use_block) {
     *shape = -1;
     *T = 1;
+    *cw = 0;
     return RM_OK;
   }
   for (const auto& c : plan->classes)
     if (c.n == n) {
       *shape = c.shape;
       *T = c.T;
+      *cw = c.cw;
       return RM_OK;
     }
   return fail(RM_EINVAL, "no instance of that size in the plan");
@@ -902,11 +940,11 @@ rm_status rm_tune(rm_ctx* ctx, rm_plan_t* plan, int32_t method, int32_t m, const
       char line[512];
       while (std::fgets(line, sizeof line, fh)) {
         char key[300];
-        int sh, T;
+        int sh, T, w;
         double us;
-        if (std::sscanf(line, " \"%299[^\"]\": [%d, %d, %lf]", key, &sh, &T, &us) == 4) {
-          char val[64];
-          std::snprintf(val, sizeof val, "[%d, %d, %.3f]", sh, T, us);
+        if (std::sscanf(line, " \"%299[^\"]\": [%d, %d, %d, %lf]", key, &sh, &T, &w, &us) == 5) {
+          char val[96];
+          std::snprintf(val, sizeof val, "[%d, %d, %d, %.3f]", sh, T, w, us);
           cache.emplace_back(key, val);
         }
       }
@@ -936,13 +974,14 @@ rm_status rm_tune(rm_ctx* ctx, rm_plan_t* plan, int32_t method, int32_t m, const
     bool found = false;
     for (auto& kv : cache)
       if (kv.first == key) {
-        int sh, T;
+        int sh, T, w;
         double us;
-        if (std::sscanf(kv.second.c_str(), "[%d, %d, %lf]", &sh, &T, &us) == 3) {
+        if (std::sscanf(kv.second.c_str(), "[%d, %d, %d, %lf]", &sh, &T, &w, &us) == 4) {
           int W, H, h;
-          if (sh >= 0 && sh < rmk::kNumBlockShapes && class_geometry(sh, T, W, H, h)) {
+          if (class_geometry(sh, T, w, W, H, h)) {
             c.shape = sh;
             c.T = T;
+            c.cw = w;
             total_us += us;
             found = true;
           }
@@ -950,37 +989,39 @@ rm_status rm_tune(rm_ctx* ctx, rm_plan_t* plan, int32_t method, int32_t m, const
       }
     if (found) continue;
     double best = 1e300;
-    int best_s = c.shape, best_T = c.T;
-    for (int sh = 0; sh < rmk::kNumBlockShapes; ++sh)
-      for (int T : rmk::kBlockTs) {
-        int W, H, h;
-        if (!class_geometry(sh, T, W, H, h)) continue;
-        c.shape = sh;
-        c.T = T;
-        plan->exec_dirty = true;
-        double t_best = 1e300;
-        for (int r = 0; r < reps + 1; ++r) {
-          int cur = 0, flips = 0;
-          RM_HIP(hipEventRecord(e0, st));
-          RM_TRY(sweep(plan, st, method, m, 0, steps, omega, alpha, b, us_, vs_, cur, flips, nullptr, nullptr,
-                       nullptr, (int)ci));
-          RM_HIP(hipEventRecord(e1, st));
-          RM_HIP(hipEventSynchronize(e1));
-          float ms = 0.f;
-          RM_HIP(hipEventElapsedTime(&ms, e0, e1));
-          if (r > 0) t_best = std::min(t_best, (double)ms * 1e3 / steps);
+    int best_s = c.shape, best_T = c.T, best_w = c.cw;
+    for (int sh = 0; sh < rmk::kNumBlockVariants; ++sh)
+      for (int T : rmk::kBlockTs)
+        for (int w : candidate_widths(c.n, sh, T)) {
+          c.shape = sh;
+          c.T = T;
+          c.cw = w;
+          plan->exec_dirty = true;
+          double t_best = 1e300;
+          for (int r = 0; r < reps + 1; ++r) {
+            int cur = 0, flips = 0;
+            RM_HIP(hipEventRecord(e0, st));
+            RM_TRY(sweep(plan, st, method, m, 0, steps, omega, alpha, b, us_, vs_, cur, flips, nullptr, nullptr,
+                         nullptr, (int)ci));
+            RM_HIP(hipEventRecord(e1, st));
+            RM_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            RM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (r > 0) t_best = std::min(t_best, (double)ms * 1e3 / steps);
+          }
+          if (t_best < best) {
+            best = t_best;
+            best_s = sh;
+            best_T = T;
+            best_w = w;
+          }
         }
-        if (t_best < best) {
-          best = t_best;
-          best_s = sh;
-          best_T = T;
-        }
-      }
     c.shape = best_s;
     c.T = best_T;
+    c.cw = best_w;
     total_us += best;
-    char val[64];
-    std::snprintf(val, sizeof val, "[%d, %d, %.3f]", best_s, best_T, best);
+    char val[96];
+    std::snprintf(val, sizeof val, "[%d, %d, %d, %.3f]", best_s, best_T, best_w, best);
     cache.emplace_back(key, val);
   }
   (void)hipEventDestroy(e0);

@@ -1,15 +1,14 @@
 // Temporal-blocked fused steps for gfx950 (overlapped tiling).
 //
-// A workgroup of CW x NS threads owns an extended tile of EW x EH points
-// (EW = CW columns, EH = NS R rows): thread t holds u, v and f of a vertical
-// strip of R points of column t mod CW in registers (consecutive threads take
-// consecutive columns, so every global access of a wave is a contiguous row
-// segment).  The workgroup runs T
+// A workgroup of 8 CW threads owns an extended tile of CW x 8R points: thread t
+// holds u, v and f of a vertical strip of R points of column t mod CW in
+// registers (consecutive threads take consecutive columns, so every global
+// access of a wave is a contiguous row segment).  CW is chosen at run time per
+// size class so that the tiles fit the instance.  The workgroup runs T
 // consecutive inner steps of Richardson(m) / NAG-Richardson(m) (Table 1) on the
 // whole extended tile without touching HBM in between:
-//   per step: u~ = u + a_i v  ->  LDS (double buffered, one barrier per step)
-//             r = f - A u~ from LDS (left/right columns from LDS, own column
-//             from registers), v' = a_i v + w_i r, u' = u + v'.
+//   per step: u~ = u + a_i v  ->  LDS
+//             r = f - A u~ from LDS, v' = a_i v + w_i r, u' = u + v'.
 // Values outside the extended tile read as 0, so the outermost ring goes wrong
 // by one point per step; the owned region is the tile inset by h >= T points and
 // is exact.  With a residual requested (h >= T + 1), ||f - A u||^2 of the final
@@ -39,58 +38,45 @@ __device__ __forceinline__ float stencil9f(const float c[5], float C, float W, f
   return acc;
 }
 
-template <int NW>
-__device__ __forceinline__ double block_sum_n(double x, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) sh[w] = x;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NW; ++k) r += sh[k];
-  }
-  return r;
-}
-
-// Stencil for the R points of this thread's strip from an LDS buffer holding the
-// current field with a zero border.  `own` are this thread's own values (the
-// buffer holds them too); results go to out[].
-template <int R, int LW>
-__device__ __forceinline__ void strip_stencil(const float* B, int lc, int lr0, const float c[5], const float own[R],
-                                              float out[R]) {
-  // LDS row index of strip row k is lr0 + k + 1, column index of this thread lc + 1
-  float Lc[R + 2], Rc[R + 2];
-#pragma unroll
-  for (int k = 0; k < R + 2; ++k) {
-    Lc[k] = B[(lr0 + k) * LW + lc];
-    Rc[k] = B[(lr0 + k) * LW + lc + 2];
-  }
-  const float top = B[lr0 * LW + lc + 1];
-  const float bot = B[(lr0 + R + 1) * LW + lc + 1];
+// Stencil of the R points of this thread's strip, all nine inputs read from the
+// LDS tile B (row stride LW, zero border; strip row k sits at LDS row
+// lr0 + k + 1, column lc + 1), walking down the strip with a three-row window.
+// f(k, A u) consumes each result as soon as it is formed.
+template <int R, int LW, typename F>
+__device__ __forceinline__ void strip_apply(const float* B, int lc, int lr0, const float c[5], F&& f) {
+  const float* q = B + lr0 * LW + lc;
+  float Lm = q[0], Cm = q[1], Rm = q[2];
+  float L0 = q[LW], C0 = q[LW + 1], R0 = q[LW + 2];
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const float S = k == 0 ? top : own[k - 1];
-    const float N = k == R - 1 ? bot : own[k + 1];
-    out[k] = stencil9f(c, own[k], Lc[k + 1], Rc[k + 1], S, N, Lc[k], Rc[k + 2], Rc[k], Lc[k + 2]);
+    const float* qn = q + (k + 2) * LW;
+    const float Lp = qn[0], Cp = qn[1], Rp = qn[2];
+    f(k, stencil9f(c, C0, L0, R0, Cm, Cp, Lm, Rp, Rm, Lp));
+    Lm = L0; Cm = C0; Rm = R0;
+    L0 = Lp; C0 = Cp; R0 = Rp;
   }
 }
 
-template <int T, int CW, int NS, int R, int METHOD>
-__global__ __launch_bounds__(CW* NS) void k_block(PlanDev p, const Tile* __restrict__ tiles, int ntiles, int h,
-                                                 const float* __restrict__ omega, const float* __restrict__ alpha,
-                                                 int m, int s0, const float* __restrict__ f,
-                                                 const float* __restrict__ u, const float* __restrict__ v,
-                                                 float* __restrict__ u_out, float* __restrict__ v_out,
-                                                 const int* __restrict__ active, double* __restrict__ partial2) {
-  constexpr int NT = CW * NS;
-  constexpr int NW = NT / 64;
-  static_assert(NT % 64 == 0, "whole waves");
-  constexpr int EW = CW, EH = R * NS;
-  constexpr int LW = EW + 2, LH = EH + 2;
-  __shared__ float buf[2][LH * LW];
-  __shared__ double sh[NW];
+// Thread t of a workgroup of 8 CW threads takes column t mod CW and the strip of
+// R rows starting at R (t / CW): the extended tile is CW x 8R points.  CW is a
+// run-time multiple of 8 (CW + 2 <= LW), so tiles can be sized to the instance.
+// One LDS buffer holds the published field; each step has two barriers (after
+// publishing, and before the next step overwrites it), which keeps the LDS and
+// register footprint small enough for two or more workgroups per CU, so that one
+// workgroup's loads and stores overlap another's arithmetic.
+template <int T, int R, int LW, int WPE, int METHOD>
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_per_eu(WPE))) void k_block(PlanDev p, const Tile* __restrict__ tiles, int ntiles, int h, int CW,
+                                               const float* __restrict__ omega, const float* __restrict__ alpha,
+                                               int m, int s0, const float* __restrict__ f,
+                                               const float* __restrict__ u, const float* __restrict__ v,
+                                               float* __restrict__ u_out, float* __restrict__ v_out,
+                                               const int* __restrict__ active, double* __restrict__ partial2) {
+  constexpr int NS = 8;
+  constexpr int EH = R * NS;
+  constexpr int LH = EH + 2;
+  __shared__ float B[LH * LW];
+  __shared__ double sh[16];
+  const int NT = CW * NS;
   const int per = ntiles >> 3;
   const Tile tl = tiles[(blockIdx.x & 7) * per + (blockIdx.x >> 3)];
   if (tl.inst < 0) return;
@@ -104,73 +90,76 @@ __global__ __launch_bounds__(CW* NS) void k_block(PlanDev p, const Tile* __restr
   const int lr0 = ((int)threadIdx.x / CW) * R;
   const int gx = tl.x0 + lc;
   const bool colin = gx >= 0 && gx < n;
+  const int gy0 = tl.y0 + lr0;
   const float* ui = u + in.off;
   const float* vi = v + in.off;
   const float* fi = f + in.off;
-  float ru[R], rv[R], rf[R], ut[R], au[R];
+  float ru[R], rv[R], rf[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const int gy = tl.y0 + lr0 + k;
+    const int gy = gy0 + k;
     const bool ok = colin && gy >= 0 && gy < n;
     const int idx = gy * n + gx;
     ru[k] = ok ? ui[idx] : 0.0f;
     rv[k] = (METHOD == M_NAG && ok) ? vi[idx] : 0.0f;
     rf[k] = ok ? fi[idx] : 0.0f;
   }
-  // zero border of both buffers (never written afterwards)
-  for (int e = threadIdx.x; e < 2 * LW + 2 * EH; e += NT) {
+  // zero border ring for the CW + 2 columns in use
+  const int LWc = CW + 2;
+  for (int e = threadIdx.x; e < 2 * LWc + 2 * EH; e += NT) {
     int idx;
-    if (e < LW) idx = e;
-    else if (e < 2 * LW) idx = (LH - 1) * LW + (e - LW);
-    else if (e < 2 * LW + EH) idx = (1 + e - 2 * LW) * LW;
-    else idx = (1 + e - 2 * LW - EH) * LW + LW - 1;
-    buf[0][idx] = 0.0f;
-    buf[1][idx] = 0.0f;
+    if (e < LWc) idx = e;
+    else if (e < 2 * LWc) idx = (LH - 1) * LW + (e - LWc);
+    else if (e < 2 * LWc + EH) idx = (1 + e - 2 * LWc) * LW;
+    else idx = (1 + e - 2 * LWc - EH) * LW + CW + 1;
+    B[idx] = 0.0f;
   }
+  float* mine = B + (lr0 + 1) * LW + lc + 1;
+  // Points outside the n x n interior publish 0 (Dirichlet); their registers
+  // are never stored.
 #pragma unroll 1
   for (int t = 0; t < T; ++t) {
     const int i = (s0 + t) % m;
     const float w = omega[tl.inst * m + i];
     const float a = METHOD == M_NAG ? alpha[tl.inst * m + i] : 0.0f;
-    float* B = buf[t & 1];
+    if (t > 0) __syncthreads();  // every read of the previous step is done
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      ut[k] = METHOD == M_NAG ? fmadd(a, rv[k], ru[k]) : ru[k];
-      B[(lr0 + k + 1) * LW + lc + 1] = ut[k];
+      const int gy = gy0 + k;
+      const bool ok = colin && gy >= 0 && gy < n;
+      const float x = METHOD == M_NAG ? fmadd(a, rv[k], ru[k]) : ru[k];
+      mine[k * LW] = ok ? x : 0.0f;
     }
     __syncthreads();
-    strip_stencil<R, LW>(B, lc, lr0, c, ut, au);
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const int gy = tl.y0 + lr0 + k;
-      const bool ok = colin && gy >= 0 && gy < n;
-      const float r = rf[k] - au[k];
+    strip_apply<R, LW>(B, lc, lr0, c, [&](int k, float au) {
+      const float r = rf[k] - au;
       const float vn = METHOD == M_NAG ? fmadd(a, rv[k], w * r) : w * r;
-      const float un = ru[k] + vn;
-      ru[k] = ok ? un : 0.0f;
-      rv[k] = ok ? vn : 0.0f;
-    }
+      ru[k] = ru[k] + vn;
+      rv[k] = vn;
+    });
   }
-  const bool colown = lc >= h && lc < EW - h && colin;
+  const bool colown = lc >= h && lc < CW - h && colin;
   double r2 = 0.0;
   if (partial2 != nullptr) {
-    float* B = buf[T & 1];
-#pragma unroll
-    for (int k = 0; k < R; ++k) B[(lr0 + k + 1) * LW + lc + 1] = ru[k];
     __syncthreads();
-    strip_stencil<R, LW>(B, lc, lr0, c, ru, au);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      const int lr = lr0 + k, gy = tl.y0 + lr;
+      const int gy = gy0 + k;
+      const bool ok = colin && gy >= 0 && gy < n;
+      mine[k * LW] = ok ? ru[k] : 0.0f;
+    }
+    __syncthreads();
+    strip_apply<R, LW>(B, lc, lr0, c, [&](int k, float au) {
+      const int lr = lr0 + k, gy = gy0 + k;
       if (colown && lr >= h && lr < EH - h && gy >= 0 && gy < n) {
-        const float r = rf[k] - au[k];
+        const float r = rf[k] - au;
         r2 += (double)r * (double)r;
       }
-    }
+    });
   }
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const int lr = lr0 + k, gy = tl.y0 + lr;
+    const int lr = lr0 + k, gy = gy0 + k;
     if (colown && lr >= h && lr < EH - h && gy >= 0 && gy < n) {
       const int64_t idx = in.off + (int64_t)gy * n + gx;
       u_out[idx] = ru[k];
@@ -178,35 +167,42 @@ __global__ __launch_bounds__(CW* NS) void k_block(PlanDev p, const Tile* __restr
     }
   }
   if (partial2 != nullptr) {
-    const double s = block_sum_n<NW>(r2, sh);
+    // fixed-order workgroup sum over NT / 64 waves
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = r2;
+    __syncthreads();
     if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int k = 0; k < NT / 64; ++k) s += sh[k];
       partial2[2 * tl.pad] = s;
       partial2[2 * tl.pad + 1] = 0.0;
     }
   }
 }
 
-template <int T, int CW, int NS, int R>
-void launch_shape(int method, const PlanDev& p, const Tile* tiles, int ntiles, int h, const float* omega,
-                  const float* alpha, int m, int s0, const float* f, const float* u, const float* v, float* u_out,
-                  float* v_out, const int* active, double* partial2, hipStream_t st) {
-  const dim3 grid(ntiles), block(CW * NS);
+template <int T, int R, int LW, int WPE>
+void launch_variant(int method, const PlanDev& p, const Tile* tiles, int ntiles, int h, int cw, const float* omega,
+                    const float* alpha, int m, int s0, const float* f, const float* u, const float* v, float* u_out,
+                    float* v_out, const int* active, double* partial2, hipStream_t st) {
+  const dim3 grid(ntiles), block(8 * cw);
   if (method == M_NAG)
-    hipLaunchKernelGGL((k_block<T, CW, NS, R, M_NAG>), grid, block, 0, st, p, tiles, ntiles, h, omega, alpha, m,
-                       s0, f, u, v, u_out, v_out, active, partial2);
+    hipLaunchKernelGGL((k_block<T, R, LW, WPE, M_NAG>), grid, block, 0, st, p, tiles, ntiles, h, cw, omega, alpha, m, s0,
+                       f, u, v, u_out, v_out, active, partial2);
   else
-    hipLaunchKernelGGL((k_block<T, CW, NS, R, M_RICH>), grid, block, 0, st, p, tiles, ntiles, h, omega, alpha,
-                       m, s0, f, u, v, u_out, v_out, active, partial2);
+    hipLaunchKernelGGL((k_block<T, R, LW, WPE, M_RICH>), grid, block, 0, st, p, tiles, ntiles, h, cw, omega, alpha, m,
+                       s0, f, u, v, u_out, v_out, active, partial2);
 }
 
-template <int CW, int NS, int R>
-bool launch_T(int T, int method, const PlanDev& p, const Tile* tiles, int ntiles, int h, const float* omega,
+template <int R, int LW, int WPE>
+bool launch_T(int T, int method, const PlanDev& p, const Tile* tiles, int ntiles, int h, int cw, const float* omega,
               const float* alpha, int m, int s0, const float* f, const float* u, const float* v, float* u_out,
               float* v_out, const int* active, double* partial2, hipStream_t st) {
-#define RM_BLOCK_CASE(TT)                                                                                        \
-  case TT:                                                                                                       \
-    launch_shape<TT, CW, NS, R>(method, p, tiles, ntiles, h, omega, alpha, m, s0, f, u, v, u_out, v_out, active, \
-                                partial2, st);                                                                   \
+#define RM_BLOCK_CASE(TT)                                                                                         \
+  case TT:                                                                                                        \
+    launch_variant<TT, R, LW, WPE>(method, p, tiles, ntiles, h, cw, omega, alpha, m, s0, f, u, v, u_out, v_out, active, \
+                              partial2, st);                                                                      \
     return true;
   switch (T) {
     RM_BLOCK_CASE(1)
@@ -221,32 +217,37 @@ bool launch_T(int T, int method, const PlanDev& p, const Tile* tiles, int ntiles
 
 }  // namespace
 
-const BlockShape kBlockShapes[kNumBlockShapes] = {
-    {64, 8, 8},    // 64 x 64, 512 threads
-    {64, 8, 16},   // 64 x 128, 512 threads
-    {96, 8, 12},   // 96 x 96, 768 threads
-    {128, 8, 8},   // 128 x 64, 1024 threads
-    {160, 6, 16},  // 160 x 96, 960 threads
+const BlockVariant kBlockVariants[kNumBlockVariants] = {
+    {8, 66},    // up to 64 x 64 points
+    {16, 66},   // up to 64 x 128
+    {8, 130},   // up to 128 x 64
+    {13, 106},  // up to 104 x 104
+    {16, 130},  // up to 128 x 128
+    {12, 98},   // up to 96 x 96
 };
 
-bool launch_block(int shape, int T, int method, const PlanDev& p, const Tile* tiles, int ntiles, int h,
+bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, const Tile* tiles, int ntiles, int h,
                   const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,
                   const float* v, float* u_out, float* v_out, const int* active, double* partial2,
                   hipStream_t st) {
-#define RM_SHAPE_CASE(S, CW, NS, R)                                                                           \
-  case S:                                                                                                     \
-    return launch_T<CW, NS, R>(T, method, p, tiles, ntiles, h, omega, alpha, m, s0, f, u, v, u_out, v_out,   \
-                               active, partial2, st);
-  switch (shape) {
-    RM_SHAPE_CASE(0, 64, 8, 8)
-    RM_SHAPE_CASE(1, 64, 8, 16)
-    RM_SHAPE_CASE(2, 96, 8, 12)
-    RM_SHAPE_CASE(3, 128, 8, 8)
-    RM_SHAPE_CASE(4, 160, 6, 16)
+  if (variant < 0 || variant >= kNumBlockVariants) return false;
+  if (cw < 8 || cw % 8 != 0 || cw + 2 > kBlockVariants[variant].lw) return false;
+#define RM_VARIANT_CASE(V, R, LW, WPE)                                                                         \
+  case V:                                                                                                      \
+    return launch_T<R, LW, WPE>(T, method, p, tiles, ntiles, h, cw, omega, alpha, m, s0, f, u, v, u_out, v_out,    \
+                           active, partial2, st);
+  switch (variant) {
+    // register caps (waves per SIMD) chosen so that two workgroups fit on a CU
+    RM_VARIANT_CASE(0, 8, 66, 8)
+    RM_VARIANT_CASE(1, 16, 66, 4)
+    RM_VARIANT_CASE(2, 8, 130, 7)
+    RM_VARIANT_CASE(3, 13, 106, 7)
+    RM_VARIANT_CASE(4, 16, 130, 4)
+    RM_VARIANT_CASE(5, 12, 98, 6)
     default:
       return false;
   }
-#undef RM_SHAPE_CASE
+#undef RM_VARIANT_CASE
 }
 
 }  // namespace rmk

@@ -97,19 +97,22 @@ void launch_meta_backward(const PlanDev& p, int m, const float* params, const fl
                           const float* d_alpha, float* per_inst, float* d_params, hipStream_t st);
 
 // ---- temporal-blocked steps (rm_block.hip) ---------------------------------
-// Extended-tile shapes: CW columns by NS strips of R rows, CW * NS threads.
-struct BlockShape {
-  int cw, ns, r;
+// Kernel variants: strips of R rows (extended tile height 8R) and an LDS row
+// stride LW (extended tile width CW <= LW - 2, CW a multiple of 8 chosen at
+// launch; 8 CW threads per workgroup).
+struct BlockVariant {
+  int r, lw;
 };
-constexpr int kNumBlockShapes = 5;
-extern const BlockShape kBlockShapes[kNumBlockShapes];
+constexpr int kNumBlockVariants = 6;
+extern const BlockVariant kBlockVariants[kNumBlockVariants];
 constexpr int kBlockTs[4] = {1, 2, 4, 8};
-// T fused steps (s0 .. s0 + T - 1) over a tile table of extended tiles inset by h
-// (h >= T; h >= T + 1 when partial2 is given, which then receives ||f - A u||^2 of
-// the final u per tile).  Returns false for an unsupported (shape, T).
-bool launch_block(int shape, int T, int method, const PlanDev& p, const Tile* tiles, int ntiles, int h,
-                  const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,
-                  const float* v, float* u_out, float* v_out, const int* active, double* partial2,
-                  hipStream_t st);
+// T fused steps (s0 .. s0 + T - 1) over a tile table of extended CW x 8R tiles
+// inset by h (h >= T; h >= T + 1 when partial2 is given, which then receives
+// ||f - A u||^2 of the final u per tile).  Returns false for an unsupported
+// (variant, T, cw).
+bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, const Tile* tiles, int ntiles,
+                  int h, const float* omega, const float* alpha, int m, int s0, const float* f,
+                  const float* u, const float* v, float* u_out, float* v_out, const int* active,
+                  double* partial2, hipStream_t st);
 
 }  // namespace rmk

@@ -102,14 +102,16 @@ class Plan:
         _check(self.lib.rm_plan_offsets(h, off), "rm_plan_offsets")
         self.offsets = np.frombuffer(off, dtype=np.int64).copy()
 
-    def set_kernel(self, shape, T, n=0):
-        """rm_plan_set_kernel: (shape, T) for the size class n (n <= 0: all); shape -1 = one-step kernel."""
-        _check(self.lib.rm_plan_set_kernel(self.handle, n, shape, T), "rm_plan_set_kernel")
+    def set_kernel(self, shape, T, n=0, cw=0):
+        """rm_plan_set_kernel: (variant, T, tile width) for the size class n (n <= 0: all);
+        shape -1 = one launch per inner step; cw <= 0 = the cost model's width."""
+        _check(self.lib.rm_plan_set_kernel(self.handle, n, shape, T, cw), "rm_plan_set_kernel")
 
     def get_kernel(self, n):
-        sh, T = ctypes.c_int32(), ctypes.c_int32()
-        _check(self.lib.rm_plan_get_kernel(self.handle, n, ctypes.byref(sh), ctypes.byref(T)), "rm_plan_get_kernel")
-        return sh.value, T.value
+        sh, T, cw = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.rm_plan_get_kernel(self.handle, n, ctypes.byref(sh), ctypes.byref(T), ctypes.byref(cw)),
+               "rm_plan_get_kernel")
+        return sh.value, T.value, cw.value
 
     def coefficients(self):
         c = (ctypes.c_double * (5 * self.B))()

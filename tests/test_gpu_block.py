@@ -1,6 +1,6 @@
 """Temporal-blocked FP32 sweeps: bitwise equal to one launch per inner step (the LDS
-race / halo detector), for every kernel shape and steps-per-launch T, on ragged
-sizes; autotuner choices and cache."""
+race / halo detector), for every kernel variant, steps-per-launch T and several
+tile widths, on ragged sizes; autotuner choices and cache."""
 import json
 import os
 
@@ -55,15 +55,16 @@ def test_blocked_equals_one_step_bitwise(ctx, method_name):
     ref, ref_h, _ = _unroll(ctx, plan, method, om, al, f, m, K, hist=True)
     for shape in range(5):
         for T in (1, 2, 4, 8):
-            try:
-                plan.set_kernel(shape, T)
-            except rm.RMError:
-                continue  # halo T + 1 does not fit this shape
-            say("blocked vs one-step", method_name, "shape", shape, "T", T)
-            got, got_h, _ = _unroll(ctx, plan, method, om, al, f, m, K, hist=True)
-            assert np.array_equal(got, ref), (shape, T, np.max(np.abs(got - ref)))
-            # the per-tile residual sums differ only in summation order
-            assert np.allclose(got_h, ref_h, rtol=1e-12, atol=0), (shape, T)
+            for cw in (0, 24, 64, 128):
+                try:
+                    plan.set_kernel(shape, T, cw=cw)
+                except rm.RMError:
+                    continue  # halo T + 1 or width does not fit this variant
+                say("blocked vs one-step", method_name, "variant", shape, "T", T, "cw", cw)
+                got, got_h, _ = _unroll(ctx, plan, method, om, al, f, m, K, hist=True)
+                assert np.array_equal(got, ref), (shape, T, cw, np.max(np.abs(got - ref)))
+                # the per-tile residual sums differ only in summation order
+                assert np.allclose(got_h, ref_h, rtol=1e-12, atol=0), (shape, T, cw)
 
 
 def test_blocked_checkpoints_and_mixed_classes(ctx):
@@ -123,7 +124,7 @@ def test_autotune_and_cache(ctx, tmp_path):
     say("tuned", us, [plan.get_kernel(k) for k in (63, 255)])
     assert us > 0
     table = json.load(open(cache))
-    assert len(table) == 2 and all(len(v) == 3 for v in table.values())
+    assert len(table) == 2 and all(len(v) == 4 for v in table.values())
     # a second plan reads the cache (no timing) and lands on the same choices
     plan2 = plan_for(ctx, batch)
     us2 = rm.rm_tune(ctx, plan2, rm.RM_NAG, m, om, al, f, cache_path=cache)
