@@ -30,6 +30,8 @@ sys.path.insert(0, ROOT)
 METRIC = "GLUP/s (stencil updates/s) fwd+adjoint, batched; time to 1e-10 rel residual"
 B, N, M, K_TRAIN, CKPT, TOL = 256, 255, 16, 64, 16, 1e-10
 HBM_PEAK_GBS = 8000.0
+# kernel choices of the autotuner for this workload (written by rm_tune on an MI355X)
+TUNE_CACHE = os.path.join(ROOT, "paper_2412_08076_amd", "tune_gfx950.json")
 BYTES_PER_LUP_NAG = 20.0  # read u, v, f; write u, v (FP32)
 
 
@@ -76,6 +78,78 @@ def cpu_baseline(steps=1024):
                       f"one FP64 NumPy process per core; wall {wall:.2f} s"}
 
 
+# ----------------------------------------------------------------------------- comparator leg
+def plain_fp64_loop(batch, omega, alpha, sample, tol=TOL, max_outer=20000):
+    """The plain per-instance FP64 GPU loop the fused batched solver is measured against:
+    one instance at a time, NAG-Richardson(16) written as separate PyTorch FP64 device
+    operations per inner step (look-ahead, 3x3 convolution for A, momentum and iterate
+    updates), the residual norm after every outer iteration read back to the host, and
+    the same weights and tolerance.  Returns (seconds for the sample, outer iterations)."""
+    import torch
+    from paper_2412_08076_amd import rm
+    times, iters = [], []
+    ctx = rm.Context(0)
+    for b in sample:
+        n = batch.n[b]
+        plan = rm.Plan(ctx, [n], eps=[batch.eps[b]], theta=[batch.theta[b]])
+        coef, _ = plan.coefficients()
+        c0, cx, cy, cpp, cpm = coef[0]
+        ker = torch.tensor([[cpp, cy, cpm], [cx, c0, cx], [cpm, cy, cpp]], dtype=torch.float64,
+                           device="cuda").view(1, 1, 3, 3)
+        f = torch.as_tensor(batch.f[b], dtype=torch.float64, device="cuda").view(1, 1, n, n)
+        w = [float(x) for x in omega[b]]
+        a = [float(x) for x in alpha[b]]
+        u = torch.zeros_like(f)
+        v = torch.zeros_like(f)
+        fn = float(torch.linalg.vector_norm(f))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = 0
+        for k in range(1, max_outer + 1):
+            for i in range(M):
+                ut = u + a[i] * v
+                r = f - torch.nn.functional.conv2d(ut, ker, padding=1)
+                v = a[i] * v + w[i] * r
+                u = u + v
+            res = float(torch.linalg.vector_norm(f - torch.nn.functional.conv2d(u, ker, padding=1))) / fn
+            if res <= tol:
+                break
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        iters.append(k)
+    return times, iters
+
+
+# ----------------------------------------------------------------------------- roofline
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_block_nag_n255_B256_traffic.json")
+
+
+def roofline(kstr, kcfg, t_step, P, copy_gbs):
+    """Roofline entry of the dominant kernel (the temporal-blocked NAG sweep).
+
+    achieved: algorithmic bytes per launch / launch time, with 20 B per point per inner
+    step (read u, v, f and write u, v in FP32 -- the traffic of a sweep that keeps
+    nothing on chip between steps) and T steps per launch.  Temporal blocking makes the
+    actual DRAM traffic per launch one such sweep (20 B per point) for all T steps, so
+    frac can exceed 1.  traffic: DRAM bytes per launch from the FETCH_SIZE / WRITE_SIZE
+    counters scaled by a copy-kernel calibration, when a committed profile exists for
+    this exact kernel configuration, else null."""
+    T = kcfg[1]
+    t_launch = t_step * T
+    alg = BYTES_PER_LUP_NAG * P * T
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            prof = json.load(fh)
+        if prof.get("kernel") == kstr:
+            traffic = prof["dram_bytes_per_launch"]
+    achieved = alg / t_launch / 1e9
+    return {"bound": "hbm", "kernel": kstr, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "launch_us": t_launch * 1e6,
+            "algorithmic_bytes_per_launch": alg, "steps_per_launch": T,
+            "min_dram_bytes_per_launch": BYTES_PER_LUP_NAG * P, "measured_copy_GBs": copy_gbs}
+
+
 # ----------------------------------------------------------------------------- GPU leg
 class Workload:
     def __init__(self):
@@ -84,6 +158,7 @@ class Workload:
         from synthetic import aniso_batch, meta_params
         self.torch, self.rm = torch, rm
         batch = aniso_batch(B, N, seed=2)
+        self.batch = batch
         self.ctx = rm.Context(0)
         self.plan = rm.Plan(self.ctx, batch.n, eps=batch.eps, theta=batch.theta)
         P = self.plan.P
@@ -183,20 +258,40 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="time only the fused sweep kernel and a 1 GiB device copy (for counter runs)")
+    ap.add_argument("--no-comparator", action="store_true", help="skip the plain FP64 loop comparator")
+    ap.add_argument("--kernel-config", default=None,
+                    help="variant,T,width of the sweep kernel instead of autotuning (e.g. 3,8,64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the batch shards by instance "
                                    "across GPUs by design, but no multi-GPU path is built"}))
         sys.exit(2)
 
-    cpu = None if args.no_cpu else cpu_baseline()  # before any GPU initialisation (forks workers)
+    cpu = None if (args.no_cpu or args.kernel_only) else cpu_baseline()  # before any GPU use (forks workers)
     print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
 
     import torch
     w = Workload()
-    tuned_us, kcfg = w.tune(os.environ.get("RM_TUNE_CACHE"))
-    print(f"[bench] tuned kernel (shape, T) = {kcfg}, {tuned_us:.1f} us per inner step", file=sys.stderr,
-          flush=True)
+    if args.kernel_config:
+        v, T, cw = (int(x) for x in args.kernel_config.split(","))
+        w.plan.set_kernel(v, T, cw=cw)
+        kcfg = w.plan.get_kernel(N)
+        rm_ = w.rm
+        rm_.rm_meta_forward(w.ctx, w.plan, M, w.params, w.om, w.al)
+    else:
+        tuned_us, kcfg = w.tune(os.environ.get("RM_TUNE_CACHE", TUNE_CACHE))
+        print(f"[bench] tuned kernel (variant, T, width) = {kcfg}, {tuned_us:.1f} us per inner step",
+              file=sys.stderr, flush=True)
+    if args.kernel_only:
+        kt = w.step_kernel_time()
+        copy_gbs = w.copy_bandwidth()
+        kstr = f"k_block variant {kcfg[0]} T={kcfg[1]} width={kcfg[2]} n={N} B={B}"
+        print(json.dumps({"kernel": kstr, "us_per_inner_step": kt * 1e6, "us_per_launch": kt * 1e6 * kcfg[1],
+                          "algorithmic_bytes_per_launch": BYTES_PER_LUP_NAG * w.P * kcfg[1],
+                          "copy_bytes": 2 * (1 << 30), "measured_copy_GBs": copy_gbs}), flush=True)
+        return
     for k in range(args.warmup):
         rep, _ = w.step()
         torch.cuda.synchronize()
@@ -215,8 +310,24 @@ def main():
     t = time.perf_counter() - t0
     ttol = float(np.mean([a.elapsed_time(b) / 1e3 for a, b in tol_times]))
     kt = w.step_kernel_time()
-    achieved = BYTES_PER_LUP_NAG * w.P / kt / 1e9
     copy_gbs = w.copy_bandwidth()
+    kstr = f"k_block variant {kcfg[0]} T={kcfg[1]} width={kcfg[2]} n={N} B={B}"
+    comparator = None
+    if not args.no_comparator:
+        sample = [0, 85, 170, 255]
+        omh = w.om.view(B, M).cpu().numpy()
+        alh = w.al.view(B, M).cpu().numpy()
+        ptimes, piters = plain_fp64_loop(w.batch, omh, alh, sample)
+        fused_iters = reps[-1]["outer_iters"]
+        est = float(np.mean(ptimes)) * B
+        comparator = {"kind": "plain per-instance FP64 GPU loop (PyTorch ops, host residual check per outer "
+                              "iteration)",
+                      "sample": f"instances {sample} of {B}, run to 1e-10; batch time extrapolated as "
+                                f"mean x {B}",
+                      "seconds_per_instance": [round(x, 4) for x in ptimes], "outer_iters": piters,
+                      "fused_outer_iters_same_instances": [int(fused_iters[i]) for i in sample],
+                      "time_to_tol_s_extrapolated": est, "speedup_time_to_tol": est / ttol}
+        print(f"[bench] comparator {comparator}", file=sys.stderr, flush=True)
     rep = reps[-1]
     out = {
         "metric": METRIC,
@@ -238,11 +349,9 @@ def main():
         "solve": {"status": int(rep["status"]), "outer_iters_median": float(np.median(rep["outer_iters"])),
                   "outer_iters_max": int(rep["outer_iters"].max()), "rounds_max": int(rep["rounds"].max()),
                   "relres_max": float(rep["relres"].max())},
-        "roofline": {"bound": "hbm", "kernel": f"k_block shape {kcfg[0]} T={kcfg[1]}", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "us_per_inner_step": kt * 1e6, "algorithmic_bytes_per_inner_step": BYTES_PER_LUP_NAG * w.P,
-                     "measured_copy_GBs": copy_gbs},
+        "roofline": roofline(kstr, kcfg, kt, w.P, copy_gbs),
         "cpu_baseline": cpu,
+        "plain_fp64_gpu_loop": comparator,
     }
     print(json.dumps(out), flush=True)
 

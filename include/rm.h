@@ -123,17 +123,19 @@ rm_status rm_plan_offsets(const rm_plan_t* plan, int64_t* off);
 rm_status rm_plan_coefficients(const rm_plan_t* plan, double* coef, double* gersh);
 
 /* Kernel configuration of the FP32 sweeps.  Instances are grouped by size n;
- * every size class runs a temporal-blocked kernel that advances T inner steps
- * per launch on extended tiles of cw x 8R points (cw a multiple of 8) with a
- * halo of T + 1 points, using 8 cw threads per workgroup.  Kernel variant
- * `shape` fixes R and the largest cw: 0: R = 8, cw <= 64; 1: R = 16, cw <= 64;
- * 2: R = 8, cw <= 128; 3: R = 13, cw <= 104; 4: R = 16, cw <= 128;
- * 5: R = 12, cw <= 96.  rm_plan
- * picks a configuration per class from a cost model; rm_tune measures.
+ * every size class runs a temporal-blocked kernel that advances up to T inner
+ * steps per launch on extended tiles of cw x 8R points (cw a multiple of 8),
+ * using 8 cw threads per workgroup.  Tile edges on the domain boundary need no
+ * halo; interior edges overlap by T + 1 points, so an instance that fits in one
+ * tile is computed without redundancy.  Kernel variant `shape` fixes R and the
+ * largest cw: 0: R = 8, cw <= 64; 1: R = 16, cw <= 64; 2: R = 8, cw <= 128;
+ * 3: R = 13, cw <= 64; 4: R = 16, cw <= 128; 5: R = 12, cw <= 96;
+ * 6: R = 13, cw <= 104.  rm_plan picks a configuration per class from a cost
+ * model; rm_tune measures.
  * rm_plan_set_kernel: set (shape, T, cw) for the class of size n (n <= 0: all
- * classes; cw <= 0: the width the cost model prefers); shape = -1 switches the
- * whole plan to one launch per inner step.  RM_EINVAL if the halo or width does
- * not fit the variant or no instance has size n. */
+ * classes; cw <= 0: the width the cost model prefers; 1 <= T <= 64); shape = -1
+ * switches the whole plan to one launch per inner step.  RM_EINVAL if the halo
+ * or width does not fit the variant or no instance has size n. */
 rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t T, int32_t cw);
 rm_status rm_plan_get_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, int32_t* T,
                              int32_t* cw);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -181,58 +182,92 @@ size_t vec_bytes(const rm_plan_t* p) {
 // ---------------------------------------------------------------------------
 // temporal-blocked execution plan
 // ---------------------------------------------------------------------------
-// Extended tile of a class: kernel variant v (strips of R rows, extended height
-// 8R), width cw, halo h = T + 1 (one ring more than the T steps need, so the
-// residual of the final iterate can be formed in the same launch).  Owned
-// region W x H = (cw - 2h) x (8R - 2h).
-bool class_geometry(int v, int T, int cw, int& W, int& H, int& h) {
-  if (v < 0 || v >= rmk::kNumBlockVariants) return false;
+// Boundary-aware 1D tiling of [0, n) by windows of length len: a window edge on
+// the domain boundary needs no halo (the zero border of the LDS tile and the
+// zeros published outside the interior are the Dirichlet condition); interior
+// edges overlap the neighbouring window by h.  Returns {window start, owned lo,
+// owned hi} per window, or nothing when len is too short for the halo.
+std::vector<std::array<int, 3>> partition(int n, int len, int h) {
+  std::vector<std::array<int, 3>> out;
+  int o = 0;
+  while (true) {
+    const int start = o > 0 ? o - h : 0;
+    if (start + len >= n) {
+      out.push_back({start, o, n});
+      break;
+    }
+    const int hi = start + len - h;
+    if (hi <= o) return {};
+    out.push_back({start, o, hi});
+    o = hi;
+  }
+  return out;
+}
+
+// Geometry of a class (n, variant v, steps per launch T, width cw): the tiles
+// across and down.  An instance that fits in one window needs no halo; otherwise
+// the halo is T + 1 (one ring more than T steps need, so the residual of the
+// final iterate can be formed in the same launch).
+bool class_geometry(int n, int v, int T, int cw, int& tx, int& ty) {
+  if (v < 0 || v >= rmk::kNumBlockVariants || T < 1) return false;
   const rmk::BlockVariant& bv = rmk::kBlockVariants[v];
-  h = T + 1;
-  W = cw - 2 * h;
-  H = 8 * bv.r - 2 * h;
-  return cw >= 8 && cw % 8 == 0 && cw + 2 <= bv.lw && W >= 1 && H >= 1;
+  if (cw < 8 || cw % 8 != 0 || cw + 2 > bv.lw) return false;
+  const int eh = 8 * bv.r;
+  const int h = T + 1;
+  tx = (int)partition(n, cw, h).size();
+  ty = (int)partition(n, eh, h).size();
+  return tx > 0 && ty > 0;
 }
 
 // Cost model used before any tuning: the larger of an arithmetic bound
 // (redundant halo work included) and an HBM bound (load u, v, f on the extended
 // tile, store u, v on the owned one, once per T steps), per inner step.
 double model_cost(int n, int v, int T, int cw) {
-  int W, H, h;
-  if (!class_geometry(v, T, cw, W, H, h)) return 1e300;
-  const double tiles = (double)((n + W - 1) / W) * (double)((n + H - 1) / H);
-  const double ext = tiles * cw * (double)(8 * rmk::kBlockVariants[v].r);
+  int tx, ty;
+  if (!class_geometry(n, v, T, cw, tx, ty)) return 1e300;
+  const double ext = (double)tx * ty * cw * (double)(8 * rmk::kBlockVariants[v].r);
   const double own = (double)n * n;
   const double compute = ext / 1.6e12;
   const double memory = (12.0 * ext + 8.0 * own) / T / 5.0e12;
   return std::max(compute, memory) + 4e-6 / T / 256.0;
 }
 
-// Tile widths worth trying for (n, v, T): the narrowest width that covers n with
-// k tiles across, for the few smallest feasible k.
+// Steps per launch tried by the tuner and the cost model.
+constexpr int kTs[] = {2, 4, 8, 16, 32};
+
+// Tile widths worth trying for (n, v, T): for the few smallest tile counts k
+// across, the narrowest multiple of 8 that covers n.
 std::vector<int> candidate_widths(int n, int v, int T) {
   std::vector<int> out;
-  const int h = T + 1;
   const int lw = rmk::kBlockVariants[v].lw;
-  for (int k = 1; k <= 64 && (int)out.size() < 4; ++k) {
-    const int own = (n + k - 1) / k;
-    const int cw = ((own + 2 * h + 7) / 8) * 8;
-    int W, H, hh;
-    if (cw + 2 > lw) continue;
-    if (!class_geometry(v, T, cw, W, H, hh)) continue;
-    if (std::find(out.begin(), out.end(), cw) == out.end()) out.push_back(cw);
-    if (own <= 8) break;
+  for (int cw = 8; cw + 2 <= lw && (int)out.size() < 64; cw += 8) {
+    int tx, ty;
+    if (!class_geometry(n, v, T, cw, tx, ty)) continue;
+    // keep cw only if it is the narrowest width with this tile count
+    int tx2 = -1, ty2;
+    if (cw > 8 && class_geometry(n, v, T, cw - 8, tx2, ty2) && tx2 == tx) continue;
+    out.push_back(cw);
   }
-  return out;
+  // favour the widest few (fewest tiles) and widths that are multiples of 32
+  std::vector<int> keep;
+  for (auto it = out.rbegin(); it != out.rend() && (int)keep.size() < 3; ++it) keep.push_back(*it);
+  for (int w : out)
+    if (w % 32 == 0 && std::find(keep.begin(), keep.end(), w) == keep.end()) keep.push_back(w);
+  for (int w : {32, 64, 96, 128}) {
+    int tx, ty;
+    if (class_geometry(n, v, T, w, tx, ty) && std::find(keep.begin(), keep.end(), w) == keep.end())
+      keep.push_back(w);
+  }
+  return keep;
 }
 
 void default_class_config(int n, int& shape, int& T, int& cw) {
   double best = 1e301;
   shape = 0;
-  T = 1;
+  T = 2;
   cw = 64;
   for (int v = 0; v < rmk::kNumBlockVariants; ++v)
-    for (int t : rmk::kBlockTs)
+    for (int t : kTs)
       for (int w : candidate_widths(n, v, t)) {
         const double c = model_cost(n, v, t, w);
         if (c < best * 0.999) {
@@ -266,21 +301,23 @@ rm_status build_exec(rm_plan_t* pl, hipStream_t st) {
   std::vector<int> ranges((size_t)pl->B * 2, 0);
   int slot = 0;
   for (auto& c : pl->classes) {
-    int W, H, h;
-    if (!class_geometry(c.shape, c.T, c.cw, W, H, h)) return fail(RM_EINVAL, "invalid kernel shape for this T");
-    std::vector<Tile> t;
+    int tx, ty;
+    if (!class_geometry(c.n, c.shape, c.T, c.cw, tx, ty)) return fail(RM_EINVAL, "invalid kernel configuration");
+    const int eh = 8 * rmk::kBlockVariants[c.shape].r;
+    const auto px = partition(c.n, c.cw, c.T + 1);
+    const auto py = partition(c.n, eh, c.T + 1);
+    std::vector<rmk::BTile> t;
     for (int b : c.insts) {
-      const int n = pl->inst[b].n;
       ranges[2 * b] = slot;
-      for (int oy = 0; oy < n; oy += H)
-        for (int ox = 0; ox < n; ox += W) t.push_back(Tile{b, ox - h, oy - h, slot++});
+      for (const auto& y : py)
+        for (const auto& x : px) t.push_back(rmk::BTile{b, x[0], y[0], slot++, x[1], x[2], y[1], y[2]});
       ranges[2 * b + 1] = slot;
     }
-    while (t.size() % 8 != 0) t.push_back(Tile{-1, 0, 0, slot++});
+    while (t.size() % 8 != 0) t.push_back(rmk::BTile{-1, 0, 0, slot++, 0, 0, 0, 0});
     c.ntiles = (int)t.size();
-    RM_TRY(c.tiles.ensure(t.size() * sizeof(Tile), st));
+    RM_TRY(c.tiles.ensure(t.size() * sizeof(rmk::BTile), st));
     RM_HIP(hipStreamSynchronize(st));
-    RM_HIP(hipMemcpy(c.tiles.ptr, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    RM_HIP(hipMemcpy(c.tiles.ptr, t.data(), t.size() * sizeof(rmk::BTile), hipMemcpyHostToDevice));
   }
   pl->nslots = slot;
   RM_TRY(pl->d_ranges.ensure(ranges.size() * sizeof(int), st));
@@ -293,14 +330,18 @@ size_t partial_slots(const rm_plan_t* pl) { return std::max<size_t>(pl->tiles.si
 
 // Advance `nsteps` FP32 inner steps (global step indices s0 ..) on the pingpong
 // pair (us, vs), starting from set `cur`; `cur` ends on the set holding the
-// result and `flips` counts the swaps.  When res_partial is given, the residual
-// ||f - A u||^2 of the final iterate is left per tile in res_partial and
-// *res_ranges tells the reduction which slots belong to which instance.
-// `only_class` >= 0 restricts the launches to one size class (autotuning).
+// result and `flips` counts the swaps (the same for every instance).  Each size
+// class advances in its own chunks of at most its T steps; for nsteps >= 2 every
+// class uses an even number of launches, so all classes end on the same set.
+// When res_partial is given, the residual ||f - A u||^2 of the final iterate is
+// left per tile in res_partial and *res_ranges tells the reduction which slots
+// belong to which instance.  `only_class` >= 0 restricts the launches to one
+// size class (autotuning).
 rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int nsteps, const float* omega,
                 const float* alpha, const float* f, float* const us[2], float* const vs[2], int& cur, int& flips,
                 const int* active, double* res_partial, const int** res_ranges, int only_class = -1) {
   const PlanDev p = pl->dev();
+  if (nsteps <= 0) return RM_OK;
   if (!pl->use_block) {
     for (int k = 0; k < nsteps; ++k) {
       rmk::launch_step<float>(method, p, p.tiles, p.ntiles, omega, alpha, m, (s0 + k) % m, f, us[cur], vs[cur],
@@ -315,30 +356,34 @@ rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int ns
     return RM_OK;
   }
   RM_TRY(build_exec(pl, st));
-  int done = 0;
-  while (done < nsteps) {
-    // chunk: the largest supported T not above the remaining steps and the
-    // smallest class T (every class advances by the same number of steps)
-    int tmax = 8;
-    for (size_t ci = 0; ci < pl->classes.size(); ++ci)
-      if (only_class < 0 || (int)ci == only_class) tmax = std::min(tmax, pl->classes[ci].T);
-    int t = 1;
-    for (int cand : rmk::kBlockTs)
-      if (cand <= tmax && cand <= nsteps - done) t = cand;
-    const bool last = done + t == nsteps;
+  // chunk plan per class
+  std::vector<std::vector<int>> chunks(pl->classes.size());
+  int L = 0;
+  for (size_t ci = 0; ci < pl->classes.size(); ++ci) {
+    if (only_class >= 0 && (int)ci != only_class) continue;
+    const int T = pl->classes[ci].T;
+    int lc = (nsteps + T - 1) / T;
+    if (nsteps >= 2 && (lc & 1)) ++lc;
+    for (int j = 0; j < lc; ++j) chunks[ci].push_back(nsteps / lc + (j < nsteps % lc ? 1 : 0));
+    L = std::max(L, lc);
+  }
+  for (int j = 0; j < L; ++j) {
+    const int rd = (cur + j) & 1;
     for (size_t ci = 0; ci < pl->classes.size(); ++ci) {
-      if (only_class >= 0 && (int)ci != only_class) continue;
+      if (j >= (int)chunks[ci].size()) continue;
       auto& c = pl->classes[ci];
-      const int h = c.T + 1;
-      if (!rmk::launch_block(c.shape, t, c.cw, method, p, c.tiles.as<Tile>(), c.ntiles, h, omega, alpha, m, s0 + done, f,
-                             us[cur], vs[cur], us[cur ^ 1], vs[cur ^ 1], active,
+      int s = s0;
+      for (int q = 0; q < j; ++q) s += chunks[ci][q];
+      const bool last = j + 1 == (int)chunks[ci].size();
+      if (!rmk::launch_block(c.shape, chunks[ci][j], c.cw, method, p, c.tiles.as<rmk::BTile>(), c.ntiles, omega,
+                             alpha, m, s, f, us[rd], vs[rd], us[rd ^ 1], vs[rd ^ 1], active,
                              last ? res_partial : nullptr, st))
         return fail(RM_EUNSUPPORTED, "block kernel configuration not built");
     }
-    cur ^= 1;
-    ++flips;
-    done += t;
   }
+  const int lfin = nsteps >= 2 ? 0 : 1;  // parity of every class's launch count
+  cur ^= lfin;
+  flips += nsteps >= 2 ? 2 : 1;
   if (res_partial != nullptr) *res_ranges = pl->d_ranges.as<int>();
   return RM_OK;
 }
@@ -872,7 +917,7 @@ rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t 
     return RM_OK;
   }
   if (shape < 0 || shape >= rmk::kNumBlockVariants) return fail(RM_EINVAL, "unknown kernel variant");
-  if (T != 1 && T != 2 && T != 4 && T != 8) return fail(RM_EINVAL, "T must be 1, 2, 4 or 8");
+  if (T < 1 || T > 64) return fail(RM_EINVAL, "T must be in 1..64");
   bool hit = false;
   for (auto& c : plan->classes) {
     if (n > 0 && c.n != n) continue;
@@ -887,8 +932,8 @@ rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t 
         }
       }
     }
-    int W, H, h;
-    if (!class_geometry(shape, T, w, W, H, h))
+    int tx, ty;
+    if (!class_geometry(c.n, shape, T, w, tx, ty))
       return fail(RM_EINVAL, "tile width / halo T + 1 does not fit this kernel variant");
     c.shape = shape;
     c.T = T;
@@ -977,8 +1022,8 @@ rm_status rm_tune(rm_ctx* ctx, rm_plan_t* plan, int32_t method, int32_t m, const
         int sh, T, w;
         double us;
         if (std::sscanf(kv.second.c_str(), "[%d, %d, %d, %lf]", &sh, &T, &w, &us) == 4) {
-          int W, H, h;
-          if (class_geometry(sh, T, w, W, H, h)) {
+          int tx, ty;
+          if (class_geometry(c.n, sh, T, w, tx, ty)) {
             c.shape = sh;
             c.T = T;
             c.cw = w;
@@ -991,7 +1036,7 @@ rm_status rm_tune(rm_ctx* ctx, rm_plan_t* plan, int32_t method, int32_t m, const
     double best = 1e300;
     int best_s = c.shape, best_T = c.T, best_w = c.cw;
     for (int sh = 0; sh < rmk::kNumBlockVariants; ++sh)
-      for (int T : rmk::kBlockTs)
+      for (int T : kTs)
         for (int w : candidate_widths(c.n, sh, T)) {
           c.shape = sh;
           c.T = T;

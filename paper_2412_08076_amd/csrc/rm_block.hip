@@ -3,20 +3,29 @@
 // A workgroup of 8 CW threads owns an extended tile of CW x 8R points: thread t
 // holds u, v and f of a vertical strip of R points of column t mod CW in
 // registers (consecutive threads take consecutive columns, so every global
-// access of a wave is a contiguous row segment).  CW is chosen at run time per
-// size class so that the tiles fit the instance.  The workgroup runs T
+// access of a wave is a contiguous row segment).  The workgroup runs T
 // consecutive inner steps of Richardson(m) / NAG-Richardson(m) (Table 1) on the
 // whole extended tile without touching HBM in between:
 //   per step: u~ = u + a_i v  ->  LDS
-//             r = f - A u~ from LDS, v' = a_i v + w_i r, u' = u + v'.
-// Values outside the extended tile read as 0, so the outermost ring goes wrong
-// by one point per step; the owned region is the tile inset by h >= T points and
-// is exact.  With a residual requested (h >= T + 1), ||f - A u||^2 of the final
-// u is accumulated over the owned points as well.
-// Points outside the n x n interior are held at u = v = 0 (Dirichlet).
+//             v' = a_i v + w_i (f - A u~) from LDS,  u' = u + v'.
+// The LDS tile has a zero border.  Where a tile edge lies on or beyond the
+// domain boundary that border (and the zeros published by points outside the
+// n x n interior) is exactly the homogeneous Dirichlet condition, so nothing
+// goes stale there.  Across an interior edge the values outside the tile are
+// missing and the outermost ring goes wrong by one point per step; tiles
+// therefore overlap by a halo of h >= T points at interior edges and each tile
+// stores only its owned rectangle (given per tile).  With a residual requested
+// (h >= T + 1), ||f - A u||^2 of the final u is accumulated over the owned
+// points as well.  An instance that fits in one tile needs no halo at all and
+// can run any number of steps per launch.
 //
-// The stencil and update are evaluated with the same fused multiply-add order as
-// the one-step kernel, so a launch of T steps reproduces T one-step launches bit
+// One LDS buffer holds the published field; each step has two barriers (after
+// publishing, and before the next step overwrites it), which keeps the LDS and
+// register footprint small enough for two or three workgroups per CU, so that
+// one workgroup's loads and stores overlap another's arithmetic.
+//
+// The update is evaluated with the same fused multiply-add sequence as the
+// one-step kernel, so a launch of T steps reproduces T one-step launches bit
 // for bit.
 #include "rm_internal.h"
 
@@ -38,12 +47,24 @@ __device__ __forceinline__ float stencil9f(const float c[5], float C, float W, f
   return acc;
 }
 
-// Stencil of the R points of this thread's strip, all nine inputs read from the
-// LDS tile B (row stride LW, zero border; strip row k sits at LDS row
-// lr0 + k + 1, column lc + 1), walking down the strip with a three-row window.
-// f(k, A u) consumes each result as soon as it is formed.
+// New momentum with the weight folded into the stencil (the same sequence as the
+// one-step kernel): v' = a v + w f - sum_j (w c_j) s_j.
+__device__ __forceinline__ float step_vf(const float wc[5], float w, float a, float f, float v, float C, float W,
+                                         float E, float S, float N, float SW, float NE, float SE, float NW) {
+  float acc = fmadd(a, v, w * f);
+  acc = fmadd(-wc[0], C, acc);
+  acc = fmadd(-wc[1], W + E, acc);
+  acc = fmadd(-wc[2], S + N, acc);
+  acc = fmadd(-wc[3], SW + NE, acc);
+  acc = fmadd(-wc[4], SE + NW, acc);
+  return acc;
+}
+
+// Walk down this thread's strip with a three-row window over the LDS tile B (row
+// stride LW, zero border; strip row k sits at LDS row lr0 + k + 1, column lc + 1)
+// and hand f(k, C, W, E, S, N, SW, NE, SE, NW) the nine inputs of every point.
 template <int R, int LW, typename F>
-__device__ __forceinline__ void strip_apply(const float* B, int lc, int lr0, const float c[5], F&& f) {
+__device__ __forceinline__ void strip_walk(const float* B, int lc, int lr0, F&& f) {
   const float* q = B + lr0 * LW + lc;
   float Lm = q[0], Cm = q[1], Rm = q[2];
   float L0 = q[LW], C0 = q[LW + 1], R0 = q[LW + 2];
@@ -51,7 +72,7 @@ __device__ __forceinline__ void strip_apply(const float* B, int lc, int lr0, con
   for (int k = 0; k < R; ++k) {
     const float* qn = q + (k + 2) * LW;
     const float Lp = qn[0], Cp = qn[1], Rp = qn[2];
-    f(k, stencil9f(c, C0, L0, R0, Cm, Cp, Lm, Rp, Rm, Lp));
+    f(k, C0, L0, R0, Cm, Cp, Lm, Rp, Rm, Lp);
     Lm = L0; Cm = C0; Rm = R0;
     L0 = Lp; C0 = Cp; R0 = Rp;
   }
@@ -59,18 +80,14 @@ __device__ __forceinline__ void strip_apply(const float* B, int lc, int lr0, con
 
 // Thread t of a workgroup of 8 CW threads takes column t mod CW and the strip of
 // R rows starting at R (t / CW): the extended tile is CW x 8R points.  CW is a
-// run-time multiple of 8 (CW + 2 <= LW), so tiles can be sized to the instance.
-// One LDS buffer holds the published field; each step has two barriers (after
-// publishing, and before the next step overwrites it), which keeps the LDS and
-// register footprint small enough for two or more workgroups per CU, so that one
-// workgroup's loads and stores overlap another's arithmetic.
-template <int T, int R, int LW, int WPE, int METHOD>
-__global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_per_eu(WPE))) void k_block(PlanDev p, const Tile* __restrict__ tiles, int ntiles, int h, int CW,
-                                               const float* __restrict__ omega, const float* __restrict__ alpha,
-                                               int m, int s0, const float* __restrict__ f,
-                                               const float* __restrict__ u, const float* __restrict__ v,
-                                               float* __restrict__ u_out, float* __restrict__ v_out,
-                                               const int* __restrict__ active, double* __restrict__ partial2) {
+// run-time multiple of 8 (CW + 2 <= LW); T >= 0 is a run-time step count (T = 0
+// copies the owned points and can still form the residual).
+template <int R, int LW, int WPE, int METHOD>
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_per_eu(WPE))) void k_block(
+    PlanDev p, const BTile* __restrict__ tiles, int ntiles, int T, int CW, const float* __restrict__ omega,
+    const float* __restrict__ alpha, int m, int s0, const float* __restrict__ f, const float* __restrict__ u,
+    const float* __restrict__ v, float* __restrict__ u_out, float* __restrict__ v_out,
+    const int* __restrict__ active, double* __restrict__ partial2) {
   constexpr int NS = 8;
   constexpr int EH = R * NS;
   constexpr int LH = EH + 2;
@@ -78,7 +95,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_pe
   __shared__ double sh[16];
   const int NT = CW * NS;
   const int per = ntiles >> 3;
-  const Tile tl = tiles[(blockIdx.x & 7) * per + (blockIdx.x >> 3)];
+  const BTile tl = tiles[(blockIdx.x & 7) * per + (blockIdx.x >> 3)];
   if (tl.inst < 0) return;
   if (active != nullptr && active[tl.inst] == 0) return;
   const Inst in = p.inst[tl.inst];
@@ -115,30 +132,33 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_pe
     B[idx] = 0.0f;
   }
   float* mine = B + (lr0 + 1) * LW + lc + 1;
-  // Points outside the n x n interior publish 0 (Dirichlet); their registers
-  // are never stored.
 #pragma unroll 1
   for (int t = 0; t < T; ++t) {
     const int i = (s0 + t) % m;
     const float w = omega[tl.inst * m + i];
     const float a = METHOD == M_NAG ? alpha[tl.inst * m + i] : 0.0f;
+    float wc[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) wc[j] = w * c[j];
     if (t > 0) __syncthreads();  // every read of the previous step is done
 #pragma unroll
     for (int k = 0; k < R; ++k) {
+      // points outside the n x n interior publish 0 (Dirichlet); their
+      // registers are never stored
       const int gy = gy0 + k;
       const bool ok = colin && gy >= 0 && gy < n;
       const float x = METHOD == M_NAG ? fmadd(a, rv[k], ru[k]) : ru[k];
       mine[k * LW] = ok ? x : 0.0f;
     }
     __syncthreads();
-    strip_apply<R, LW>(B, lc, lr0, c, [&](int k, float au) {
-      const float r = rf[k] - au;
-      const float vn = METHOD == M_NAG ? fmadd(a, rv[k], w * r) : w * r;
+    strip_walk<R, LW>(B, lc, lr0, [&](int k, float C, float W, float E, float S, float N, float SW, float NE,
+                                      float SE, float NW) {
+      const float vn = step_vf(wc, w, a, rf[k], rv[k], C, W, E, S, N, SW, NE, SE, NW);
       ru[k] = ru[k] + vn;
       rv[k] = vn;
     });
   }
-  const bool colown = lc >= h && lc < CW - h && colin;
+  const bool colown = gx >= tl.ox0 && gx < tl.ox1;
   double r2 = 0.0;
   if (partial2 != nullptr) {
     __syncthreads();
@@ -149,18 +169,19 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_pe
       mine[k * LW] = ok ? ru[k] : 0.0f;
     }
     __syncthreads();
-    strip_apply<R, LW>(B, lc, lr0, c, [&](int k, float au) {
-      const int lr = lr0 + k, gy = gy0 + k;
-      if (colown && lr >= h && lr < EH - h && gy >= 0 && gy < n) {
-        const float r = rf[k] - au;
+    strip_walk<R, LW>(B, lc, lr0, [&](int k, float C, float W, float E, float S, float N, float SW, float NE,
+                                      float SE, float NW) {
+      const int gy = gy0 + k;
+      if (colown && gy >= tl.oy0 && gy < tl.oy1) {
+        const float r = rf[k] - stencil9f(c, C, W, E, S, N, SW, NE, SE, NW);
         r2 += (double)r * (double)r;
       }
     });
   }
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const int lr = lr0 + k, gy = gy0 + k;
-    if (colown && lr >= h && lr < EH - h && gy >= 0 && gy < n) {
+    const int gy = gy0 + k;
+    if (colown && gy >= tl.oy0 && gy < tl.oy1) {
       const int64_t idx = in.off + (int64_t)gy * n + gx;
       u_out[idx] = ru[k];
       if (METHOD == M_NAG) v_out[idx] = rv[k];
@@ -176,43 +197,23 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_pe
     if (threadIdx.x == 0) {
       double s = 0.0;
       for (int k = 0; k < NT / 64; ++k) s += sh[k];
-      partial2[2 * tl.pad] = s;
-      partial2[2 * tl.pad + 1] = 0.0;
+      partial2[2 * tl.slot] = s;
+      partial2[2 * tl.slot + 1] = 0.0;
     }
   }
 }
 
-template <int T, int R, int LW, int WPE>
-void launch_variant(int method, const PlanDev& p, const Tile* tiles, int ntiles, int h, int cw, const float* omega,
+template <int R, int LW, int WPE>
+void launch_variant(int T, int cw, int method, const PlanDev& p, const BTile* tiles, int ntiles, const float* omega,
                     const float* alpha, int m, int s0, const float* f, const float* u, const float* v, float* u_out,
                     float* v_out, const int* active, double* partial2, hipStream_t st) {
   const dim3 grid(ntiles), block(8 * cw);
   if (method == M_NAG)
-    hipLaunchKernelGGL((k_block<T, R, LW, WPE, M_NAG>), grid, block, 0, st, p, tiles, ntiles, h, cw, omega, alpha, m, s0,
+    hipLaunchKernelGGL((k_block<R, LW, WPE, M_NAG>), grid, block, 0, st, p, tiles, ntiles, T, cw, omega, alpha, m, s0,
                        f, u, v, u_out, v_out, active, partial2);
   else
-    hipLaunchKernelGGL((k_block<T, R, LW, WPE, M_RICH>), grid, block, 0, st, p, tiles, ntiles, h, cw, omega, alpha, m,
+    hipLaunchKernelGGL((k_block<R, LW, WPE, M_RICH>), grid, block, 0, st, p, tiles, ntiles, T, cw, omega, alpha, m,
                        s0, f, u, v, u_out, v_out, active, partial2);
-}
-
-template <int R, int LW, int WPE>
-bool launch_T(int T, int method, const PlanDev& p, const Tile* tiles, int ntiles, int h, int cw, const float* omega,
-              const float* alpha, int m, int s0, const float* f, const float* u, const float* v, float* u_out,
-              float* v_out, const int* active, double* partial2, hipStream_t st) {
-#define RM_BLOCK_CASE(TT)                                                                                         \
-  case TT:                                                                                                        \
-    launch_variant<TT, R, LW, WPE>(method, p, tiles, ntiles, h, cw, omega, alpha, m, s0, f, u, v, u_out, v_out, active, \
-                              partial2, st);                                                                      \
-    return true;
-  switch (T) {
-    RM_BLOCK_CASE(1)
-    RM_BLOCK_CASE(2)
-    RM_BLOCK_CASE(4)
-    RM_BLOCK_CASE(8)
-    default:
-      return false;
-  }
-#undef RM_BLOCK_CASE
 }
 
 }  // namespace
@@ -221,29 +222,32 @@ const BlockVariant kBlockVariants[kNumBlockVariants] = {
     {8, 66},    // up to 64 x 64 points
     {16, 66},   // up to 64 x 128
     {8, 130},   // up to 128 x 64
-    {13, 106},  // up to 104 x 104
+    {13, 66},   // up to 64 x 104
     {16, 130},  // up to 128 x 128
     {12, 98},   // up to 96 x 96
+    {13, 106},  // up to 104 x 104
 };
 
-bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, const Tile* tiles, int ntiles, int h,
+bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, const BTile* tiles, int ntiles,
                   const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,
                   const float* v, float* u_out, float* v_out, const int* active, double* partial2,
                   hipStream_t st) {
-  if (variant < 0 || variant >= kNumBlockVariants) return false;
+  if (variant < 0 || variant >= kNumBlockVariants || T < 0) return false;
   if (cw < 8 || cw % 8 != 0 || cw + 2 > kBlockVariants[variant].lw) return false;
-#define RM_VARIANT_CASE(V, R, LW, WPE)                                                                         \
-  case V:                                                                                                      \
-    return launch_T<R, LW, WPE>(T, method, p, tiles, ntiles, h, cw, omega, alpha, m, s0, f, u, v, u_out, v_out,    \
-                           active, partial2, st);
+#define RM_VARIANT_CASE(V, R, LW, WPE)                                                                        \
+  case V:                                                                                                     \
+    launch_variant<R, LW, WPE>(T, cw, method, p, tiles, ntiles, omega, alpha, m, s0, f, u, v, u_out, v_out, \
+                               active, partial2, st);                                                         \
+    return true;
+  // register caps (waves per SIMD) chosen so that two or three workgroups fit on a CU
   switch (variant) {
-    // register caps (waves per SIMD) chosen so that two workgroups fit on a CU
     RM_VARIANT_CASE(0, 8, 66, 8)
     RM_VARIANT_CASE(1, 16, 66, 4)
     RM_VARIANT_CASE(2, 8, 130, 7)
-    RM_VARIANT_CASE(3, 13, 106, 7)
+    RM_VARIANT_CASE(3, 13, 66, 6)
     RM_VARIANT_CASE(4, 16, 130, 4)
     RM_VARIANT_CASE(5, 12, 98, 6)
+    RM_VARIANT_CASE(6, 13, 106, 6)
     default:
       return false;
   }

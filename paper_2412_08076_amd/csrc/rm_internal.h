@@ -103,16 +103,24 @@ void launch_meta_backward(const PlanDev& p, int m, const float* params, const fl
 struct BlockVariant {
   int r, lw;
 };
-constexpr int kNumBlockVariants = 6;
+constexpr int kNumBlockVariants = 7;
 extern const BlockVariant kBlockVariants[kNumBlockVariants];
-constexpr int kBlockTs[4] = {1, 2, 4, 8};
-// T fused steps (s0 .. s0 + T - 1) over a tile table of extended CW x 8R tiles
-// inset by h (h >= T; h >= T + 1 when partial2 is given, which then receives
-// ||f - A u||^2 of the final u per tile).  Returns false for an unsupported
-// (variant, T, cw).
-bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, const Tile* tiles, int ntiles,
-                  int h, const float* omega, const float* alpha, int m, int s0, const float* f,
-                  const float* u, const float* v, float* u_out, float* v_out, const int* active,
-                  double* partial2, hipStream_t st);
+
+// One extended tile of a block table: origin (x0, y0) of its CW x 8R window in
+// instance coordinates, the slot of its residual partial, and the owned
+// rectangle [ox0, ox1) x [oy0, oy1) it stores.  inst < 0 marks padding.
+struct BTile {
+  int32_t inst, x0, y0, slot;
+  int32_t ox0, ox1, oy0, oy1;
+};
+
+// T fused steps (s0 .. s0 + T - 1) over a table of extended tiles.  Tiles must
+// overlap by at least T points at interior edges (T + 1 when partial2 is given,
+// which then receives ||f - A u||^2 of the final u over each tile's owned part).
+// Returns false for an unsupported (variant, cw).
+bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, const BTile* tiles, int ntiles,
+                  const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,
+                  const float* v, float* u_out, float* v_out, const int* active, double* partial2,
+                  hipStream_t st);
 
 }  // namespace rmk

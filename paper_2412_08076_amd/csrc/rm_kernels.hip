@@ -54,6 +54,23 @@ __device__ __forceinline__ T stencil9(const T c[5], T C, T W, T E, T S, T N, T S
   return acc;
 }
 
+// One inner step's new momentum at a point, with the weight folded into the
+// stencil: v' = a v + w f - sum_j (w c_j) s_j, where wc[j] = w c_j and the s_j are
+// the centre and the symmetric neighbour pairs of the look-ahead field (same
+// pairing and order as stencil9).  Every kernel that advances the iteration uses
+// exactly this sequence, so they agree bit for bit.
+template <typename T>
+__device__ __forceinline__ T step_v(const T wc[5], T w, T a, T f, T v, T C, T W, T E, T S, T N, T SW, T NE, T SE,
+                                    T NW) {
+  T acc = fmadd(a, v, w * f);
+  acc = fmadd(-wc[0], C, acc);
+  acc = fmadd(-wc[1], W + E, acc);
+  acc = fmadd(-wc[2], S + N, acc);
+  acc = fmadd(-wc[3], SW + NE, acc);
+  acc = fmadd(-wc[4], SE + NW, acc);
+  return acc;
+}
+
 // Stencil at LDS position (lx, ly) of a (TY+2) x LDS_W tile.
 template <typename T>
 __device__ __forceinline__ T stencil_lds(const T* s, int lx, int ly, const T c[5]) {
@@ -218,12 +235,17 @@ __global__ __launch_bounds__(WG) void k_step(PlanDev p, const Tile* tiles, const
   else
     stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return ui[Y * n + X]; });
   __syncthreads();
+  T wc[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) wc[k] = w * c[k];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
     if (gx < n && gy < n) {
-      const T r = rf[k] - stencil_lds(s, tx + 1, ly + 1, c);
-      const T vn = METHOD == M_NAG ? fmadd(a, rv[k], w * r) : w * r;
+      const T* rs = s + ly * LDS_W + tx + 1;
+      const T* rc = rs + LDS_W;
+      const T* rn = rc + LDS_W;
+      const T vn = step_v(wc, w, a, rf[k], rv[k], rc[0], rc[-1], rc[1], rs[0], rn[0], rs[-1], rn[1], rs[1], rn[-1]);
       const int64_t idx = in.off + (int64_t)gy * n + gx;
       u_out[idx] = ru[k] + vn;
       if (METHOD == M_NAG) v_out[idx] = vn;

@@ -53,8 +53,8 @@ def test_blocked_equals_one_step_bitwise(ctx, method_name):
     f = dev(batch.f_packed(), torch.float32)
     plan.set_kernel(-1, 1)
     ref, ref_h, _ = _unroll(ctx, plan, method, om, al, f, m, K, hist=True)
-    for shape in range(5):
-        for T in (1, 2, 4, 8):
+    for shape in range(7):
+        for T in (1, 2, 3, 8, 16):
             for cw in (0, 24, 64, 128):
                 try:
                     plan.set_kernel(shape, T, cw=cw)
