@@ -252,6 +252,108 @@ class Workload:
         return best
 
 
+def secondary_workload(name, tune_cache):
+    """The other measured shapes (one JSON line each; the headline line is the default
+    workload): 'uneven' -- 512 instances of mixed size, one plan; 'train' -- the training
+    step on 64 problems of n = 127; 'single' -- one isotropic n = 63 problem."""
+    import torch
+    from paper_2412_08076_amd import rm
+    from synthetic import aniso_batch, meta_params, single_isotropic, uneven_batch
+    ctx = rm.Context(0)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    out = {"workload": name}
+    if name == "single":
+        batch = single_isotropic(63, seed=0)
+        plan = rm.Plan(ctx, batch.n, eps=batch.eps, theta=batch.theta)
+        coef, _ = plan.coefficients()
+        # Chebyshev(8) weights from the closed-form extreme eigenvalues of the eps = 1 stencil
+        c = np.cos(np.pi / 64)
+        lmin, lmax = (4.0 / 3.0) * (2 - c - c * c), (8 + 4 * c * c) / 3.0
+        x = np.cos((2 * np.arange(1, 9) - 1) * np.pi / 16)
+        om = torch.tensor(2.0 / (lmax + lmin + (lmax - lmin) * x), dtype=torch.float32, device="cuda")
+        b64 = torch.as_tensor(batch.f_packed()).cuda()
+        x64 = torch.zeros_like(b64)
+        opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F64, m=8, K=400)
+        e0, e1 = ev(), ev()
+        e0.record(); rm.rm_solve(ctx, plan, rm.RM_RICHARDSON, opts, om, None, b64, x64); e1.record()
+        torch.cuda.synchronize()
+        r2 = torch.empty(1, dtype=torch.float64, device="cuda"); b2 = torch.empty_like(r2)
+        rm.rm_residual(ctx, plan, b64, x64, r2=r2, b2=b2)
+        out.update({"fp64_400_steps_ms": e0.elapsed_time(e1), "relres_400": float((r2 / b2).sqrt())})
+        for tol in (1e-10, 1e-12):
+            x64.zero_()
+            o = rm.solve_opts(mode=rm.RM_TO_TOL, m=8, tol=tol, tol_inner=1e-3, max_outer=20000, max_rounds=12,
+                              check_every=4)
+            t0 = time.perf_counter(); rep = rm.rm_solve(ctx, plan, rm.RM_RICHARDSON, o, om, None, b64, x64)
+            out[f"to_tol_{tol:g}"] = {"s": time.perf_counter() - t0, "outer": int(rep["outer_iters"][0]),
+                                      "rounds": int(rep["rounds"][0]), "relres": float(rep["relres"][0])}
+        return out
+    m = 16
+    if name == "train":
+        batch = aniso_batch(64, 127, seed=3)
+    else:
+        batch = uneven_batch(seed=4)
+    plan = rm.Plan(ctx, batch.n, eps=batch.eps, theta=batch.theta)
+    P, Bn = plan.P, plan.B
+    params = torch.as_tensor(meta_params(m=m, seed=0), dtype=torch.float32).cuda()
+    om = torch.empty(Bn * m, dtype=torch.float32, device="cuda"); al = torch.empty_like(om)
+    rm.rm_meta_forward(ctx, plan, m, params, om, al)
+    b32 = torch.as_tensor(batch.f_packed(), dtype=torch.float32).cuda()
+    us = rm.rm_tune(ctx, plan, rm.RM_NAG, m, om, al, b32, cache_path=tune_cache)
+    out["kernels"] = {int(n): plan.get_kernel(int(n)) for n in sorted(set(batch.n))}
+    out["tuned_us_per_step"] = us
+    K = 64
+    x = torch.zeros(P, dtype=torch.float32, device="cuda")
+    if name == "train":
+        ck = torch.empty(K // 16 * 2 * P, dtype=torch.float32, device="cuda")
+        loss = torch.empty(Bn, dtype=torch.float32, device="cuda")
+        gl = torch.full((Bn,), 1.0 / Bn, dtype=torch.float32, device="cuda")
+        dw = torch.empty_like(om); da = torch.empty_like(om); dp = torch.empty_like(params)
+        opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=K, ckpt_every=16)
+        def step():
+            rm.rm_meta_forward(ctx, plan, m, params, om, al)
+            x.zero_()
+            rm.rm_solve(ctx, plan, rm.RM_NAG, opts, om, al, b32, x, ckpt=ck)
+            rm.rm_residual(ctx, plan, b32, x, rel2=loss)
+            rm.rm_solve_adjoint(ctx, plan, rm.RM_NAG, opts, om, al, b32, ck, dw, da, g_loss=gl)
+            rm.rm_meta_backward(ctx, plan, m, params, dw, da, dp)
+        step(); torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(5):
+            step()
+        e1.record(); torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 5e3
+        out.update({"ms_per_training_step": t * 1e3, "glups_fwd_adjoint": 2 * K * P / t / 1e9,
+                    "loss_mean": float(loss.mean())})
+        return out
+    # uneven: unrolled throughput and the refined solve with caps
+    opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=K)
+    rm.rm_solve(ctx, plan, rm.RM_NAG, opts, om, al, b32, x); torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record(); rm.rm_solve(ctx, plan, rm.RM_NAG, opts, om, al, b32, x); e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3
+    out.update({"points": P, "unroll_glups": K * P / t / 1e9, "unroll_us_per_step": t / K * 1e6})
+    b64 = torch.as_tensor(batch.f_packed()).cuda()
+    x64 = torch.zeros_like(b64)
+    o = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=TOL, tol_inner=1e-3, max_outer=20000, max_rounds=10,
+                      check_every=8)
+    t0 = time.perf_counter(); rep = rm.rm_solve(ctx, plan, rm.RM_NAG, o, om, al, b64, x64)
+    tt = time.perf_counter() - t0
+    ns = np.array(batch.n)
+    lups = float(np.sum(rep["outer_iters"].astype(np.float64) * m * ns.astype(np.float64) ** 2))
+    per = {}
+    for n in sorted(set(batch.n)):
+        sel = ns == n
+        per[int(n)] = {"outer_median": float(np.median(rep["outer_iters"][sel])),
+                       "outer_max": int(rep["outer_iters"][sel].max()),
+                       "converged": int(np.sum(rep["inst_status"][sel] == 0)), "count": int(sel.sum()),
+                       "relres_max": float(rep["relres"][sel].max())}
+    out.update({"to_tol_s": tt, "to_tol_glups": lups / tt / 1e9, "status": int(rep["status"]), "per_size": per})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,7 +365,13 @@ def main():
     ap.add_argument("--no-comparator", action="store_true", help="skip the plain FP64 loop comparator")
     ap.add_argument("--kernel-config", default=None,
                     help="variant,T,width of the sweep kernel instead of autotuning (e.g. 3,8,64)")
+    ap.add_argument("--workload", default="aniso", choices=["aniso", "uneven", "train", "single"],
+                    help="aniso (default, the headline line) or one of the secondary shapes")
     args = ap.parse_args()
+    if args.workload != "aniso":
+        print(json.dumps(secondary_workload(args.workload, os.environ.get("RM_TUNE_CACHE", TUNE_CACHE))),
+              flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the batch shards by instance "
                                    "across GPUs by design, but no multi-GPU path is built"}))

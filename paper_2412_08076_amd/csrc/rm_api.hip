@@ -502,8 +502,9 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   std::vector<long long> outer_tot(B, 0);
   std::vector<double> r2_h(B), b2_h(B), relres(B, 0.0), prev_rho(B, 0.0), target2_h(B, 0.0);
   std::vector<int> strikes(B, 0);
-  // stagnation window in outer iterations: at least 256 inner steps
-  const int stall = std::max(16, (256 + o->m - 1) / o->m);
+  // stagnation window in outer iterations: at least 1024 inner steps (slowly
+  // converging large instances gain only a few percent per hundred steps)
+  const int stall = std::max(16, (1024 + o->m - 1) / o->m);
   rmk::launch_fill_i32(status, 0, B, st);
   RM_HIP(hipMemcpyAsync(mask, mask_h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
   int flips_per_outer = 0;
@@ -853,9 +854,11 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   RM_TRY(pl->vecC.ensure(fbytes, st));  // ub1
   RM_TRY(pl->vecD.ensure(fbytes, st));  // vb1
   RM_TRY(pl->vecE.ensure(fbytes, st));  // r_K
-  RM_TRY(pl->partial.ensure(pl->tiles.size() * 2 * sizeof(double), st));
+  const int nslot = (int)pl->tiles.size();
+  RM_TRY(pl->partial.ensure((size_t)nslot * 2 * sizeof(double) * E, st));
   RM_TRY(pl->red.ensure((size_t)B * 4 * sizeof(double), st));
   RM_TRY(pl->acc.ensure((size_t)B * m * 2 * sizeof(double), st));
+  if (pl->use_block) RM_TRY(build_exec(pl, st));
   float* S = pl->states.as<float>();  // slot t: (u, v) before step c*E + t, t = 1..E; slot 0 unused
                                       // (the checkpoint itself serves as slot 0)
   float* ubs[2] = {pl->vecA.as<float>(), pl->vecC.as<float>()};
@@ -872,19 +875,35 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
     return t == 0 ? ckpt + (int64_t)c * 2 * P + P : S + (int64_t)t * 2 * P + P;
   };
   // forward recompute of segment c into slots 1..E-1; the last segment also
-  // produces slot E, the final state u_K
-  auto recompute = [&](int c) {
+  // produces slot E, the final state u_K.  The blocked kernels store every
+  // intermediate state of a launch and reproduce the one-step kernel bit for bit.
+  auto recompute = [&](int c) -> rm_status {
     const int steps = c == nseg - 1 ? E : E - 1;
-    for (int t = 0; t < steps; ++t) {
-      float* uo = S + (int64_t)(t + 1) * 2 * P;
-      rmk::launch_step<float>(method, p, p.tiles, p.ntiles, omega, alpha, m, (c * E + t) % m, b, su(c, t), sv(c, t),
-                              uo, uo + P, nullptr, st);
+    if (!pl->use_block) {
+      for (int t = 0; t < steps; ++t) {
+        float* uo = S + (int64_t)(t + 1) * 2 * P;
+        rmk::launch_step<float>(method, p, p.tiles, p.ntiles, omega, alpha, m, (c * E + t) % m, b, su(c, t),
+                                sv(c, t), uo, uo + P, nullptr, st);
+      }
+      return RM_OK;
     }
+    for (auto& cl : pl->classes) {
+      for (int s0 = 0; s0 < steps;) {
+        const int t = std::min(cl.T, steps - s0);
+        float* uo = S + (int64_t)(s0 + t) * 2 * P;
+        if (!rmk::launch_block(cl.shape, t, cl.cw, method, p, cl.tiles.as<rmk::BTile>(), cl.ntiles, omega, alpha, m,
+                               c * E + s0, b, su(c, s0), sv(c, s0), uo, uo + P, nullptr, nullptr, st,
+                               S + (int64_t)(s0 + 1) * 2 * P, 2 * P))
+          return fail(RM_EUNSUPPORTED, "block kernel configuration not built");
+        s0 += t;
+      }
+    }
+    return RM_OK;
   };
   rmk::launch_fill_f64(acc_w, 0.0, (int64_t)B * m * 2, st);
   rmk::launch_fill_f32(vbs[0], 0.f, P, st);
   // terminal values
-  recompute(nseg - 1);
+  RM_TRY(recompute(nseg - 1));
   const float* uK = S + (int64_t)E * 2 * P;
   if (g_uK == nullptr) {
     rmk::launch_residual<float>(p, p.tiles, p.ntiles, b, uK, rK, partial, nullptr, st);
@@ -896,14 +915,14 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   }
   int cur = 0;
   for (int c = nseg - 1; c >= 0; --c) {
-    if (c != nseg - 1) recompute(c);
+    if (c != nseg - 1) RM_TRY(recompute(c));
     for (int t = E - 1; t >= 0; --t) {
       const int i = (c * E + t) % m;
       rmk::launch_adj_step(method, p, omega, alpha, m, i, b, su(c, t), sv(c, t), ubs[cur], vbs[cur],
-                           ubs[cur ^ 1], vbs[cur ^ 1], d_b, partial, st);
-      rmk::launch_adj_accumulate(p, partial, m, i, acc_w, acc_a, st);
+                           ubs[cur ^ 1], vbs[cur ^ 1], d_b, partial + (size_t)t * 2 * nslot, st);
       cur ^= 1;
     }
+    rmk::launch_adj_accumulate(p, partial, nslot, E, c * E, m, acc_w, acc_a, st);
   }
   rmk::launch_f64_to_f32(acc_w, d_omega, (int64_t)B * m, st);
   rmk::launch_f64_to_f32(acc_a, d_alpha, (int64_t)B * m, st);

@@ -82,12 +82,16 @@ __device__ __forceinline__ void strip_walk(const float* B, int lc, int lr0, F&& 
 // R rows starting at R (t / CW): the extended tile is CW x 8R points.  CW is a
 // run-time multiple of 8 (CW + 2 <= LW); T >= 0 is a run-time step count (T = 0
 // copies the owned points and can still form the residual).
-template <int R, int LW, int WPE, int METHOD>
+// With STORE, the owned (u, v) after every step but the last are also written to
+// states + t * state_stride (u) and + state_stride / 2 (v) for t = 0 .. T - 2 (the
+// adjoint's forward recompute keeps every intermediate state).
+template <int R, int LW, int WPE, int METHOD, bool STORE>
 __global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_per_eu(WPE))) void k_block(
     PlanDev p, const BTile* __restrict__ tiles, int ntiles, int T, int CW, const float* __restrict__ omega,
     const float* __restrict__ alpha, int m, int s0, const float* __restrict__ f, const float* __restrict__ u,
     const float* __restrict__ v, float* __restrict__ u_out, float* __restrict__ v_out,
-    const int* __restrict__ active, double* __restrict__ partial2) {
+    const int* __restrict__ active, double* __restrict__ partial2, float* __restrict__ states,
+    int64_t state_stride) {
   constexpr int NS = 8;
   constexpr int EH = R * NS;
   constexpr int LH = EH + 2;
@@ -157,6 +161,18 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_pe
       ru[k] = ru[k] + vn;
       rv[k] = vn;
     });
+    if (STORE && t + 1 < T && gx >= tl.ox0 && gx < tl.ox1) {
+      float* su = states + (int64_t)t * state_stride + in.off;
+      float* sv = su + state_stride / 2;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int gy = gy0 + k;
+        if (gy >= tl.oy0 && gy < tl.oy1) {
+          su[gy * n + gx] = ru[k];
+          if (METHOD == M_NAG) sv[gy * n + gx] = rv[k];
+        }
+      }
+    }
   }
   const bool colown = gx >= tl.ox0 && gx < tl.ox1;
   double r2 = 0.0;
@@ -206,14 +222,18 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_pe
 template <int R, int LW, int WPE>
 void launch_variant(int T, int cw, int method, const PlanDev& p, const BTile* tiles, int ntiles, const float* omega,
                     const float* alpha, int m, int s0, const float* f, const float* u, const float* v, float* u_out,
-                    float* v_out, const int* active, double* partial2, hipStream_t st) {
+                    float* v_out, const int* active, double* partial2, float* states, int64_t state_stride,
+                    hipStream_t st) {
   const dim3 grid(ntiles), block(8 * cw);
-  if (method == M_NAG)
-    hipLaunchKernelGGL((k_block<R, LW, WPE, M_NAG>), grid, block, 0, st, p, tiles, ntiles, T, cw, omega, alpha, m, s0,
-                       f, u, v, u_out, v_out, active, partial2);
-  else
-    hipLaunchKernelGGL((k_block<R, LW, WPE, M_RICH>), grid, block, 0, st, p, tiles, ntiles, T, cw, omega, alpha, m,
-                       s0, f, u, v, u_out, v_out, active, partial2);
+#define RM_LAUNCH(MM, SS)                                                                                          \
+  hipLaunchKernelGGL((k_block<R, LW, WPE, MM, SS>), grid, block, 0, st, p, tiles, ntiles, T, cw, omega, alpha, m, \
+                     s0, f, u, v, u_out, v_out, active, partial2, states, state_stride)
+  if (method == M_NAG) {
+    if (states != nullptr) RM_LAUNCH(M_NAG, true); else RM_LAUNCH(M_NAG, false);
+  } else {
+    if (states != nullptr) RM_LAUNCH(M_RICH, true); else RM_LAUNCH(M_RICH, false);
+  }
+#undef RM_LAUNCH
 }
 
 }  // namespace
@@ -231,13 +251,13 @@ const BlockVariant kBlockVariants[kNumBlockVariants] = {
 bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, const BTile* tiles, int ntiles,
                   const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,
                   const float* v, float* u_out, float* v_out, const int* active, double* partial2,
-                  hipStream_t st) {
+                  hipStream_t st, float* states, int64_t state_stride) {
   if (variant < 0 || variant >= kNumBlockVariants || T < 0) return false;
   if (cw < 8 || cw % 8 != 0 || cw + 2 > kBlockVariants[variant].lw) return false;
 #define RM_VARIANT_CASE(V, R, LW, WPE)                                                                        \
   case V:                                                                                                     \
     launch_variant<R, LW, WPE>(T, cw, method, p, tiles, ntiles, omega, alpha, m, s0, f, u, v, u_out, v_out, \
-                               active, partial2, st);                                                         \
+                               active, partial2, states, state_stride, st);                                   \
     return true;
   // register caps (waves per SIMD) chosen so that two or three workgroups fit on a CU
   switch (variant) {

@@ -86,9 +86,12 @@ void launch_adj_step(int method, const PlanDev& p, const float* omega, const flo
                      int i, const float* f, const float* u, const float* v, const float* ub,
                      const float* vb, float* ub_out, float* vb_out, float* fb, double* partial2,
                      hipStream_t st);
-// acc[b*m + i] += per-instance sums of partial2 (two components to acc_w, acc_a)
-void launch_adj_accumulate(const PlanDev& p, const double* partial2, int m, int i, double* acc_w,
-                           double* acc_a, hipStream_t st);
+// After the reverse steps of one checkpoint segment (steps s = s_first .. s_first + E - 1,
+// whose tile partials sit at partial2 + t * 2 * nslot for t = s - s_first): for t from
+// E - 1 down to 0, acc_w[b*m + (s mod m)] += sum over the instance's tiles of component 0,
+// acc_a likewise with component 1.
+void launch_adj_accumulate(const PlanDev& p, const double* partial2, int nslot, int E, int s_first, int m,
+                           double* acc_w, double* acc_a, hipStream_t st);
 void launch_f64_to_f32(const double* src, float* dst, int64_t count, hipStream_t st);
 // meta network
 void launch_meta_forward(const PlanDev& p, int m, const float* params, float* omega, float* alpha,
@@ -118,9 +121,12 @@ struct BTile {
 // overlap by at least T points at interior edges (T + 1 when partial2 is given,
 // which then receives ||f - A u||^2 of the final u over each tile's owned part).
 // Returns false for an unsupported (variant, cw).
+// With `states` given, the owned state after every step but the last is also stored:
+// u at states + t * state_stride, v at states + t * state_stride + state_stride / 2
+// (t = 0 .. T - 2), offsets as in the packed vectors.
 bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, const BTile* tiles, int ntiles,
                   const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,
                   const float* v, float* u_out, float* v_out, const int* active, double* partial2,
-                  hipStream_t st);
+                  hipStream_t st, float* states = nullptr, int64_t state_stride = 0);
 
 }  // namespace rmk

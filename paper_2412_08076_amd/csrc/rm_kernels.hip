@@ -519,21 +519,25 @@ __global__ __launch_bounds__(WG) void k_adj_step(PlanDev p, const float* __restr
   }
 }
 
-__global__ __launch_bounds__(64) void k_adj_accumulate(PlanDev p, const double* __restrict__ partial2, int m,
-                                                       int i, double* __restrict__ acc_w,
+__global__ __launch_bounds__(64) void k_adj_accumulate(PlanDev p, const double* __restrict__ partial2, int nslot,
+                                                       int E, int s_first, int m, double* __restrict__ acc_w,
                                                        double* __restrict__ acc_a) {
   const int b = blockIdx.x;
   const Inst in = p.inst[b];
-  double s0 = 0.0, s1 = 0.0;
-  for (int t = in.tile_begin + (int)threadIdx.x; t < in.tile_end; t += 64) {
-    s0 += partial2[2 * t];
-    s1 += partial2[2 * t + 1];
-  }
-  s0 = wave_sum(s0);
-  s1 = wave_sum(s1);
-  if (threadIdx.x == 0) {
-    acc_w[b * m + i] += s0;
-    acc_a[b * m + i] += s1;
+  for (int t = E - 1; t >= 0; --t) {
+    const double* q = partial2 + (size_t)t * 2 * nslot;
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = in.tile_begin + (int)threadIdx.x; k < in.tile_end; k += 64) {
+      s0 += q[2 * k];
+      s1 += q[2 * k + 1];
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (threadIdx.x == 0) {
+      const int i = (s_first + t) % m;
+      acc_w[b * m + i] += s0;
+      acc_a[b * m + i] += s1;
+    }
   }
 }
 
@@ -746,9 +750,9 @@ void launch_adj_step(int method, const PlanDev& p, const float* omega, const flo
                        ub, vb, ub_out, vb_out, fb, partial2);
 }
 
-void launch_adj_accumulate(const PlanDev& p, const double* partial2, int m, int i, double* acc_w,
-                           double* acc_a, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_accumulate, dim3(p.B), dim3(64), 0, st, p, partial2, m, i, acc_w, acc_a);
+void launch_adj_accumulate(const PlanDev& p, const double* partial2, int nslot, int E, int s_first, int m,
+                           double* acc_w, double* acc_a, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_accumulate, dim3(p.B), dim3(64), 0, st, p, partial2, nslot, E, s_first, m, acc_w, acc_a);
 }
 
 void launch_meta_forward(const PlanDev& p, int m, const float* params, float* omega, float* alpha,

@@ -447,3 +447,52 @@ def test_config2_full_size_sampled(ctx):
         c = oracle_coef(batch, b)
         got = xh[batch.offsets[b]:batch.offsets[b + 1]].reshape(255, 255)
         assert abs(problem.relres(c, batch.f[b], got) - rep["relres"][b]) <= 1e-12
+
+
+def test_uneven_batch_sampled(ctx):
+    """Mixed sizes from the uneven workload's size set in one plan (one size class each):
+    FP32 NAG unroll against the oracle on one instance of every size."""
+    rm = _rm()
+    ns = [63] * 4 + [127] * 3 + [255] * 2 + [511] + [1023]
+    say("uneven batch", ns)
+    batch = random_batch(ns, seed=91)
+    plan = plan_for(ctx, batch)
+    say("kernels", {n: plan.get_kernel(n) for n in sorted(set(ns))})
+    m, K = 16, 32
+    om, al = _nag_weights(batch, m, seed=7, lo=0.9, hi=1.0, alo=0.9, ahi=0.99)
+    x = torch.zeros(plan.P, dtype=torch.float32, device="cuda")
+    hist = torch.empty(K // m * plan.B, dtype=torch.float64, device="cuda")
+    opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=K)
+    rm.rm_solve(ctx, plan, rm.RM_NAG, opts, dev(om, torch.float32), dev(al, torch.float32),
+                dev(batch.f_packed(), torch.float32), x, hist=hist)
+    xs = unpack_vec(host(x), ns)
+    hs = host(hist).reshape(K // m, plan.B)
+    for b in (0, 4, 7, 9, 10):
+        c = oracle_coef(batch, b)
+        f32 = batch.f[b].astype(np.float32).astype(np.float64)
+        u, _, h = iterate.run(iterate.NAG, c, f32, om[b].astype(np.float64), K, alpha=al[b].astype(np.float64),
+                              history=True)
+        fn = np.linalg.norm(f32)
+        err = np.linalg.norm(problem.apply_A(c, xs[b] - u)) / fn
+        assert err <= 1e-5, (b, ns[b], err)
+        assert np.allclose(np.sqrt(hs[:, b]) / fn, h, rtol=1e-4)
+
+
+def test_uneven_refined_solve(ctx):
+    rm = _rm()
+    ns = [7, 63, 63, 127, 200, 33]
+    say("uneven refined", ns)
+    batch = random_batch(ns, seed=93, eps_range=(1e-2, 1.0))
+    plan = plan_for(ctx, batch)
+    m = 16
+    om, al = _nag_weights(batch, m, seed=8, lo=0.9, hi=1.0, alo=0.95, ahi=0.95)
+    x = torch.zeros(plan.P, dtype=torch.float64, device="cuda")
+    opts = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=1e-10, tol_inner=1e-3, max_outer=20000, max_rounds=10)
+    rep = rm.rm_solve(ctx, plan, rm.RM_NAG, opts, dev(om, torch.float32), dev(al, torch.float32),
+                      dev(batch.f_packed()), x)
+    say("report", rep)
+    assert rep["status"] == rm.RM_OK and np.all(rep["relres"] <= 1e-10)
+    xs = unpack_vec(host(x), ns)
+    for b in range(batch.B):
+        c = oracle_coef(batch, b)
+        assert abs(problem.relres(c, batch.f[b], xs[b]) - rep["relres"][b]) <= 1e-12
