@@ -11,6 +11,7 @@ RM_Q1_ANISO, RM_FD5_HELMHOLTZ = 0, 1
 RM_RICHARDSON, RM_NAG = 0, 1
 RM_F32, RM_F64 = 0, 1
 RM_UNROLL, RM_TO_TOL = 0, 1
+RM_FLAG_GRAPH = 1
 
 # every symbol include/rm.h declares
 EXPORTS = [
@@ -31,6 +32,7 @@ class rm_solve_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("dtype", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("K", ctypes.c_int32), ("ckpt_every", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("tol_inner", ctypes.c_double)]
 
 

@@ -79,6 +79,10 @@ struct rm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   int* host_flag = nullptr;  // pinned, polled by the refined solve
+  // the refined solve runs on a stream of its own (graph capture is not
+  // possible on a legacy default stream) after waiting for `stream`
+  hipStream_t work = nullptr;
+  hipEvent_t handoff = nullptr;
 };
 
 struct rm_plan_s {
@@ -229,7 +233,11 @@ double model_cost(int n, int v, int T, int cw) {
   const double own = (double)n * n;
   const double compute = ext / 1.6e12;
   const double memory = (12.0 * ext + 8.0 * own) / T / 5.0e12;
-  return std::max(compute, memory) + 4e-6 / T / 256.0;
+  // measured on MI355X: widths that are not multiples of 32 make waves straddle
+  // strips (slower LDS and global access), and workgroups wider than 64 columns
+  // fit fewer per CU
+  const double shape_penalty = (cw % 32 != 0 ? 1.3 : 1.0) * (cw > 64 ? 1.15 : 1.0);
+  return std::max(compute, memory) * shape_penalty + 4e-6 / T / 256.0;
 }
 
 // Steps per launch tried by the tuner and the cost model.
@@ -466,9 +474,25 @@ rm_status solve_unroll(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
 // ---------------------------------------------------------------------------
 // FP64 iterative refinement around FP32 inner solves (blocks)
 // ---------------------------------------------------------------------------
+// One captured outer iteration of the inner solve, replayed with hipGraphLaunch.
+struct GraphHolder {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~GraphHolder() {
+    if (exec != nullptr) (void)hipGraphExecDestroy(exec);
+    if (graph != nullptr) (void)hipGraphDestroy(graph);
+  }
+};
+
 rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_opts* o, const float* omega,
                        const float* alpha, const double* b, double* x, rm_report* rep) {
-  hipStream_t st = ctx->stream;
+  if (ctx->work == nullptr) {
+    RM_HIP(hipStreamCreateWithFlags(&ctx->work, hipStreamNonBlocking));
+    RM_HIP(hipEventCreateWithFlags(&ctx->handoff, hipEventDisableTiming));
+  }
+  RM_HIP(hipEventRecord(ctx->handoff, ctx->stream));
+  RM_HIP(hipStreamWaitEvent(ctx->work, ctx->handoff, 0));
+  hipStream_t st = ctx->work;
   const int B = pl->B;
   const size_t fb = vec_bytes<float>(pl);
   RM_TRY(pl->vecA.ensure(fb, st));  // r32
@@ -479,7 +503,7 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   RM_TRY(build_exec(pl, st));
   RM_TRY(pl->partial.ensure(partial_slots(pl) * 2 * sizeof(double), st));
   RM_TRY(pl->red.ensure((size_t)B * 6 * sizeof(double), st));
-  RM_TRY(pl->flags.ensure(((size_t)B * 5 + 16) * sizeof(int), st));
+  RM_TRY(pl->flags.ensure(((size_t)B * 6 + 16) * sizeof(int), st));
   float* r32 = pl->vecA.as<float>();
   float* ds[2] = {pl->vecB.as<float>(), pl->vecD.as<float>()};
   float* vs[2] = {pl->vecC.as<float>(), pl->vecE.as<float>()};
@@ -494,7 +518,8 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   int* status = active + 2 * B;           // [B]
   int* mask = active + 3 * B;             // [B]
   int* since = active + 4 * B;            // [B]  outer iterations since the last 10 % gain
-  int* n_active = active + 5 * B;         // [1]
+  int* gains = active + 5 * B;            // [B]  10 % gains so far in this round
+  int* n_active = active + 6 * B;         // [1]
   double* partial = pl->partial.as<double>();
   const PlanDev p = pl->dev();
 
@@ -502,12 +527,14 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   std::vector<long long> outer_tot(B, 0);
   std::vector<double> r2_h(B), b2_h(B), relres(B, 0.0), prev_rho(B, 0.0), target2_h(B, 0.0);
   std::vector<int> strikes(B, 0);
-  // stagnation window in outer iterations: at least 1024 inner steps (slowly
-  // converging large instances gain only a few percent per hundred steps)
-  const int stall = std::max(16, (1024 + o->m - 1) / o->m);
+  // stagnation window bounds in outer iterations (about 256 and 4096 inner steps)
+  const int stall_min = std::max(16, (256 + o->m - 1) / o->m);
+  const int stall_max = std::max(16, (4096 + o->m - 1) / o->m);
   rmk::launch_fill_i32(status, 0, B, st);
   RM_HIP(hipMemcpyAsync(mask, mask_h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
   int flips_per_outer = 0;
+  GraphHolder graph;
+  bool use_graph = (o->flags & RM_FLAG_GRAPH) != 0;
   for (int j = 0;; ++j) {
     if (j > 0) rmk::launch_refine_update(p, x, ds[0], ds[1], count, flips_per_outer, mask, st);
     rmk::launch_refine_residual(p, b, x, r32, ds[0], vs[0], partial, mask, st);
@@ -557,16 +584,46 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     RM_HIP(hipMemcpyAsync(target2, target2_h.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
     rmk::launch_fill_i32(count, 0, B, st);
     rmk::launch_fill_i32(since, 0, B, st);
+    rmk::launch_fill_i32(gains, 0, B, st);
     int cur = 0;
-    for (int k = 1;; ++k) {
+    // one outer iteration: sweep of m steps with the residual fused into its last
+    // launch, per-instance reduction, convergence bookkeeping
+    auto outer_iteration = [&]() -> rm_status {
       int flips = 0;
       const int* ranges = nullptr;
       RM_TRY(sweep(pl, st, method, o->m, 0, o->m, omega, alpha, r32, ds, vs, cur, flips, active, partial, &ranges));
       flips_per_outer = flips;
       rmk::launch_reduce_partials(p, partial, res2, nullptr, 1, nullptr, st, ranges);
       rmk::launch_fill_i32(n_active, 0, 1, st);
-      rmk::launch_inner_flags(B, res2, rhs2, target2, best2, since, stall, o->max_outer, active, count, status,
-                              n_active, st);
+      rmk::launch_inner_flags(B, res2, rhs2, target2, best2, since, gains, stall_min, stall_max, o->max_outer,
+                              active, count, status, n_active, st);
+      return RM_OK;
+    };
+    // The iteration returns to buffer set 0, so one captured iteration can be
+    // replayed; captured once per call and reused by every round.
+    if (use_graph && graph.exec == nullptr) {
+      const int cur0 = cur;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        const rm_status sc = outer_iteration();
+        const hipError_t ec = hipStreamEndCapture(st, &graph.graph);
+        if (sc != RM_OK || ec != hipSuccess || cur != cur0 ||
+            hipGraphInstantiate(&graph.exec, graph.graph, nullptr, nullptr, 0) != hipSuccess) {
+          if (graph.graph != nullptr) (void)hipGraphDestroy(graph.graph);
+          graph.graph = nullptr;
+          graph.exec = nullptr;
+          use_graph = false;
+        }
+      } else {
+        use_graph = false;
+      }
+      (void)hipGetLastError();
+      cur = cur0;
+    }
+    for (int k = 1;; ++k) {
+      if (use_graph)
+        RM_HIP(hipGraphLaunch(graph.exec, st));
+      else
+        RM_TRY(outer_iteration());
       if (k % o->check_every == 0 || k >= o->max_outer) {
         RM_HIP(hipMemcpyAsync(ctx->host_flag, n_active, sizeof(int), hipMemcpyDeviceToHost, st));
         RM_HIP(hipStreamSynchronize(st));
@@ -656,6 +713,8 @@ rm_status rm_create(rm_ctx** out, int32_t device, void* hip_stream) {
 rm_status rm_destroy(rm_ctx* ctx) {
   if (ctx == nullptr) return RM_OK;
   if (ctx->host_flag != nullptr) (void)hipHostFree(ctx->host_flag);
+  if (ctx->work != nullptr) (void)hipStreamDestroy(ctx->work);
+  if (ctx->handoff != nullptr) (void)hipEventDestroy(ctx->handoff);
   delete ctx;
   return RM_OK;
 }

@@ -73,8 +73,8 @@ void launch_refine_update(const PlanDev& p, double* x, const float* d0, const fl
                           const int* outer_count, int flips, const int* round_mask, hipStream_t st);
 // inner-solve bookkeeping after one outer iteration (one thread per instance)
 void launch_inner_flags(int B, const double* res2, const double* rhs2, const double* target2,
-                        double* best2, int* since, int stall, int cap, int* active, int* outer_count,
-                        int* status, int* n_active, hipStream_t st);
+                        double* best2, int* since, int* gains, int stall_min, int stall_max, int cap,
+                        int* active, int* outer_count, int* status, int* n_active, hipStream_t st);
 void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st);
 void launch_fill_f32(float* p, float value, int64_t count, hipStream_t st);
 void launch_fill_f64(double* p, double value, int64_t count, hipStream_t st);

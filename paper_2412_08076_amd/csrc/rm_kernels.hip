@@ -351,13 +351,18 @@ __global__ __launch_bounds__(WG) void k_refine_update(PlanDev p, double* __restr
 }
 
 // After one outer iteration of an inner solve: stop instances whose residual
-// reached their target (or that hit the cap, stagnated -- no 10 % reduction of
-// the residual within `stall` outer iterations -- or went non-finite / grew
-// beyond 1e6 times the right-hand side), count the rest.
+// reached their target, hit the cap, went non-finite or grew beyond 1e6 times
+// the right-hand side, or stagnated; count the rest.  Stagnation: no 10 %
+// reduction of the best residual for W outer iterations, where W is six times
+// the instance's own average spacing of such reductions so far in this round,
+// clamped to [stall_min, stall_max] (stall_max before the first reduction):
+// an instance at its FP32 floor stops quickly, a slowly converging large one is
+// given time.
 __global__ void k_inner_flags(int B, const double* __restrict__ res2, const double* __restrict__ rhs2,
                               const double* __restrict__ target2, double* __restrict__ best2,
-                              int* __restrict__ since, int stall, int cap, int* __restrict__ active,
-                              int* __restrict__ outer_count, int* __restrict__ status, int* __restrict__ n_active) {
+                              int* __restrict__ since, int* __restrict__ gains, int stall_min, int stall_max,
+                              int cap, int* __restrict__ active, int* __restrict__ outer_count,
+                              int* __restrict__ status, int* __restrict__ n_active) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B || active[b] == 0) return;
   const int cnt = outer_count[b] + 1;
@@ -372,10 +377,13 @@ __global__ void k_inner_flags(int B, const double* __restrict__ res2, const doub
   } else if (r2 < 0.81 * best2[b]) {
     best2[b] = r2;
     since[b] = 0;
-  } else if (since[b] + 1 >= stall) {
-    keep = 0;
+    gains[b] = gains[b] + 1;
   } else {
-    since[b] = since[b] + 1;
+    const int g = gains[b];
+    int w = g == 0 ? stall_max : (6 * cnt) / g;
+    w = w < stall_min ? stall_min : (w > stall_max ? stall_max : w);
+    if (since[b] + 1 >= w) keep = 0;
+    else since[b] = since[b] + 1;
   }
   active[b] = keep;
   if (keep) atomicAdd(n_active, 1);
@@ -714,10 +722,10 @@ void launch_refine_update(const PlanDev& p, double* x, const float* d0, const fl
 }
 
 void launch_inner_flags(int B, const double* res2, const double* rhs2, const double* target2, double* best2,
-                        int* since, int stall, int cap, int* active, int* outer_count, int* status, int* n_active,
-                        hipStream_t st) {
+                        int* since, int* gains, int stall_min, int stall_max, int cap, int* active, int* outer_count,
+                        int* status, int* n_active, hipStream_t st) {
   hipLaunchKernelGGL(k_inner_flags, dim3((B + 255) / 256), dim3(256), 0, st, B, res2, rhs2, target2, best2, since,
-                     stall, cap, active, outer_count, status, n_active);
+                     gains, stall_min, stall_max, cap, active, outer_count, status, n_active);
 }
 
 void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st) {

@@ -166,3 +166,27 @@ def test_adjoint_blocked_recompute_bitwise(ctx):
     for o in outs[1:]:
         for a, b in zip(o, outs[0]):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("ns,m", [([63], 8), ([33, 64, 100, 255], 16), ([40, 41], 3)])
+def test_refined_solve_graph_replays_match_eager(ctx, ns, m):
+    """The refined solve replays one captured outer iteration per step, with its own
+    eager refinement kernels and host polls between replays; every result must equal
+    the run that launches the kernels one by one."""
+    from paper_2412_08076_amd import rm
+    batch = random_batch(ns, seed=29, eps_range=(1e-2, 1.0))
+    om, al = _weights(batch, m, 9)
+    b = dev(batch.f_packed())
+    outs = []
+    for graph in (False, True, True):  # eager reference, then two calls with graph replay
+        plan = plan_for(ctx, batch)
+        x = torch.zeros(plan.P, dtype=torch.float64, device="cuda")
+        opts = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=1e-10, tol_inner=1e-3, max_outer=20000, max_rounds=10,
+                             check_every=3, graph=graph)
+        rep = rm.rm_solve(ctx, plan, rm.RM_NAG, opts, om, al, b, x)
+        say("graph" if graph else "eager", ns, m, rep["outer_iters"], rep["rounds"])
+        assert rep["status"] == rm.RM_OK
+        outs.append((host(x), rep["outer_iters"], rep["rounds"], rep["relres"]))
+    for o in outs[1:]:
+        for a, e in zip(o, outs[0]):
+            assert np.array_equal(a, e)
