@@ -1,15 +1,21 @@
-"""Reverse-mode derivative of a K-step NAG-Richardson(m) unroll, test infrastructure only.
+"""Reverse-mode derivative of a K-step unroll of the Table-1 schemes, test infrastructure only.
 
 Training (§2.2, Algorithm 1, loss L2 of eq. loss-fun-relative-res) back-propagates
 through K inner steps of a Table-1 scheme.  This oracle differentiates the
-NAG-Richardson(m) row literally; Richardson(m) is the case alpha = 0.
+NAGex-Richardson(m) row literally; the other rows are its special cases:
+NAG (look-ahead factor equal to the momentum factor), MOM (no look-ahead) and
+Richardson (no momentum).  An optional weighted-Jacobi preconditioner with a
+constant diagonal (§2.1, eq. momentum-m-Binv with B^{-1} = D^{-1}) multiplies the
+residual by dinv = 1/D.
 
 Forward step s (weight index i = s mod m), from the state (u, v) before the step:
-    u~ = u + alpha_i v;  r_s = f - A u~;  v' = alpha_i v + omega_i r_s;  u' = u + v'.
+    u~ = u + at_i v;  r_s = f - A u~;  v' = a_i v + omega_i dinv r_s;  u' = u + v'.
 Reverse step, given the adjoints (ub, vb) of (u', v') and g = vb + ub:
-    omega_bar_i += <g, r_s>,  rb = omega_i g,  f_bar += rb,  ut_bar = -A rb
+    omega_bar_i += dinv <g, r_s>,  rb = omega_i dinv g,  f_bar += rb,  ut_bar = -A rb
     (A is symmetric, so A^T = A),
-    alpha_bar_i += <g + ut_bar, v>,  ub <- ub + ut_bar,  vb <- alpha_i (g + ut_bar).
+    alpha_bar_i += <g, v>,  alpha_t_bar_i += <ut_bar, v>,
+    ub <- ub + ut_bar,  vb <- a_i g + at_i ut_bar.
+For NAG the two momentum gradients add up: alpha_bar_i = <g + ut_bar, v>.
 Terminal values for the squared relative residual L = ||f - A u_K||^2 / ||f||^2:
     ub_K = -2 A r_K / ||f||^2,  vb_K = 0,  f_bar = 2 r_K / ||f||^2 - 2 L f / ||f||^2.
 A user-supplied seed g_uK replaces ub_K and the f_bar terminal term.
@@ -21,30 +27,51 @@ import numpy as np
 
 from .problem import apply_A
 
+RICHARDSON, MOM, NAG, NAGEX = "richardson", "mom", "nag", "nagex"
 
-def unroll_states(coef, f, omega, alpha, K, u0=None, v0=None):
-    """States (u_s, v_s) for s = 0..K of the NAG-Richardson(m) unroll."""
+
+def _factors(method, alpha, alpha_t, m):
+    z = np.zeros(m)
+    if method == RICHARDSON:
+        return z, z
+    a = np.asarray(alpha, dtype=np.float64)
+    if method == MOM:
+        return a, z
+    if method == NAG:
+        return a, a
+    if method == NAGEX:
+        return a, np.asarray(alpha_t, dtype=np.float64)
+    raise ValueError(method)
+
+
+def unroll_states(coef, f, omega, alpha, K, u0=None, v0=None, method=NAG, alpha_t=None, dinv=1.0):
+    """States (u_s, v_s) for s = 0..K of the unroll."""
     m = len(omega)
+    a, at = _factors(method, alpha, alpha_t, m)
     u = np.zeros_like(f, dtype=np.float64) if u0 is None else np.array(u0, dtype=np.float64)
     v = np.zeros_like(f, dtype=np.float64) if v0 is None else np.array(v0, dtype=np.float64)
     us, vs = [u], [v]
     for s in range(K):
         i = s % m
-        ut = u + alpha[i] * v
+        ut = u + at[i] * v
         r = f - apply_A(coef, ut)
-        v = alpha[i] * v + omega[i] * r
+        v = a[i] * v + omega[i] * dinv * r
         u = u + v
         us.append(u)
         vs.append(v)
     return us, vs
 
 
-def loss_and_grads(coef, f, omega, alpha, K, g_uK=None, u0=None, v0=None):
-    """Returns (L, d_omega[m], d_alpha[m], d_f).  With g_uK given, L is <g_uK, u_K>."""
+def loss_and_grads_general(method, coef, f, omega, K, alpha=None, alpha_t=None, dinv=1.0, g_uK=None):
+    """Returns (L, d_omega[m], d_alpha[m], d_alpha_t[m], d_f).
+
+    With g_uK given, L is <g_uK, u_K>.  d_alpha is the gradient through the momentum
+    term and d_alpha_t through the look-ahead; for NAG the gradient with respect to
+    its single factor is d_alpha + d_alpha_t."""
     omega = np.asarray(omega, dtype=np.float64)
-    alpha = np.asarray(alpha, dtype=np.float64)
     m = len(omega)
-    us, vs = unroll_states(coef, f, omega, alpha, K, u0, v0)
+    a, at = _factors(method, alpha, alpha_t, m)
+    us, vs = unroll_states(coef, f, omega, a, K, method=NAGEX, alpha_t=at, dinv=dinv)
     fn2 = float(np.sum(f * f))
     if g_uK is None:
         rK = f - apply_A(coef, us[K])
@@ -58,16 +85,26 @@ def loss_and_grads(coef, f, omega, alpha, K, g_uK=None, u0=None, v0=None):
     vb = np.zeros_like(f, dtype=np.float64)
     d_omega = np.zeros(m)
     d_alpha = np.zeros(m)
+    d_alpha_t = np.zeros(m)
     for s in range(K, 0, -1):
         i = (s - 1) % m
         u, v = us[s - 1], vs[s - 1]
-        r = f - apply_A(coef, u + alpha[i] * v)
+        r = f - apply_A(coef, u + at[i] * v)
         g = vb + ub
-        d_omega[i] += float(np.sum(g * r))
-        rb = omega[i] * g
+        d_omega[i] += dinv * float(np.sum(g * r))
+        rb = omega[i] * dinv * g
         fb = fb + rb
         ut_bar = -apply_A(coef, rb)
-        d_alpha[i] += float(np.sum((g + ut_bar) * v))
+        d_alpha[i] += float(np.sum(g * v))
+        d_alpha_t[i] += float(np.sum(ut_bar * v))
         ub = ub + ut_bar
-        vb = alpha[i] * (g + ut_bar)
-    return L, d_omega, d_alpha, fb
+        vb = a[i] * g + at[i] * ut_bar
+    return L, d_omega, d_alpha, d_alpha_t, fb
+
+
+def loss_and_grads(coef, f, omega, alpha, K, g_uK=None, u0=None, v0=None):
+    """NAG-Richardson(m): returns (L, d_omega[m], d_alpha[m], d_f)."""
+    if u0 is not None or v0 is not None:
+        raise NotImplementedError("the unroll starts from u = v = 0")
+    L, dw, da, dat, df = loss_and_grads_general(NAG, coef, f, omega, K, alpha=alpha, g_uK=g_uK)
+    return L, dw, da + dat, df

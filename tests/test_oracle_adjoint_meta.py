@@ -140,3 +140,86 @@ def test_meta_head_at_initialisation_is_contractive():
     om, al, _ = meta.forward(params, 16, np.log10(eps), theta, G)
     assert np.all(om * G[:, None] < 1.2) and np.all(om * G[:, None] > 0.8)
     assert np.all(np.abs(al - 0.99) < 0.01)
+
+
+def _torch_unroll_general(coef, f, omega, alpha, alpha_t, K, dinv):
+    """The NAGex recurrence with a Jacobi scale, written with torch.conv2d and autograd."""
+    w = torch.tensor(omega, dtype=torch.float64, requires_grad=True)
+    a = torch.tensor(alpha, dtype=torch.float64, requires_grad=True)
+    at = torch.tensor(alpha_t, dtype=torch.float64, requires_grad=True)
+    ft = torch.tensor(f, dtype=torch.float64, requires_grad=True)
+    c0, cx, cy, cpp, cpm = coef
+    ker = torch.tensor([[cpp, cy, cpm], [cx, c0, cx], [cpm, cy, cpp]], dtype=torch.float64).view(1, 1, 3, 3)
+
+    def A(x):
+        return torch.nn.functional.conv2d(x.view(1, 1, *x.shape), ker, padding=1).view(*x.shape)
+
+    m = len(omega)
+    u = torch.zeros_like(ft)
+    v = torch.zeros_like(ft)
+    for s in range(K):
+        i = s % m
+        r = ft - A(u + at[i] * v)
+        v = a[i] * v + w[i] * dinv * r
+        u = u + v
+    r = ft - A(u)
+    L = (r * r).sum() / (ft * ft).sum()
+    L.backward()
+    return L.item(), w.grad.numpy(), a.grad.numpy(), at.grad.numpy(), ft.grad.numpy()
+
+
+@pytest.mark.parametrize("method", [adjoint.RICHARDSON, adjoint.MOM, adjoint.NAG, adjoint.NAGEX])
+@pytest.mark.parametrize("dinv", [1.0, 0.37])
+def test_general_adjoint_matches_torch_autograd(method, dinv):
+    coef, f, omega, alpha, rng = _setup(seed=4, n=8, m=3)
+    alpha_t = rng.uniform(0.1, 0.9, 3)
+    omega = omega / dinv if dinv != 1.0 else omega
+    K = 12
+    L, dw, da, dat, df = adjoint.loss_and_grads_general(method, coef, f, omega, K, alpha=alpha,
+                                                          alpha_t=alpha_t, dinv=dinv)
+    z = np.zeros(3)
+    a_eff = {adjoint.RICHARDSON: z, adjoint.MOM: alpha, adjoint.NAG: alpha, adjoint.NAGEX: alpha}[method]
+    at_eff = {adjoint.RICHARDSON: z, adjoint.MOM: z, adjoint.NAG: alpha, adjoint.NAGEX: alpha_t}[method]
+    Lt, dwt, dat_, datt, dft = _torch_unroll_general(coef, f, omega, a_eff, at_eff, K, dinv)
+    assert abs(L - Lt) <= 1e-13 * abs(Lt)
+    assert np.allclose(dw, dwt, rtol=1e-10, atol=1e-14)
+    assert np.allclose(df, dft, rtol=1e-10, atol=1e-14)
+    if method == adjoint.NAG:
+        # one factor drives both the momentum and the look-ahead
+        assert np.allclose(da + dat, dat_ + datt, rtol=1e-10, atol=1e-14)
+    elif method != adjoint.RICHARDSON:
+        assert np.allclose(da, dat_, rtol=1e-10, atol=1e-14)
+        if method == adjoint.NAGEX:
+            assert np.allclose(dat, datt, rtol=1e-10, atol=1e-14)
+
+
+def test_general_adjoint_central_differences_nagex():
+    coef, f, omega, alpha, rng = _setup(seed=6, n=7, m=3)
+    alpha_t = rng.uniform(0.1, 0.9, 3)
+    dinv, K, d = 0.5, 9, 1e-6
+    omega = omega / dinv
+
+    def loss(w, a, at):
+        us, _ = adjoint.unroll_states(coef, f, w, a, K, method=adjoint.NAGEX, alpha_t=at, dinv=dinv)
+        r = f - problem.apply_A(coef, us[K])
+        return float(np.sum(r * r) / np.sum(f * f))
+
+    L, dw, da, dat, _ = adjoint.loss_and_grads_general(adjoint.NAGEX, coef, f, omega, K, alpha=alpha,
+                                                        alpha_t=alpha_t, dinv=dinv)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = d
+        for grad, fd in ((dw, (loss(omega + e, alpha, alpha_t) - loss(omega - e, alpha, alpha_t)) / (2 * d)),
+                         (da, (loss(omega, alpha + e, alpha_t) - loss(omega, alpha - e, alpha_t)) / (2 * d)),
+                         (dat, (loss(omega, alpha, alpha_t + e) - loss(omega, alpha, alpha_t - e)) / (2 * d))):
+            assert abs(fd - grad[i]) <= 1e-6 * max(abs(grad[i]), 1e-3 * np.max(np.abs(grad)))
+
+
+def test_oracle_jacobi_unroll_matches_iterate_preconditioner():
+    # the adjoint's forward with dinv equals the Table-1 scheme with B^{-1} = dinv I
+    coef, f, omega, alpha, rng = _setup(seed=8, n=6, m=4)
+    alpha_t = rng.uniform(0.1, 0.9, 4)
+    dinv = 1.0 / coef[0]
+    us, vs = adjoint.unroll_states(coef, f, omega, alpha, 10, method=adjoint.NAGEX, alpha_t=alpha_t, dinv=dinv)
+    u, v = iterate.run(iterate.NAGEX, coef, f, omega, 10, alpha=alpha, alpha_t=alpha_t, binv=lambda r: dinv * r)
+    assert np.allclose(us[10], u, atol=1e-13) and np.allclose(vs[10], v, atol=1e-13)
