@@ -56,8 +56,12 @@ typedef enum {
 
 typedef enum { RM_Q1_ANISO = 0, RM_FD5_HELMHOLTZ = 1 } rm_op;
 
-/* Table 1 of the paper, last column.  RM_RICHARDSON ignores alpha. */
-typedef enum { RM_RICHARDSON = 0, RM_NAG = 1 } rm_method;
+/* Table 1 of the paper, last column.  All four run in the NAGex form
+ *   u~ = u + at_i v;  v' = a_i v + omega_i B^{-1} (f - A u~);  u' = u + v'
+ * with: RM_RICHARDSON a = at = 0 (alpha ignored, may be NULL); RM_NAG at = a;
+ * RM_MOM at = 0; RM_NAGEX a and at independent.  alpha holds a as [B][m]; for
+ * RM_NAGEX it holds [2][B][m]: a, then at. */
+typedef enum { RM_RICHARDSON = 0, RM_NAG = 1, RM_MOM = 2, RM_NAGEX = 3 } rm_method;
 
 typedef enum { RM_F32 = 0, RM_F64 = 1 } rm_dtype;
 
@@ -97,6 +101,13 @@ typedef struct {
  * are identical either way; on ROCm 7.2 / MI355X replay measured 1-20 % slower
  * than direct launches for this loop, so it is off by default. */
 #define RM_FLAG_GRAPH 1
+/* RM_FLAG_JACOBI: weighted-Jacobi preconditioning (§2.1, eq. momentum-m-Binv with
+ * B^{-1} = D^{-1}, D the constant diagonal of the instance's operator): every
+ * omega_i is multiplied by 1/D; a relaxation factor is the caller's scaling of
+ * omega.  Accepted by rm_solve (both modes) and rm_solve_adjoint (which then
+ * returns the gradient with respect to the unscaled omega).  RM_EINVAL if an
+ * instance has a zero diagonal. */
+#define RM_FLAG_JACOBI 2
 
 /* Per-instance results of RM_TO_TOL (host arrays of length B, any may be NULL). */
 typedef struct {
@@ -190,8 +201,8 @@ rm_status rm_residual(rm_ctx* ctx, const rm_plan_t* plan, int32_t dtype, const v
  *   result.  ckpt and hist must be NULL.  rep (host) receives per-instance
  *   counts, final FP64 relative residuals and status; the call returns the
  *   worst per-instance status.
- * omega: device float [B][m]; alpha: device float [B][m] (ignored, may be NULL,
- * for RM_RICHARDSON). */
+ * omega: device float [B][m]; alpha: device float [B][m] ([2][B][m] for RM_NAGEX;
+ * ignored, may be NULL, for RM_RICHARDSON). */
 rm_status rm_solve(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, const rm_solve_opts* opts,
                    const float* omega, const float* alpha, const void* b, void* x, void* ckpt,
                    double* hist, rm_report* rep);
@@ -204,7 +215,9 @@ rm_status rm_solve(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, const rm_
  *   g_uK:  device float [P_tot], the seed dJ/du_K; or NULL for the loss mode
  *          J = sum_b g_loss[b] * ||b - A u_K||^2 / ||b||^2.
  *   g_loss: device float [B] (loss mode only; NULL = all ones).
- *   d_omega, d_alpha: device float [B][m], overwritten with dJ/domega, dJ/dalpha.
+ *   d_omega: device float [B][m]; d_alpha: device float [B][m] ([2][B][m] for
+ *          RM_NAGEX: momentum then look-ahead factor; zeros for RM_RICHARDSON),
+ *          overwritten with dJ/domega, dJ/dalpha.
  *   d_b: device float [P_tot] or NULL, overwritten with dJ/db.
  *   loss: device float [B] or NULL (loss mode: ||b - A u_K||^2 / ||b||^2).
  * Asynchronous.  Dot products are accumulated per tile in FP64 and summed in a

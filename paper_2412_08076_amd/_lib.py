@@ -8,10 +8,11 @@ LIB_PATH = os.path.join(HERE, "librm.so")
 
 RM_OK, RM_EINVAL, RM_ENOMEM, RM_EHIP, RM_ENOTCONV, RM_EDIVERGED, RM_EUNSUPPORTED = range(7)
 RM_Q1_ANISO, RM_FD5_HELMHOLTZ = 0, 1
-RM_RICHARDSON, RM_NAG = 0, 1
+RM_RICHARDSON, RM_NAG, RM_MOM, RM_NAGEX = 0, 1, 2, 3
 RM_F32, RM_F64 = 0, 1
 RM_UNROLL, RM_TO_TOL = 0, 1
 RM_FLAG_GRAPH = 1
+RM_FLAG_JACOBI = 2
 
 # every symbol include/rm.h declares
 EXPORTS = [

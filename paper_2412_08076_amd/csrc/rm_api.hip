@@ -111,6 +111,7 @@ struct rm_plan_s {
   };
   bool use_block = true;
   bool exec_dirty = true;
+  int jacobi = 0;  // set per call from RM_FLAG_JACOBI
   std::vector<ClassExec> classes;
   DevBuf d_ranges;  // int [B][2]: slot range of each instance over all class tables
   int nslots = 0;
@@ -124,6 +125,7 @@ struct rm_plan_s {
     p.coef64 = d_coef64.as<double>();
     p.mu = d_mu.as<float>();
     p.gersh = d_gersh.as<float>();
+    p.jacobi = jacobi;
     return p;
   }
   ~rm_plan_s() {
@@ -656,11 +658,14 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
 rm_status validate_weights(const rm_plan_t* pl, int method, const rm_solve_opts* o, const float* omega,
                            const float* alpha) {
   if (o == nullptr) return fail(RM_EINVAL, "null opts");
-  if (method != RM_RICHARDSON && method != RM_NAG) return fail(RM_EINVAL, "unknown method");
+  if (method < RM_RICHARDSON || method > RM_NAGEX) return fail(RM_EINVAL, "unknown method");
   if (o->m < 1 || o->m > kMaxM) return fail(RM_EINVAL, "m must be in 1..64");
   if (omega == nullptr) return fail(RM_EINVAL, "null omega");
-  if (method == RM_NAG && alpha == nullptr) return fail(RM_EINVAL, "NAG needs alpha");
-  (void)pl;
+  if (method != RM_RICHARDSON && alpha == nullptr) return fail(RM_EINVAL, "this method needs alpha");
+  if (o->flags & ~(RM_FLAG_GRAPH | RM_FLAG_JACOBI)) return fail(RM_EINVAL, "unknown flag");
+  if (o->flags & RM_FLAG_JACOBI)
+    for (int b = 0; b < pl->B; ++b)
+      if (pl->coef[(size_t)b * 8] == 0.0) return fail(RM_EINVAL, "Jacobi needs a non-zero diagonal");
   return RM_OK;
 }
 
@@ -750,6 +755,7 @@ rm_status rm_plan(rm_ctx* ctx, int32_t B, const rm_instance* inst, rm_plan_t** o
     pl->off[b + 1] = pl->off[b] + (int64_t)n * n;
     double* c = &pl->coef[(size_t)b * 8];
     stencil_coefficients(inst[b], c);
+    c[5] = c[0] != 0.0 ? 1.0 / c[0] : 0.0;  // 1/D for weighted-Jacobi preconditioning
     pl->gersh[b] = std::fabs(c[0]) + 2.0 * (std::fabs(c[1]) + std::fabs(c[2]) + std::fabs(c[3]) + std::fabs(c[4]));
     for (int k = 0; k < 8; ++k) coef32[(size_t)b * 8 + k] = (float)c[k];
     g32[b] = (float)pl->gersh[b];
@@ -863,6 +869,7 @@ rm_status rm_solve(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, const rm_
   RM_TRY(validate_weights(plan, method, opts, omega, alpha));
   if (b == nullptr || x == nullptr) return fail(RM_EINVAL, "null b or x");
   rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
+  pl->jacobi = (opts->flags & RM_FLAG_JACOBI) ? 1 : 0;
   const int m = opts->m;
   if (opts->mode == RM_UNROLL) {
     if (opts->K < 0 || opts->K % m != 0) return fail(RM_EINVAL, "K must be a non-negative multiple of m");
@@ -902,10 +909,12 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   if (b == nullptr || ckpt_v == nullptr || d_omega == nullptr || d_alpha == nullptr)
     return fail(RM_EINVAL, "null b, ckpt, d_omega or d_alpha");
   rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
+  pl->jacobi = (opts->flags & RM_FLAG_JACOBI) ? 1 : 0;
   hipStream_t st = ctx->stream;
   const int B = pl->B;
   const int64_t P = pl->P;
   const float* ckpt = static_cast<const float*>(ckpt_v);
+  const int na = method == RM_NAGEX ? 2 : 1;  // momentum gradient blocks of d_alpha
   const size_t fbytes = vec_bytes<float>(pl);
   RM_TRY(pl->states.ensure(fbytes * 2 * (size_t)(E + 1), st));
   RM_TRY(pl->vecA.ensure(fbytes, st));  // ub0
@@ -914,9 +923,9 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   RM_TRY(pl->vecD.ensure(fbytes, st));  // vb1
   RM_TRY(pl->vecE.ensure(fbytes, st));  // r_K
   const int nslot = (int)pl->tiles.size();
-  RM_TRY(pl->partial.ensure((size_t)nslot * 2 * sizeof(double) * E, st));
+  RM_TRY(pl->partial.ensure((size_t)nslot * 4 * sizeof(double) * E, st));
   RM_TRY(pl->red.ensure((size_t)B * 4 * sizeof(double), st));
-  RM_TRY(pl->acc.ensure((size_t)B * m * 2 * sizeof(double), st));
+  RM_TRY(pl->acc.ensure((size_t)B * m * (1 + na) * sizeof(double), st));
   if (pl->use_block) RM_TRY(build_exec(pl, st));
   float* S = pl->states.as<float>();  // slot t: (u, v) before step c*E + t, t = 1..E; slot 0 unused
                                       // (the checkpoint itself serves as slot 0)
@@ -959,7 +968,7 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
     }
     return RM_OK;
   };
-  rmk::launch_fill_f64(acc_w, 0.0, (int64_t)B * m * 2, st);
+  rmk::launch_fill_f64(acc_w, 0.0, (int64_t)B * m * (1 + na), st);
   rmk::launch_fill_f32(vbs[0], 0.f, P, st);
   // terminal values
   RM_TRY(recompute(nseg - 1));
@@ -978,13 +987,13 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
     for (int t = E - 1; t >= 0; --t) {
       const int i = (c * E + t) % m;
       rmk::launch_adj_step(method, p, omega, alpha, m, i, b, su(c, t), sv(c, t), ubs[cur], vbs[cur],
-                           ubs[cur ^ 1], vbs[cur ^ 1], d_b, partial + (size_t)t * 2 * nslot, st);
+                           ubs[cur ^ 1], vbs[cur ^ 1], d_b, partial + (size_t)t * 4 * nslot, st);
       cur ^= 1;
     }
-    rmk::launch_adj_accumulate(p, partial, nslot, E, c * E, m, acc_w, acc_a, st);
+    rmk::launch_adj_accumulate(method, p, partial, nslot, E, c * E, m, acc_w, acc_a, st);
   }
   rmk::launch_f64_to_f32(acc_w, d_omega, (int64_t)B * m, st);
-  rmk::launch_f64_to_f32(acc_a, d_alpha, (int64_t)B * m, st);
+  rmk::launch_f64_to_f32(acc_a, d_alpha, (int64_t)B * m * na, st);
   return last_launch();
 }
 
@@ -1045,10 +1054,11 @@ rm_status rm_plan_get_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, i
 rm_status rm_tune(rm_ctx* ctx, rm_plan_t* plan, int32_t method, int32_t m, const float* omega, const float* alpha,
                   const float* b, const char* cache_path, double* us_per_step) {
   RM_TRY(check_ctx_plan(ctx, plan));
-  if (method != RM_RICHARDSON && method != RM_NAG) return fail(RM_EINVAL, "unknown method");
+  if (method < RM_RICHARDSON || method > RM_NAGEX) return fail(RM_EINVAL, "unknown method");
   if (m < 1 || m > kMaxM) return fail(RM_EINVAL, "m must be in 1..64");
-  if (omega == nullptr || b == nullptr || (method == RM_NAG && alpha == nullptr))
+  if (omega == nullptr || b == nullptr || (method != RM_RICHARDSON && alpha == nullptr))
     return fail(RM_EINVAL, "null omega, alpha or b");
+  plan->jacobi = 0;
   hipStream_t st = ctx->stream;
   hipDeviceProp_t prop;
   RM_HIP(hipGetDeviceProperties(&prop, ctx->device));

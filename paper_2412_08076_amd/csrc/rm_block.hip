@@ -4,9 +4,10 @@
 // holds u, v and f of a vertical strip of R points of column t mod CW in
 // registers (consecutive threads take consecutive columns, so every global
 // access of a wave is a contiguous row segment).  The workgroup runs T
-// consecutive inner steps of Richardson(m) / NAG-Richardson(m) (Table 1) on the
+// consecutive inner steps of a Table-1 scheme (Richardson(m), MOM-, NAG- or
+// NAGex-Richardson(m), optionally with weighted-Jacobi preconditioning) on the
 // whole extended tile without touching HBM in between:
-//   per step: u~ = u + a_i v  ->  LDS
+//   per step: u~ = u + at_i v  ->  LDS
 //             v' = a_i v + w_i (f - A u~) from LDS,  u' = u + v'.
 // The LDS tile has a zero border.  Where a tile edge lies on or beyond the
 // domain boundary that border (and the zeros published by points outside the
@@ -122,7 +123,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_pe
     const bool ok = colin && gy >= 0 && gy < n;
     const int idx = gy * n + gx;
     ru[k] = ok ? ui[idx] : 0.0f;
-    rv[k] = (METHOD == M_NAG && ok) ? vi[idx] : 0.0f;
+    rv[k] = (uses_momentum(METHOD) && ok) ? vi[idx] : 0.0f;
     rf[k] = ok ? fi[idx] : 0.0f;
   }
   // zero border ring for the CW + 2 columns in use
@@ -139,8 +140,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_pe
 #pragma unroll 1
   for (int t = 0; t < T; ++t) {
     const int i = (s0 + t) % m;
-    const float w = omega[tl.inst * m + i];
-    const float a = METHOD == M_NAG ? alpha[tl.inst * m + i] : 0.0f;
+    float w, a, at;
+    step_factors<float, METHOD>(p, omega, alpha, m, tl.inst, i, w, a, at);
     float wc[5];
 #pragma unroll
     for (int j = 0; j < 5; ++j) wc[j] = w * c[j];
@@ -151,7 +152,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_pe
       // registers are never stored
       const int gy = gy0 + k;
       const bool ok = colin && gy >= 0 && gy < n;
-      const float x = METHOD == M_NAG ? fmadd(a, rv[k], ru[k]) : ru[k];
+      const float x = uses_lookahead(METHOD) ? fmadd(at, rv[k], ru[k]) : ru[k];
       mine[k * LW] = ok ? x : 0.0f;
     }
     __syncthreads();
@@ -169,7 +170,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_pe
         const int gy = gy0 + k;
         if (gy >= tl.oy0 && gy < tl.oy1) {
           su[gy * n + gx] = ru[k];
-          if (METHOD == M_NAG) sv[gy * n + gx] = rv[k];
+          if (uses_momentum(METHOD)) sv[gy * n + gx] = rv[k];
         }
       }
     }
@@ -200,7 +201,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_pe
     if (colown && gy >= tl.oy0 && gy < tl.oy1) {
       const int64_t idx = in.off + (int64_t)gy * n + gx;
       u_out[idx] = ru[k];
-      if (METHOD == M_NAG) v_out[idx] = rv[k];
+      if (uses_momentum(METHOD)) v_out[idx] = rv[k];
     }
   }
   if (partial2 != nullptr) {
@@ -228,10 +229,12 @@ void launch_variant(int T, int cw, int method, const PlanDev& p, const BTile* ti
 #define RM_LAUNCH(MM, SS)                                                                                          \
   hipLaunchKernelGGL((k_block<R, LW, WPE, MM, SS>), grid, block, 0, st, p, tiles, ntiles, T, cw, omega, alpha, m, \
                      s0, f, u, v, u_out, v_out, active, partial2, states, state_stride)
-  if (method == M_NAG) {
-    if (states != nullptr) RM_LAUNCH(M_NAG, true); else RM_LAUNCH(M_NAG, false);
-  } else {
-    if (states != nullptr) RM_LAUNCH(M_RICH, true); else RM_LAUNCH(M_RICH, false);
+  const bool store = states != nullptr;
+  switch (method) {
+    case M_NAG: if (store) RM_LAUNCH(M_NAG, true); else RM_LAUNCH(M_NAG, false); break;
+    case M_MOM: if (store) RM_LAUNCH(M_MOM, true); else RM_LAUNCH(M_MOM, false); break;
+    case M_NAGEX: if (store) RM_LAUNCH(M_NAGEX, true); else RM_LAUNCH(M_NAGEX, false); break;
+    default: if (store) RM_LAUNCH(M_RICH, true); else RM_LAUNCH(M_RICH, false); break;
   }
 #undef RM_LAUNCH
 }

@@ -30,7 +30,10 @@ struct Inst {
   int32_t pad;
 };
 
-enum { M_RICH = 0, M_NAG = 1 };
+// Table-1 schemes (values equal rm_method).
+enum { M_RICH = 0, M_NAG = 1, M_MOM = 2, M_NAGEX = 3 };
+constexpr bool uses_momentum(int method) { return method != M_RICH; }
+constexpr bool uses_lookahead(int method) { return method == M_NAG || method == M_NAGEX; }
 
 // Device-side view of a plan.
 struct PlanDev {
@@ -38,11 +41,24 @@ struct PlanDev {
   int32_t ntiles;       // padded length
   const Inst* inst;     // [B]
   int32_t B;
-  const float* coef32;  // [B][8], slots 0..4 used
-  const double* coef64; // [B][8]
+  const float* coef32;  // [B][8]: slots 0..4 stencil, slot 5 = 1 / centre (Jacobi)
+  const double* coef64; // [B][8], same layout
   const float* mu;      // [B][2]  (log10 eps, theta) or (0, kappa)
   const float* gersh;   // [B]
+  int32_t jacobi;       // 1: weighted-Jacobi preconditioning, omega scaled by 1 / centre
 };
+
+// Per-step factors of a Table-1 scheme for instance b, weight index i: the weight
+// (times 1/D under Jacobi preconditioning), the momentum factor and the look-ahead
+// factor (NAG: the momentum factor; NAGex: the second half of alpha, [2][B][m]).
+template <typename T, int METHOD>
+__device__ __forceinline__ void step_factors(const PlanDev& p, const float* omega, const float* alpha, int m,
+                                             int b, int i, T& w, T& a, T& at) {
+  w = (T)omega[b * m + i];
+  if (p.jacobi) w = w * (sizeof(T) == 4 ? (T)p.coef32[b * 8 + 5] : (T)p.coef64[b * 8 + 5]);
+  a = uses_momentum(METHOD) ? (T)alpha[b * m + i] : T(0);
+  at = METHOD == M_NAG ? a : (METHOD == M_NAGEX ? (T)alpha[(p.B + b) * m + i] : T(0));
+}
 
 // ---- launchers (all asynchronous on `st`) ---------------------------------
 // y = A x                                      (dtype float or double)
@@ -52,7 +68,7 @@ void launch_apply(const PlanDev& p, const Tile* tiles, int ntiles, const T* x, T
 template <typename T>
 void launch_residual(const PlanDev& p, const Tile* tiles, int ntiles, const T* b, const T* x, T* r,
                      double* partial2, const int* active, hipStream_t st);
-// one fused inner step of Richardson(m) (method M_RICH) or NAG-Richardson(m)
+// one fused inner step of a Table-1 scheme (method M_RICH, M_NAG, M_MOM or M_NAGEX)
 template <typename T>
 void launch_step(int method, const PlanDev& p, const Tile* tiles, int ntiles, const float* omega,
                  const float* alpha, int m, int i, const T* f, const T* u, const T* v, T* u_out,
@@ -81,17 +97,20 @@ void launch_fill_f64(double* p, double value, int64_t count, hipStream_t st);
 // adjoint: terminal values of the squared-relative-residual loss
 void launch_adj_terminal(const PlanDev& p, const float* b, const float* rK, const double* r2b2,
                          const float* g_loss, float* ub, float* fb, float* loss, hipStream_t st);
-// adjoint: one reverse step (see rm_solve_adjoint); partial2 gets <g, r_s>, <g + ut_bar, v>
+// adjoint: one reverse step (see rm_solve_adjoint); partial4 gets per tile
+// <g, r_s>, <g, v>, <ut_bar, v> (4 doubles per slot)
 void launch_adj_step(int method, const PlanDev& p, const float* omega, const float* alpha, int m,
                      int i, const float* f, const float* u, const float* v, const float* ub,
-                     const float* vb, float* ub_out, float* vb_out, float* fb, double* partial2,
+                     const float* vb, float* ub_out, float* vb_out, float* fb, double* partial4,
                      hipStream_t st);
 // After the reverse steps of one checkpoint segment (steps s = s_first .. s_first + E - 1,
-// whose tile partials sit at partial2 + t * 2 * nslot for t = s - s_first): for t from
-// E - 1 down to 0, acc_w[b*m + (s mod m)] += sum over the instance's tiles of component 0,
-// acc_a likewise with component 1.
-void launch_adj_accumulate(const PlanDev& p, const double* partial2, int nslot, int E, int s_first, int m,
-                           double* acc_w, double* acc_a, hipStream_t st);
+// whose tile partials sit at partial4 + t * 4 * nslot for t = s - s_first): for t from
+// E - 1 down to 0 and i = s mod m, sum each component over the instance's tiles and add
+// acc_w[b*m + i] += (Jacobi ? 1/D : 1) * <g, r>, the momentum gradient to acc_a
+// (NAG: <g, v> + <ut_bar, v>; MOM, NAGex: <g, v>) and, for NAGex, <ut_bar, v> to
+// acc_a[(B + b)*m + i].
+void launch_adj_accumulate(int method, const PlanDev& p, const double* partial4, int nslot, int E, int s_first,
+                           int m, double* acc_w, double* acc_a, hipStream_t st);
 void launch_f64_to_f32(const double* src, float* dst, int64_t count, hipStream_t st);
 // meta network
 void launch_meta_forward(const PlanDev& p, int m, const float* params, float* omega, float* alpha,

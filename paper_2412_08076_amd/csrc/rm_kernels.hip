@@ -194,9 +194,10 @@ __global__ __launch_bounds__(WG) void k_apply(PlanDev p, const Tile* tiles, cons
 }
 
 // ---------------------------------------------------------------------------
-// One fused inner step (Table 1, last column):
-//   NAG:        u~ = u + a_i v; r = f - A u~; v' = a_i v + w_i r; u' = u + v'
-//   Richardson: r = f - A u;    v' = w_i r;    u' = u + v'
+// One fused inner step of the Table-1 schemes (last column) in NAGex form:
+//   u~ = u + at_i v;  r = f - A u~;  v' = a_i v + w_i r;  u' = u + v'
+// with at = a (NAG), at = 0 (MOM), a = at = 0 (Richardson); under weighted-Jacobi
+// preconditioning w_i carries the factor 1/D of the constant diagonal.
 // ---------------------------------------------------------------------------
 template <typename T, int METHOD>
 __global__ __launch_bounds__(WG) void k_step(PlanDev p, const Tile* tiles, const float* __restrict__ omega,
@@ -212,8 +213,8 @@ __global__ __launch_bounds__(WG) void k_step(PlanDev p, const Tile* tiles, const
   const int n = in.n;
   T c[5];
   load_coef<T>(p, tl.inst, c);
-  const T w = (T)omega[tl.inst * m + i];
-  const T a = METHOD == M_NAG ? (T)alpha[tl.inst * m + i] : T(0);
+  T w, a, at;
+  step_factors<T, METHOD>(p, omega, alpha, m, tl.inst, i, w, a, at);
   const T* ui = u + in.off;
   const T* vi = v + in.off;
   const T* fi = f + in.off;
@@ -226,12 +227,12 @@ __global__ __launch_bounds__(WG) void k_step(PlanDev p, const Tile* tiles, const
     const bool in_ = gx < n && gy < n;
     const int idx = gy * n + gx;
     ru[k] = in_ ? ui[idx] : T(0);
-    rv[k] = (METHOD == M_NAG && in_) ? vi[idx] : T(0);
+    rv[k] = (uses_momentum(METHOD) && in_) ? vi[idx] : T(0);
     rf[k] = in_ ? fi[idx] : T(0);
-    s[(ly + 1) * LDS_W + tx + 1] = METHOD == M_NAG ? fmadd(a, rv[k], ru[k]) : ru[k];
+    s[(ly + 1) * LDS_W + tx + 1] = uses_lookahead(METHOD) ? fmadd(at, rv[k], ru[k]) : ru[k];
   }
-  if (METHOD == M_NAG)
-    stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return fmadd(a, vi[Y * n + X], ui[Y * n + X]); });
+  if (uses_lookahead(METHOD))
+    stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return fmadd(at, vi[Y * n + X], ui[Y * n + X]); });
   else
     stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return ui[Y * n + X]; });
   __syncthreads();
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(WG) void k_step(PlanDev p, const Tile* tiles, const
       const T vn = step_v(wc, w, a, rf[k], rv[k], rc[0], rc[-1], rc[1], rs[0], rn[0], rs[-1], rn[1], rs[1], rn[-1]);
       const int64_t idx = in.off + (int64_t)gy * n + gx;
       u_out[idx] = ru[k] + vn;
-      if (METHOD == M_NAG) v_out[idx] = vn;
+      if (uses_momentum(METHOD)) v_out[idx] = vn;
     }
   }
 }
@@ -449,10 +450,11 @@ __global__ __launch_bounds__(WG) void k_adj_terminal(PlanDev p, const float* __r
   }
 }
 
-// Reverse of one forward step s (weight index i), from the forward state
-// (u, v) = (u_{s-1}, v_{s-1}) and the adjoints (ub, vb) of (u_s, v_s):
-//   g = vb + ub;  r_s = f - A(u + a v);  wbar += <g, r_s>;  rb = w g;  fb += rb;
-//   ut_bar = -A rb;  abar += <g + ut_bar, v>;  ub' = ub + ut_bar;  vb' = a (g + ut_bar).
+// Reverse of one forward step s (weight index i) of the NAGex-form recurrence, from
+// the forward state (u, v) = (u_{s-1}, v_{s-1}) and the adjoints (ub, vb) of
+// (u_s, v_s):  g = vb + ub;  r_s = f - A(u + at v);  rb = w g;  fb += rb;
+// ut_bar = -A rb (A is symmetric);  ub' = ub + ut_bar;  vb' = a g + at ut_bar
+// (NAG: a (g + ut_bar)).  Per tile it leaves <g, r_s>, <g, v> and <ut_bar, v>.
 template <int METHOD>
 __global__ __launch_bounds__(WG) void k_adj_step(PlanDev p, const float* __restrict__ omega,
                                                  const float* __restrict__ alpha, int m, int i,
@@ -460,7 +462,7 @@ __global__ __launch_bounds__(WG) void k_adj_step(PlanDev p, const float* __restr
                                                  const float* __restrict__ v, const float* __restrict__ ub,
                                                  const float* __restrict__ vb, float* __restrict__ ub_out,
                                                  float* __restrict__ vb_out, float* __restrict__ fb,
-                                                 double* __restrict__ partial2) {
+                                                 double* __restrict__ partial4) {
   __shared__ float su[(TY + 2) * LDS_W];
   __shared__ float sg[(TY + 2) * LDS_W];
   __shared__ double sh[NWAVE];
@@ -471,8 +473,8 @@ __global__ __launch_bounds__(WG) void k_adj_step(PlanDev p, const float* __restr
   const int n = in.n;
   float c[5];
   load_coef<float>(p, bi, c);
-  const float w = omega[bi * m + i];
-  const float a = METHOD == M_NAG ? alpha[bi * m + i] : 0.0f;
+  float w, a, at;
+  step_factors<float, METHOD>(p, omega, alpha, m, bi, i, w, a, at);
   const float* ui = u + in.off;
   const float* vi = v + in.off;
   const float* ubi = ub + in.off;
@@ -486,22 +488,23 @@ __global__ __launch_bounds__(WG) void k_adj_step(PlanDev p, const float* __restr
     const bool in_ = gx < n && gy < n;
     const int idx = gy * n + gx;
     const float uu = in_ ? ui[idx] : 0.0f;
-    rv[k] = (METHOD == M_NAG && in_) ? vi[idx] : 0.0f;
+    rv[k] = (uses_momentum(METHOD) && in_) ? vi[idx] : 0.0f;
     rub[k] = in_ ? ubi[idx] : 0.0f;
-    const float vbb = (METHOD == M_NAG && in_) ? vbi[idx] : 0.0f;
+    const float vbb = (uses_momentum(METHOD) && in_) ? vbi[idx] : 0.0f;
     rg[k] = vbb + rub[k];
-    su[(ly + 1) * LDS_W + tx + 1] = METHOD == M_NAG ? fmadd(a, rv[k], uu) : uu;
+    su[(ly + 1) * LDS_W + tx + 1] = uses_lookahead(METHOD) ? fmadd(at, rv[k], uu) : uu;
     sg[(ly + 1) * LDS_W + tx + 1] = rg[k];
   }
-  if (METHOD == M_NAG) {
-    stage_halo(su, tl.x0, tl.y0, n, [&](int X, int Y) { return fmadd(a, vi[Y * n + X], ui[Y * n + X]); });
-    stage_halo(sg, tl.x0, tl.y0, n, [&](int X, int Y) { return vbi[Y * n + X] + ubi[Y * n + X]; });
-  } else {
+  if (uses_lookahead(METHOD))
+    stage_halo(su, tl.x0, tl.y0, n, [&](int X, int Y) { return fmadd(at, vi[Y * n + X], ui[Y * n + X]); });
+  else
     stage_halo(su, tl.x0, tl.y0, n, [&](int X, int Y) { return ui[Y * n + X]; });
+  if (uses_momentum(METHOD))
+    stage_halo(sg, tl.x0, tl.y0, n, [&](int X, int Y) { return vbi[Y * n + X] + ubi[Y * n + X]; });
+  else
     stage_halo(sg, tl.x0, tl.y0, n, [&](int X, int Y) { return ubi[Y * n + X]; });
-  }
   __syncthreads();
-  double pw = 0.0, pa = 0.0;
+  double pw = 0.0, pg = 0.0, pl = 0.0;
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
@@ -510,41 +513,53 @@ __global__ __launch_bounds__(WG) void k_adj_step(PlanDev p, const float* __restr
       const float r = f[idx] - stencil_lds(su, tx + 1, ly + 1, c);
       const float g = rg[k];
       const float utb = -(w * stencil_lds(sg, tx + 1, ly + 1, c));
-      const float gu = g + utb;
       pw += (double)g * (double)r;
-      pa += (double)gu * (double)rv[k];
+      pg += (double)g * (double)rv[k];
+      pl += (double)utb * (double)rv[k];
       ub_out[idx] = rub[k] + utb;
-      if (METHOD == M_NAG) vb_out[idx] = a * gu;
+      if (METHOD == M_NAG) vb_out[idx] = a * (g + utb);
+      if (METHOD == M_MOM) vb_out[idx] = a * g;
+      if (METHOD == M_NAGEX) vb_out[idx] = fmadd(at, utb, a * g);
       if (fb != nullptr) fb[idx] = fmadd(w, g, fb[idx]);
     }
   }
   const double t0 = block_sum(pw, sh);
   __syncthreads();
-  const double t1 = block_sum(pa, sh);
+  const double t1 = block_sum(pg, sh);
+  __syncthreads();
+  const double t2 = block_sum(pl, sh);
   if (threadIdx.x == 0) {
-    partial2[2 * tl.pad + 0] = t0;
-    partial2[2 * tl.pad + 1] = t1;
+    partial4[4 * tl.pad + 0] = t0;
+    partial4[4 * tl.pad + 1] = t1;
+    partial4[4 * tl.pad + 2] = t2;
+    partial4[4 * tl.pad + 3] = 0.0;
   }
 }
 
-__global__ __launch_bounds__(64) void k_adj_accumulate(PlanDev p, const double* __restrict__ partial2, int nslot,
+template <int METHOD>
+__global__ __launch_bounds__(64) void k_adj_accumulate(PlanDev p, const double* __restrict__ partial4, int nslot,
                                                        int E, int s_first, int m, double* __restrict__ acc_w,
                                                        double* __restrict__ acc_a) {
   const int b = blockIdx.x;
   const Inst in = p.inst[b];
+  const double dinv = p.jacobi ? p.coef64[b * 8 + 5] : 1.0;
   for (int t = E - 1; t >= 0; --t) {
-    const double* q = partial2 + (size_t)t * 2 * nslot;
-    double s0 = 0.0, s1 = 0.0;
+    const double* q = partial4 + (size_t)t * 4 * nslot;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int k = in.tile_begin + (int)threadIdx.x; k < in.tile_end; k += 64) {
-      s0 += q[2 * k];
-      s1 += q[2 * k + 1];
+      s0 += q[4 * k];
+      s1 += q[4 * k + 1];
+      s2 += q[4 * k + 2];
     }
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
     if (threadIdx.x == 0) {
       const int i = (s_first + t) % m;
-      acc_w[b * m + i] += s0;
-      acc_a[b * m + i] += s1;
+      acc_w[b * m + i] += dinv * s0;
+      if (METHOD == M_NAG) acc_a[b * m + i] += s1 + s2;
+      if (METHOD == M_MOM || METHOD == M_NAGEX) acc_a[b * m + i] += s1;
+      if (METHOD == M_NAGEX) acc_a[(p.B + b) * m + i] += s2;
     }
   }
 }
@@ -683,12 +698,16 @@ template <typename T>
 void launch_step(int method, const PlanDev& p, const Tile* tiles, int ntiles, const float* omega,
                  const float* alpha, int m, int i, const T* f, const T* u, const T* v, T* u_out, T* v_out,
                  const int* active, hipStream_t st) {
-  if (method == M_NAG)
-    hipLaunchKernelGGL((k_step<T, M_NAG>), dim3(ntiles), dim3(WG), 0, st, p, tiles, omega, alpha, m, i, f, u,
-                       v, u_out, v_out, active);
-  else
-    hipLaunchKernelGGL((k_step<T, M_RICH>), dim3(ntiles), dim3(WG), 0, st, p, tiles, omega, alpha, m, i, f,
-                       u, v, u_out, v_out, active);
+#define RM_STEP(MM)                                                                                           \
+  hipLaunchKernelGGL((k_step<T, MM>), dim3(ntiles), dim3(WG), 0, st, p, tiles, omega, alpha, m, i, f, u, v, \
+                     u_out, v_out, active)
+  switch (method) {
+    case M_NAG: RM_STEP(M_NAG); break;
+    case M_MOM: RM_STEP(M_MOM); break;
+    case M_NAGEX: RM_STEP(M_NAGEX); break;
+    default: RM_STEP(M_RICH); break;
+  }
+#undef RM_STEP
 }
 
 template void launch_apply<float>(const PlanDev&, const Tile*, int, const float*, float*, hipStream_t);
@@ -749,18 +768,30 @@ void launch_adj_terminal(const PlanDev& p, const float* b, const float* rK, cons
 
 void launch_adj_step(int method, const PlanDev& p, const float* omega, const float* alpha, int m, int i,
                      const float* f, const float* u, const float* v, const float* ub, const float* vb,
-                     float* ub_out, float* vb_out, float* fb, double* partial2, hipStream_t st) {
-  if (method == M_NAG)
-    hipLaunchKernelGGL(k_adj_step<M_NAG>, dim3(p.ntiles), dim3(WG), 0, st, p, omega, alpha, m, i, f, u, v, ub,
-                       vb, ub_out, vb_out, fb, partial2);
-  else
-    hipLaunchKernelGGL(k_adj_step<M_RICH>, dim3(p.ntiles), dim3(WG), 0, st, p, omega, alpha, m, i, f, u, v,
-                       ub, vb, ub_out, vb_out, fb, partial2);
+                     float* ub_out, float* vb_out, float* fb, double* partial4, hipStream_t st) {
+#define RM_ADJ(MM)                                                                                                \
+  hipLaunchKernelGGL(k_adj_step<MM>, dim3(p.ntiles), dim3(WG), 0, st, p, omega, alpha, m, i, f, u, v, ub, vb, \
+                     ub_out, vb_out, fb, partial4)
+  switch (method) {
+    case M_NAG: RM_ADJ(M_NAG); break;
+    case M_MOM: RM_ADJ(M_MOM); break;
+    case M_NAGEX: RM_ADJ(M_NAGEX); break;
+    default: RM_ADJ(M_RICH); break;
+  }
+#undef RM_ADJ
 }
 
-void launch_adj_accumulate(const PlanDev& p, const double* partial2, int nslot, int E, int s_first, int m,
-                           double* acc_w, double* acc_a, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_accumulate, dim3(p.B), dim3(64), 0, st, p, partial2, nslot, E, s_first, m, acc_w, acc_a);
+void launch_adj_accumulate(int method, const PlanDev& p, const double* partial4, int nslot, int E, int s_first,
+                           int m, double* acc_w, double* acc_a, hipStream_t st) {
+#define RM_ACC(MM) \
+  hipLaunchKernelGGL(k_adj_accumulate<MM>, dim3(p.B), dim3(64), 0, st, p, partial4, nslot, E, s_first, m, acc_w, acc_a)
+  switch (method) {
+    case M_NAG: RM_ACC(M_NAG); break;
+    case M_MOM: RM_ACC(M_MOM); break;
+    case M_NAGEX: RM_ACC(M_NAGEX); break;
+    default: RM_ACC(M_RICH); break;
+  }
+#undef RM_ACC
 }
 
 void launch_meta_forward(const PlanDev& p, int m, const float* params, float* omega, float* alpha,

@@ -10,13 +10,13 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (RM_EDIVERGED, RM_ENOTCONV, RM_F32, RM_F64, RM_FD5_HELMHOLTZ, RM_NAG, RM_OK,
-                   RM_Q1_ANISO, RM_RICHARDSON, RM_TO_TOL, RM_UNROLL)
+from ._lib import (RM_EDIVERGED, RM_ENOTCONV, RM_F32, RM_F64, RM_FD5_HELMHOLTZ, RM_MOM, RM_NAG, RM_NAGEX,
+                   RM_OK, RM_Q1_ANISO, RM_RICHARDSON, RM_TO_TOL, RM_UNROLL)
 
 __all__ = [
     "RMError", "Context", "Plan", "rm_tune", "rm_apply_A", "rm_residual", "rm_solve", "rm_solve_adjoint",
     "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count", "solve_opts",
-    "RM_Q1_ANISO", "RM_FD5_HELMHOLTZ", "RM_RICHARDSON", "RM_NAG", "RM_F32", "RM_F64",
+    "RM_Q1_ANISO", "RM_FD5_HELMHOLTZ", "RM_RICHARDSON", "RM_NAG", "RM_MOM", "RM_NAGEX", "RM_F32", "RM_F64",
     "RM_UNROLL", "RM_TO_TOL", "RM_OK", "RM_ENOTCONV", "RM_EDIVERGED",
 ]
 
@@ -132,11 +132,11 @@ class Plan:
 
 
 def solve_opts(mode=RM_UNROLL, dtype=RM_F32, m=16, K=0, ckpt_every=0, max_outer=100000, max_rounds=8,
-               check_every=4, tol=1e-10, tol_inner=1e-3, graph=False):
+               check_every=4, tol=1e-10, tol_inner=1e-3, graph=False, jacobi=False):
     o = _lib.rm_solve_opts()
     o.mode, o.dtype, o.m, o.K, o.ckpt_every = mode, dtype, m, K, ckpt_every
     o.max_outer, o.max_rounds, o.check_every = max_outer, max_rounds, check_every
-    o.flags = _lib.RM_FLAG_GRAPH if graph else 0
+    o.flags = (_lib.RM_FLAG_GRAPH if graph else 0) | (_lib.RM_FLAG_JACOBI if jacobi else 0)
     o.reserved = 0
     o.tol, o.tol_inner = tol, tol_inner
     return o
@@ -145,8 +145,9 @@ def solve_opts(mode=RM_UNROLL, dtype=RM_F32, m=16, K=0, ckpt_every=0, max_outer=
 def rm_tune(ctx, plan, method, m, omega, alpha, b, cache_path=None):
     """Autotune every size class of the plan on its data; returns the summed us per step."""
     us = ctypes.c_double()
+    na = 2 if method == RM_NAGEX else 1
     _check(ctx.lib.rm_tune(ctx.handle, plan.handle, method, m, _ptr(omega, torch.float32, plan.B * m, "omega"),
-                           _ptr(alpha, torch.float32, plan.B * m, "alpha") if alpha is not None else None,
+                           _ptr(alpha, torch.float32, na * plan.B * m, "alpha") if alpha is not None else None,
                            _ptr(b, torch.float32, plan.P, "b"),
                            cache_path.encode() if cache_path else None, ctypes.byref(us)), "rm_tune")
     return us.value
@@ -171,8 +172,9 @@ def rm_solve(ctx, plan, method, opts, omega, alpha, b, x, ckpt=None, hist=None):
     """UNROLL: returns None (asynchronous).  TO_TOL: blocks and returns a dict of
     per-instance numpy arrays (outer_iters, rounds, relres, status) plus 'status'."""
     m = opts.m
+    na = 2 if method == RM_NAGEX else 1
     om = _ptr(omega, torch.float32, plan.B * m, "omega")
-    al = _ptr(alpha, torch.float32, plan.B * m, "alpha") if alpha is not None else None
+    al = _ptr(alpha, torch.float32, na * plan.B * m, "alpha") if alpha is not None else None
     if opts.mode == RM_UNROLL:
         vdt = torch.float32 if opts.dtype == RM_F32 else torch.float64
         ck = None
@@ -207,14 +209,15 @@ def rm_solve_adjoint(ctx, plan, method, opts, omega, alpha, b, ckpt, d_omega, d_
                      g_loss=None, d_b=None, loss=None):
     m = opts.m
     P, B = plan.P, plan.B
+    na = 2 if method == RM_NAGEX else 1
     st = ctx.lib.rm_solve_adjoint(
         ctx.handle, plan.handle, method, ctypes.byref(opts),
         _ptr(omega, torch.float32, B * m, "omega"),
-        _ptr(alpha, torch.float32, B * m, "alpha") if alpha is not None else None,
+        _ptr(alpha, torch.float32, na * B * m, "alpha") if alpha is not None else None,
         _ptr(b, torch.float32, P, "b"),
         _ptr(ckpt, torch.float32, (opts.K // opts.ckpt_every) * 2 * P, "ckpt"),
         _ptr(g_uK, torch.float32, P, "g_uK"), _ptr(g_loss, torch.float32, B, "g_loss"),
-        _ptr(d_omega, torch.float32, B * m, "d_omega"), _ptr(d_alpha, torch.float32, B * m, "d_alpha"),
+        _ptr(d_omega, torch.float32, B * m, "d_omega"), _ptr(d_alpha, torch.float32, na * B * m, "d_alpha"),
         _ptr(d_b, torch.float32, P, "d_b"), _ptr(loss, torch.float32, B, "loss"))
     _check(st, "rm_solve_adjoint")
 

@@ -32,27 +32,31 @@ def _weights(batch, m, seed):
     return dev(om, torch.float32), dev(al, torch.float32)
 
 
-def _unroll(ctx, plan, method, om, al, f, m, K, hist=False, ckpt_every=0):
+def _unroll(ctx, plan, method, om, al, f, m, K, hist=False, ckpt_every=0, jacobi=False):
     from paper_2412_08076_amd import rm
     x = torch.zeros(plan.P, dtype=torch.float32, device="cuda")
     h = torch.zeros(K // m * plan.B, dtype=torch.float64, device="cuda") if hist else None
     ck = torch.zeros(K // ckpt_every * 2 * plan.P, dtype=torch.float32, device="cuda") if ckpt_every else None
-    opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=K, ckpt_every=ckpt_every)
+    opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=K, ckpt_every=ckpt_every, jacobi=jacobi)
     rm.rm_solve(ctx, plan, method, opts, om, al, f, x, ckpt=ck, hist=h)
     return host(x), (host(h) if hist else None), (host(ck) if ckpt_every else None)
 
 
-@pytest.mark.parametrize("method_name", ["nag", "richardson"])
-def test_blocked_equals_one_step_bitwise(ctx, method_name):
+@pytest.mark.parametrize("method_name,jacobi", [("nag", False), ("richardson", False), ("mom", True),
+                                                ("nagex", False), ("nagex", True)])
+def test_blocked_equals_one_step_bitwise(ctx, method_name, jacobi):
     from paper_2412_08076_amd import rm
-    method = rm.RM_NAG if method_name == "nag" else rm.RM_RICHARDSON
+    method = {"nag": rm.RM_NAG, "richardson": rm.RM_RICHARDSON, "mom": rm.RM_MOM,
+              "nagex": rm.RM_NAGEX}[method_name]
     batch = random_batch(NS, seed=5)
     plan = plan_for(ctx, batch)
     m, K = 16, 48
     om, al = _weights(batch, m, 1)
+    if method_name == "nagex":
+        al = torch.cat([al, 0.5 * al])
     f = dev(batch.f_packed(), torch.float32)
     plan.set_kernel(-1, 1)
-    ref, ref_h, _ = _unroll(ctx, plan, method, om, al, f, m, K, hist=True)
+    ref, ref_h, _ = _unroll(ctx, plan, method, om, al, f, m, K, hist=True, jacobi=jacobi)
     for shape in range(7):
         for T in (1, 2, 3, 8, 16):
             for cw in (0, 24, 64, 128):
@@ -60,8 +64,8 @@ def test_blocked_equals_one_step_bitwise(ctx, method_name):
                     plan.set_kernel(shape, T, cw=cw)
                 except rm.RMError:
                     continue  # halo T + 1 or width does not fit this variant
-                say("blocked vs one-step", method_name, "variant", shape, "T", T, "cw", cw)
-                got, got_h, _ = _unroll(ctx, plan, method, om, al, f, m, K, hist=True)
+                say("blocked vs one-step", method_name, jacobi, "variant", shape, "T", T, "cw", cw)
+                got, got_h, _ = _unroll(ctx, plan, method, om, al, f, m, K, hist=True, jacobi=jacobi)
                 assert np.array_equal(got, ref), (shape, T, cw, np.max(np.abs(got - ref)))
                 # the per-tile residual sums differ only in summation order
                 assert np.allclose(got_h, ref_h, rtol=1e-12, atol=0), (shape, T, cw)

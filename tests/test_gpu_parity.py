@@ -496,3 +496,126 @@ def test_uneven_refined_solve(ctx):
     for b in range(batch.B):
         c = oracle_coef(batch, b)
         assert abs(problem.relres(c, batch.f[b], xs[b]) - rep["relres"][b]) <= 1e-12
+
+
+SCHEMES = [("mom", False), ("nagex", False), ("mom", True), ("nagex", True), ("nag", True), ("richardson", True)]
+
+
+def _scheme_weights(batch, m, seed, jacobi):
+    """omega scaled so that omega * lambda_max / (jacobi ? D : 1) stays below about 1."""
+    rng = np.random.default_rng(seed)
+    om = np.zeros((batch.B, m))
+    for b in range(batch.B):
+        c = oracle_coef(batch, b)
+        G = problem.gershgorin(c)
+        om[b] = rng.uniform(0.5, 1.0, m) / G * (c[0] if jacobi else 1.0)
+    al = rng.uniform(0.5, 0.9, (batch.B, m))
+    at = rng.uniform(0.2, 0.9, (batch.B, m))
+    return om.astype(np.float32), al.astype(np.float32), at.astype(np.float32)
+
+
+def _meth(rm, name):
+    return {"richardson": rm.RM_RICHARDSON, "nag": rm.RM_NAG, "mom": rm.RM_MOM, "nagex": rm.RM_NAGEX}[name]
+
+
+@pytest.mark.parametrize("name,jacobi", SCHEMES)
+def test_fp32_unroll_all_schemes(ctx, name, jacobi):
+    """MOM- and NAGex-Richardson(m), and weighted-Jacobi preconditioning, against the
+    oracle's Table-1 iterations (B^{-1} = I / D)."""
+    rm = _rm()
+    ns = [5, 63, 65, 130]
+    say("fp32 unroll", name, "jacobi" if jacobi else "")
+    batch = random_batch(ns, seed=101)
+    plan = plan_for(ctx, batch)
+    m, K = 4, 32
+    om, al, at = _scheme_weights(batch, m, 3, jacobi)
+    alpha = np.concatenate([al.ravel(), at.ravel()]) if name == "nagex" else al.ravel()
+    x = torch.zeros(plan.P, dtype=torch.float32, device="cuda")
+    opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=K, jacobi=jacobi)
+    rm.rm_solve(ctx, plan, _meth(rm, name), opts, dev(om, torch.float32), dev(alpha, torch.float32),
+                dev(batch.f_packed(), torch.float32), x)
+    xs = unpack_vec(host(x), ns)
+    for b in range(batch.B):
+        c = oracle_coef(batch, b)
+        f32 = batch.f[b].astype(np.float32).astype(np.float64)
+        binv = (lambda r, d=c[0]: r / d) if jacobi else None
+        kw = dict(alpha=al[b].astype(np.float64), alpha_t=at[b].astype(np.float64))
+        if name == "richardson":
+            kw = {}
+        u, _ = iterate.run(name, c, f32, om[b].astype(np.float64), K, binv=binv, **kw)
+        err = np.linalg.norm(problem.apply_A(c, xs[b] - u)) / np.linalg.norm(f32)
+        assert err <= 1e-5, (name, jacobi, b, err)
+
+
+@pytest.mark.parametrize("name,jacobi", SCHEMES)
+def test_adjoint_all_schemes(ctx, name, jacobi):
+    rm = _rm()
+    ns = [7, 40, 65]
+    say("adjoint", name, "jacobi" if jacobi else "")
+    batch = random_batch(ns, seed=103)
+    plan = plan_for(ctx, batch)
+    m, K, E = 4, 16, 8
+    om, al, at = _scheme_weights(batch, m, 5, jacobi)
+    alpha = np.concatenate([al.ravel(), at.ravel()]) if name == "nagex" else al.ravel()
+    na = 2 if name == "nagex" else 1
+    f32 = batch.f_packed().astype(np.float32)
+    opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=K, ckpt_every=E, jacobi=jacobi)
+    x = torch.zeros(plan.P, dtype=torch.float32, device="cuda")
+    ck = torch.empty(K // E * 2 * plan.P, dtype=torch.float32, device="cuda")
+    omd, ald, fd = dev(om, torch.float32), dev(alpha, torch.float32), dev(f32, torch.float32)
+    meth = _meth(rm, name)
+    rm.rm_solve(ctx, plan, meth, opts, omd, ald, fd, x, ckpt=ck)
+    dw = torch.empty(plan.B * m, dtype=torch.float32, device="cuda")
+    da = torch.empty(na * plan.B * m, dtype=torch.float32, device="cuda")
+    db = torch.empty(plan.P, dtype=torch.float32, device="cuda")
+    loss = torch.empty(plan.B, dtype=torch.float32, device="cuda")
+    rm.rm_solve_adjoint(ctx, plan, meth, opts, omd, ald, fd, ck, dw, da, d_b=db, loss=loss)
+    dwh = host(dw).reshape(plan.B, m)
+    dah = host(da).reshape(na, plan.B, m)
+    dbs = unpack_vec(host(db), ns)
+    fs = unpack_vec(f32.astype(np.float64), ns)
+    for b in range(batch.B):
+        c = oracle_coef(batch, b)
+        dinv = 1.0 / c[0] if jacobi else 1.0
+        L, gw, ga, gat, gf = adjoint.loss_and_grads_general(name, c, fs[b], om[b].astype(np.float64), K,
+                                                            alpha=al[b].astype(np.float64),
+                                                            alpha_t=at[b].astype(np.float64), dinv=dinv)
+        assert abs(host(loss)[b] - L) <= 1e-5 * L
+        assert np.max(np.abs(dwh[b] - gw)) <= 1e-4 * np.max(np.abs(gw))
+        assert np.max(np.abs(dbs[b] - gf)) <= 1e-4 * np.max(np.abs(gf))
+        if name == "nag":
+            want = ga + gat
+        elif name == "richardson":
+            want = np.zeros(m)
+        else:
+            want = ga
+        if name == "richardson":
+            assert np.all(dah[0, b] == 0.0)
+        else:
+            assert np.max(np.abs(dah[0, b] - want)) <= 1e-4 * np.max(np.abs(want))
+        if name == "nagex":
+            assert np.max(np.abs(dah[1, b] - gat)) <= 1e-4 * np.max(np.abs(gat))
+
+
+@pytest.mark.parametrize("name,jacobi", [("mom", True), ("nagex", False)])
+def test_refined_solve_other_schemes(ctx, name, jacobi):
+    rm = _rm()
+    ns = [33, 64]
+    say("refined", name, jacobi)
+    batch = random_batch(ns, seed=107, eps_range=(0.1, 1.0))
+    plan = plan_for(ctx, batch)
+    m = 8
+    om, al, at = _scheme_weights(batch, m, 7, jacobi)
+    al[:] = 0.9
+    at[:] = 0.7
+    alpha = np.concatenate([al.ravel(), at.ravel()]) if name == "nagex" else al.ravel()
+    x = torch.zeros(plan.P, dtype=torch.float64, device="cuda")
+    opts = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=1e-10, max_outer=20000, max_rounds=10, jacobi=jacobi)
+    rep = rm.rm_solve(ctx, plan, _meth(rm, name), opts, dev(om, torch.float32), dev(alpha, torch.float32),
+                      dev(batch.f_packed()), x)
+    say("report", rep)
+    assert rep["status"] == rm.RM_OK
+    xs = unpack_vec(host(x), ns)
+    for b in range(batch.B):
+        assert abs(problem.relres(oracle_coef(batch, b), batch.f[b], xs[b]) - rep["relres"][b]) <= 1e-12
+        assert rep["relres"][b] <= 1e-10
