@@ -62,6 +62,35 @@ def unroll_states(coef, f, omega, alpha, K, u0=None, v0=None, method=NAG, alpha_
     return us, vs
 
 
+def reverse(method, coef, f, omega, us, vs, ub, vb, alpha=None, alpha_t=None, dinv=1.0):
+    """Reverse sweep over a stored unroll (us[0..K], vs[0..K]) from the adjoints (ub, vb)
+    of (u_K, v_K).  Returns (ub_0, vb_0, d_omega, d_alpha, d_alpha_t, f_bar increment)."""
+    omega = np.asarray(omega, dtype=np.float64)
+    m = len(omega)
+    a, at = _factors(method, alpha, alpha_t, m)
+    K = len(us) - 1
+    ub = np.array(ub, dtype=np.float64)
+    vb = np.array(vb, dtype=np.float64)
+    fb = np.zeros_like(ub)
+    d_omega = np.zeros(m)
+    d_alpha = np.zeros(m)
+    d_alpha_t = np.zeros(m)
+    for s in range(K, 0, -1):
+        i = (s - 1) % m
+        u, v = us[s - 1], vs[s - 1]
+        r = f - apply_A(coef, u + at[i] * v)
+        g = vb + ub
+        d_omega[i] += dinv * float(np.sum(g * r))
+        rb = omega[i] * dinv * g
+        fb = fb + rb
+        ut_bar = -apply_A(coef, rb)
+        d_alpha[i] += float(np.sum(g * v))
+        d_alpha_t[i] += float(np.sum(ut_bar * v))
+        ub = ub + ut_bar
+        vb = a[i] * g + at[i] * ut_bar
+    return ub, vb, d_omega, d_alpha, d_alpha_t, fb
+
+
 def loss_and_grads_general(method, coef, f, omega, K, alpha=None, alpha_t=None, dinv=1.0, g_uK=None):
     """Returns (L, d_omega[m], d_alpha[m], d_alpha_t[m], d_f).
 
@@ -83,23 +112,9 @@ def loss_and_grads_general(method, coef, f, omega, K, alpha=None, alpha_t=None, 
         ub = np.array(g_uK, dtype=np.float64)
         fb = np.zeros_like(f, dtype=np.float64)
     vb = np.zeros_like(f, dtype=np.float64)
-    d_omega = np.zeros(m)
-    d_alpha = np.zeros(m)
-    d_alpha_t = np.zeros(m)
-    for s in range(K, 0, -1):
-        i = (s - 1) % m
-        u, v = us[s - 1], vs[s - 1]
-        r = f - apply_A(coef, u + at[i] * v)
-        g = vb + ub
-        d_omega[i] += dinv * float(np.sum(g * r))
-        rb = omega[i] * dinv * g
-        fb = fb + rb
-        ut_bar = -apply_A(coef, rb)
-        d_alpha[i] += float(np.sum(g * v))
-        d_alpha_t[i] += float(np.sum(ut_bar * v))
-        ub = ub + ut_bar
-        vb = a[i] * g + at[i] * ut_bar
-    return L, d_omega, d_alpha, d_alpha_t, fb
+    _, _, d_omega, d_alpha, d_alpha_t, dfb = reverse(NAGEX, coef, f, omega, us, vs, ub, vb, alpha=a,
+                                                     alpha_t=at, dinv=dinv)
+    return L, d_omega, d_alpha, d_alpha_t, fb + dfb
 
 
 def loss_and_grads(coef, f, omega, alpha, K, g_uK=None, u0=None, v0=None):
