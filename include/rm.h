@@ -121,7 +121,9 @@ typedef struct rm_ctx rm_ctx;
 typedef struct rm_plan_s rm_plan_t;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
- * (a hipStream_t; NULL = the default stream).  *out receives the handle. */
+ * (a hipStream_t; NULL = the default stream).  *out receives the handle.
+ * rm_destroy waits for the stream; plans built on the context should be freed
+ * first, and a plan that outlives it accepts only rm_plan_free. */
 rm_status rm_create(rm_ctx** out, int32_t device, void* hip_stream);
 rm_status rm_destroy(rm_ctx* ctx);
 
@@ -227,6 +229,48 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
                            const float* b, const void* ckpt, const float* g_uK,
                            const float* g_loss, float* d_omega, float* d_alpha, float* d_b,
                            float* loss);
+
+/* Two-grid cycle of the Helmholtz multilevel variant (§3: the smoothing
+ * iteration eq. dl-him-b with a Table-1 scheme as smoother, then the spectral
+ * correction eq. dl-him-h on a coarse grid).  One cycle from u_k:
+ *   m inner steps of `method` from (u_k, v = 0) with omega_1 .. omega_m -> u_h;
+ *   u_{k+1} = u_h + P S (symbol * (S R (b - A u_h) S)) S,
+ * R full weighting onto the coarse grid (coarse point (I, J) on fine point
+ * (2I+1, 2J+1), nc = (n - 1) / 2 per direction), P bilinear interpolation
+ * (P = 4 R^T), S the orthonormal DST-I of the coarse grid (S = S^T = S^-1, the
+ * eigenvector basis of every constant-coefficient Dirichlet operator there).
+ * Every instance needs n + 1 a power of two, 8 <= n + 1 <= 1024; otherwise
+ * RM_EUNSUPPORTED.
+ * Coarse fields are packed like fine ones: instance b at coff[b], nc x nc, row
+ * = y.  rm_plan_coarse_points returns their total Pc (-1 if the plan does not
+ * qualify); rm_plan_coarse_offsets fills host coff[B].
+ * symbol: device float [Pc], instance b's block [q][p] multiplies the sine
+ *   coefficient of mode sin(p pi x) sin(q pi y) (p, q = 1..nc, stored at
+ *   [q-1][p-1]).
+ * rm_twogrid_solve (asynchronous): K = opts->K cycles in FP32 (opts->mode
+ *   RM_UNROLL, opts->dtype RM_F32, opts->m smoothing steps per cycle,
+ *   RM_FLAG_JACOBI honoured) from u = x.  b, x: device float [P_tot]; x is
+ *   overwritten with u_K.  ckpt: device float [K][P_tot] or NULL, receives u_k
+ *   at the start of every cycle (the adjoint needs it).  hist: device double
+ *   [K][B] or NULL, receives ||b - A u_{k+1}||^2 after every cycle.
+ * omega, alpha: as for rm_solve. */
+int64_t rm_plan_coarse_points(const rm_plan_t* plan);
+rm_status rm_plan_coarse_offsets(const rm_plan_t* plan, int64_t* coff);
+rm_status rm_twogrid_solve(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
+                           const rm_solve_opts* opts, const float* omega, const float* alpha,
+                           const float* symbol, const float* b, float* x, float* ckpt,
+                           double* hist);
+/* Reverse mode through the K cycles rm_twogrid_solve performed (from any start
+ * x; the start is ckpt slot 0), with the same plan, method, opts, omega, alpha,
+ * symbol and b, and its ckpt (required).  Smoothing states are recomputed per cycle.  g_uK, g_loss,
+ * d_omega, d_alpha, d_b, loss: as for rm_solve_adjoint.  d_symbol: device float
+ * [Pc], overwritten with dJ/dsymbol.  Asynchronous; repeated calls give bitwise
+ * identical results. */
+rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
+                             const rm_solve_opts* opts, const float* omega, const float* alpha,
+                             const float* symbol, const float* b, const float* ckpt,
+                             const float* g_uK, const float* g_loss, float* d_omega,
+                             float* d_alpha, float* d_symbol, float* d_b, float* loss);
 
 /* Meta network (§2.2-2.3).  params: device float [5457 for m = 16; in general
  * 64*2 + 64 + 64*64 + 64 + (m+1)*64 + (m+1)], layout

@@ -19,7 +19,8 @@ EXPORTS = [
     "rm_create", "rm_destroy", "rm_plan", "rm_plan_free", "rm_plan_batch", "rm_plan_points",
     "rm_plan_offsets", "rm_plan_coefficients", "rm_plan_set_kernel", "rm_plan_get_kernel", "rm_tune",
     "rm_apply_A", "rm_residual", "rm_solve",
-    "rm_solve_adjoint", "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count",
+    "rm_solve_adjoint", "rm_plan_coarse_points", "rm_plan_coarse_offsets", "rm_twogrid_solve",
+    "rm_twogrid_adjoint", "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count",
     "rm_status_string", "rm_last_error",
 ]
 
@@ -72,6 +73,11 @@ def load():
         "rm_solve": (st, [P, P, I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P, P,
                           ctypes.POINTER(rm_report)]),
         "rm_solve_adjoint": (st, [P, P, I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P, P, P, P, P, P]),
+        "rm_plan_coarse_points": (I64, [P]),
+        "rm_plan_coarse_offsets": (st, [P, ctypes.POINTER(I64)]),
+        "rm_twogrid_solve": (st, [P, P, I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P, P, P]),
+        "rm_twogrid_adjoint": (st, [P, P, I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P, P, P, P, P, P, P,
+                                    P]),
         "rm_meta_forward": (st, [P, P, I32, P, P, P]),
         "rm_meta_backward": (st, [P, P, I32, P, P, P, P]),
         "rm_meta_param_count": (I32, [I32]),

@@ -83,6 +83,9 @@ struct rm_ctx {
   // possible on a legacy default stream) after waiting for `stream`
   hipStream_t work = nullptr;
   hipEvent_t handoff = nullptr;
+  // plans built on this context; rm_destroy detaches them so that a later
+  // rm_plan_free does not reach the freed context
+  std::vector<rm_plan_s*> plans;
 };
 
 struct rm_plan_s {
@@ -115,6 +118,21 @@ struct rm_plan_s {
   std::vector<ClassExec> classes;
   DevBuf d_ranges;  // int [B][2]: slot range of each instance over all class tables
   int nslots = 0;
+  // two-grid correction: coarse layout, tile and row-group tables, twiddles and
+  // coarse scratch, built on first use
+  struct TwoGrid {
+    bool ready = false;
+    int64_t Pc = 0;
+    std::vector<int64_t> coff;
+    DevBuf d_inst, d_rtiles, d_groups, d_tw, c0, c1, shat, fine2, zero;
+    int nrtiles = 0, ngroups = 0;
+  } tg;
+  rmk::TgDev tgdev() const {
+    rmk::TgDev g;
+    g.inst = tg.d_inst.as<rmk::TgInst>();
+    g.tw = tg.d_tw.as<float2>();
+    return g;
+  }
   PlanDev dev() const {
     PlanDev p;
     p.tiles = d_tiles.as<Tile>();
@@ -130,7 +148,9 @@ struct rm_plan_s {
   }
   ~rm_plan_s() {
     for (DevBuf* b : {&d_tiles, &d_inst, &d_coef32, &d_coef64, &d_mu, &d_gersh, &partial, &red, &flags, &vecA,
-                      &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges})
+                      &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges, &tg.d_inst,
+                      &tg.d_rtiles, &tg.d_groups, &tg.d_tw, &tg.c0, &tg.c1, &tg.shat, &tg.fine2,
+                      &tg.zero})
       b->release();
     for (auto& c : classes) c.tiles.release();
   }
@@ -669,6 +689,114 @@ rm_status validate_weights(const rm_plan_t* pl, int method, const rm_solve_opts*
   return RM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// two-grid cycle (smoothing + sine-transform coarse correction)
+// ---------------------------------------------------------------------------
+rm_status twogrid_layout(rm_plan_t* pl) {
+  auto& tg = pl->tg;
+  if (!tg.coff.empty()) return RM_OK;
+  std::vector<int64_t> coff((size_t)pl->B);
+  int64_t c = 0;
+  for (int b = 0; b < pl->B; ++b) {
+    const int M = pl->inst[b].n + 1;
+    if (M < 8 || M > rmk::kTgMaxFFT || (M & (M - 1)) != 0)
+      return fail(RM_EUNSUPPORTED, "the two-grid cycle needs n + 1 a power of two in 8..1024 (instance " +
+                                       std::to_string(b) + " has n = " + std::to_string(M - 1) + ")");
+    const int nc = (M - 2) / 2;
+    coff[b] = c;
+    c += (int64_t)nc * nc;
+  }
+  tg.coff = std::move(coff);
+  tg.Pc = c;
+  return RM_OK;
+}
+
+rm_status twogrid_setup(rm_plan_t* pl, hipStream_t st) {
+  auto& tg = pl->tg;
+  if (tg.ready) return RM_OK;
+  RM_TRY(twogrid_layout(pl));
+  std::vector<rmk::TgInst> ti((size_t)pl->B);
+  std::vector<Tile> rt, grp;
+  for (int b = 0; b < pl->B; ++b) {
+    const int M = pl->inst[b].n + 1, nc = (M - 2) / 2;
+    int lg = 0;
+    while ((1 << lg) < M) ++lg;
+    ti[b] = rmk::TgInst{tg.coff[b], nc, lg, (float)(1.0 / std::sqrt((double)M)), 0};
+    for (int y = 0; y < nc; y += 8)
+      for (int x = 0; x < nc; x += 64) rt.push_back(Tile{b, x, y, 0});
+    for (int y = 0; y < nc; y += 16) grp.push_back(Tile{b, 0, y, 0});
+  }
+  while (rt.size() % 8 != 0) rt.push_back(Tile{-1, 0, 0, 0});
+  std::vector<float2> tw(rmk::kTgMaxFFT / 2);
+  for (int k = 0; k < rmk::kTgMaxFFT / 2; ++k) {
+    const double a = 2.0 * M_PI * k / rmk::kTgMaxFFT;
+    tw[k] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  }
+  RM_TRY(tg.d_inst.ensure(ti.size() * sizeof(rmk::TgInst), st));
+  RM_TRY(tg.d_rtiles.ensure(rt.size() * sizeof(Tile), st));
+  RM_TRY(tg.d_groups.ensure(grp.size() * sizeof(Tile), st));
+  RM_TRY(tg.d_tw.ensure(tw.size() * sizeof(float2), st));
+  RM_HIP(hipStreamSynchronize(st));
+  RM_HIP(hipMemcpy(tg.d_inst.ptr, ti.data(), ti.size() * sizeof(rmk::TgInst), hipMemcpyHostToDevice));
+  RM_HIP(hipMemcpy(tg.d_rtiles.ptr, rt.data(), rt.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  RM_HIP(hipMemcpy(tg.d_groups.ptr, grp.data(), grp.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  RM_HIP(hipMemcpy(tg.d_tw.ptr, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
+  tg.nrtiles = (int)rt.size();
+  tg.ngroups = (int)grp.size();
+  const size_t cb = (size_t)std::max<int64_t>(tg.Pc, 1) * sizeof(float);
+  RM_TRY(tg.c0.ensure(cb, st));
+  RM_TRY(tg.c1.ensure(cb, st));
+  tg.ready = true;
+  return RM_OK;
+}
+
+// u_out = u_in + P S (symbol * (S R (f - A u_in) S)) S   (u_out may equal u_in)
+void twogrid_correct(rm_plan_t* pl, hipStream_t st, const float* f, const float* u_in, float* u_out,
+                     const float* symbol) {
+  const PlanDev p = pl->dev();
+  const rmk::TgDev g = pl->tgdev();
+  auto& tg = pl->tg;
+  float* c0 = tg.c0.as<float>();
+  float* c1 = tg.c1.as<float>();
+  const Tile* grp = tg.d_groups.as<Tile>();
+  rmk::launch_tg_restrict(0, p, g, tg.d_rtiles.as<Tile>(), tg.nrtiles, f, u_in, c0, 1.f, st);
+  rmk::launch_tg_dst(0, g, grp, tg.ngroups, c0, c1, nullptr, nullptr, nullptr, nullptr, st);
+  rmk::launch_tg_dst(1, g, grp, tg.ngroups, c1, c1, symbol, nullptr, nullptr, nullptr, st);
+  rmk::launch_tg_dst(2, g, grp, tg.ngroups, c1, c0, nullptr, nullptr, nullptr, nullptr, st);
+  rmk::launch_tg_prolong(p, g, c0, u_in, u_out, st);
+}
+
+rm_status twogrid_forward(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_opts* o, const float* omega,
+                          const float* alpha, const float* symbol, const float* b, float* x, float* ckpt,
+                          double* hist) {
+  hipStream_t st = ctx->stream;
+  const int64_t P = pl->P;
+  RM_TRY(twogrid_setup(pl, st));
+  RM_TRY(pl->vecA.ensure(vec_bytes<float>(pl), st));
+  RM_TRY(pl->vecB.ensure(vec_bytes<float>(pl), st));
+  RM_TRY(pl->vecC.ensure(vec_bytes<float>(pl), st));
+  if (pl->use_block) RM_TRY(build_exec(pl, st));
+  RM_TRY(pl->partial.ensure(partial_slots(pl) * 2 * sizeof(double), st));
+  const PlanDev p = pl->dev();
+  float* fu[2] = {x, pl->vecB.as<float>()};
+  float* fv[2] = {pl->vecA.as<float>(), pl->vecC.as<float>()};
+  int cur = 0, flips = 0;
+  for (int k = 0; k < o->K; ++k) {
+    if (ckpt != nullptr)
+      RM_HIP(hipMemcpyAsync(ckpt + (int64_t)k * P, fu[cur], P * sizeof(float), hipMemcpyDeviceToDevice, st));
+    rmk::launch_fill_f32(fv[cur], 0.f, P, st);
+    const int* ranges = nullptr;
+    RM_TRY(sweep(pl, st, method, o->m, 0, o->m, omega, alpha, b, fu, fv, cur, flips, nullptr, nullptr, &ranges));
+    twogrid_correct(pl, st, b, fu[cur], fu[cur], symbol);
+    if (hist != nullptr) {
+      rmk::launch_residual<float>(p, p.tiles, p.ntiles, b, fu[cur], nullptr, pl->partial.as<double>(), nullptr, st);
+      rmk::launch_reduce_partials(p, pl->partial.as<double>(), hist + (int64_t)k * pl->B, nullptr, 1, nullptr, st);
+    }
+  }
+  if (cur == 1) RM_HIP(hipMemcpyAsync(x, fu[1], P * sizeof(float), hipMemcpyDeviceToDevice, st));
+  return last_launch();
+}
+
 }  // namespace
 
 namespace {
@@ -717,6 +845,8 @@ rm_status rm_create(rm_ctx** out, int32_t device, void* hip_stream) {
 
 rm_status rm_destroy(rm_ctx* ctx) {
   if (ctx == nullptr) return RM_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (rm_plan_s* pl : ctx->plans) pl->ctx = nullptr;
   if (ctx->host_flag != nullptr) (void)hipHostFree(ctx->host_flag);
   if (ctx->work != nullptr) (void)hipStreamDestroy(ctx->work);
   if (ctx->handoff != nullptr) (void)hipEventDestroy(ctx->handoff);
@@ -796,13 +926,18 @@ rm_status rm_plan(rm_ctx* ctx, int32_t B, const rm_instance* inst, rm_plan_t** o
     delete pl;
     return s;
   }
+  ctx->plans.push_back(pl);
   *out = pl;
   return RM_OK;
 }
 
 rm_status rm_plan_free(rm_plan_t* plan) {
   if (plan == nullptr) return RM_OK;
-  if (plan->ctx != nullptr) (void)hipStreamSynchronize(plan->ctx->stream);
+  if (plan->ctx != nullptr) {
+    (void)hipStreamSynchronize(plan->ctx->stream);
+    auto& v = plan->ctx->plans;
+    v.erase(std::remove(v.begin(), v.end(), plan), v.end());
+  }
   delete plan;
   return RM_OK;
 }
@@ -991,6 +1126,156 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
       cur ^= 1;
     }
     rmk::launch_adj_accumulate(method, p, partial, nslot, E, c * E, m, acc_w, acc_a, st);
+  }
+  rmk::launch_f64_to_f32(acc_w, d_omega, (int64_t)B * m, st);
+  rmk::launch_f64_to_f32(acc_a, d_alpha, (int64_t)B * m * na, st);
+  return last_launch();
+}
+
+int64_t rm_plan_coarse_points(const rm_plan_t* plan) {
+  if (plan == nullptr) return -1;
+  rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
+  if (twogrid_layout(pl) != RM_OK) return -1;
+  return pl->tg.Pc;
+}
+
+rm_status rm_plan_coarse_offsets(const rm_plan_t* plan, int64_t* coff) {
+  if (plan == nullptr || coff == nullptr) return fail(RM_EINVAL, "null plan or coff");
+  rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
+  RM_TRY(twogrid_layout(pl));
+  std::memcpy(coff, pl->tg.coff.data(), pl->tg.coff.size() * sizeof(int64_t));
+  return RM_OK;
+}
+
+rm_status rm_twogrid_solve(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, const rm_solve_opts* opts,
+                           const float* omega, const float* alpha, const float* symbol, const float* b, float* x,
+                           float* ckpt, double* hist) {
+  RM_TRY(check_ctx_plan(ctx, plan));
+  RM_TRY(validate_weights(plan, method, opts, omega, alpha));
+  if (opts->mode != RM_UNROLL || opts->dtype != RM_F32)
+    return fail(RM_EUNSUPPORTED, "the two-grid cycle runs as an FP32 RM_UNROLL of K cycles");
+  if (opts->K < 0) return fail(RM_EINVAL, "K (cycles) must be >= 0");
+  if (symbol == nullptr || b == nullptr || x == nullptr) return fail(RM_EINVAL, "null symbol, b or x");
+  rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
+  RM_TRY(twogrid_layout(pl));
+  pl->jacobi = (opts->flags & RM_FLAG_JACOBI) ? 1 : 0;
+  return twogrid_forward(ctx, pl, method, opts, omega, alpha, symbol, b, x, ckpt, hist);
+}
+
+rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, const rm_solve_opts* opts,
+                             const float* omega, const float* alpha, const float* symbol, const float* b,
+                             const float* ckpt, const float* g_uK, const float* g_loss, float* d_omega,
+                             float* d_alpha, float* d_symbol, float* d_b, float* loss) {
+  RM_TRY(check_ctx_plan(ctx, plan));
+  RM_TRY(validate_weights(plan, method, opts, omega, alpha));
+  if (opts->mode != RM_UNROLL || opts->dtype != RM_F32)
+    return fail(RM_EUNSUPPORTED, "the two-grid adjoint follows an FP32 RM_UNROLL of K cycles");
+  if (opts->K < 1) return fail(RM_EINVAL, "K (cycles) must be >= 1");
+  if (symbol == nullptr || b == nullptr || ckpt == nullptr || d_omega == nullptr || d_alpha == nullptr ||
+      d_symbol == nullptr)
+    return fail(RM_EINVAL, "null symbol, b, ckpt, d_omega, d_alpha or d_symbol");
+  rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
+  RM_TRY(twogrid_layout(pl));
+  pl->jacobi = (opts->flags & RM_FLAG_JACOBI) ? 1 : 0;
+  hipStream_t st = ctx->stream;
+  RM_TRY(twogrid_setup(pl, st));
+  auto& tg = pl->tg;
+  const int B = pl->B, m = opts->m, K = opts->K;
+  const int64_t P = pl->P;
+  const int na = method == RM_NAGEX ? 2 : 1;
+  const size_t fbytes = vec_bytes<float>(pl);
+  const size_t cbytes = (size_t)std::max<int64_t>(tg.Pc, 1) * sizeof(float);
+  RM_TRY(pl->states.ensure(fbytes * 2 * (size_t)(m + 1), st));
+  RM_TRY(pl->vecA.ensure(fbytes, st));
+  RM_TRY(pl->vecB.ensure(fbytes, st));
+  RM_TRY(pl->vecC.ensure(fbytes, st));
+  RM_TRY(pl->vecD.ensure(fbytes, st));
+  RM_TRY(pl->vecE.ensure(fbytes, st));
+  RM_TRY(tg.fine2.ensure(fbytes, st));
+  RM_TRY(tg.zero.ensure(fbytes, st));
+  RM_TRY(tg.shat.ensure(cbytes, st));
+  const int nslot = (int)pl->tiles.size();
+  RM_TRY(pl->partial.ensure((size_t)nslot * 4 * sizeof(double) * m, st));
+  RM_TRY(pl->red.ensure((size_t)B * 4 * sizeof(double), st));
+  RM_TRY(pl->acc.ensure((size_t)B * m * (1 + na) * sizeof(double), st));
+  if (pl->use_block) RM_TRY(build_exec(pl, st));
+  const PlanDev p = pl->dev();
+  const rmk::TgDev g = pl->tgdev();
+  float* S = pl->states.as<float>();  // slot t = 1..m: (u, v) after t smoothing steps
+  float* ubs[2] = {pl->vecA.as<float>(), pl->vecC.as<float>()};
+  float* vbs[2] = {pl->vecB.as<float>(), pl->vecD.as<float>()};
+  float* rK = pl->vecE.as<float>();
+  float* uK = tg.fine2.as<float>();
+  float* zero = tg.zero.as<float>();
+  float* c0 = tg.c0.as<float>();
+  float* c1 = tg.c1.as<float>();
+  float* shat = tg.shat.as<float>();
+  const Tile* grp = tg.d_groups.as<Tile>();
+  double* partial = pl->partial.as<double>();
+  double* r2b2 = pl->red.as<double>();
+  double* acc_w = pl->acc.as<double>();
+  double* acc_a = acc_w + (size_t)B * m;
+  rmk::launch_fill_f32(zero, 0.f, P, st);
+  rmk::launch_fill_f64(acc_w, 0.0, (int64_t)B * m * (1 + na), st);
+  rmk::launch_fill_f32(d_symbol, 0.f, tg.Pc, st);
+  int cur = 0;
+  for (int k = K - 1; k >= 0; --k) {
+    const float* u0 = ckpt + (int64_t)k * P;
+    auto su = [&](int t) -> const float* { return t == 0 ? u0 : S + (int64_t)t * 2 * P; };
+    auto sv = [&](int t) -> const float* { return t == 0 ? zero : S + (int64_t)t * 2 * P + P; };
+    // recompute the m smoothing states of cycle k
+    if (!pl->use_block) {
+      for (int t = 0; t < m; ++t) {
+        float* uo = S + (int64_t)(t + 1) * 2 * P;
+        rmk::launch_step<float>(method, p, p.tiles, p.ntiles, omega, alpha, m, t, b, su(t), sv(t), uo, uo + P,
+                                nullptr, st);
+      }
+    } else {
+      for (auto& cl : pl->classes) {
+        for (int s0 = 0; s0 < m;) {
+          const int t = std::min(cl.T, m - s0);
+          float* uo = S + (int64_t)(s0 + t) * 2 * P;
+          if (!rmk::launch_block(cl.shape, t, cl.cw, method, p, cl.tiles.as<rmk::BTile>(), cl.ntiles, omega, alpha,
+                                 m, s0, b, su(s0), sv(s0), uo, uo + P, nullptr, nullptr, st,
+                                 S + (int64_t)(s0 + 1) * 2 * P, 2 * P))
+            return fail(RM_EUNSUPPORTED, "block kernel configuration not built");
+          s0 += t;
+        }
+      }
+    }
+    const float* uh = su(m);
+    if (k == K - 1) {
+      // u_K and the terminal adjoint
+      twogrid_correct(pl, st, b, uh, uK, symbol);
+      if (g_uK == nullptr) {
+        rmk::launch_residual<float>(p, p.tiles, p.ntiles, b, uK, rK, partial, nullptr, st);
+        rmk::launch_reduce_partials(p, partial, r2b2, r2b2 + 1, 2, nullptr, st);
+        rmk::launch_adj_terminal(p, b, rK, r2b2, g_loss, ubs[cur], d_b, loss, st);
+      } else {
+        RM_HIP(hipMemcpyAsync(ubs[cur], g_uK, P * sizeof(float), hipMemcpyDeviceToDevice, st));
+        if (d_b != nullptr) rmk::launch_fill_f32(d_b, 0.f, P, st);
+      }
+    }
+    // sine coefficients of the restricted residual at the smoothed iterate
+    rmk::launch_tg_restrict(0, p, g, tg.d_rtiles.as<Tile>(), tg.nrtiles, b, uh, c0, 1.f, st);
+    rmk::launch_tg_dst(0, g, grp, tg.ngroups, c0, c1, nullptr, nullptr, nullptr, nullptr, st);
+    rmk::launch_tg_dst(1, g, grp, tg.ngroups, c1, c1, nullptr, nullptr, shat, nullptr, st);
+    // through the correction: c_bar = P^T ub = 4 R ub, symbol gradient, y_bar = C c_bar,
+    // r_bar = R^T y_bar, f_bar += r_bar, ub_h = ub - A r_bar
+    rmk::launch_tg_restrict(1, p, g, tg.d_rtiles.as<Tile>(), tg.nrtiles, nullptr, ubs[cur], c0, 4.f, st);
+    rmk::launch_tg_dst(0, g, grp, tg.ngroups, c0, c1, nullptr, nullptr, nullptr, nullptr, st);
+    rmk::launch_tg_dst(1, g, grp, tg.ngroups, c1, c1, symbol, shat, nullptr, d_symbol, st);
+    rmk::launch_tg_dst(2, g, grp, tg.ngroups, c1, c0, nullptr, nullptr, nullptr, nullptr, st);
+    rmk::launch_tg_adj_correct(p, g, c0, ubs[cur], ubs[cur ^ 1], d_b, st);
+    cur ^= 1;
+    // through the smoothing, which starts from v = 0 (its adjoint is dropped)
+    rmk::launch_fill_f32(vbs[cur], 0.f, P, st);
+    for (int t = m - 1; t >= 0; --t) {
+      rmk::launch_adj_step(method, p, omega, alpha, m, t, b, su(t), sv(t), ubs[cur], vbs[cur], ubs[cur ^ 1],
+                           vbs[cur ^ 1], d_b, partial + (size_t)t * 4 * nslot, st);
+      cur ^= 1;
+    }
+    rmk::launch_adj_accumulate(method, p, partial, nslot, m, 0, m, acc_w, acc_a, st);
   }
   rmk::launch_f64_to_f32(acc_w, d_omega, (int64_t)B * m, st);
   rmk::launch_f64_to_f32(acc_a, d_alpha, (int64_t)B * m * na, st);

@@ -148,4 +148,41 @@ bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, cons
                   const float* v, float* u_out, float* v_out, const int* active, double* partial2,
                   hipStream_t st, float* states = nullptr, int64_t state_stride = 0);
 
+// ---- two-grid correction (rm_twogrid.hip) -------------------------------------
+// Largest FFT length n + 1 of the coarse sine transform.
+constexpr int kTgMaxFFT = 1024;
+
+// Per-instance coarse layout: packed offset of the nc x nc coarse field, nc,
+// log2(n + 1) and the orthonormal DST scale 1 / sqrt(n + 1).
+struct TgInst {
+  int64_t coff;
+  int32_t nc, lg;
+  float scale;
+  int32_t pad;
+};
+
+struct TgDev {
+  const TgInst* inst;  // [B]
+  const float2* tw;    // [kTgMaxFFT / 2]: exp(-2 pi i k / kTgMaxFFT)
+};
+
+// mode 0: rc = scale * R (f - A u), the residual in FP64;  mode 1: rc = scale * R u.  tiles: 64 x 8 coarse
+// points each (x0, y0 coarse), table length a multiple of 8.
+void launch_tg_restrict(int mode, const PlanDev& p, const TgDev& g, const Tile* tiles, int ntiles, const float* f,
+                        const float* u, float* rc, float scale, hipStream_t st);
+// Sine-transform passes over groups of 16 coarse rows (y0 = first row):
+// pass 0: in[J][I] -> out[p][J];  pass 2: in[p][J] -> out[J][I];
+// pass 1: in[p][J] -> [p][q]; shat_out given: store it and stop; else
+//         dsym[q][p] += coef * shat[p][q] (if dsym), coef *= symbol[q][p] (if symbol),
+//         and transform back -> out[p][J] (out may equal in).
+void launch_tg_dst(int pass, const TgDev& g, const Tile* groups, int ngroups, const float* in, float* out,
+                   const float* symbol, const float* shat, float* shat_out, float* dsym, hipStream_t st);
+// uo = ui + P ec (uo may equal ui), over the plan's fine tile table.
+void launch_tg_prolong(const PlanDev& p, const TgDev& g, const float* ec, const float* ui, float* uo,
+                       hipStream_t st);
+// ub_out = ub - A R^T ybar (R^T = P / 4, stencil summed in FP64) and fb += R^T ybar
+// (fb may be null); ub_out must not alias ub.
+void launch_tg_adj_correct(const PlanDev& p, const TgDev& g, const float* ybar, const float* ub, float* ub_out,
+                           float* fb, hipStream_t st);
+
 }  // namespace rmk

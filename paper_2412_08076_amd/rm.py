@@ -5,6 +5,7 @@ torch CUDA (HIP) tensors for the device pointers.  Shapes, dtypes, devices and
 contiguity are checked here; every computation happens in the HIP kernels.
 """
 import ctypes
+import weakref
 
 import numpy as np
 import torch
@@ -15,6 +16,7 @@ from ._lib import (RM_EDIVERGED, RM_ENOTCONV, RM_F32, RM_F64, RM_FD5_HELMHOLTZ, 
 
 __all__ = [
     "RMError", "Context", "Plan", "rm_tune", "rm_apply_A", "rm_residual", "rm_solve", "rm_solve_adjoint",
+    "rm_twogrid_solve", "rm_twogrid_adjoint",
     "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count", "solve_opts",
     "RM_Q1_ANISO", "RM_FD5_HELMHOLTZ", "RM_RICHARDSON", "RM_NAG", "RM_MOM", "RM_NAGEX", "RM_F32", "RM_F64",
     "RM_UNROLL", "RM_TO_TOL", "RM_OK", "RM_ENOTCONV", "RM_EDIVERGED",
@@ -64,9 +66,13 @@ class Context:
         h = ctypes.c_void_p()
         _check(self.lib.rm_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream)), "rm_create")
         self.handle = h
+        self._plans = weakref.WeakSet()
 
     def close(self):
+        """Free the context's remaining plans, then the context itself."""
         if getattr(self, "handle", None):
+            for plan in list(getattr(self, "_plans", ())):
+                plan.close()
             self.lib.rm_destroy(self.handle)
             self.handle = None
 
@@ -95,6 +101,7 @@ class Plan:
         h = ctypes.c_void_p()
         _check(self.lib.rm_plan(ctx.handle, B, arr, ctypes.byref(h)), "rm_plan")
         self.handle = h
+        ctx._plans.add(self)
         self.B = B
         self.n = [int(k) for k in n]
         self.P = int(self.lib.rm_plan_points(h))
@@ -112,6 +119,16 @@ class Plan:
         _check(self.lib.rm_plan_get_kernel(self.handle, n, ctypes.byref(sh), ctypes.byref(T), ctypes.byref(cw)),
                "rm_plan_get_kernel")
         return sh.value, T.value, cw.value
+
+    def coarse_points(self):
+        """rm_plan_coarse_points: total coarse points of the two-grid cycle (-1 if the
+        plan's sizes do not qualify)."""
+        return int(self.lib.rm_plan_coarse_points(self.handle))
+
+    def coarse_offsets(self):
+        off = (ctypes.c_int64 * self.B)()
+        _check(self.lib.rm_plan_coarse_offsets(self.handle, off), "rm_plan_coarse_offsets")
+        return np.frombuffer(off, dtype=np.int64).copy()
 
     def coefficients(self):
         c = (ctypes.c_double * (5 * self.B))()
@@ -220,6 +237,38 @@ def rm_solve_adjoint(ctx, plan, method, opts, omega, alpha, b, ckpt, d_omega, d_
         _ptr(d_omega, torch.float32, B * m, "d_omega"), _ptr(d_alpha, torch.float32, na * B * m, "d_alpha"),
         _ptr(d_b, torch.float32, P, "d_b"), _ptr(loss, torch.float32, B, "loss"))
     _check(st, "rm_solve_adjoint")
+
+
+def rm_twogrid_solve(ctx, plan, method, opts, omega, alpha, symbol, b, x, ckpt=None, hist=None):
+    """K = opts.K two-grid cycles in FP32 from u = x (asynchronous)."""
+    m, K, P, B = opts.m, opts.K, plan.P, plan.B
+    na = 2 if method == RM_NAGEX else 1
+    Pc = plan.coarse_points()
+    st = ctx.lib.rm_twogrid_solve(
+        ctx.handle, plan.handle, method, ctypes.byref(opts),
+        _ptr(omega, torch.float32, B * m, "omega"),
+        _ptr(alpha, torch.float32, na * B * m, "alpha") if alpha is not None else None,
+        _ptr(symbol, torch.float32, Pc, "symbol"), _ptr(b, torch.float32, P, "b"), _ptr(x, torch.float32, P, "x"),
+        _ptr(ckpt, torch.float32, K * P, "ckpt"), _ptr(hist, torch.float64, K * B, "hist"))
+    _check(st, "rm_twogrid_solve")
+
+
+def rm_twogrid_adjoint(ctx, plan, method, opts, omega, alpha, symbol, b, ckpt, d_omega, d_alpha, d_symbol,
+                       g_uK=None, g_loss=None, d_b=None, loss=None):
+    m, K, P, B = opts.m, opts.K, plan.P, plan.B
+    na = 2 if method == RM_NAGEX else 1
+    Pc = plan.coarse_points()
+    st = ctx.lib.rm_twogrid_adjoint(
+        ctx.handle, plan.handle, method, ctypes.byref(opts),
+        _ptr(omega, torch.float32, B * m, "omega"),
+        _ptr(alpha, torch.float32, na * B * m, "alpha") if alpha is not None else None,
+        _ptr(symbol, torch.float32, Pc, "symbol"), _ptr(b, torch.float32, P, "b"),
+        _ptr(ckpt, torch.float32, K * P, "ckpt"),
+        _ptr(g_uK, torch.float32, P, "g_uK"), _ptr(g_loss, torch.float32, B, "g_loss"),
+        _ptr(d_omega, torch.float32, B * m, "d_omega"), _ptr(d_alpha, torch.float32, na * B * m, "d_alpha"),
+        _ptr(d_symbol, torch.float32, Pc, "d_symbol"), _ptr(d_b, torch.float32, P, "d_b"),
+        _ptr(loss, torch.float32, B, "loss"))
+    _check(st, "rm_twogrid_adjoint")
 
 
 def rm_meta_param_count(m):

@@ -18,7 +18,7 @@ import numpy as np
 
 __all__ = [
     "Batch", "single_isotropic", "aniso_batch", "uneven_batch", "helmholtz_batch",
-    "random_batch", "meta_params", "pack", "unpack_vec", "offsets_of",
+    "random_batch", "meta_params", "pack", "unpack_vec", "offsets_of", "twogrid_symbol",
 ]
 
 META_HIDDEN = 64
@@ -118,6 +118,22 @@ def helmholtz_batch(B=32, n=511, seed=5, sigma_cells=2.0):
         dy2 = (x[:, None] - centres[b, 1]) ** 2
         f.append(np.exp(-(dx2 + dy2) / (2.0 * (sigma_cells * h) ** 2)))
     return Batch([n] * B, kappa=kappa, f=f, op="helmholtz")
+
+
+def twogrid_symbol(kappa, n, seed=None, spread=0.0, reg=1.0):
+    """Coarse symbol [nc][nc] ([q-1][p-1] for mode sin(p pi x) sin(q pi y)) standing in
+    for a learned one: the reciprocal of lam = (4/h^2)(sin^2(p pi h/2) + sin^2(q pi h/2))
+    - kappa^2 (h = 1/(n+1), p, q = 1..nc) taken as lam / (lam^2 + reg^2), times an
+    optional seeded factor U(1 - spread, 1 + spread).  Returned as float64."""
+    nc = (n - 1) // 2
+    h = 1.0 / (n + 1)
+    k = np.arange(1, nc + 1)
+    s = (4.0 / (h * h)) * np.sin(k * np.pi * h / 2.0) ** 2
+    lam = s[:, None] + s[None, :] - float(kappa) ** 2
+    sym = lam / (lam * lam + reg * reg)
+    if spread > 0.0:
+        sym = sym * np.random.default_rng(seed).uniform(1.0 - spread, 1.0 + spread, size=sym.shape)
+    return sym
 
 
 def meta_params(m=16, seed=0, beta0=0.99, last_std=0.01):

@@ -619,3 +619,30 @@ def test_refined_solve_other_schemes(ctx, name, jacobi):
     for b in range(batch.B):
         assert abs(problem.relres(oracle_coef(batch, b), batch.f[b], xs[b]) - rep["relres"][b]) <= 1e-12
         assert rep["relres"][b] <= 1e-10
+
+
+def test_context_destroyed_before_its_plans():
+    """Destroying a context first detaches its plans: freeing them afterwards must not
+    reach the freed context (C level), and the binding closes live plans first."""
+    need_gpu()
+    import ctypes
+    from paper_2412_08076_amd import _lib, rm
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.rm_create(ctypes.byref(h), 0, None) == rm.RM_OK
+    inst = (_lib.rm_instance * 2)()
+    for b, n in enumerate((15, 33)):
+        inst[b].n, inst[b].op, inst[b].eps, inst[b].theta, inst[b].kappa = n, rm.RM_Q1_ANISO, 0.5, 0.3, 0.0
+    plans = []
+    for _ in range(2):
+        p = ctypes.c_void_p()
+        assert lib.rm_plan(h, 2, inst, ctypes.byref(p)) == rm.RM_OK
+        plans.append(p)
+    assert lib.rm_plan_free(plans[0]) == rm.RM_OK
+    assert lib.rm_destroy(h) == rm.RM_OK
+    assert lib.rm_plan_free(plans[1]) == rm.RM_OK
+    ctx = rm.Context(0)
+    plan = rm.Plan(ctx, [15, 33], eps=[0.5, 0.5], theta=[0.3, 0.3])
+    ctx.close()
+    assert plan.handle is None
+    plan.close()
