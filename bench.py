@@ -288,6 +288,8 @@ def secondary_workload(name, tune_cache):
             out[f"to_tol_{tol:g}"] = {"s": time.perf_counter() - t0, "outer": int(rep["outer_iters"][0]),
                                       "rounds": int(rep["rounds"][0]), "relres": float(rep["relres"][0])}
         return out
+    if name == "twogrid":
+        return twogrid_workload(ctx, tune_cache)
     m = 16
     if name == "train":
         batch = aniso_batch(64, 127, seed=3)
@@ -354,6 +356,66 @@ def secondary_workload(name, tune_cache):
     return out
 
 
+def twogrid_workload(ctx, tune_cache, K=4, m=8, reps=5):
+    """Two-grid Helmholtz: 32 problems, n = 511, kappa ~ U(20, 80), Gaussian point
+    sources; K cycles of NAG-Richardson(8) smoothing (Chebyshev weights on the upper
+    quarter of the spectrum, alpha = 0.1) plus the sine-transform coarse correction
+    with a fine-grid spectral symbol; then the adjoint of the K cycles."""
+    import torch
+    from paper_2412_08076_amd import rm
+    from synthetic import helmholtz_batch, smoothing_weights, twogrid_symbol
+    batch = helmholtz_batch(32, 511, seed=5)
+    plan = rm.Plan(ctx, batch.n, kappa=batch.kappa, op=rm.RM_FD5_HELMHOLTZ)
+    P, Bn, Pc = plan.P, plan.B, plan.coarse_points()
+    _, G = plan.coefficients()
+    om = torch.tensor(np.stack([smoothing_weights(G[b], m) for b in range(Bn)]).ravel(), dtype=torch.float32,
+                      device="cuda")
+    al = torch.full((Bn * m,), 0.1, dtype=torch.float32, device="cuda")
+    coff = plan.coarse_offsets()
+    sym = np.zeros(Pc)
+    for b in range(Bn):
+        s_b = twogrid_symbol(batch.kappa[b], batch.n[b])
+        sym[coff[b]:coff[b] + s_b.size] = s_b.ravel()
+    sym = torch.tensor(sym, dtype=torch.float32, device="cuda")
+    b32 = torch.as_tensor(batch.f_packed(), dtype=torch.float32).cuda()
+    us = rm.rm_tune(ctx, plan, rm.RM_NAG, m, om, al, b32, cache_path=tune_cache)
+    x = torch.zeros(P, dtype=torch.float32, device="cuda")
+    ck = torch.empty(K * P, dtype=torch.float32, device="cuda")
+    hist = torch.empty(K * Bn, dtype=torch.float64, device="cuda")
+    dw = torch.empty_like(om); da = torch.empty_like(om); ds = torch.empty_like(sym)
+    db = torch.empty_like(b32); loss = torch.empty(Bn, dtype=torch.float32, device="cuda")
+    opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=K)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def fwd():
+        x.zero_()
+        rm.rm_twogrid_solve(ctx, plan, rm.RM_NAG, opts, om, al, sym, b32, x, ckpt=ck, hist=hist)
+
+    def adj():
+        rm.rm_twogrid_adjoint(ctx, plan, rm.RM_NAG, opts, om, al, sym, b32, ck, dw, da, ds, d_b=db, loss=loss)
+
+    fwd(); adj(); torch.cuda.synchronize()
+    e = [ev() for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        fwd()
+    e[1].record()
+    for _ in range(reps):
+        adj()
+    e[2].record(); torch.cuda.synchronize()
+    tf = e[0].elapsed_time(e[1]) / reps / 1e3
+    ta = e[1].elapsed_time(e[2]) / reps / 1e3
+    b2 = torch.as_tensor(np.array([np.sum(f * f) for f in batch.f])).cuda()
+    rel = (hist.view(K, Bn) / b2).sqrt().cpu().numpy()
+    lups = K * m * P
+    return {"workload": "twogrid", "config": "Helmholtz B=32 n=511 kappa~U(20,80), NAG-Richardson(8) smoothing + "
+            "sine-transform coarse correction on 255^2, K=%d cycles" % K, "kernel": plan.get_kernel(511),
+            "tuned_us_per_step": us, "ms_forward": tf * 1e3, "ms_per_cycle": tf / K * 1e3, "ms_adjoint": ta * 1e3,
+            "glups_forward": lups / tf / 1e9, "glups_fwd_adjoint": 2 * lups / (tf + ta) / 1e9,
+            "relres_median_per_cycle": [float(np.median(r)) for r in rel],
+            "relres_max_after_K": float(rel[-1].max()), "loss_mean": float(loss.mean())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,7 +427,7 @@ def main():
     ap.add_argument("--no-comparator", action="store_true", help="skip the plain FP64 loop comparator")
     ap.add_argument("--kernel-config", default=None,
                     help="variant,T,width of the sweep kernel instead of autotuning (e.g. 3,8,64)")
-    ap.add_argument("--workload", default="aniso", choices=["aniso", "uneven", "train", "single"],
+    ap.add_argument("--workload", default="aniso", choices=["aniso", "uneven", "train", "single", "twogrid"],
                     help="aniso (default, the headline line) or one of the secondary shapes")
     args = ap.parse_args()
     if args.workload != "aniso":

@@ -125,7 +125,7 @@ struct rm_plan_s {
     int64_t Pc = 0;
     std::vector<int64_t> coff;
     DevBuf d_inst, d_rtiles, d_groups, d_tw, c0, c1, shat, fine2, zero;
-    int nrtiles = 0, ngroups = 0;
+    int nrtiles = 0, ngroups = 0, mmax = 0;
   } tg;
   rmk::TgDev tgdev() const {
     rmk::TgDev g;
@@ -724,7 +724,8 @@ rm_status twogrid_setup(rm_plan_t* pl, hipStream_t st) {
     ti[b] = rmk::TgInst{tg.coff[b], nc, lg, (float)(1.0 / std::sqrt((double)M)), 0};
     for (int y = 0; y < nc; y += 8)
       for (int x = 0; x < nc; x += 64) rt.push_back(Tile{b, x, y, 0});
-    for (int y = 0; y < nc; y += 16) grp.push_back(Tile{b, 0, y, 0});
+    for (int y = 0; y < nc; y += 8) grp.push_back(Tile{b, 0, y, 0});
+    tg.mmax = std::max(tg.mmax, M);
   }
   while (rt.size() % 8 != 0) rt.push_back(Tile{-1, 0, 0, 0});
   std::vector<float2> tw(rmk::kTgMaxFFT / 2);
@@ -760,9 +761,9 @@ void twogrid_correct(rm_plan_t* pl, hipStream_t st, const float* f, const float*
   float* c1 = tg.c1.as<float>();
   const Tile* grp = tg.d_groups.as<Tile>();
   rmk::launch_tg_restrict(0, p, g, tg.d_rtiles.as<Tile>(), tg.nrtiles, f, u_in, c0, 1.f, st);
-  rmk::launch_tg_dst(0, g, grp, tg.ngroups, c0, c1, nullptr, nullptr, nullptr, nullptr, st);
-  rmk::launch_tg_dst(1, g, grp, tg.ngroups, c1, c1, symbol, nullptr, nullptr, nullptr, st);
-  rmk::launch_tg_dst(2, g, grp, tg.ngroups, c1, c0, nullptr, nullptr, nullptr, nullptr, st);
+  rmk::launch_tg_dst(0, g, grp, tg.ngroups, tg.mmax, c0, c1, nullptr, nullptr, nullptr, nullptr, st);
+  rmk::launch_tg_dst(1, g, grp, tg.ngroups, tg.mmax, c1, c1, symbol, nullptr, nullptr, nullptr, st);
+  rmk::launch_tg_dst(2, g, grp, tg.ngroups, tg.mmax, c1, c0, nullptr, nullptr, nullptr, nullptr, st);
   rmk::launch_tg_prolong(p, g, c0, u_in, u_out, st);
 }
 
@@ -1258,14 +1259,14 @@ rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
     }
     // sine coefficients of the restricted residual at the smoothed iterate
     rmk::launch_tg_restrict(0, p, g, tg.d_rtiles.as<Tile>(), tg.nrtiles, b, uh, c0, 1.f, st);
-    rmk::launch_tg_dst(0, g, grp, tg.ngroups, c0, c1, nullptr, nullptr, nullptr, nullptr, st);
-    rmk::launch_tg_dst(1, g, grp, tg.ngroups, c1, c1, nullptr, nullptr, shat, nullptr, st);
+    rmk::launch_tg_dst(0, g, grp, tg.ngroups, tg.mmax, c0, c1, nullptr, nullptr, nullptr, nullptr, st);
+    rmk::launch_tg_dst(1, g, grp, tg.ngroups, tg.mmax, c1, c1, nullptr, nullptr, shat, nullptr, st);
     // through the correction: c_bar = P^T ub = 4 R ub, symbol gradient, y_bar = C c_bar,
     // r_bar = R^T y_bar, f_bar += r_bar, ub_h = ub - A r_bar
     rmk::launch_tg_restrict(1, p, g, tg.d_rtiles.as<Tile>(), tg.nrtiles, nullptr, ubs[cur], c0, 4.f, st);
-    rmk::launch_tg_dst(0, g, grp, tg.ngroups, c0, c1, nullptr, nullptr, nullptr, nullptr, st);
-    rmk::launch_tg_dst(1, g, grp, tg.ngroups, c1, c1, symbol, shat, nullptr, d_symbol, st);
-    rmk::launch_tg_dst(2, g, grp, tg.ngroups, c1, c0, nullptr, nullptr, nullptr, nullptr, st);
+    rmk::launch_tg_dst(0, g, grp, tg.ngroups, tg.mmax, c0, c1, nullptr, nullptr, nullptr, nullptr, st);
+    rmk::launch_tg_dst(1, g, grp, tg.ngroups, tg.mmax, c1, c1, symbol, shat, nullptr, d_symbol, st);
+    rmk::launch_tg_dst(2, g, grp, tg.ngroups, tg.mmax, c1, c0, nullptr, nullptr, nullptr, nullptr, st);
     rmk::launch_tg_adj_correct(p, g, c0, ubs[cur], ubs[cur ^ 1], d_b, st);
     cur ^= 1;
     // through the smoothing, which starts from v = 0 (its adjoint is dropped)

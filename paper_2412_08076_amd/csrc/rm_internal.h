@@ -170,12 +170,13 @@ struct TgDev {
 // points each (x0, y0 coarse), table length a multiple of 8.
 void launch_tg_restrict(int mode, const PlanDev& p, const TgDev& g, const Tile* tiles, int ntiles, const float* f,
                         const float* u, float* rc, float scale, hipStream_t st);
-// Sine-transform passes over groups of 16 coarse rows (y0 = first row):
+// Sine-transform passes over groups of 8 coarse rows (y0 = first row); mmax is the
+// largest n + 1 among the instances of the launch (sizes the LDS):
 // pass 0: in[J][I] -> out[p][J];  pass 2: in[p][J] -> out[J][I];
 // pass 1: in[p][J] -> [p][q]; shat_out given: store it and stop; else
 //         dsym[q][p] += coef * shat[p][q] (if dsym), coef *= symbol[q][p] (if symbol),
 //         and transform back -> out[p][J] (out may equal in).
-void launch_tg_dst(int pass, const TgDev& g, const Tile* groups, int ngroups, const float* in, float* out,
+void launch_tg_dst(int pass, const TgDev& g, const Tile* groups, int ngroups, int mmax, const float* in, float* out,
                    const float* symbol, const float* shat, float* shat_out, float* dsym, hipStream_t st);
 // uo = ui + P ec (uo may equal ui), over the plan's fine tile table.
 void launch_tg_prolong(const PlanDev& p, const TgDev& g, const float* ec, const float* ui, float* uo,

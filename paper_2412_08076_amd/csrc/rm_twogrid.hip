@@ -46,14 +46,14 @@ constexpr int RU_W = RR_W + 2, RU_H = RR_H + 2;
 
 // The residual is formed in FP64 from the FP32 iterate: on a smooth, large u the
 // terms of f - A u cancel, and FP32 rounding there would be amplified by the symbol
-// on the low modes (to ~1e-4 relative at n = 255).  Full weighting is summed in FP64
-// and rounded to FP32 once.
+// on the low modes (to ~1e-4 relative at n = 255).  Once formed, the residual is
+// rounded to FP32 (relative error eps |r|, harmless) for the full weighting.
 template <int MODE>  // 0: rc = scale R (f - A u);  1: rc = scale R u
 __global__ __launch_bounds__(WG) void k_tg_restrict(PlanDev p, TgDev g, const Tile* __restrict__ tiles,
                                                     const float* __restrict__ f, const float* __restrict__ u,
                                                     float* __restrict__ rc, float scale) {
   __shared__ float su[MODE == 0 ? RU_H * RU_W : 1];
-  __shared__ double sr[RR_H * RR_W];
+  __shared__ float sr[RR_H * RR_W];
   const Tile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
   if (t.inst < 0) return;
   const Inst in = p.inst[t.inst];
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(WG) void k_tg_restrict(PlanDev p, TgDev g, const Ti
     for (int k = threadIdx.x; k < RR_H * RR_W; k += WG) {
       const int ly = k / RR_W, lx = k - ly * RR_W;
       const int gx = fx0 + lx, gy = fy0 + ly;
-      double r = 0.0;
+      float r = 0.f;
       if (gx < n && gy < n) {
         const float* s = su + (ly + 1) * RU_W + (lx + 1);
         double acc = c[0] * (double)s[0];
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(WG) void k_tg_restrict(PlanDev p, TgDev g, const Ti
         acc = __builtin_fma(c[2], (double)s[-RU_W] + (double)s[RU_W], acc);
         acc = __builtin_fma(c[3], (double)s[-RU_W - 1] + (double)s[RU_W + 1], acc);
         acc = __builtin_fma(c[4], (double)s[-RU_W + 1] + (double)s[RU_W - 1], acc);
-        r = (double)fi[(int64_t)gy * n + gx] - acc;
+        r = (float)((double)fi[(int64_t)gy * n + gx] - acc);
       }
       sr[k] = r;
     }
@@ -91,20 +91,20 @@ __global__ __launch_bounds__(WG) void k_tg_restrict(PlanDev p, TgDev g, const Ti
     for (int k = threadIdx.x; k < RR_H * RR_W; k += WG) {
       const int ly = k / RR_W, lx = k - ly * RR_W;
       const int gx = fx0 + lx, gy = fy0 + ly;
-      sr[k] = (gx < n && gy < n) ? (double)ui[(int64_t)gy * n + gx] : 0.0;
+      sr[k] = (gx < n && gy < n) ? ui[(int64_t)gy * n + gx] : 0.f;
     }
   }
   __syncthreads();
-  const double w = (double)scale * 0.0625;  // (1/16) [1 2 1; 2 4 2; 1 2 1]
+  const float w = scale * 0.0625f;  // (1/16) [1 2 1; 2 4 2; 1 2 1]
   const int tx = threadIdx.x & 63;
   for (int ty = threadIdx.x >> 6; ty < RT_Y; ty += WG / 64) {
     const int I = t.x0 + tx, J = t.y0 + ty;
     if (I < nc && J < nc) {
-      const double* s = sr + (2 * ty + 1) * RR_W + 2 * tx + 1;
-      double acc = (s[-RR_W - 1] + s[-RR_W + 1]) + (s[RR_W - 1] + s[RR_W + 1]);
-      acc = __builtin_fma(2.0, (s[-1] + s[1]) + (s[-RR_W] + s[RR_W]), acc);
-      acc = __builtin_fma(4.0, s[0], acc);
-      rc[gi.coff + (int64_t)J * nc + I] = (float)(acc * w);
+      const float* s = sr + (2 * ty + 1) * RR_W + 2 * tx + 1;
+      float acc = (s[-RR_W - 1] + s[-RR_W + 1]) + (s[RR_W - 1] + s[RR_W + 1]);
+      acc = fmadd(2.f, (s[-1] + s[1]) + (s[-RR_W] + s[RR_W]), acc);
+      acc = fmadd(4.f, s[0], acc);
+      rc[gi.coff + (int64_t)J * nc + I] = acc * w;
     }
   }
 }
@@ -116,34 +116,54 @@ __global__ __launch_bounds__(WG) void k_tg_restrict(PlanDev p, TgDev g, const Ti
 // X the unnormalised DST-I; the orthonormal coefficients are -Im Z_k / sqrt(M)
 // (row a) and Re Z_k / sqrt(M) (row b), k = 1..nc.
 // ---------------------------------------------------------------------------
-constexpr int DG = 16;         // rows per workgroup
+constexpr int DG = 8;          // rows per workgroup
 constexpr int DPAIR = DG / 2;  // complex FFTs per workgroup
 constexpr int DMAX = kTgMaxFFT;
 constexpr int DITEMS = DG * (DMAX / 2) / WG;  // coefficients per thread (pass B repack)
 
 __device__ __forceinline__ int bitrev(int t, int lg) { return (int)(__builtin_bitreverse32((unsigned)t) >> (32 - lg)); }
 
-// In-place radix-2 decimation-in-time FFT of DPAIR sequences of length M = 2^lg
-// stored back to back in z, input in bit-reversed order, output in natural order.
-// tw[k] = exp(-2 pi i k / DMAX), k < DMAX / 2.
-__device__ __forceinline__ void fft_pairs(float2* z, int M, int lg, const float2* __restrict__ tw) {
-  const int nb = DPAIR * (M >> 1);
-  for (int l = 1; l <= lg; ++l) {
-    const int half = 1 << (l - 1);
-    const int tws = DMAX >> l;
-    for (int bi = threadIdx.x; bi < nb; bi += WG) {
-      const int q = bi >> (lg - 1);
-      const int b = bi & ((M >> 1) - 1);
-      const int pos = b & (half - 1);
-      const int i0 = q * M + ((b >> (l - 1)) << l) + pos;
-      const int i1 = i0 + half;
-      const float2 w = tw[pos * tws];
-      const float2 x1 = z[i1];
-      const float2 x0 = z[i0];
-      const float tr = fmadd(w.x, x1.x, -(w.y * x1.y));
-      const float ti = fmadd(w.x, x1.y, w.y * x1.x);
-      z[i0] = make_float2(x0.x + tr, x0.y + ti);
-      z[i1] = make_float2(x0.x - tr, x0.y - ti);
+__device__ __forceinline__ float2 cmul(float2 w, float2 x) {
+  return make_float2(fmadd(w.x, x.x, -(w.y * x.y)), fmadd(w.x, x.y, w.y * x.x));
+}
+
+// In-place decimation-in-time FFT of DPAIR sequences of length M = 2^lg stored back
+// to back in z, input in bit-reversed order, output in natural order.  Radix-2
+// stages are fused in pairs (each thread takes four points through two stages in
+// registers); an odd lg starts with one plain radix-2 stage.  tws[k] = exp(-2 pi i k / M).
+__device__ __forceinline__ void fft_pairs(float2* z, int M, int lg, const float2* tws) {
+  int l = 1;
+  if (lg & 1) {
+    for (int bi = threadIdx.x; bi < DPAIR * (M >> 1); bi += WG) {
+      const int i0 = 2 * bi;  // pairs (2b, 2b + 1) of every sequence, twiddle 1
+      const float2 x0 = z[i0], x1 = z[i0 + 1];
+      z[i0] = make_float2(x0.x + x1.x, x0.y + x1.y);
+      z[i0 + 1] = make_float2(x0.x - x1.x, x0.y - x1.y);
+    }
+    __syncthreads();
+    l = 2;
+  }
+  for (; l < lg; l += 2) {
+    const int h = 1 << (l - 1);
+    for (int bi = threadIdx.x; bi < DPAIR * (M >> 2); bi += WG) {
+      const int q = bi >> (lg - 2);
+      const int b = bi & ((M >> 2) - 1);
+      const int pos = b & (h - 1);
+      const int i0 = q * M + ((b >> (l - 1)) << (l + 1)) + pos;
+      const float2 a0 = z[i0], a1 = z[i0 + h], a2 = z[i0 + 2 * h], a3 = z[i0 + 3 * h];
+      // stage l (length 2h): (a0, a1) and (a2, a3) with exp(-2 pi i pos / 2h)
+      const float2 w1 = tws[pos * (M >> l)];
+      float2 t = cmul(w1, a1);
+      const float2 b0 = make_float2(a0.x + t.x, a0.y + t.y), b1 = make_float2(a0.x - t.x, a0.y - t.y);
+      t = cmul(w1, a3);
+      const float2 b2 = make_float2(a2.x + t.x, a2.y + t.y), b3 = make_float2(a2.x - t.x, a2.y - t.y);
+      // stage l + 1 (length 4h): (b0, b2) with exp(-2 pi i pos / 4h), (b1, b3) with pos + h
+      t = cmul(tws[pos * (M >> (l + 1))], b2);
+      z[i0] = make_float2(b0.x + t.x, b0.y + t.y);
+      z[i0 + 2 * h] = make_float2(b0.x - t.x, b0.y - t.y);
+      t = cmul(tws[(pos + h) * (M >> (l + 1))], b3);
+      z[i0 + h] = make_float2(b1.x + t.x, b1.y + t.y);
+      z[i0 + 3 * h] = make_float2(b1.x - t.x, b1.y - t.y);
     }
     __syncthreads();
   }
@@ -160,7 +180,7 @@ __device__ __forceinline__ void put_odd(float2* z, int M, int lg, int rr, int t,
 
 __device__ __forceinline__ void zero_ends(float2* z, int M, int lg) {
   for (int q = threadIdx.x; q < DPAIR; q += WG) {
-    z[q * M + 0] = make_float2(0.f, 0.f);            // t = 0
+    z[q * M + 0] = make_float2(0.f, 0.f);                   // t = 0
     z[q * M + bitrev(M >> 1, lg)] = make_float2(0.f, 0.f);  // t = M / 2
   }
 }
@@ -178,12 +198,16 @@ __device__ __forceinline__ float coeff(const float2* z, int M, int rr, int k, fl
 //             symbol given:   coef[p][q] *= symbol[q][p];
 //             transform back along q -> out[p][J]
 // MODE 2 (C): rows J gathered from in[p][J] -> out[J][I] (transform along p)
+// Dynamic LDS: DPAIR * Mmax sequences plus Mmax / 2 twiddles (float2), Mmax the
+// largest n + 1 of the launch.
 template <int MODE>
-__global__ __launch_bounds__(WG) void k_tg_dst(TgDev g, const Tile* __restrict__ groups, const float* in,
+__global__ __launch_bounds__(WG) void k_tg_dst(TgDev g, const Tile* __restrict__ groups, int mmax, const float* in,
                                                float* out, const float* __restrict__ symbol,
                                                const float* __restrict__ shat, float* __restrict__ shat_out,
                                                float* __restrict__ dsym) {
-  __shared__ float2 z[DPAIR * DMAX];
+  extern __shared__ float2 lds[];
+  float2* z = lds;
+  float2* tws = lds + DPAIR * mmax;
   const Tile t = groups[blockIdx.x];
   if (t.inst < 0) return;
   const TgInst gi = g.inst[t.inst];
@@ -192,10 +216,11 @@ __global__ __launch_bounds__(WG) void k_tg_dst(TgDev g, const Tile* __restrict__
   const int r0 = t.y0;
   const float* src = in + gi.coff;
   float* dst = out + gi.coff;
+  for (int k = threadIdx.x; k < (M >> 1); k += WG) tws[k] = g.tw[k * (DMAX / M)];
   // load the group's rows into the odd extensions
   if (MODE == 2) {
     for (int idx = threadIdx.x; idx < DG * nc; idx += WG) {
-      const int rr = idx & (DG - 1), c = idx >> 4;
+      const int rr = idx & (DG - 1), c = idx >> 3;
       const int r = r0 + rr;
       put_odd(z, M, lg, rr, c + 1, r < nc ? src[(int64_t)c * nc + r] : 0.f);
     }
@@ -207,10 +232,10 @@ __global__ __launch_bounds__(WG) void k_tg_dst(TgDev g, const Tile* __restrict__
   }
   zero_ends(z, M, lg);
   __syncthreads();
-  fft_pairs(z, M, lg, g.tw);
+  fft_pairs(z, M, lg, tws);
   if (MODE == 0) {
     for (int idx = threadIdx.x; idx < DG * nc; idx += WG) {
-      const int rr = idx & (DG - 1), k = idx >> 4;
+      const int rr = idx & (DG - 1), k = idx >> 3;
       const int r = r0 + rr;
       if (r < nc) dst[(int64_t)k * nc + r] = coeff(z, M, rr, k + 1, sc);
     }
@@ -239,7 +264,7 @@ __global__ __launch_bounds__(WG) void k_tg_dst(TgDev g, const Tile* __restrict__
 #pragma unroll
   for (int j = 0; j < DITEMS; ++j) {
     const int idx = threadIdx.x + j * WG;
-    const int rr = idx & (DG - 1), k = idx >> 4;
+    const int rr = idx & (DG - 1), k = idx >> 3;
     const int r = r0 + rr;
     float x = 0.f;
     if (k < nc && r < nc) {
@@ -254,12 +279,12 @@ __global__ __launch_bounds__(WG) void k_tg_dst(TgDev g, const Tile* __restrict__
 #pragma unroll
   for (int j = 0; j < DITEMS; ++j) {
     const int idx = threadIdx.x + j * WG;
-    const int rr = idx & (DG - 1), k = idx >> 4;
+    const int rr = idx & (DG - 1), k = idx >> 3;
     if (k < nc) put_odd(z, M, lg, rr, k + 1, vals[j]);
   }
   zero_ends(z, M, lg);
   __syncthreads();
-  fft_pairs(z, M, lg, g.tw);
+  fft_pairs(z, M, lg, tws);
   for (int rr = 0; rr < DG; ++rr) {
     const int r = r0 + rr;
     if (r >= nc) break;
@@ -267,32 +292,44 @@ __global__ __launch_bounds__(WG) void k_tg_dst(TgDev g, const Tile* __restrict__
   }
 }
 
-// Bilinear interpolation of the coarse field e at fine point (i, j) (zero outside):
-// along each axis an odd index sits on coarse (i - 1) / 2, an even one halfway between
-// i/2 - 1 and i/2.
-__device__ __forceinline__ float interp_row(const float* e, int nc, int J, int i) {
-  auto at = [&](int I) { return (I >= 0 && I < nc) ? e[(int64_t)J * nc + I] : 0.f; };
-  if (i & 1) return at((i - 1) >> 1);
-  return 0.5f * (at((i >> 1) - 1) + at(i >> 1));
+// Coarse window of a fine tile at (x0, y0) (both even): coarse columns from
+// x0/2 - 2 and rows from y0/2 - 2, zero outside the coarse grid.  It covers the
+// bilinear interpolation of the tile and its one-point halo.
+constexpr int CW_W = TX / 2 + 4, CW_H = TY / 2 + 4;
+
+__device__ __forceinline__ void stage_coarse(float* cw, const float* e, int nc, int x0, int y0) {
+  const int I0 = x0 / 2 - 2, J0 = y0 / 2 - 2;
+  for (int k = threadIdx.x; k < CW_W * CW_H; k += WG) {
+    const int JJ = k / CW_W, II = k - JJ * CW_W;
+    const int I = I0 + II, J = J0 + JJ;
+    cw[k] = (I >= 0 && I < nc && J >= 0 && J < nc) ? e[(int64_t)J * nc + I] : 0.f;
+  }
 }
 
-__device__ __forceinline__ float interp(const float* e, int nc, int i, int j) {
-  if (j & 1) return interp_row(e, nc, (j - 1) >> 1, i);
-  const int Ja = (j >> 1) - 1, Jb = j >> 1;
-  const float a = Ja >= 0 ? interp_row(e, nc, Ja, i) : 0.f;
-  const float b = Jb < nc ? interp_row(e, nc, Jb, i) : 0.f;
-  return 0.5f * (a + b);
+// Bilinear interpolation at fine point (i, j) from the window: along each axis an
+// odd index sits on coarse (i - 1) / 2, an even one halfway between i/2 - 1 and i/2.
+__device__ __forceinline__ float interp(const float* cw, int x0, int y0, int i, int j) {
+  const int I0 = x0 / 2 - 2, J0 = y0 / 2 - 2;
+  auto row = [&](int J) -> float {
+    const float* r = cw + (J - J0) * CW_W - I0;
+    if (i & 1) return r[(i - 1) >> 1];
+    return 0.5f * (r[(i >> 1) - 1] + r[i >> 1]);
+  };
+  if (j & 1) return row((j - 1) >> 1);
+  return 0.5f * (row((j >> 1) - 1) + row(j >> 1));
 }
 
 // uo = ui + P ec (uo may equal ui)
 __global__ __launch_bounds__(WG) void k_tg_prolong(PlanDev p, TgDev g, const float* __restrict__ ec,
                                                    const float* ui, float* uo) {
+  __shared__ float cw[CW_W * CW_H];
   const Tile tl = p.tiles[xcd_remap(blockIdx.x, gridDim.x)];
   if (tl.inst < 0) return;
   const Inst in = p.inst[tl.inst];
   const TgInst gi = g.inst[tl.inst];
-  const int n = in.n, nc = gi.nc;
-  const float* e = ec + gi.coff;
+  const int n = in.n;
+  stage_coarse(cw, ec + gi.coff, gi.nc, tl.x0, tl.y0);
+  __syncthreads();
   const int i = tl.x0 + (threadIdx.x & 63);
   if (i >= n) return;
   const int ty0 = threadIdx.x >> 6;
@@ -301,7 +338,7 @@ __global__ __launch_bounds__(WG) void k_tg_prolong(PlanDev p, TgDev g, const flo
     const int j = tl.y0 + ty0 + 4 * k;
     if (j >= n) break;
     const int64_t idx = in.off + (int64_t)j * n + i;
-    uo[idx] = ui[idx] + interp(e, nc, i, j);
+    uo[idx] = ui[idx] + interp(cw, tl.x0, tl.y0, i, j);
   }
 }
 
@@ -313,17 +350,19 @@ constexpr int AW = TX + 2;
 __global__ __launch_bounds__(WG) void k_tg_adj_correct(PlanDev p, TgDev g, const float* __restrict__ ybar,
                                                        const float* __restrict__ ub, float* __restrict__ ub_out,
                                                        float* __restrict__ fb) {
+  __shared__ float cw[CW_W * CW_H];
   __shared__ float s[(TY + 2) * AW];
   const Tile tl = p.tiles[xcd_remap(blockIdx.x, gridDim.x)];
   if (tl.inst < 0) return;
   const Inst in = p.inst[tl.inst];
   const TgInst gi = g.inst[tl.inst];
-  const int n = in.n, nc = gi.nc;
-  const float* e = ybar + gi.coff;
+  const int n = in.n;
+  stage_coarse(cw, ybar + gi.coff, gi.nc, tl.x0, tl.y0);
+  __syncthreads();
   for (int k = threadIdx.x; k < (TY + 2) * AW; k += WG) {
     const int ly = k / AW, lx = k - ly * AW;
     const int gx = tl.x0 + lx - 1, gy = tl.y0 + ly - 1;
-    s[k] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? 0.25f * interp(e, nc, gx, gy) : 0.f;
+    s[k] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? 0.25f * interp(cw, tl.x0, tl.y0, gx, gy) : 0.f;
   }
   __syncthreads();
   double c[5];
@@ -359,17 +398,18 @@ void launch_tg_restrict(int mode, const PlanDev& p, const TgDev& g, const Tile* 
     hipLaunchKernelGGL((k_tg_restrict<1>), dim3(ntiles), dim3(WG), 0, st, p, g, tiles, f, u, rc, scale);
 }
 
-void launch_tg_dst(int pass, const TgDev& g, const Tile* groups, int ngroups, const float* in, float* out,
+void launch_tg_dst(int pass, const TgDev& g, const Tile* groups, int ngroups, int mmax, const float* in, float* out,
                    const float* symbol, const float* shat, float* shat_out, float* dsym, hipStream_t st) {
+  const size_t lds = (size_t)(DPAIR * mmax + mmax / 2) * sizeof(float2);
   if (pass == 0)
-    hipLaunchKernelGGL((k_tg_dst<0>), dim3(ngroups), dim3(WG), 0, st, g, groups, in, out, symbol, shat, shat_out,
-                       dsym);
+    hipLaunchKernelGGL((k_tg_dst<0>), dim3(ngroups), dim3(WG), lds, st, g, groups, mmax, in, out, symbol, shat,
+                       shat_out, dsym);
   else if (pass == 1)
-    hipLaunchKernelGGL((k_tg_dst<1>), dim3(ngroups), dim3(WG), 0, st, g, groups, in, out, symbol, shat, shat_out,
-                       dsym);
+    hipLaunchKernelGGL((k_tg_dst<1>), dim3(ngroups), dim3(WG), lds, st, g, groups, mmax, in, out, symbol, shat,
+                       shat_out, dsym);
   else
-    hipLaunchKernelGGL((k_tg_dst<2>), dim3(ngroups), dim3(WG), 0, st, g, groups, in, out, symbol, shat, shat_out,
-                       dsym);
+    hipLaunchKernelGGL((k_tg_dst<2>), dim3(ngroups), dim3(WG), lds, st, g, groups, mmax, in, out, symbol, shat,
+                       shat_out, dsym);
 }
 
 void launch_tg_prolong(const PlanDev& p, const TgDev& g, const float* ec, const float* ui, float* uo,

@@ -18,7 +18,7 @@ import numpy as np
 
 __all__ = [
     "Batch", "single_isotropic", "aniso_batch", "uneven_batch", "helmholtz_batch",
-    "random_batch", "meta_params", "pack", "unpack_vec", "offsets_of", "twogrid_symbol",
+    "random_batch", "meta_params", "pack", "unpack_vec", "offsets_of", "twogrid_symbol", "smoothing_weights",
 ]
 
 META_HIDDEN = 64
@@ -134,6 +134,16 @@ def twogrid_symbol(kappa, n, seed=None, spread=0.0, reg=1.0):
     if spread > 0.0:
         sym = sym * np.random.default_rng(seed).uniform(1.0 - spread, 1.0 + spread, size=sym.shape)
     return sym
+
+
+def smoothing_weights(lmax, m, lo_frac=0.25):
+    """Stand-in smoother weights: reciprocals of the m Chebyshev points of
+    [lo_frac * lmax, lmax], ordered largest, smallest, second largest, ... ."""
+    a, b = lo_frac * lmax, lmax
+    x = np.cos((2.0 * np.arange(1, m + 1) - 1.0) * np.pi / (2.0 * m))
+    w = np.sort(2.0 / (a + b + (b - a) * x))
+    order = [w[-1 - k // 2] if k % 2 == 0 else w[k // 2] for k in range(m)]
+    return np.array(order)
 
 
 def meta_params(m=16, seed=0, beta0=0.99, last_std=0.01):
