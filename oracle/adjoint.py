@@ -4,15 +4,15 @@ Training (§2.2, Algorithm 1, loss L2 of eq. loss-fun-relative-res) back-propaga
 through K inner steps of a Table-1 scheme.  This oracle differentiates the
 NAGex-Richardson(m) row literally; the other rows are its special cases:
 NAG (look-ahead factor equal to the momentum factor), MOM (no look-ahead) and
-Richardson (no momentum).  An optional weighted-Jacobi preconditioner with a
-constant diagonal (§2.1, eq. momentum-m-Binv with B^{-1} = D^{-1}) multiplies the
-residual by dinv = 1/D.
+Richardson (no momentum).  A preconditioner (§2.1, eq. momentum-m-Binv) enters as
+B^{-1} applied to the residual: a constant-diagonal weighted Jacobi scale dinv = 1/D,
+or any symmetric B^{-1} passed as a callable `binv` (SSOR is symmetric when A is).
 
 Forward step s (weight index i = s mod m), from the state (u, v) before the step:
-    u~ = u + at_i v;  r_s = f - A u~;  v' = a_i v + omega_i dinv r_s;  u' = u + v'.
+    u~ = u + at_i v;  r_s = f - A u~;  v' = a_i v + omega_i B^{-1} r_s;  u' = u + v'.
 Reverse step, given the adjoints (ub, vb) of (u', v') and g = vb + ub:
-    omega_bar_i += dinv <g, r_s>,  rb = omega_i dinv g,  f_bar += rb,  ut_bar = -A rb
-    (A is symmetric, so A^T = A),
+    omega_bar_i += <g, B^{-1} r_s>,  rb = omega_i B^{-1} g,  f_bar += rb,  ut_bar = -A rb
+    (A and B^{-1} are symmetric),
     alpha_bar_i += <g, v>,  alpha_t_bar_i += <ut_bar, v>,
     ub <- ub + ut_bar,  vb <- a_i g + at_i ut_bar.
 For NAG the two momentum gradients add up: alpha_bar_i = <g + ut_bar, v>.
@@ -44,10 +44,15 @@ def _factors(method, alpha, alpha_t, m):
     raise ValueError(method)
 
 
-def unroll_states(coef, f, omega, alpha, K, u0=None, v0=None, method=NAG, alpha_t=None, dinv=1.0):
+def _precond(dinv, binv):
+    return (lambda r: dinv * r) if binv is None else binv
+
+
+def unroll_states(coef, f, omega, alpha, K, u0=None, v0=None, method=NAG, alpha_t=None, dinv=1.0, binv=None):
     """States (u_s, v_s) for s = 0..K of the unroll."""
     m = len(omega)
     a, at = _factors(method, alpha, alpha_t, m)
+    pre = _precond(dinv, binv)
     u = np.zeros_like(f, dtype=np.float64) if u0 is None else np.array(u0, dtype=np.float64)
     v = np.zeros_like(f, dtype=np.float64) if v0 is None else np.array(v0, dtype=np.float64)
     us, vs = [u], [v]
@@ -55,19 +60,20 @@ def unroll_states(coef, f, omega, alpha, K, u0=None, v0=None, method=NAG, alpha_
         i = s % m
         ut = u + at[i] * v
         r = f - apply_A(coef, ut)
-        v = a[i] * v + omega[i] * dinv * r
+        v = a[i] * v + omega[i] * pre(r)
         u = u + v
         us.append(u)
         vs.append(v)
     return us, vs
 
 
-def reverse(method, coef, f, omega, us, vs, ub, vb, alpha=None, alpha_t=None, dinv=1.0):
+def reverse(method, coef, f, omega, us, vs, ub, vb, alpha=None, alpha_t=None, dinv=1.0, binv=None):
     """Reverse sweep over a stored unroll (us[0..K], vs[0..K]) from the adjoints (ub, vb)
     of (u_K, v_K).  Returns (ub_0, vb_0, d_omega, d_alpha, d_alpha_t, f_bar increment)."""
     omega = np.asarray(omega, dtype=np.float64)
     m = len(omega)
     a, at = _factors(method, alpha, alpha_t, m)
+    pre = _precond(dinv, binv)
     K = len(us) - 1
     ub = np.array(ub, dtype=np.float64)
     vb = np.array(vb, dtype=np.float64)
@@ -80,8 +86,8 @@ def reverse(method, coef, f, omega, us, vs, ub, vb, alpha=None, alpha_t=None, di
         u, v = us[s - 1], vs[s - 1]
         r = f - apply_A(coef, u + at[i] * v)
         g = vb + ub
-        d_omega[i] += dinv * float(np.sum(g * r))
-        rb = omega[i] * dinv * g
+        d_omega[i] += float(np.sum(g * pre(r)))
+        rb = omega[i] * pre(g)
         fb = fb + rb
         ut_bar = -apply_A(coef, rb)
         d_alpha[i] += float(np.sum(g * v))
@@ -91,7 +97,7 @@ def reverse(method, coef, f, omega, us, vs, ub, vb, alpha=None, alpha_t=None, di
     return ub, vb, d_omega, d_alpha, d_alpha_t, fb
 
 
-def loss_and_grads_general(method, coef, f, omega, K, alpha=None, alpha_t=None, dinv=1.0, g_uK=None):
+def loss_and_grads_general(method, coef, f, omega, K, alpha=None, alpha_t=None, dinv=1.0, g_uK=None, binv=None):
     """Returns (L, d_omega[m], d_alpha[m], d_alpha_t[m], d_f).
 
     With g_uK given, L is <g_uK, u_K>.  d_alpha is the gradient through the momentum
@@ -100,7 +106,7 @@ def loss_and_grads_general(method, coef, f, omega, K, alpha=None, alpha_t=None, 
     omega = np.asarray(omega, dtype=np.float64)
     m = len(omega)
     a, at = _factors(method, alpha, alpha_t, m)
-    us, vs = unroll_states(coef, f, omega, a, K, method=NAGEX, alpha_t=at, dinv=dinv)
+    us, vs = unroll_states(coef, f, omega, a, K, method=NAGEX, alpha_t=at, dinv=dinv, binv=binv)
     fn2 = float(np.sum(f * f))
     if g_uK is None:
         rK = f - apply_A(coef, us[K])
@@ -113,7 +119,7 @@ def loss_and_grads_general(method, coef, f, omega, K, alpha=None, alpha_t=None, 
         fb = np.zeros_like(f, dtype=np.float64)
     vb = np.zeros_like(f, dtype=np.float64)
     _, _, d_omega, d_alpha, d_alpha_t, dfb = reverse(NAGEX, coef, f, omega, us, vs, ub, vb, alpha=a,
-                                                     alpha_t=at, dinv=dinv)
+                                                     alpha_t=at, dinv=dinv, binv=binv)
     return L, d_omega, d_alpha, d_alpha_t, fb + dfb
 
 
