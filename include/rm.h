@@ -93,6 +93,7 @@ typedef struct {
   int32_t reserved;    /* must be 0                                               */
   double tol;          /* RM_TO_TOL: target ||b - A x|| / ||b|| (FP64)            */
   double tol_inner;    /* RM_TO_TOL: inner relative residual that ends a round    */
+  double relax;        /* RM_FLAG_SSOR: relaxation factor a, 0 < a < 2           */
 } rm_solve_opts;
 
 /* RM_FLAG_GRAPH: RM_TO_TOL captures one outer iteration of the inner solve (its
@@ -108,6 +109,15 @@ typedef struct {
  * returns the gradient with respect to the unscaled omega).  RM_EINVAL if an
  * instance has a zero diagonal. */
 #define RM_FLAG_JACOBI 2
+/* RM_FLAG_SSOR: SSOR preconditioning (§2.1, the SSOR entry of the stationary
+ * preconditioners), B^{-1} = a (2 - a) (D - aU)^{-1} D (D - aL)^{-1} with A = D - L - U
+ * and a = opts->relax.  L and U follow the four-colour ordering colour(i, j) =
+ * (i mod 2) + 2 (j mod 2) on 0-based interior indices (the paper does not state an
+ * ordering; this one leaves no two points of a colour coupled, so each triangular
+ * solve is four parallel passes).  Every step is then one launch (no temporal
+ * blocking).  Accepted wherever RM_FLAG_JACOBI is; the two exclude each other;
+ * RM_EINVAL unless 0 < relax < 2. */
+#define RM_FLAG_SSOR 4
 
 /* Per-instance results of RM_TO_TOL (host arrays of length B, any may be NULL). */
 typedef struct {

@@ -13,6 +13,7 @@ RM_F32, RM_F64 = 0, 1
 RM_UNROLL, RM_TO_TOL = 0, 1
 RM_FLAG_GRAPH = 1
 RM_FLAG_JACOBI = 2
+RM_FLAG_SSOR = 4
 
 # every symbol include/rm.h declares
 EXPORTS = [
@@ -35,7 +36,7 @@ class rm_solve_opts(ctypes.Structure):
                 ("K", ctypes.c_int32), ("ckpt_every", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("tol", ctypes.c_double), ("tol_inner", ctypes.c_double)]
+                ("tol", ctypes.c_double), ("tol_inner", ctypes.c_double), ("relax", ctypes.c_double)]
 
 
 class rm_report(ctypes.Structure):

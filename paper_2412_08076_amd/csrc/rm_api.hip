@@ -115,6 +115,8 @@ struct rm_plan_s {
   bool use_block = true;
   bool exec_dirty = true;
   int jacobi = 0;  // set per call from RM_FLAG_JACOBI
+  int ssor = 0;    // set per call from RM_FLAG_SSOR, with the relaxation factor
+  double relax = 1.0;
   std::vector<ClassExec> classes;
   DevBuf d_ranges;  // int [B][2]: slot range of each instance over all class tables
   int nslots = 0;
@@ -358,6 +360,38 @@ rm_status build_exec(rm_plan_t* pl, hipStream_t st) {
 
 size_t partial_slots(const rm_plan_t* pl) { return std::max<size_t>(pl->tiles.size(), (size_t)pl->nslots); }
 
+// Temporal-blocked sweeps serve the unpreconditioned and Jacobi steps; an SSOR step
+// needs its whole tile in one launch.
+bool blocked(const rm_plan_t* pl) { return pl->use_block && !pl->ssor; }
+
+// One inner step over the plan's one-step tile table, plain or SSOR-preconditioned.
+template <typename T>
+void one_step(const rm_plan_t* pl, const PlanDev& p, int method, const float* omega, const float* alpha, int m, int i,
+              const T* f, const T* u, const T* v, T* u_out, T* v_out, const int* active, hipStream_t st) {
+  if (pl->ssor)
+    rmk::launch_ssor_step<T>(method, p, p.tiles, p.ntiles, omega, alpha, m, i, pl->relax, f, u, v, u_out, v_out,
+                             active, st);
+  else
+    rmk::launch_step<T>(method, p, p.tiles, p.ntiles, omega, alpha, m, i, f, u, v, u_out, v_out, active, st);
+}
+
+void adj_one_step(const rm_plan_t* pl, const PlanDev& p, int method, const float* omega, const float* alpha, int m,
+                  int i, const float* f, const float* u, const float* v, const float* ub, const float* vb,
+                  float* ub_out, float* vb_out, float* fb, double* partial4, hipStream_t st) {
+  if (pl->ssor)
+    rmk::launch_adj_ssor_step(method, p, omega, alpha, m, i, pl->relax, f, u, v, ub, vb, ub_out, vb_out, fb, partial4,
+                              st);
+  else
+    rmk::launch_adj_step(method, p, omega, alpha, m, i, f, u, v, ub, vb, ub_out, vb_out, fb, partial4, st);
+}
+
+// Preconditioner of this call (validated by validate_weights).
+void set_precond(rm_plan_t* pl, const rm_solve_opts* o) {
+  pl->jacobi = (o->flags & RM_FLAG_JACOBI) ? 1 : 0;
+  pl->ssor = (o->flags & RM_FLAG_SSOR) ? 1 : 0;
+  pl->relax = pl->ssor ? o->relax : 1.0;
+}
+
 // Advance `nsteps` FP32 inner steps (global step indices s0 ..) on the pingpong
 // pair (us, vs), starting from set `cur`; `cur` ends on the set holding the
 // result and `flips` counts the swaps (the same for every instance).  Each size
@@ -372,10 +406,10 @@ rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int ns
                 const int* active, double* res_partial, const int** res_ranges, int only_class = -1) {
   const PlanDev p = pl->dev();
   if (nsteps <= 0) return RM_OK;
-  if (!pl->use_block) {
+  if (!blocked(pl)) {
     for (int k = 0; k < nsteps; ++k) {
-      rmk::launch_step<float>(method, p, p.tiles, p.ntiles, omega, alpha, m, (s0 + k) % m, f, us[cur], vs[cur],
-                              us[cur ^ 1], vs[cur ^ 1], active, st);
+      one_step<float>(pl, p, method, omega, alpha, m, (s0 + k) % m, f, us[cur], vs[cur], us[cur ^ 1], vs[cur ^ 1],
+                      active, st);
       cur ^= 1;
       ++flips;
     }
@@ -481,8 +515,7 @@ rm_status solve_unroll(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
       RM_HIP(hipMemcpyAsync(slot, us[cur], P * sizeof(T), hipMemcpyDeviceToDevice, st));
       RM_HIP(hipMemcpyAsync(slot + P, vs[cur], P * sizeof(T), hipMemcpyDeviceToDevice, st));
     }
-    rmk::launch_step<T>(method, p, p.tiles, p.ntiles, omega, alpha, o->m, s % o->m, b, us[cur], vs[cur],
-                        us[nxt], vs[nxt], nullptr, st);
+    one_step<T>(pl, p, method, omega, alpha, o->m, s % o->m, b, us[cur], vs[cur], us[nxt], vs[nxt], nullptr, st);
     if (hist != nullptr && (s + 1) % o->m == 0) {
       const int k = (s + 1) / o->m - 1;
       rmk::launch_residual<T>(p, p.tiles, p.ntiles, b, us[nxt], nullptr, pl->partial.as<double>(), nullptr, st);
@@ -682,10 +715,14 @@ rm_status validate_weights(const rm_plan_t* pl, int method, const rm_solve_opts*
   if (o->m < 1 || o->m > kMaxM) return fail(RM_EINVAL, "m must be in 1..64");
   if (omega == nullptr) return fail(RM_EINVAL, "null omega");
   if (method != RM_RICHARDSON && alpha == nullptr) return fail(RM_EINVAL, "this method needs alpha");
-  if (o->flags & ~(RM_FLAG_GRAPH | RM_FLAG_JACOBI)) return fail(RM_EINVAL, "unknown flag");
-  if (o->flags & RM_FLAG_JACOBI)
+  if (o->flags & ~(RM_FLAG_GRAPH | RM_FLAG_JACOBI | RM_FLAG_SSOR)) return fail(RM_EINVAL, "unknown flag");
+  if ((o->flags & RM_FLAG_JACOBI) && (o->flags & RM_FLAG_SSOR))
+    return fail(RM_EINVAL, "RM_FLAG_JACOBI and RM_FLAG_SSOR exclude each other");
+  if ((o->flags & RM_FLAG_SSOR) && !(o->relax > 0.0 && o->relax < 2.0))
+    return fail(RM_EINVAL, "SSOR needs 0 < relax < 2");
+  if (o->flags & (RM_FLAG_JACOBI | RM_FLAG_SSOR))
     for (int b = 0; b < pl->B; ++b)
-      if (pl->coef[(size_t)b * 8] == 0.0) return fail(RM_EINVAL, "Jacobi needs a non-zero diagonal");
+      if (pl->coef[(size_t)b * 8] == 0.0) return fail(RM_EINVAL, "the preconditioner needs a non-zero diagonal");
   return RM_OK;
 }
 
@@ -1005,7 +1042,7 @@ rm_status rm_solve(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, const rm_
   RM_TRY(validate_weights(plan, method, opts, omega, alpha));
   if (b == nullptr || x == nullptr) return fail(RM_EINVAL, "null b or x");
   rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
-  pl->jacobi = (opts->flags & RM_FLAG_JACOBI) ? 1 : 0;
+  set_precond(pl, opts);
   const int m = opts->m;
   if (opts->mode == RM_UNROLL) {
     if (opts->K < 0 || opts->K % m != 0) return fail(RM_EINVAL, "K must be a non-negative multiple of m");
@@ -1045,7 +1082,7 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   if (b == nullptr || ckpt_v == nullptr || d_omega == nullptr || d_alpha == nullptr)
     return fail(RM_EINVAL, "null b, ckpt, d_omega or d_alpha");
   rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
-  pl->jacobi = (opts->flags & RM_FLAG_JACOBI) ? 1 : 0;
+  set_precond(pl, opts);
   hipStream_t st = ctx->stream;
   const int B = pl->B;
   const int64_t P = pl->P;
@@ -1083,11 +1120,11 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   // intermediate state of a launch and reproduce the one-step kernel bit for bit.
   auto recompute = [&](int c) -> rm_status {
     const int steps = c == nseg - 1 ? E : E - 1;
-    if (!pl->use_block) {
+    if (!blocked(pl)) {
       for (int t = 0; t < steps; ++t) {
         float* uo = S + (int64_t)(t + 1) * 2 * P;
-        rmk::launch_step<float>(method, p, p.tiles, p.ntiles, omega, alpha, m, (c * E + t) % m, b, su(c, t),
-                                sv(c, t), uo, uo + P, nullptr, st);
+        one_step<float>(pl, p, method, omega, alpha, m, (c * E + t) % m, b, su(c, t), sv(c, t), uo, uo + P, nullptr,
+                        st);
       }
       return RM_OK;
     }
@@ -1122,7 +1159,7 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
     if (c != nseg - 1) RM_TRY(recompute(c));
     for (int t = E - 1; t >= 0; --t) {
       const int i = (c * E + t) % m;
-      rmk::launch_adj_step(method, p, omega, alpha, m, i, b, su(c, t), sv(c, t), ubs[cur], vbs[cur],
+      adj_one_step(pl, p, method, omega, alpha, m, i, b, su(c, t), sv(c, t), ubs[cur], vbs[cur],
                            ubs[cur ^ 1], vbs[cur ^ 1], d_b, partial + (size_t)t * 4 * nslot, st);
       cur ^= 1;
     }
@@ -1159,7 +1196,7 @@ rm_status rm_twogrid_solve(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   if (symbol == nullptr || b == nullptr || x == nullptr) return fail(RM_EINVAL, "null symbol, b or x");
   rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
   RM_TRY(twogrid_layout(pl));
-  pl->jacobi = (opts->flags & RM_FLAG_JACOBI) ? 1 : 0;
+  set_precond(pl, opts);
   return twogrid_forward(ctx, pl, method, opts, omega, alpha, symbol, b, x, ckpt, hist);
 }
 
@@ -1177,7 +1214,7 @@ rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
     return fail(RM_EINVAL, "null symbol, b, ckpt, d_omega, d_alpha or d_symbol");
   rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
   RM_TRY(twogrid_layout(pl));
-  pl->jacobi = (opts->flags & RM_FLAG_JACOBI) ? 1 : 0;
+  set_precond(pl, opts);
   hipStream_t st = ctx->stream;
   RM_TRY(twogrid_setup(pl, st));
   auto& tg = pl->tg;
@@ -1225,11 +1262,10 @@ rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
     auto su = [&](int t) -> const float* { return t == 0 ? u0 : S + (int64_t)t * 2 * P; };
     auto sv = [&](int t) -> const float* { return t == 0 ? zero : S + (int64_t)t * 2 * P + P; };
     // recompute the m smoothing states of cycle k
-    if (!pl->use_block) {
+    if (!blocked(pl)) {
       for (int t = 0; t < m; ++t) {
         float* uo = S + (int64_t)(t + 1) * 2 * P;
-        rmk::launch_step<float>(method, p, p.tiles, p.ntiles, omega, alpha, m, t, b, su(t), sv(t), uo, uo + P,
-                                nullptr, st);
+        one_step<float>(pl, p, method, omega, alpha, m, t, b, su(t), sv(t), uo, uo + P, nullptr, st);
       }
     } else {
       for (auto& cl : pl->classes) {
@@ -1272,7 +1308,7 @@ rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
     // through the smoothing, which starts from v = 0 (its adjoint is dropped)
     rmk::launch_fill_f32(vbs[cur], 0.f, P, st);
     for (int t = m - 1; t >= 0; --t) {
-      rmk::launch_adj_step(method, p, omega, alpha, m, t, b, su(t), sv(t), ubs[cur], vbs[cur], ubs[cur ^ 1],
+      adj_one_step(pl, p, method, omega, alpha, m, t, b, su(t), sv(t), ubs[cur], vbs[cur], ubs[cur ^ 1],
                            vbs[cur ^ 1], d_b, partial + (size_t)t * 4 * nslot, st);
       cur ^= 1;
     }
@@ -1345,6 +1381,7 @@ rm_status rm_tune(rm_ctx* ctx, rm_plan_t* plan, int32_t method, int32_t m, const
   if (omega == nullptr || b == nullptr || (method != RM_RICHARDSON && alpha == nullptr))
     return fail(RM_EINVAL, "null omega, alpha or b");
   plan->jacobi = 0;
+  plan->ssor = 0;
   hipStream_t st = ctx->stream;
   hipDeviceProp_t prop;
   RM_HIP(hipGetDeviceProperties(&prop, ctx->device));

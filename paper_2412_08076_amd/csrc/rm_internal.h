@@ -148,6 +148,20 @@ bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, cons
                   const float* v, float* u_out, float* v_out, const int* active, double* partial2,
                   hipStream_t st, float* states = nullptr, int64_t state_stride = 0);
 
+// ---- SSOR-preconditioned steps (rm_ssor.hip) ----------------------------------
+// One inner step of a Table-1 scheme with the four-colour SSOR preconditioner of
+// relaxation factor `relax` (0 < relax < 2), over the plan's one-step tile table.
+template <typename T>
+void launch_ssor_step(int method, const PlanDev& p, const Tile* tiles, int ntiles, const float* omega,
+                      const float* alpha, int m, int i, double relax, const T* f, const T* u, const T* v, T* u_out,
+                      T* v_out, const int* active, hipStream_t st);
+// Reverse of one SSOR-preconditioned step; partial4 as for launch_adj_step, slot 0
+// holding <g, B^{-1} r>.
+void launch_adj_ssor_step(int method, const PlanDev& p, const float* omega, const float* alpha, int m, int i,
+                          double relax, const float* f, const float* u, const float* v, const float* ub,
+                          const float* vb, float* ub_out, float* vb_out, float* fb, double* partial4,
+                          hipStream_t st);
+
 // ---- two-grid correction (rm_twogrid.hip) -------------------------------------
 // Largest FFT length n + 1 of the coarse sine transform.
 constexpr int kTgMaxFFT = 1024;

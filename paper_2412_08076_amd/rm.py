@@ -149,13 +149,16 @@ class Plan:
 
 
 def solve_opts(mode=RM_UNROLL, dtype=RM_F32, m=16, K=0, ckpt_every=0, max_outer=100000, max_rounds=8,
-               check_every=4, tol=1e-10, tol_inner=1e-3, graph=False, jacobi=False):
+               check_every=4, tol=1e-10, tol_inner=1e-3, graph=False, jacobi=False, ssor=None):
+    """rm_solve_opts; ssor = the SSOR relaxation factor (None: no SSOR preconditioning)."""
     o = _lib.rm_solve_opts()
     o.mode, o.dtype, o.m, o.K, o.ckpt_every = mode, dtype, m, K, ckpt_every
     o.max_outer, o.max_rounds, o.check_every = max_outer, max_rounds, check_every
-    o.flags = (_lib.RM_FLAG_GRAPH if graph else 0) | (_lib.RM_FLAG_JACOBI if jacobi else 0)
+    o.flags = ((_lib.RM_FLAG_GRAPH if graph else 0) | (_lib.RM_FLAG_JACOBI if jacobi else 0)
+               | (_lib.RM_FLAG_SSOR if ssor is not None else 0))
     o.reserved = 0
     o.tol, o.tol_inner = tol, tol_inner
+    o.relax = 1.0 if ssor is None else float(ssor)
     return o
 
 
