@@ -290,6 +290,8 @@ def secondary_workload(name, tune_cache):
         return out
     if name == "twogrid":
         return twogrid_workload(ctx, tune_cache)
+    if name == "ssor":
+        return ssor_workload(ctx)
     m = 16
     if name == "train":
         batch = aniso_batch(64, 127, seed=3)
@@ -354,6 +356,43 @@ def secondary_workload(name, tune_cache):
                        "relres_max": float(rep["relres"][sel].max())}
     out.update({"to_tol_s": tt, "to_tol_glups": lups / tt / 1e9, "status": int(rep["status"]), "per_size": per})
     return out
+
+
+def ssor_workload(ctx, m=3, relax=1.0, w=1.2, a=0.96):
+    """SSOR-preconditioned NAGex-Richardson(3) on the headline batch (256 anisotropic
+    problems, n = 255), FP64-refined to 1e-10, with fixed stand-in weights (omega = 1.2,
+    alpha = alpha~ = 0.96, relaxation factor 1.0): outer iterations, time to tolerance and
+    the cost of one preconditioned step."""
+    import torch
+    from paper_2412_08076_amd import rm
+    from synthetic import aniso_batch
+    batch = aniso_batch(B, N, seed=2)
+    plan = rm.Plan(ctx, batch.n, eps=batch.eps, theta=batch.theta)
+    Bn, P = plan.B, plan.P
+    om = torch.full((Bn * m,), w, dtype=torch.float32, device="cuda")
+    al = torch.full((2 * Bn * m,), a, dtype=torch.float32, device="cuda")
+    b32 = torch.as_tensor(batch.f_packed(), dtype=torch.float32).cuda()
+    x32 = torch.zeros(P, dtype=torch.float32, device="cuda")
+    K = 48
+    opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=K, ssor=relax)
+    rm.rm_solve(ctx, plan, rm.RM_NAGEX, opts, om, al, b32, x32); torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(); rm.rm_solve(ctx, plan, rm.RM_NAGEX, opts, om, al, b32, x32); e1.record()
+    torch.cuda.synchronize()
+    t_step = e0.elapsed_time(e1) / 1e3 / K
+    b64 = torch.as_tensor(batch.f_packed()).cuda()
+    x64 = torch.zeros_like(b64)
+    o = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=TOL, tol_inner=1e-3, max_outer=20000, max_rounds=10, check_every=8,
+                      ssor=relax)
+    t0 = time.perf_counter(); rep = rm.rm_solve(ctx, plan, rm.RM_NAGEX, o, om, al, b64, x64)
+    tt = time.perf_counter() - t0
+    steps = rep["outer_iters"].astype(np.float64) * m
+    return {"workload": "ssor", "config": "aniso-Q1 batch B=256 n=255, NAGex-Richardson(3) + four-colour SSOR "
+            "(relax 1.0), omega 1.2, alpha = alpha~ = 0.96, FP64-refined to 1e-10", "us_per_step": t_step * 1e6,
+            "glups_per_step": P / t_step / 1e9, "to_tol_s": tt, "status": int(rep["status"]),
+            "outer_median": float(np.median(rep["outer_iters"])), "outer_max": int(rep["outer_iters"].max()),
+            "rounds_max": int(rep["rounds"].max()), "relres_max": float(rep["relres"].max()),
+            "to_tol_glups": float(np.sum(steps) * N * N) / tt / 1e9}
 
 
 def twogrid_workload(ctx, tune_cache, K=4, m=8, reps=5):
@@ -427,7 +466,7 @@ def main():
     ap.add_argument("--no-comparator", action="store_true", help="skip the plain FP64 loop comparator")
     ap.add_argument("--kernel-config", default=None,
                     help="variant,T,width of the sweep kernel instead of autotuning (e.g. 3,8,64)")
-    ap.add_argument("--workload", default="aniso", choices=["aniso", "uneven", "train", "single", "twogrid"],
+    ap.add_argument("--workload", default="aniso", choices=["aniso", "uneven", "train", "single", "twogrid", "ssor"],
                     help="aniso (default, the headline line) or one of the secondary shapes")
     args = ap.parse_args()
     if args.workload != "aniso":
