@@ -282,6 +282,31 @@ rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
                              const float* g_uK, const float* g_loss, float* d_omega,
                              float* d_alpha, float* d_symbol, float* d_b, float* loss);
 
+/* Restarted flexible GMRES with a neural solver as the preconditioner (§3.2: FGMRES,
+ * restart 20, preconditioned by a multilevel neural solver).  Every instance runs its
+ * own FGMRES in FP64 (basis, Hessenberg, Givens rotations); the preconditioner maps
+ * v to the FP32 result z of `inner` applied to A z = fl32(v) from z = 0:
+ *   inner == NULL:            z = fl32(v) (plain restarted GMRES);
+ *   symbol == NULL:           inner->K inner steps of `method` (inner->m weights,
+ *                             RM_FLAG_JACOBI / RM_FLAG_SSOR honoured);
+ *   symbol != NULL:           inner->K two-grid cycles (see rm_twogrid_solve).
+ * inner->mode must be RM_UNROLL, inner->dtype RM_F32.  Because the preconditioner is an
+ * iteration, its action may vary between steps; FGMRES keeps the directions z_j.
+ * Instance b stops when ||b - A x|| / ||b|| <= tol (tested on the FP64 residual at each
+ * restart, estimated by the rotations in between) or after max_iter Arnoldi steps.
+ * b, x: device double [P_tot]; x is the initial guess and receives the result.
+ * rep (host, may be NULL): Arnoldi steps (outer_iters), cycles (rounds), the last true
+ * relative residual and RM_OK / RM_ENOTCONV / RM_EDIVERGED per instance.  Blocks; the
+ * call returns the worst per-instance status. */
+typedef struct {
+  int32_t restart;   /* Krylov dimension per cycle, 1..64 */
+  int32_t max_iter;  /* Arnoldi steps per instance        */
+  double tol;        /* relative residual target          */
+} rm_fgmres_opts;
+rm_status rm_fgmres(rm_ctx* ctx, const rm_plan_t* plan, const rm_fgmres_opts* fo, int32_t method,
+                    const rm_solve_opts* inner, const float* omega, const float* alpha,
+                    const float* symbol, const double* b, double* x, rm_report* rep);
+
 /* Meta network (§2.2-2.3).  params: device float [5457 for m = 16; in general
  * 64*2 + 64 + 64*64 + 64 + (m+1)*64 + (m+1)], layout
  *   W1[64][2], b1[64], W2[64][64], b2[64], W3[m+1][64], b3[m+1]  (out x in).

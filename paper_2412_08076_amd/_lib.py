@@ -21,7 +21,7 @@ EXPORTS = [
     "rm_plan_offsets", "rm_plan_coefficients", "rm_plan_set_kernel", "rm_plan_get_kernel", "rm_tune",
     "rm_apply_A", "rm_residual", "rm_solve",
     "rm_solve_adjoint", "rm_plan_coarse_points", "rm_plan_coarse_offsets", "rm_twogrid_solve",
-    "rm_twogrid_adjoint", "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count",
+    "rm_twogrid_adjoint", "rm_fgmres", "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count",
     "rm_status_string", "rm_last_error",
 ]
 
@@ -37,6 +37,10 @@ class rm_solve_opts(ctypes.Structure):
                 ("max_rounds", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("tol_inner", ctypes.c_double), ("relax", ctypes.c_double)]
+
+
+class rm_fgmres_opts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class rm_report(ctypes.Structure):
@@ -79,6 +83,8 @@ def load():
         "rm_twogrid_solve": (st, [P, P, I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P, P, P]),
         "rm_twogrid_adjoint": (st, [P, P, I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P, P, P, P, P, P, P,
                                     P]),
+        "rm_fgmres": (st, [P, P, ctypes.POINTER(rm_fgmres_opts), I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P,
+                           ctypes.POINTER(rm_report)]),
         "rm_meta_forward": (st, [P, P, I32, P, P, P]),
         "rm_meta_backward": (st, [P, P, I32, P, P, P, P]),
         "rm_meta_param_count": (I32, [I32]),

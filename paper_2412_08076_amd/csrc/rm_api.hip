@@ -129,6 +129,11 @@ struct rm_plan_s {
     DevBuf d_inst, d_rtiles, d_groups, d_tw, c0, c1, shat, fine2, zero;
     int nrtiles = 0, ngroups = 0, mmax = 0;
   } tg;
+  // flexible GMRES: basis (FP64), preconditioned directions (FP32), work vectors and
+  // per-instance state
+  struct Fgm {
+    DevBuf V, Z, w, t, b32, dbl, ints, partial;
+  } fg;
   rmk::TgDev tgdev() const {
     rmk::TgDev g;
     g.inst = tg.d_inst.as<rmk::TgInst>();
@@ -152,7 +157,7 @@ struct rm_plan_s {
     for (DevBuf* b : {&d_tiles, &d_inst, &d_coef32, &d_coef64, &d_mu, &d_gersh, &partial, &red, &flags, &vecA,
                       &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges, &tg.d_inst,
                       &tg.d_rtiles, &tg.d_groups, &tg.d_tw, &tg.c0, &tg.c1, &tg.shat, &tg.fine2,
-                      &tg.zero})
+                      &tg.zero, &fg.V, &fg.Z, &fg.w, &fg.t, &fg.b32, &fg.dbl, &fg.ints, &fg.partial})
       b->release();
     for (auto& c : classes) c.tiles.release();
   }
@@ -1317,6 +1322,145 @@ rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
   rmk::launch_f64_to_f32(acc_w, d_omega, (int64_t)B * m, st);
   rmk::launch_f64_to_f32(acc_a, d_alpha, (int64_t)B * m * na, st);
   return last_launch();
+}
+
+rm_status rm_fgmres(rm_ctx* ctx, const rm_plan_t* plan, const rm_fgmres_opts* fo, int32_t method,
+                    const rm_solve_opts* inner, const float* omega, const float* alpha, const float* symbol,
+                    const double* b, double* x, rm_report* rep) {
+  RM_TRY(check_ctx_plan(ctx, plan));
+  if (fo == nullptr || b == nullptr || x == nullptr) return fail(RM_EINVAL, "null opts, b or x");
+  const int R = fo->restart;
+  if (R < 1 || R > 64) return fail(RM_EINVAL, "restart must be in 1..64");
+  if (fo->max_iter < 1 || !(fo->tol > 0.0)) return fail(RM_EINVAL, "need max_iter >= 1 and tol > 0");
+  rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
+  if (inner != nullptr) {
+    RM_TRY(validate_weights(plan, method, inner, omega, alpha));
+    if (inner->mode != RM_UNROLL || inner->dtype != RM_F32 || inner->K < 1)
+      return fail(RM_EINVAL, "the preconditioner is an FP32 RM_UNROLL with K >= 1 (steps, or two-grid cycles)");
+    if (symbol != nullptr) RM_TRY(twogrid_layout(pl));
+    set_precond(pl, inner);
+  } else if (symbol != nullptr) {
+    return fail(RM_EINVAL, "a symbol needs inner options");
+  }
+  hipStream_t st = ctx->stream;
+  const int B = pl->B;
+  const int64_t P = pl->P;
+  const int nslot = (int)pl->tiles.size();
+  const size_t pd = (size_t)std::max<int64_t>(P, 1);
+  auto& fg = pl->fg;
+  RM_TRY(fg.V.ensure(pd * (R + 1) * sizeof(double), st));
+  RM_TRY(fg.Z.ensure(pd * R * sizeof(float), st));
+  RM_TRY(fg.w.ensure(pd * sizeof(double), st));
+  RM_TRY(fg.t.ensure(pd * sizeof(double), st));
+  RM_TRY(fg.b32.ensure(pd * sizeof(float), st));
+  // doubles: H [B][R][R+1], cs, sn, y [B][R], g [B][R+1], hn2, relres, est [B], r2b2 [B][2]
+  const size_t nH = (size_t)B * R * (R + 1), nR = (size_t)B * R, nG = (size_t)B * (R + 1);
+  RM_TRY(fg.dbl.ensure((nH + 3 * nR + nG + 5 * (size_t)B) * sizeof(double), st));
+  RM_TRY(fg.ints.ensure((size_t)5 * B * sizeof(int), st));
+  RM_TRY(fg.partial.ensure((size_t)nslot * (R + 1) * sizeof(double), st));
+  double* V = fg.V.as<double>();
+  float* Z = fg.Z.as<float>();
+  double* w = fg.w.as<double>();
+  double* t64 = fg.t.as<double>();
+  float* b32 = fg.b32.as<float>();
+  double* H = fg.dbl.as<double>();
+  double* cs = H + nH;
+  double* sn = cs + nR;
+  double* yv = sn + nR;
+  double* g = yv + nR;
+  double* hn2 = g + nG;
+  double* relres = hn2 + B;
+  double* est = relres + B;
+  double* r2b2 = est + B;
+  int* iters = fg.ints.as<int>();
+  int* jdone = iters + B;
+  int* active = jdone + B;
+  int* running = active + B;
+  int* status = running + B;
+  double* partial = fg.partial.as<double>();
+  const PlanDev p = pl->dev();
+  // finished instances keep flowing through the preconditioner: give their basis
+  // vectors defined contents
+  rmk::launch_fill_f64(V, 0.0, (int64_t)(R + 1) * P, st);
+  rmk::launch_fill_i32(iters, 0, B, st);
+  rmk::launch_fill_i32(running, 1, B, st);
+  rmk::launch_fill_i32(status, RM_ENOTCONV, B, st);
+  std::vector<int> h_active((size_t)B), h_round((size_t)B, 0);
+  auto any_active = [&]() -> rm_status {
+    RM_HIP(hipMemcpyAsync(h_active.data(), active, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, st));
+    RM_HIP(hipStreamSynchronize(st));
+    return RM_OK;
+  };
+  auto count = [&]() {
+    int c = 0;
+    for (int v : h_active) c += v != 0;
+    return c;
+  };
+  for (;;) {
+    // true residual, convergence, v_0 = r / beta
+    rmk::launch_residual<double>(p, p.tiles, p.ntiles, b, x, V, partial, nullptr, st);
+    rmk::launch_reduce_partials(p, partial, r2b2, r2b2 + 1, 2, nullptr, st);
+    rmk::launch_fgm_start(B, r2b2, fo->tol, fo->max_iter, iters, running, active, status, relres, g, R + 1, jdone,
+                          st);
+    rmk::launch_scale(p, V, r2b2, 2, V, active, st);
+    RM_TRY(any_active());
+    if (count() == 0) break;
+    for (int b0 = 0; b0 < B; ++b0) h_round[b0] += h_active[b0] != 0;
+    for (int j = 0; j < R; ++j) {
+      double* Vj = V + (int64_t)j * P;
+      float* Zj = Z + (int64_t)j * P;
+      // z_j = M(v_j): the FP32 preconditioner applied to A z = fl32(v_j) from z = 0
+      rmk::launch_f64_to_f32(Vj, b32, P, st);
+      if (inner == nullptr) {
+        RM_HIP(hipMemcpyAsync(Zj, b32, P * sizeof(float), hipMemcpyDeviceToDevice, st));
+      } else {
+        rmk::launch_fill_f32(Zj, 0.f, P, st);
+        if (symbol != nullptr)
+          RM_TRY(twogrid_forward(ctx, pl, method, inner, omega, alpha, symbol, b32, Zj, nullptr, nullptr));
+        else
+          RM_TRY(solve_unroll<float>(ctx, pl, method, inner, omega, alpha, b32, Zj, nullptr, nullptr));
+      }
+      // w = A z_j in FP64, then two passes of classical Gram-Schmidt against v_0..v_j
+      rmk::launch_f32_to_f64(Zj, t64, P, st);
+      rmk::launch_apply<double>(p, p.tiles, p.ntiles, t64, w, st);
+      double* Hj = H + (int64_t)j * (R + 1);
+      const int ldh = R * (R + 1);
+      rmk::launch_mdot(p, V, P, j + 1, w, active, partial, nslot, st);
+      rmk::launch_mreduce(p, partial, j + 1, nslot, active, Hj, ldh, 0, false, st);
+      rmk::launch_maxpy(p, V, P, j + 1, Hj, ldh, 0, w, active, st);
+      rmk::launch_mdot(p, V, P, j + 1, w, active, partial, nslot, st);
+      rmk::launch_mreduce(p, partial, j + 1, nslot, active, yv, R, 0, false, st);
+      rmk::launch_maxpy(p, V, P, j + 1, yv, R, 0, w, active, st);
+      rmk::launch_mreduce(p, partial, j + 1, nslot, active, Hj, ldh, 0, true, st);
+      rmk::launch_mdot(p, w, P, 1, w, active, partial, nslot, st);
+      rmk::launch_mreduce(p, partial, 1, nslot, active, hn2, 1, 0, false, st);
+      rmk::launch_scale(p, w, hn2, 1, V + (int64_t)(j + 1) * P, active, st);
+      rmk::launch_fgm_givens(B, j, R, H, hn2, cs, sn, g, r2b2, fo->tol, fo->max_iter, iters, jdone, active, est, st);
+      RM_TRY(any_active());
+      if (count() == 0) break;
+    }
+    rmk::launch_fgm_backsolve(B, R, H, g, jdone, yv, st);
+    rmk::launch_fgm_xupdate(p, Z, P, yv, R, jdone, x, st);
+  }
+  RM_TRY(last_launch());
+  std::vector<int> h_it((size_t)B), h_st((size_t)B);
+  std::vector<double> h_rel((size_t)B);
+  RM_HIP(hipMemcpy(h_it.data(), iters, (size_t)B * sizeof(int), hipMemcpyDeviceToHost));
+  RM_HIP(hipMemcpy(h_st.data(), status, (size_t)B * sizeof(int), hipMemcpyDeviceToHost));
+  RM_HIP(hipMemcpy(h_rel.data(), relres, (size_t)B * sizeof(double), hipMemcpyDeviceToHost));
+  rm_status worst = RM_OK;
+  for (int b0 = 0; b0 < B; ++b0) {
+    if (rep != nullptr) {
+      if (rep->outer_iters) rep->outer_iters[b0] = h_it[b0];
+      if (rep->rounds) rep->rounds[b0] = h_round[b0];
+      if (rep->relres) rep->relres[b0] = h_rel[b0];
+      if (rep->status) rep->status[b0] = h_st[b0];
+    }
+    if (h_st[b0] == RM_EDIVERGED) worst = RM_EDIVERGED;
+    else if (h_st[b0] == RM_ENOTCONV && worst == RM_OK) worst = RM_ENOTCONV;
+  }
+  if (worst != RM_OK) g_last_error = "some instances did not reach tol";
+  return worst;
 }
 
 rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t T, int32_t cw) {

@@ -162,6 +162,33 @@ void launch_adj_ssor_step(int method, const PlanDev& p, const float* omega, cons
                           const float* vb, float* ub_out, float* vb_out, float* fb, double* partial4,
                           hipStream_t st);
 
+// ---- batched flexible GMRES (rm_krylov.hip) -----------------------------------
+// partial[i * nslot + slot] = per-tile dot of w with V + i * stride, i < nvec (active
+// instances only).
+void launch_mdot(const PlanDev& p, const double* V, int64_t stride, int nvec, const double* w, const int* active,
+                 double* partial, int nslot, hipStream_t st);
+// out[b * ldo + col0 + i] = (or +=) the instance's sum of those partials, in tile order.
+void launch_mreduce(const PlanDev& p, const double* partial, int nvec, int nslot, const int* active, double* out,
+                    int ldo, int col0, bool accumulate, hipStream_t st);
+// w -= sum_i h[b * ldh + col0 + i] (V + i * stride).
+void launch_maxpy(const PlanDev& p, const double* V, int64_t stride, int nvec, const double* h, int ldh, int col0,
+                  double* w, const int* active, hipStream_t st);
+// dst = src / sqrt(nrm2[b * ldn]) (0 for a zero norm).
+void launch_scale(const PlanDev& p, const double* src, const double* nrm2, int ldn, double* dst, const int* active,
+                  hipStream_t st);
+void launch_f32_to_f64(const float* s, double* d, int64_t count, hipStream_t st);
+// Per-instance cycle start, Givens step, back substitution and x += Z y; H is
+// [B][restart columns][restart + 1], g [B][restart + 1], cs, sn, y [B][restart].
+void launch_fgm_start(int B, const double* r2b2, double tol, int max_iter, const int* iters, int* running,
+                      int* active, int* status, double* relres, double* g, int ldg, int* jdone, hipStream_t st);
+void launch_fgm_givens(int B, int j, int restart, double* H, const double* hn2, double* cs, double* sn, double* g,
+                       const double* r2b2, double tol, int max_iter, int* iters, int* jdone, int* active, double* est,
+                       hipStream_t st);
+void launch_fgm_backsolve(int B, int restart, const double* H, const double* g, const int* jdone, double* y,
+                          hipStream_t st);
+void launch_fgm_xupdate(const PlanDev& p, const float* Z, int64_t stride, const double* y, int restart,
+                        const int* jdone, double* x, hipStream_t st);
+
 // ---- two-grid correction (rm_twogrid.hip) -------------------------------------
 // Largest FFT length n + 1 of the coarse sine transform.
 constexpr int kTgMaxFFT = 1024;

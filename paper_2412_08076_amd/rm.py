@@ -16,7 +16,7 @@ from ._lib import (RM_EDIVERGED, RM_ENOTCONV, RM_F32, RM_F64, RM_FD5_HELMHOLTZ, 
 
 __all__ = [
     "RMError", "Context", "Plan", "rm_tune", "rm_apply_A", "rm_residual", "rm_solve", "rm_solve_adjoint",
-    "rm_twogrid_solve", "rm_twogrid_adjoint",
+    "rm_twogrid_solve", "rm_twogrid_adjoint", "rm_fgmres",
     "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count", "solve_opts",
     "RM_Q1_ANISO", "RM_FD5_HELMHOLTZ", "RM_RICHARDSON", "RM_NAG", "RM_MOM", "RM_NAGEX", "RM_F32", "RM_F64",
     "RM_UNROLL", "RM_TO_TOL", "RM_OK", "RM_ENOTCONV", "RM_EDIVERGED",
@@ -272,6 +272,38 @@ def rm_twogrid_adjoint(ctx, plan, method, opts, omega, alpha, symbol, b, ckpt, d
         _ptr(d_symbol, torch.float32, Pc, "d_symbol"), _ptr(d_b, torch.float32, P, "d_b"),
         _ptr(loss, torch.float32, B, "loss"))
     _check(st, "rm_twogrid_adjoint")
+
+
+def rm_fgmres(ctx, plan, b, x, restart=20, max_iter=200, tol=1e-6, method=RM_NAG, inner=None, omega=None,
+              alpha=None, symbol=None):
+    """Batched FGMRES; blocks and returns the per-instance report like rm_solve(TO_TOL)."""
+    B = plan.B
+    fo = _lib.rm_fgmres_opts(restart, max_iter, tol)
+    om = al = sy = None
+    if inner is not None:
+        m = inner.m
+        na = 2 if method == RM_NAGEX else 1
+        om = _ptr(omega, torch.float32, B * m, "omega")
+        al = _ptr(alpha, torch.float32, na * B * m, "alpha") if alpha is not None else None
+        sy = _ptr(symbol, torch.float32, plan.coarse_points(), "symbol") if symbol is not None else None
+    outer = (ctypes.c_int32 * B)()
+    rounds = (ctypes.c_int32 * B)()
+    relres = (ctypes.c_double * B)()
+    status = (ctypes.c_int32 * B)()
+    rep = _lib.rm_report(outer, rounds, relres, status)
+    st = ctx.lib.rm_fgmres(ctx.handle, plan.handle, ctypes.byref(fo), method,
+                           ctypes.byref(inner) if inner is not None else None, om, al, sy,
+                           _ptr(b, torch.float64, plan.P, "b"), _ptr(x, torch.float64, plan.P, "x"),
+                           ctypes.byref(rep))
+    if st not in (RM_OK, RM_ENOTCONV, RM_EDIVERGED):
+        _check(st, "rm_fgmres")
+    return {
+        "status": st,
+        "outer_iters": np.frombuffer(outer, dtype=np.int32).copy(),
+        "rounds": np.frombuffer(rounds, dtype=np.int32).copy(),
+        "relres": np.frombuffer(relres, dtype=np.float64).copy(),
+        "inst_status": np.frombuffer(status, dtype=np.int32).copy(),
+    }
 
 
 def rm_meta_param_count(m):
