@@ -292,6 +292,8 @@ def secondary_workload(name, tune_cache):
         return twogrid_workload(ctx, tune_cache)
     if name == "ssor":
         return ssor_workload(ctx)
+    if name == "fgmres":
+        return fgmres_workload(ctx, tune_cache)
     m = 16
     if name == "train":
         batch = aniso_batch(64, 127, seed=3)
@@ -395,6 +397,50 @@ def ssor_workload(ctx, m=3, relax=1.0, w=1.2, a=0.96):
             "to_tol_glups": float(np.sum(steps) * N * N) / tt / 1e9}
 
 
+def _helmholtz_setup(ctx, m):
+    """Plan, stand-in smoother weights and coarse symbol of the two-grid Helmholtz batch."""
+    import torch
+    from paper_2412_08076_amd import rm
+    from synthetic import helmholtz_batch, smoothing_weights, twogrid_symbol
+    batch = helmholtz_batch(32, 511, seed=5)
+    plan = rm.Plan(ctx, batch.n, kappa=batch.kappa, op=rm.RM_FD5_HELMHOLTZ)
+    Bn = plan.B
+    _, G = plan.coefficients()
+    om = torch.tensor(np.stack([smoothing_weights(G[b], m) for b in range(Bn)]).ravel(), dtype=torch.float32,
+                      device="cuda")
+    al = torch.full((Bn * m,), 0.1, dtype=torch.float32, device="cuda")
+    coff = plan.coarse_offsets()
+    sym = np.zeros(plan.coarse_points())
+    for b in range(Bn):
+        s_b = twogrid_symbol(batch.kappa[b], batch.n[b])
+        sym[coff[b]:coff[b] + s_b.size] = s_b.ravel()
+    return batch, plan, om, al, torch.tensor(sym, dtype=torch.float32, device="cuda")
+
+
+def fgmres_workload(ctx, tune_cache, m=8):
+    """FGMRES(20) on the two-grid Helmholtz batch (32 problems, n = 511), preconditioned by
+    one two-grid cycle (NAG-Richardson(8) smoothing + sine-transform correction), to 1e-6
+    and to 1e-10."""
+    import torch
+    from paper_2412_08076_amd import rm
+    batch, plan, om, al, sym = _helmholtz_setup(ctx, m)
+    b64 = torch.as_tensor(batch.f_packed()).cuda()
+    rm.rm_tune(ctx, plan, rm.RM_NAG, m, om, al, b64.float(), cache_path=tune_cache)
+    inner = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=1)
+    out = {"workload": "fgmres", "config": "Helmholtz B=32 n=511 kappa~U(20,80), FGMRES(20) in FP64 preconditioned "
+           "by one FP32 two-grid cycle (NAG-Richardson(8) smoothing + sine-transform coarse correction)"}
+    for tol in (1e-6, 1e-10):
+        x = torch.zeros_like(b64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = rm.rm_fgmres(ctx, plan, b64, x, restart=20, max_iter=400, tol=tol, method=rm.RM_NAG, inner=inner,
+                           omega=om, alpha=al, symbol=sym)
+        tt = time.perf_counter() - t0
+        out[f"tol_{tol:g}"] = {"s": tt, "status": int(rep["status"]), "iters_median": float(np.median(rep["outer_iters"])),
+                               "iters_max": int(rep["outer_iters"].max()), "relres_max": float(rep["relres"].max())}
+    return out
+
+
 def twogrid_workload(ctx, tune_cache, K=4, m=8, reps=5):
     """Two-grid Helmholtz: 32 problems, n = 511, kappa ~ U(20, 80), Gaussian point
     sources; K cycles of NAG-Richardson(8) smoothing (Chebyshev weights on the upper
@@ -466,7 +512,7 @@ def main():
     ap.add_argument("--no-comparator", action="store_true", help="skip the plain FP64 loop comparator")
     ap.add_argument("--kernel-config", default=None,
                     help="variant,T,width of the sweep kernel instead of autotuning (e.g. 3,8,64)")
-    ap.add_argument("--workload", default="aniso", choices=["aniso", "uneven", "train", "single", "twogrid", "ssor"],
+    ap.add_argument("--workload", default="aniso", choices=["aniso", "uneven", "train", "single", "twogrid", "ssor", "fgmres"],
                     help="aniso (default, the headline line) or one of the secondary shapes")
     args = ap.parse_args()
     if args.workload != "aniso":

@@ -1379,9 +1379,6 @@ rm_status rm_fgmres(rm_ctx* ctx, const rm_plan_t* plan, const rm_fgmres_opts* fo
   int* status = running + B;
   double* partial = fg.partial.as<double>();
   const PlanDev p = pl->dev();
-  // finished instances keep flowing through the preconditioner: give their basis
-  // vectors defined contents
-  rmk::launch_fill_f64(V, 0.0, (int64_t)(R + 1) * P, st);
   rmk::launch_fill_i32(iters, 0, B, st);
   rmk::launch_fill_i32(running, 1, B, st);
   rmk::launch_fill_i32(status, RM_ENOTCONV, B, st);
@@ -1410,7 +1407,8 @@ rm_status rm_fgmres(rm_ctx* ctx, const rm_plan_t* plan, const rm_fgmres_opts* fo
       double* Vj = V + (int64_t)j * P;
       float* Zj = Z + (int64_t)j * P;
       // z_j = M(v_j): the FP32 preconditioner applied to A z = fl32(v_j) from z = 0
-      rmk::launch_f64_to_f32(Vj, b32, P, st);
+      // (instances outside this cycle get a zero right-hand side, whatever Vj holds)
+      rmk::launch_to_f32_masked(p, Vj, b32, active, st);
       if (inner == nullptr) {
         RM_HIP(hipMemcpyAsync(Zj, b32, P * sizeof(float), hipMemcpyDeviceToDevice, st));
       } else {

@@ -177,6 +177,8 @@ void launch_maxpy(const PlanDev& p, const double* V, int64_t stride, int nvec, c
 void launch_scale(const PlanDev& p, const double* src, const double* nrm2, int ldn, double* dst, const int* active,
                   hipStream_t st);
 void launch_f32_to_f64(const float* s, double* d, int64_t count, hipStream_t st);
+// dst = fl32(src) for active instances, 0 for the others.
+void launch_to_f32_masked(const PlanDev& p, const double* src, float* dst, const int* active, hipStream_t st);
 // Per-instance cycle start, Givens step, back substitution and x += Z y; H is
 // [B][restart columns][restart + 1], g [B][restart + 1], cs, sn, y [B][restart].
 void launch_fgm_start(int B, const double* r2b2, double tol, int max_iter, const int* iters, int* running,

@@ -71,20 +71,25 @@ __global__ __launch_bounds__(WG) void k_mdot(PlanDev p, const double* __restrict
   }
 }
 
-// out[b * ldo + col0 + i] (+)= sum over the instance's tiles, in tile order, of
-// partial[i * nslot + slot]; one thread per (instance, vector).
-__global__ void k_mreduce(PlanDev p, const double* __restrict__ partial, int nvec, int nslot,
-                          const int* __restrict__ active, double* __restrict__ out, int ldo, int col0,
-                          int accumulate) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= p.B * nvec) return;
+// out[b * ldo + col0 + i] (+)= sum over the instance's tiles of partial[i * nslot + slot]:
+// one wave per (instance, vector), lanes striding over the tiles in order, then a
+// fixed shuffle tree (deterministic).
+__global__ __launch_bounds__(64) void k_mreduce(PlanDev p, const double* __restrict__ partial, int nvec, int nslot,
+                                                const int* __restrict__ active, double* __restrict__ out, int ldo,
+                                                int col0, int accumulate) {
+  const int t = blockIdx.x;
   const int b = t / nvec, i = t - b * nvec;
   if (active[b] == 0) return;
   const Inst in = p.inst[b];
   double s = 0.0;
-  for (int k = in.tile_begin; k < in.tile_end; ++k) s += partial[(int64_t)i * nslot + p.tiles[k].pad];
-  double* o = out + (int64_t)b * ldo + col0 + i;
-  *o = accumulate ? *o + s : s;
+  for (int k = in.tile_begin + (int)threadIdx.x; k < in.tile_end; k += 64)
+    s += partial[(int64_t)i * nslot + p.tiles[k].pad];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (threadIdx.x == 0) {
+    double* o = out + (int64_t)b * ldo + col0 + i;
+    *o = accumulate ? *o + s : s;
+  }
 }
 
 // w -= sum_i h[b * ldh + col0 + i] V_i over the plan's tiles.
@@ -130,6 +135,26 @@ __global__ __launch_bounds__(WG) void k_scale(PlanDev p, const double* __restric
     if (gy >= n) break;
     const int64_t idx = in.off + (int64_t)gy * n + gx;
     dst[idx] = src[idx] * inv;
+  }
+}
+
+// dst = fl32(src) on the instances in the current cycle, 0 on the others.
+__global__ __launch_bounds__(WG) void k_to_f32_masked(PlanDev p, const double* __restrict__ src,
+                                                      float* __restrict__ dst, const int* __restrict__ active) {
+  const Tile tl = p.tiles[xcd_remap(blockIdx.x, gridDim.x)];
+  if (tl.inst < 0) return;
+  const Inst in = p.inst[tl.inst];
+  const int n = in.n;
+  const bool on = active[tl.inst] != 0;
+  const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+  const int gx = tl.x0 + tx;
+  if (gx >= n) return;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int gy = tl.y0 + ty0 + NW * k;
+    if (gy >= n) break;
+    const int64_t idx = in.off + (int64_t)gy * n + gx;
+    dst[idx] = on ? (float)src[idx] : 0.f;
   }
 }
 
@@ -262,8 +287,7 @@ void launch_mdot(const PlanDev& p, const double* V, int64_t stride, int nvec, co
 }
 void launch_mreduce(const PlanDev& p, const double* partial, int nvec, int nslot, const int* active, double* out,
                     int ldo, int col0, bool accumulate, hipStream_t st) {
-  const int n = p.B * nvec;
-  hipLaunchKernelGGL(k_mreduce, dim3((n + 63) / 64), dim3(64), 0, st, p, partial, nvec, nslot, active, out, ldo, col0,
+  hipLaunchKernelGGL(k_mreduce, dim3(p.B * nvec), dim3(64), 0, st, p, partial, nvec, nslot, active, out, ldo, col0,
                      accumulate ? 1 : 0);
 }
 void launch_maxpy(const PlanDev& p, const double* V, int64_t stride, int nvec, const double* h, int ldh, int col0,
@@ -273,6 +297,9 @@ void launch_maxpy(const PlanDev& p, const double* V, int64_t stride, int nvec, c
 void launch_scale(const PlanDev& p, const double* src, const double* nrm2, int ldn, double* dst, const int* active,
                   hipStream_t st) {
   hipLaunchKernelGGL(k_scale, dim3(p.ntiles), dim3(WG), 0, st, p, src, nrm2, ldn, dst, active);
+}
+void launch_to_f32_masked(const PlanDev& p, const double* src, float* dst, const int* active, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_f32_masked, dim3(p.ntiles), dim3(WG), 0, st, p, src, dst, active);
 }
 void launch_f32_to_f64(const float* s, double* d, int64_t count, hipStream_t st) {
   hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, s, d, count);
