@@ -162,8 +162,9 @@ rm_status rm_plan_coefficients(const rm_plan_t* plan, double* coef, double* gers
  * tile is computed without redundancy.  Kernel variant `shape` fixes R and the
  * largest cw: 0: R = 8, cw <= 64; 1: R = 16, cw <= 64; 2: R = 8, cw <= 128;
  * 3: R = 13, cw <= 64; 4: R = 16, cw <= 128; 5: R = 12, cw <= 96;
- * 6: R = 13, cw <= 104.  rm_plan picks a configuration per class from a cost
- * model; rm_tune measures.
+ * 6: R = 13, cw <= 104; 7: R = 32, cw <= 64; 8: R = 32, cw <= 96 (a 256-row tile
+ * covers n <= 256 without a vertical halo).  rm_plan picks a configuration per class
+ * from a cost model; rm_tune measures.
  * rm_plan_set_kernel: set (shape, T, cw) for the class of size n (n <= 0: all
  * classes; cw <= 0: the width the cost model prefers; 1 <= T <= 64); shape = -1
  * switches the whole plan to one launch per inner step.  RM_EINVAL if the halo

@@ -87,7 +87,7 @@ __device__ __forceinline__ void strip_walk(const float* B, int lc, int lr0, F&& 
 // states + t * state_stride (u) and + state_stride / 2 (v) for t = 0 .. T - 2 (the
 // adjoint's forward recompute keeps every intermediate state).
 template <int R, int LW, int WPE, int METHOD, bool STORE>
-__global__ __attribute__((amdgpu_flat_work_group_size(64, 1024), amdgpu_waves_per_eu(WPE))) void k_block(
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 8 * (LW - 2)), amdgpu_waves_per_eu(WPE))) void k_block(
     PlanDev p, const BTile* __restrict__ tiles, int ntiles, int T, int CW, const float* __restrict__ omega,
     const float* __restrict__ alpha, int m, int s0, const float* __restrict__ f, const float* __restrict__ u,
     const float* __restrict__ v, float* __restrict__ u_out, float* __restrict__ v_out,
@@ -249,6 +249,8 @@ const BlockVariant kBlockVariants[kNumBlockVariants] = {
     {16, 130},  // up to 128 x 128
     {12, 98},   // up to 96 x 96
     {13, 106},  // up to 104 x 104
+    {32, 66},   // up to 64 x 256: one tile covers n <= 256 vertically (no y halo)
+    {32, 98},   // up to 96 x 256
 };
 
 bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, const BTile* tiles, int ntiles,
@@ -262,7 +264,8 @@ bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, cons
     launch_variant<R, LW, WPE>(T, cw, method, p, tiles, ntiles, omega, alpha, m, s0, f, u, v, u_out, v_out, \
                                active, partial2, states, state_stride, st);                                   \
     return true;
-  // register caps (waves per SIMD) chosen so that two or three workgroups fit on a CU
+  // register caps (waves per SIMD) chosen so that two or three workgroups fit on a CU;
+  // the 32-row strips need 168 registers and run one workgroup per CU
   switch (variant) {
     RM_VARIANT_CASE(0, 8, 66, 8)
     RM_VARIANT_CASE(1, 16, 66, 4)
@@ -271,6 +274,8 @@ bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, cons
     RM_VARIANT_CASE(4, 16, 130, 4)
     RM_VARIANT_CASE(5, 12, 98, 6)
     RM_VARIANT_CASE(6, 13, 106, 6)
+    RM_VARIANT_CASE(7, 32, 66, 3)
+    RM_VARIANT_CASE(8, 32, 98, 3)
     default:
       return false;
   }

@@ -125,7 +125,7 @@ void launch_meta_backward(const PlanDev& p, int m, const float* params, const fl
 struct BlockVariant {
   int r, lw;
 };
-constexpr int kNumBlockVariants = 7;
+constexpr int kNumBlockVariants = 9;
 extern const BlockVariant kBlockVariants[kNumBlockVariants];
 
 // One extended tile of a block table: origin (x0, y0) of its CW x 8R window in

@@ -57,3 +57,30 @@ def test_host_only_entry_points(lib):
         _lib.RM_EINVAL
     assert b"null" in lib.rm_last_error()
     assert lib.rm_plan_points(None) == -1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof and field offsets of every struct in include/rm.h, compiled by gcc, equal
+    the ctypes declarations of the binding."""
+    structs = {
+        "rm_instance": _lib.rm_instance,
+        "rm_solve_opts": _lib.rm_solve_opts,
+        "rm_report": _lib.rm_report,
+        "rm_fgmres_opts": _lib.rm_fgmres_opts,
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                      check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)

@@ -57,7 +57,7 @@ def test_blocked_equals_one_step_bitwise(ctx, method_name, jacobi):
     f = dev(batch.f_packed(), torch.float32)
     plan.set_kernel(-1, 1)
     ref, ref_h, _ = _unroll(ctx, plan, method, om, al, f, m, K, hist=True, jacobi=jacobi)
-    for shape in range(7):
+    for shape in range(9):
         for T in (1, 2, 3, 8, 16):
             for cw in (0, 24, 64, 128):
                 try:
