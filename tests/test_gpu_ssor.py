@@ -156,3 +156,32 @@ def test_ssor_options_and_blocking_independence(ctx):
         outs.append(host(x))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+
+
+def test_unroll_loss_autograd_with_ssor(ctx):
+    """UnrollLoss with SSOR preconditioning: autograd gradients equal the oracle's."""
+    from paper_2412_08076_amd import rm
+    from paper_2412_08076_amd.autograd import UnrollLoss
+    ns = [17, 40]
+    batch = random_batch(ns, seed=73)
+    plan = plan_for(ctx, batch)
+    m, K, E, relax = 3, 6, 3, 1.2
+    om, al, at = _weights(batch.B, m, 9)
+    f32 = batch.f_packed().astype(np.float32)
+    omega = dev(om, torch.float32).requires_grad_(True)
+    alpha = dev(np.stack([al, at]), torch.float32).requires_grad_(True)
+    b = dev(f32, torch.float32).requires_grad_(True)
+    loss = UnrollLoss.apply(omega, alpha, b, ctx, plan, rm.RM_NAGEX, m, K, E, ("ssor", relax))
+    loss.sum().backward()
+    gb = unpack_vec(host(b.grad), ns)
+    fs = unpack_vec(f32.astype(np.float64), ns)
+    ga_all = host(alpha.grad)
+    for i in range(batch.B):
+        c = oracle_coef(batch, i)
+        L, gw, ga, gat, gf = adjoint.loss_and_grads_general("nagex", c, fs[i], om[i], K, alpha=al[i], alpha_t=at[i],
+                                                            binv=precond.ssor_binv(c, float(np.float32(relax))))
+        rel = lambda got, want: np.max(np.abs(got - want)) / np.max(np.abs(want))
+        assert abs(host(loss)[i] - L) <= 1e-5 * L
+        assert rel(host(omega.grad)[i], gw) <= 1e-4
+        assert rel(ga_all[0, i], ga) <= 1e-4 and rel(ga_all[1, i], gat) <= 1e-4
+        assert rel(gb[i], gf) <= 1e-4

@@ -247,3 +247,37 @@ def test_twogrid_full_size_sampled(ctx):
             say("  instance", b, "kappa", round(batch.kappa[b], 2), "relres", rr, rr_gpu, "err", err)
             assert err <= 1e-5
             assert abs(rr_gpu - rr) <= 1e-5 * max(1.0, rr)
+
+
+def test_twogrid_autograd_function(ctx):
+    """TwoGridLoss: weighted per-instance losses back-propagated through torch autograd
+    equal the oracle's gradients for omega, alpha, the symbol and b."""
+    from paper_2412_08076_amd import rm
+    from paper_2412_08076_amd.autograd import TwoGridLoss
+    ns = [15, 31, 63]
+    batch = _batch(ns, seed=71)
+    plan = plan_for(ctx, batch)
+    m, K = 3, 2
+    om, al, _, syms = _inputs(batch, m, 8, resonant=False)
+    sym_d, coff = _symbol_dev(plan, syms)
+    f32 = batch.f_packed().astype(np.float32)
+    omega = dev(om, torch.float32).requires_grad_(True)
+    alpha = dev(al, torch.float32).requires_grad_(True)
+    symbol = sym_d.clone().requires_grad_(True)
+    b = dev(f32, torch.float32).requires_grad_(True)
+    wts = torch.tensor([0.5, 1.0, 2.0], dtype=torch.float32, device="cuda")
+    loss = TwoGridLoss.apply(omega, alpha, symbol, b, ctx, plan, rm.RM_NAG, m, K)
+    (loss * wts).sum().backward()
+    gb = unpack_vec(host(b.grad), ns)
+    fs = unpack_vec(f32.astype(np.float64), ns)
+    for i in range(batch.B):
+        c = oracle_coef(batch, i)
+        L, gw, ga, gat, gs, gf = twogrid.loss_and_grads("nag", c, fs[i], om[i], syms[i], K, alpha=al[i])
+        w = float(wts[i])
+        nc = (ns[i] - 1) // 2
+        rel = lambda got, want: np.max(np.abs(got - want)) / np.max(np.abs(want))
+        assert abs(host(loss)[i] - L) <= 1e-5 * L
+        assert rel(host(omega.grad)[i], w * gw) <= 1e-4
+        assert rel(host(alpha.grad)[i], w * (ga + gat)) <= 1e-4
+        assert rel(host(symbol.grad)[coff[i]:coff[i] + nc * nc].reshape(nc, nc), w * gs) <= 1e-4
+        assert rel(gb[i], w * gf) <= 1e-4
