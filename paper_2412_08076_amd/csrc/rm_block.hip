@@ -28,25 +28,13 @@
 // The update is evaluated with the same fused multiply-add sequence as the
 // one-step kernel, so a launch of T steps reproduces T one-step launches bit
 // for bit.
-#include "rm_internal.h"
+#include "rm_device.h"
 
 #pragma clang fp contract(off)
 
 namespace rmk {
 
 namespace {
-
-__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
-__device__ __forceinline__ float stencil9f(const float c[5], float C, float W, float E, float S, float N, float SW,
-                                           float NE, float SE, float NW) {
-  float acc = c[0] * C;
-  acc = fmadd(c[1], W + E, acc);
-  acc = fmadd(c[2], S + N, acc);
-  acc = fmadd(c[3], SW + NE, acc);
-  acc = fmadd(c[4], SE + NW, acc);
-  return acc;
-}
 
 // New momentum with the weight folded into the stencil (the same sequence as the
 // one-step kernel): v' = a v + w f - sum_j (w c_j) s_j.
@@ -190,7 +178,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 8 * (LW - 2)), amdgpu_
                                       float SE, float NW) {
       const int gy = gy0 + k;
       if (colown && gy >= tl.oy0 && gy < tl.oy1) {
-        const float r = rf[k] - stencil9f(c, C, W, E, S, N, SW, NE, SE, NW);
+        const float r = rf[k] - stencil9<float>(c, C, W, E, S, N, SW, NE, SE, NW);
         r2 += (double)r * (double)r;
       }
     });

@@ -1,0 +1,72 @@
+// Device helpers shared by the kernel files (internal).  Every kernel that evaluates
+// the stencil uses stencil9's fixed order of operations, so different kernels that
+// apply the same update produce the same bits.
+#pragma once
+
+#include "rm_internal.h"
+
+namespace rmk {
+namespace {
+
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Tile tables are padded to a multiple of 8 entries; hardware dispatches workgroups
+// round robin over the 8 XCDs, so XCD k (blocks bid = k mod 8) takes the contiguous
+// range [k * nb / 8, (k + 1) * nb / 8) and neighbouring tiles share one L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+  const int per = nb >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+// Weighted 9-point sum in a fixed order: C centre, W/E = x -+ 1, S/N = y -+ 1, then
+// the diagonal pairs (1,1)/(-1,-1) and (-1,1)/(1,-1).
+template <typename T>
+__device__ __forceinline__ T stencil9(const T c[5], T C, T W, T E, T S, T N, T SW, T NE, T SE, T NW) {
+  T acc = c[0] * C;
+  acc = fmadd(c[1], W + E, acc);
+  acc = fmadd(c[2], S + N, acc);
+  acc = fmadd(c[3], SW + NE, acc);
+  acc = fmadd(c[4], SE + NW, acc);
+  return acc;
+}
+
+// The five stencil coefficients of instance b in the precision of T.
+template <typename T>
+__device__ __forceinline__ void load_coef(const PlanDev& p, int b, T c[5]);
+template <>
+__device__ __forceinline__ void load_coef<float>(const PlanDev& p, int b, float c[5]) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) c[k] = p.coef32[b * 8 + k];
+}
+template <>
+__device__ __forceinline__ void load_coef<double>(const PlanDev& p, int b, double c[5]) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) c[k] = p.coef64[b * 8 + k];
+}
+
+// Sum over a workgroup of WG threads in a fixed order (shuffle tree per wave, then the
+// waves in order); the result is valid in thread 0.  Safe to call repeatedly.
+__device__ __forceinline__ double block_sum(double x, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = x;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < WG / 64; ++k) r += sh[k];
+  }
+  return r;
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+}  // namespace
+}  // namespace rmk

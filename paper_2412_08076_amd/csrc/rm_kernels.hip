@@ -21,7 +21,7 @@
 // All floating-point combinations are written as explicit fused multiply-adds
 // with contraction switched off, so the single-step, adjoint-recompute and any
 // other kernel that evaluates the same stencil produce identical bits.
-#include "rm_internal.h"
+#include "rm_device.h"
 
 #pragma clang fp contract(off)
 
@@ -32,27 +32,6 @@ namespace {
 constexpr int LDS_W = TX + 2;
 constexpr int RPT = TY / (WG / TX);  // rows per thread
 constexpr int NWAVE = WG / 64;
-
-__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-__device__ __forceinline__ int xcd_remap(int bid, int nb) {
-  // nb is a multiple of 8: XCD k (blocks bid = k mod 8) gets the contiguous range
-  // [k * nb / 8, (k + 1) * nb / 8) of the tile table.
-  const int per = nb >> 3;
-  return (bid & 7) * per + (bid >> 3);
-}
-
-// Weighted 9-point sum in a fixed order: C centre, W/E = x -+ 1, S/N = y -+ 1.
-template <typename T>
-__device__ __forceinline__ T stencil9(const T c[5], T C, T W, T E, T S, T N, T SW, T NE, T SE, T NW) {
-  T acc = c[0] * C;
-  acc = fmadd(c[1], W + E, acc);
-  acc = fmadd(c[2], S + N, acc);
-  acc = fmadd(c[3], SW + NE, acc);
-  acc = fmadd(c[4], SE + NW, acc);
-  return acc;
-}
 
 // One inner step's new momentum at a point, with the weight folded into the
 // stencil: v' = a v + w f - sum_j (w c_j) s_j, where wc[j] = w c_j and the s_j are
@@ -100,40 +79,6 @@ __device__ __forceinline__ void stage_halo(T* s, int x0, int y0, int n, F&& val)
     const bool in = (gx >= 0) && (gx < n) && (gy >= 0) && (gy < n);
     s[hy * LDS_W + hx] = in ? val(gx, gy) : T(0);
   }
-}
-
-template <typename T>
-__device__ __forceinline__ void load_coef(const PlanDev& p, int b, T c[5]);
-template <>
-__device__ __forceinline__ void load_coef<float>(const PlanDev& p, int b, float c[5]) {
-#pragma unroll
-  for (int k = 0; k < 5; ++k) c[k] = p.coef32[b * 8 + k];
-}
-template <>
-__device__ __forceinline__ void load_coef<double>(const PlanDev& p, int b, double c[5]) {
-#pragma unroll
-  for (int k = 0; k < 5; ++k) c[k] = p.coef64[b * 8 + k];
-}
-
-// Sum over the workgroup (fixed order); the result is valid in thread 0.
-__device__ __forceinline__ double block_sum(double x, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) sh[w] = x;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NWAVE; ++k) r += sh[k];
-  }
-  return r;
-}
-
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
 }
 
 // ---------------------------------------------------------------------------

@@ -8,7 +8,7 @@
 // every basis vector (w read once into registers), a second sums them per instance in
 // tile order (deterministic), a third subtracts.  The small per-instance algebra
 // (Givens rotations, residual estimate, back substitution) runs one thread per instance.
-#include "rm_internal.h"
+#include "rm_device.h"
 
 #pragma clang fp contract(off)
 
@@ -18,26 +18,6 @@ namespace {
 
 constexpr int NW = WG / 64;
 constexpr int RPT = TY / NW;  // rows per thread of a 64 x 32 tile
-
-__device__ __forceinline__ int xcd_remap(int bid, int nb) {
-  const int per = nb >> 3;
-  return (bid & 7) * per + (bid >> 3);
-}
-
-__device__ __forceinline__ double block_sum(double x, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[w] = x;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NW; ++k) r += sh[k];
-  }
-  return r;
-}
 
 // partial[i * nslot + slot] = sum over the tile of w * V_i, i < nvec (V_i = V + i * stride).
 __global__ __launch_bounds__(WG) void k_mdot(PlanDev p, const double* __restrict__ V, int64_t stride, int nvec,

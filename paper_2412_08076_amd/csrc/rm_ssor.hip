@@ -17,21 +17,13 @@
 // region carries a halo of 6 (7 for the look-ahead field the residual needs) and is
 // swept in place.  Points outside the domain hold 0 and are never updated (Dirichlet).
 // Temporal blocking would need a halo of 7 per step, so none is attempted.
-#include "rm_internal.h"
+#include "rm_device.h"
 
 #pragma clang fp contract(off)
 
 namespace rmk {
 
 namespace {
-
-__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-__device__ __forceinline__ int xcd_remap(int bid, int nb) {
-  const int per = nb >> 3;
-  return (bid & 7) * per + (bid >> 3);
-}
 
 constexpr int HR = 6;               // halo of the swept region
 constexpr int HU = HR + 1;          // halo of the field the residual is formed from
@@ -43,19 +35,6 @@ constexpr int UW = TX + 2 * HU;     // 78 x 46 (= PW x PH)
 constexpr int UH = TY + 2 * HU;
 constexpr int NW = WG / 64;
 static_assert(UW == PW && UH == PH, "the padded region and the residual input coincide");
-
-template <typename T>
-__device__ __forceinline__ void load_coef5(const PlanDev& p, int b, T c[5]);
-template <>
-__device__ __forceinline__ void load_coef5<float>(const PlanDev& p, int b, float c[5]) {
-#pragma unroll
-  for (int k = 0; k < 5; ++k) c[k] = p.coef32[b * 8 + k];
-}
-template <>
-__device__ __forceinline__ void load_coef5<double>(const PlanDev& p, int b, double c[5]) {
-#pragma unroll
-  for (int k = 0; k < 5; ++k) c[k] = p.coef64[b * 8 + k];
-}
 
 // In-place SSOR sweeps on a padded LDS field s: a W x H region (W, H even) at offset
 // (1, 1) of a (W + 2)-wide array whose outer ring is 0; region origin (ox, oy) in
@@ -115,21 +94,6 @@ __device__ __forceinline__ T stencil_at(const T* q, int W, const T c[5]) {
   return acc;
 }
 
-// Sum over the workgroup in a fixed order; valid in thread 0.
-__device__ __forceinline__ double block_sum(double x, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) sh[w] = x;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NW; ++k) r += sh[k];
-  }
-  return r;
-}
-
 // One SSOR-preconditioned inner step (NAGex form):
 //   u~ = u + at v;  r = f - A u~;  v' = a v + w B^{-1} r;  u' = u + v'.
 template <typename T, int METHOD>
@@ -148,7 +112,7 @@ __global__ __launch_bounds__(WG) void k_ssor_step(PlanDev p, const Tile* __restr
   const Inst in = p.inst[bi];
   const int n = in.n;
   T c[5];
-  load_coef5<T>(p, bi, c);
+  load_coef<T>(p, bi, c);
   const T dinv = sizeof(T) == 4 ? (T)p.coef32[bi * 8 + 5] : (T)p.coef64[bi * 8 + 5];
   T w, a, at;
   step_factors<T, METHOD>(p, omega, alpha, m, bi, i, w, a, at);
@@ -219,7 +183,7 @@ __global__ __launch_bounds__(WG) void k_adj_ssor_step(PlanDev p, const float* __
   const Inst in = p.inst[bi];
   const int n = in.n;
   float c[5];
-  load_coef5<float>(p, bi, c);
+  load_coef<float>(p, bi, c);
   const float dinv = p.coef32[bi * 8 + 5];
   float w, a, at;
   step_factors<float, METHOD>(p, omega, alpha, m, bi, i, w, a, at);

@@ -23,20 +23,13 @@
 //                  right-hand-side gradient.
 // The coarse fields are a few percent of the fine traffic; the FFT stages are
 // LDS-bound at these lengths.
-#include "rm_internal.h"
+#include "rm_device.h"
 
 #pragma clang fp contract(off)
 
 namespace rmk {
 
 namespace {
-
-__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
-__device__ __forceinline__ int xcd_remap(int bid, int nb) {
-  const int per = nb >> 3;
-  return (bid & 7) * per + (bid >> 3);
-}
 
 // restriction tile: RT_X x RT_Y coarse points; the residual window around it is
 // (2 RT_X + 1) x (2 RT_Y + 1) fine points and needs u on one more ring
