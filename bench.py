@@ -30,6 +30,14 @@ sys.path.insert(0, ROOT)
 METRIC = "GLUP/s (stencil updates/s) fwd+adjoint, batched; time to 1e-10 rel residual"
 B, N, M, K_TRAIN, CKPT, TOL = 256, 255, 16, 64, 16, 1e-10
 HBM_PEAK_GBS = 8000.0
+# FP32 arithmetic rate without packed FP32 (disabled at compile time for this GPU):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop per FMA x 2.4 GHz
+FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# flops of one NAG-Richardson point update as the kernels evaluate it: v' = a v + w f
+# - sum_j (w c_j) s_j over the four symmetric pairs and the centre (1 mul + 1 FMA,
+# 4 pair adds, 5 FMAs), u' = u + v' (1 add), next look-ahead u + a' v' (1 FMA)
+FLOPS_PER_LUP_NAG = 20.0
+STREAM_SHAPE = 9
 # kernel choices of the autotuner for this workload (written by rm_tune on an MI355X)
 TUNE_CACHE = os.path.join(ROOT, "paper_2412_08076_amd", "tune_gfx950.json")
 BYTES_PER_LUP_NAG = 20.0  # read u, v, f; write u, v (FP32)
@@ -121,32 +129,47 @@ def plain_fp64_loop(batch, omega, alpha, sample, tol=TOL, max_outer=20000):
 
 
 # ----------------------------------------------------------------------------- roofline
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_block_nag_n255_B256_traffic.json")
+TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
+                 ("k_stream_nag_n255_B256_traffic.json", "k_block_nag_n255_B256_traffic.json")]
+
+
+def kernel_name(kcfg):
+    sh, T, cw = kcfg
+    if sh == STREAM_SHAPE:
+        return f"k_stream T={T} window={cw} n={N} B={B}"
+    return f"k_block variant {sh} T={T} width={cw} n={N} B={B}"
 
 
 def roofline(kstr, kcfg, t_step, P, copy_gbs):
     """Roofline entry of the dominant kernel (the temporal-blocked NAG sweep).
 
-    achieved: algorithmic bytes per launch / launch time, with 20 B per point per inner
-    step (read u, v, f and write u, v in FP32 -- the traffic of a sweep that keeps
-    nothing on chip between steps) and T steps per launch.  Temporal blocking makes the
-    actual DRAM traffic per launch one such sweep (20 B per point) for all T steps, so
-    frac can exceed 1.  traffic: DRAM bytes per launch from the FETCH_SIZE / WRITE_SIZE
-    counters scaled by a copy-kernel calibration, when a committed profile exists for
-    this exact kernel configuration, else null."""
+    The sweep keeps T steps on chip and moves one sweep's data per launch, so it is
+    bound by FP32 arithmetic, not HBM: achieved = algorithmic flops per launch (20 per
+    point update, T updates per point) / launch time, against the non-packed FP32 rate
+    derived from the unit counts and clock.  traffic: DRAM bytes per launch from the
+    FETCH_SIZE / WRITE_SIZE counters scaled by a copy-kernel calibration, when a
+    committed profile exists for this exact kernel configuration, else null.  The HBM
+    view is kept alongside: 20 B per point per step (the traffic of a sweep that keeps
+    nothing on chip) over the launch time, which exceeds the HBM peak by design."""
     T = kcfg[1]
     t_launch = t_step * T
-    alg = BYTES_PER_LUP_NAG * P * T
+    alg_bytes = BYTES_PER_LUP_NAG * P * T
+    flops = FLOPS_PER_LUP_NAG * P * T
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            prof = json.load(fh)
-        if prof.get("kernel") == kstr:
-            traffic = prof["dram_bytes_per_launch"]
-    achieved = alg / t_launch / 1e9
-    return {"bound": "hbm", "kernel": kstr, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "launch_us": t_launch * 1e6,
-            "algorithmic_bytes_per_launch": alg, "steps_per_launch": T,
+    for path in TRAFFIC_FILES:
+        if os.path.exists(path):
+            with open(path) as fh:
+                prof = json.load(fh)
+            if prof.get("kernel") == kstr:
+                traffic = prof["dram_bytes_per_launch"]
+    achieved = flops / t_launch / 1e12
+    hbm_eff = alg_bytes / t_launch / 1e9
+    return {"bound": "alu", "kernel": kstr, "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic, "launch_us": t_launch * 1e6,
+            "algorithmic_flops_per_launch": flops, "steps_per_launch": T,
+            "dram_GBs_at_traffic": (traffic / t_launch / 1e9) if traffic else None,
+            "hbm_effective": {"achieved": hbm_eff, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": hbm_eff / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg_bytes},
             "min_dram_bytes_per_launch": BYTES_PER_LUP_NAG * P, "measured_copy_GBs": copy_gbs}
 
 
@@ -542,7 +565,7 @@ def main():
     if args.kernel_only:
         kt = w.step_kernel_time()
         copy_gbs = w.copy_bandwidth()
-        kstr = f"k_block variant {kcfg[0]} T={kcfg[1]} width={kcfg[2]} n={N} B={B}"
+        kstr = kernel_name(kcfg)
         print(json.dumps({"kernel": kstr, "us_per_inner_step": kt * 1e6, "us_per_launch": kt * 1e6 * kcfg[1],
                           "algorithmic_bytes_per_launch": BYTES_PER_LUP_NAG * w.P * kcfg[1],
                           "copy_bytes": 2 * (1 << 30), "measured_copy_GBs": copy_gbs}), flush=True)
@@ -566,7 +589,7 @@ def main():
     ttol = float(np.mean([a.elapsed_time(b) / 1e3 for a, b in tol_times]))
     kt = w.step_kernel_time()
     copy_gbs = w.copy_bandwidth()
-    kstr = f"k_block variant {kcfg[0]} T={kcfg[1]} width={kcfg[2]} n={N} B={B}"
+    kstr = kernel_name(kcfg)
     comparator = None
     if not args.no_comparator:
         sample = [0, 85, 170, 255]
@@ -603,7 +626,8 @@ def main():
         "time_to_tol_s": ttol,
         "solve": {"status": int(rep["status"]), "outer_iters_median": float(np.median(rep["outer_iters"])),
                   "outer_iters_max": int(rep["outer_iters"].max()), "rounds_max": int(rep["rounds"].max()),
-                  "relres_max": float(rep["relres"].max())},
+                  "relres_max": float(rep["relres"].max()), "kernel": kstr,
+                  "tail_kernel": kernel_name(w.plan.get_tail_kernel(N))},
         "roofline": roofline(kstr, kcfg, kt, w.P, copy_gbs),
         "cpu_baseline": cpu,
         "plain_fp64_gpu_loop": comparator,

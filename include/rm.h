@@ -163,22 +163,46 @@ rm_status rm_plan_coefficients(const rm_plan_t* plan, double* coef, double* gers
  * largest cw: 0: R = 8, cw <= 64; 1: R = 16, cw <= 64; 2: R = 8, cw <= 128;
  * 3: R = 13, cw <= 64; 4: R = 16, cw <= 128; 5: R = 12, cw <= 96;
  * 6: R = 13, cw <= 104; 7: R = 32, cw <= 64; 8: R = 32, cw <= 96 (a 256-row tile
- * covers n <= 256 without a vertical halo).  rm_plan picks a configuration per class
- * from a cost model; rm_tune measures.
+ * covers n <= 256 without a vertical halo).  Shape 9 is the row-streaming kernel
+ * (n <= 512, T <= 8): one workgroup of 64 ceil(n / 64) threads holds whole rows and
+ * pipelines the T steps down a window of cw rows (cw >= n: the whole height, no
+ * halo; otherwise windows overlap by T + 1 rows).  rm_plan picks a configuration
+ * per class from a cost model; rm_tune measures.  All shapes reproduce one launch
+ * per inner step bit for bit.
  * rm_plan_set_kernel: set (shape, T, cw) for the class of size n (n <= 0: all
  * classes; cw <= 0: the width the cost model prefers; 1 <= T <= 64); shape = -1
- * switches the whole plan to one launch per inner step.  RM_EINVAL if the halo
- * or width does not fit the variant or no instance has size n. */
+ * switches the whole plan to one launch per inner step.  It also resets the
+ * class's tail configuration (below).  RM_EINVAL if the halo or width does not
+ * fit the variant or no instance has size n. */
 rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t T, int32_t cw);
 rm_status rm_plan_get_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, int32_t* T,
                              int32_t* cw);
 
+/* Tail configuration of a size class: the kernel the refined RM_TO_TOL solve uses
+ * once the fraction of instances still active drops below the switch point.  A
+ * row-streaming launch costs about the same for one active instance as for all of
+ * them, a tiled launch costs in proportion, so after rm_plan_set_kernel the tail is
+ * the main configuration, or the cost model's best tiled variant when the main one
+ * is row-streaming.  Same arguments and errors as rm_plan_set_kernel (shape >= 0).
+ * rm_plan_set_tail_switch: active fraction below which the tails run (frac <= 1;
+ * 0: never; 1: always; < 0, the default: the ratio rm_tune measured between the
+ * main configuration's launch with one instance active and the tail's with all
+ * active, or 0.35 before tuning).  Results do not depend on the switch: every
+ * configuration computes the same iterates. */
+rm_status rm_plan_set_tail_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t T, int32_t cw);
+rm_status rm_plan_get_tail_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, int32_t* T,
+                                  int32_t* cw);
+rm_status rm_plan_set_tail_switch(rm_plan_t* plan, double frac);
+
 /* Autotuner: for every size class, time each valid (shape, T, cw) on this plan's
  * data (16 inner steps of `method` with the given device weights and right-hand
- * side, best of 3) and keep the fastest.  cache_path (host string, may be NULL)
+ * side, best of 3) and keep the fastest as the main configuration and the fastest
+ * tiled one as the tail; when the main one is row-streaming, also time it with one
+ * instance active (the switch point).  cache_path (host string, may be NULL)
  * names a JSON file of choices keyed by "<gfx arch> n=<n> B=<class size>
- * m=<m> method=<method>": classes found there are not timed again, new results
- * are written back.  *us_per_step (may be NULL) receives the summed per-step
+ * m=<m> method=<method>", each [shape, T, cw, us, tail shape, tail T, tail cw,
+ * tail us, one-active us] (entries of only the first four keep the model's
+ * tail): classes found there are not timed again, new results are written back.  *us_per_step (may be NULL) receives the summed per-step
  * time of the chosen configurations in microseconds.  Blocks. */
 rm_status rm_tune(rm_ctx* ctx, rm_plan_t* plan, int32_t method, int32_t m, const float* omega,
                   const float* alpha, const float* b, const char* cache_path, double* us_per_step);

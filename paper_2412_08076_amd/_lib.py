@@ -18,7 +18,8 @@ RM_FLAG_SSOR = 4
 # every symbol include/rm.h declares
 EXPORTS = [
     "rm_create", "rm_destroy", "rm_plan", "rm_plan_free", "rm_plan_batch", "rm_plan_points",
-    "rm_plan_offsets", "rm_plan_coefficients", "rm_plan_set_kernel", "rm_plan_get_kernel", "rm_tune",
+    "rm_plan_offsets", "rm_plan_coefficients", "rm_plan_set_kernel", "rm_plan_get_kernel",
+    "rm_plan_set_tail_kernel", "rm_plan_get_tail_kernel", "rm_plan_set_tail_switch", "rm_tune",
     "rm_apply_A", "rm_residual", "rm_solve",
     "rm_solve_adjoint", "rm_plan_coarse_points", "rm_plan_coarse_offsets", "rm_twogrid_solve",
     "rm_twogrid_adjoint", "rm_fgmres", "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count",
@@ -72,6 +73,9 @@ def load():
         "rm_plan_coefficients": (st, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
         "rm_plan_set_kernel": (st, [P, I32, I32, I32, I32]),
         "rm_plan_get_kernel": (st, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "rm_plan_set_tail_kernel": (st, [P, I32, I32, I32, I32]),
+        "rm_plan_get_tail_kernel": (st, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "rm_plan_set_tail_switch": (st, [P, D]),
         "rm_tune": (st, [P, P, I32, I32, P, P, P, ctypes.c_char_p, ctypes.POINTER(D)]),
         "rm_apply_A": (st, [P, P, I32, P, P]),
         "rm_residual": (st, [P, P, I32, P, P, P, P, P, P]),

@@ -105,12 +105,21 @@ struct rm_plan_s {
   // FP32 sweeps: temporal-blocked kernels, one configuration per size class
   struct ClassExec {
     int n = 0;
-    int shape = 0;  // kernel variant, index into rmk::kBlockVariants
+    int shape = 0;  // kernel shape: tiled variant (index into rmk::kBlockVariants) or row-streaming
     int T = 1;      // steps per launch
-    int cw = 64;    // extended tile width (multiple of 8)
+    int cw = 64;    // extended tile width (multiple of 8), or row-window height (row-streaming)
     std::vector<int> insts;
     DevBuf tiles;
     int ntiles = 0;
+    // Tail configuration: used by the refined solve once few instances are still
+    // active.  A row-streaming launch takes about as long for one active instance
+    // as for many (each workgroup walks its rows one after another), while the
+    // small tiles of a tiled variant cost in proportion to the active instances.
+    int tshape = 0, tT = 1, tcw = 64;
+    DevBuf ttiles;
+    int tntiles = 0;
+    double us = 0.0, tus = 0.0;  // tuned time per inner step, whole class active
+    double floor_us = 0.0;       // main configuration with one instance active
   };
   bool use_block = true;
   bool exec_dirty = true;
@@ -119,7 +128,9 @@ struct rm_plan_s {
   double relax = 1.0;
   std::vector<ClassExec> classes;
   DevBuf d_ranges;  // int [B][2]: slot range of each instance over all class tables
+  DevBuf d_tranges; // the same over the tail tables
   int nslots = 0;
+  double tail_frac = -1.0;  // active fraction below which the refined solve uses the tails (< 0: measured)
   // two-grid correction: coarse layout, tile and row-group tables, twiddles and
   // coarse scratch, built on first use
   struct TwoGrid {
@@ -155,11 +166,14 @@ struct rm_plan_s {
   }
   ~rm_plan_s() {
     for (DevBuf* b : {&d_tiles, &d_inst, &d_coef32, &d_coef64, &d_mu, &d_gersh, &partial, &red, &flags, &vecA,
-                      &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges, &tg.d_inst,
+                      &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges, &d_tranges, &tg.d_inst,
                       &tg.d_rtiles, &tg.d_groups, &tg.d_tw, &tg.c0, &tg.c1, &tg.shat, &tg.fine2,
                       &tg.zero, &fg.V, &fg.Z, &fg.w, &fg.t, &fg.b32, &fg.dbl, &fg.ints, &fg.partial})
       b->release();
-    for (auto& c : classes) c.tiles.release();
+    for (auto& c : classes) {
+      c.tiles.release();
+      c.ttiles.release();
+    }
   }
 };
 
@@ -237,11 +251,22 @@ std::vector<std::array<int, 3>> partition(int n, int len, int h) {
   return out;
 }
 
+// Kernel shapes: the tiled variants 0 .. kNumBlockVariants - 1, then the row-streaming
+// kernel, whose "width" is the height of its row windows (whole rows across).
+constexpr int kStreamShape = rmk::kNumBlockVariants;
+constexpr int kNumShapes = kStreamShape + 1;
+
 // Geometry of a class (n, variant v, steps per launch T, width cw): the tiles
 // across and down.  An instance that fits in one window needs no halo; otherwise
 // the halo is T + 1 (one ring more than T steps need, so the residual of the
 // final iterate can be formed in the same launch).
 bool class_geometry(int n, int v, int T, int cw, int& tx, int& ty) {
+  if (v == kStreamShape) {
+    if (n > rmk::kStreamMaxN || T < 1 || T > rmk::kStreamMaxT || cw < 1) return false;
+    tx = 1;
+    ty = (int)partition(n, cw, T + 1).size();
+    return ty > 0;
+  }
   if (v < 0 || v >= rmk::kNumBlockVariants || T < 1) return false;
   const rmk::BlockVariant& bv = rmk::kBlockVariants[v];
   if (cw < 8 || cw % 8 != 0 || cw + 2 > bv.lw) return false;
@@ -255,9 +280,20 @@ bool class_geometry(int n, int v, int T, int cw, int& tx, int& ty) {
 // Cost model used before any tuning: the larger of an arithmetic bound
 // (redundant halo work included) and an HBM bound (load u, v, f on the extended
 // tile, store u, v on the owned one, once per T steps), per inner step.
-double model_cost(int n, int v, int T, int cw) {
+double model_cost(int n, int v, int T, int cw, int count) {
   int tx, ty;
   if (!class_geometry(n, v, T, cw, tx, ty)) return 1e300;
+  if (v == kStreamShape) {
+    // whole rows in one workgroup: only the row windows overlap; a grid of fewer
+    // waves than SIMDs leaves the rest idle
+    const int nw = (n + 63) / 64;
+    const double rows = std::min<double>((double)ty * cw, (double)n + 2.0 * (ty - 1) * (T + 1));
+    const double ext = rows * 64.0 * nw;
+    const double fill = std::min(1.0, (double)count * ty * nw / 1024.0);
+    const double compute = ext / 2.4e12 / fill;
+    const double memory = (12.0 * rows * n + 8.0 * n * (double)n) / T / 5.0e12;
+    return std::max(compute, memory) + 4e-6 / T / 256.0;
+  }
   const double ext = (double)tx * ty * cw * (double)(8 * rmk::kBlockVariants[v].r);
   const double own = (double)n * n;
   const double compute = ext / 1.6e12;
@@ -276,6 +312,17 @@ constexpr int kTs[] = {2, 4, 8, 16, 32};
 // across, the narrowest multiple of 8 that covers n.
 std::vector<int> candidate_widths(int n, int v, int T) {
   std::vector<int> out;
+  if (v == kStreamShape) {
+    // windows for 1, 2, 3, 4, 6 or 8 row segments per instance
+    const int h = T + 1;
+    for (int S : {1, 2, 3, 4, 6, 8}) {
+      const int len = S == 1 ? n : (n + 2 * (S - 1) * h + S - 1) / S;
+      int tx, ty;
+      if (class_geometry(n, v, T, len, tx, ty) && ty == S && std::find(out.begin(), out.end(), len) == out.end())
+        out.push_back(len);
+    }
+    return out;
+  }
   const int lw = rmk::kBlockVariants[v].lw;
   for (int cw = 8; cw + 2 <= lw && (int)out.size() < 64; cw += 8) {
     int tx, ty;
@@ -298,15 +345,15 @@ std::vector<int> candidate_widths(int n, int v, int T) {
   return keep;
 }
 
-void default_class_config(int n, int& shape, int& T, int& cw) {
+void default_class_config(int n, int count, int& shape, int& T, int& cw, int nshapes = kNumShapes) {
   double best = 1e301;
   shape = 0;
   T = 2;
   cw = 64;
-  for (int v = 0; v < rmk::kNumBlockVariants; ++v)
+  for (int v = 0; v < nshapes; ++v)
     for (int t : kTs)
       for (int w : candidate_widths(n, v, t)) {
-        const double c = model_cost(n, v, t, w);
+        const double c = model_cost(n, v, t, w, count);
         if (c < best * 0.999) {
           best = c;
           shape = v;
@@ -314,6 +361,19 @@ void default_class_config(int n, int& shape, int& T, int& cw) {
           cw = w;
         }
       }
+}
+
+// The tail is the main configuration unless that is the row-streaming kernel; then it
+// is the cost model's best tiled variant.
+void set_default_tail(rm_plan_s::ClassExec& c) {
+  if (c.shape == kStreamShape) {
+    default_class_config(c.n, (int)c.insts.size(), c.tshape, c.tT, c.tcw, rmk::kNumBlockVariants);
+  } else {
+    c.tshape = c.shape;
+    c.tT = c.T;
+    c.tcw = c.cw;
+  }
+  c.us = c.tus = c.floor_us = 0.0;
 }
 
 void init_classes(rm_plan_t* pl) {
@@ -325,40 +385,53 @@ void init_classes(rm_plan_t* pl) {
   for (int n : sizes) {
     rm_plan_s::ClassExec c;
     c.n = n;
-    default_class_config(n, c.shape, c.T, c.cw);
     for (int b = 0; b < pl->B; ++b)
       if (pl->inst[b].n == n) c.insts.push_back(b);
+    default_class_config(n, (int)c.insts.size(), c.shape, c.T, c.cw);
+    set_default_tail(c);
     pl->classes.push_back(std::move(c));
   }
   pl->exec_dirty = true;
 }
 
+// Tile table of one configuration of a class; residual slots are numbered from `slot`
+// on and each instance's slot range goes to ranges[2b], ranges[2b + 1].
+rm_status build_table(const rm_plan_s::ClassExec& c, int shape, int T, int cw, int& slot, std::vector<int>& ranges,
+                      DevBuf& tiles, int& ntiles, hipStream_t st) {
+  int tx, ty;
+  if (!class_geometry(c.n, shape, T, cw, tx, ty)) return fail(RM_EINVAL, "invalid kernel configuration");
+  const bool stream = shape == kStreamShape;
+  const int eh = stream ? cw : 8 * rmk::kBlockVariants[shape].r;
+  const auto px = stream ? std::vector<std::array<int, 3>>{{0, 0, c.n}} : partition(c.n, cw, T + 1);
+  const auto py = partition(c.n, eh, T + 1);
+  std::vector<rmk::BTile> t;
+  for (int b : c.insts) {
+    ranges[2 * b] = slot;
+    for (const auto& y : py)
+      for (const auto& x : px) t.push_back(rmk::BTile{b, x[0], y[0], slot++, x[1], x[2], y[1], y[2]});
+    ranges[2 * b + 1] = slot;
+  }
+  while (t.size() % 8 != 0) t.push_back(rmk::BTile{-1, 0, 0, slot++, 0, 0, 0, 0});
+  ntiles = (int)t.size();
+  RM_TRY(tiles.ensure(t.size() * sizeof(rmk::BTile), st));
+  RM_HIP(hipStreamSynchronize(st));
+  RM_HIP(hipMemcpy(tiles.ptr, t.data(), t.size() * sizeof(rmk::BTile), hipMemcpyHostToDevice));
+  return RM_OK;
+}
+
 rm_status build_exec(rm_plan_t* pl, hipStream_t st) {
   if (!pl->exec_dirty) return RM_OK;
-  std::vector<int> ranges((size_t)pl->B * 2, 0);
-  int slot = 0;
+  std::vector<int> ranges((size_t)pl->B * 2, 0), tranges((size_t)pl->B * 2, 0);
+  int slot = 0, tslot = 0;
   for (auto& c : pl->classes) {
-    int tx, ty;
-    if (!class_geometry(c.n, c.shape, c.T, c.cw, tx, ty)) return fail(RM_EINVAL, "invalid kernel configuration");
-    const int eh = 8 * rmk::kBlockVariants[c.shape].r;
-    const auto px = partition(c.n, c.cw, c.T + 1);
-    const auto py = partition(c.n, eh, c.T + 1);
-    std::vector<rmk::BTile> t;
-    for (int b : c.insts) {
-      ranges[2 * b] = slot;
-      for (const auto& y : py)
-        for (const auto& x : px) t.push_back(rmk::BTile{b, x[0], y[0], slot++, x[1], x[2], y[1], y[2]});
-      ranges[2 * b + 1] = slot;
-    }
-    while (t.size() % 8 != 0) t.push_back(rmk::BTile{-1, 0, 0, slot++, 0, 0, 0, 0});
-    c.ntiles = (int)t.size();
-    RM_TRY(c.tiles.ensure(t.size() * sizeof(rmk::BTile), st));
-    RM_HIP(hipStreamSynchronize(st));
-    RM_HIP(hipMemcpy(c.tiles.ptr, t.data(), t.size() * sizeof(rmk::BTile), hipMemcpyHostToDevice));
+    RM_TRY(build_table(c, c.shape, c.T, c.cw, slot, ranges, c.tiles, c.ntiles, st));
+    RM_TRY(build_table(c, c.tshape, c.tT, c.tcw, tslot, tranges, c.ttiles, c.tntiles, st));
   }
-  pl->nslots = slot;
+  pl->nslots = std::max(slot, tslot);
   RM_TRY(pl->d_ranges.ensure(ranges.size() * sizeof(int), st));
   RM_HIP(hipMemcpy(pl->d_ranges.ptr, ranges.data(), ranges.size() * sizeof(int), hipMemcpyHostToDevice));
+  RM_TRY(pl->d_tranges.ensure(tranges.size() * sizeof(int), st));
+  RM_HIP(hipMemcpy(pl->d_tranges.ptr, tranges.data(), tranges.size() * sizeof(int), hipMemcpyHostToDevice));
   pl->exec_dirty = false;
   return RM_OK;
 }
@@ -368,6 +441,21 @@ size_t partial_slots(const rm_plan_t* pl) { return std::max<size_t>(pl->tiles.si
 // Temporal-blocked sweeps serve the unpreconditioned and Jacobi steps; an SSOR step
 // needs its whole tile in one launch.
 bool blocked(const rm_plan_t* pl) { return pl->use_block && !pl->ssor; }
+
+// T fused steps of one size class with its main (tail = false) or tail configuration
+// (see rmk::launch_block and rmk::launch_stream).
+bool launch_class(const rm_plan_s::ClassExec& c, int T, int method, const PlanDev& p, const float* omega,
+                  const float* alpha, int m, int s0, const float* f, const float* u, const float* v, float* u_out,
+                  float* v_out, const int* active, double* partial2, hipStream_t st, float* states = nullptr,
+                  int64_t state_stride = 0, bool tail = false) {
+  const int shape = tail ? c.tshape : c.shape, cw = tail ? c.tcw : c.cw, nt = tail ? c.tntiles : c.ntiles;
+  const rmk::BTile* tiles = (tail ? c.ttiles : c.tiles).as<rmk::BTile>();
+  if (shape == kStreamShape)
+    return rmk::launch_stream(T, cw, c.n, method, p, tiles, nt, omega, alpha, m, s0, f, u, v, u_out, v_out, active,
+                              partial2, st, states, state_stride);
+  return rmk::launch_block(shape, T, cw, method, p, tiles, nt, omega, alpha, m, s0, f, u, v, u_out, v_out, active,
+                           partial2, st, states, state_stride);
+}
 
 // One inner step over the plan's one-step tile table, plain or SSOR-preconditioned.
 template <typename T>
@@ -405,10 +493,11 @@ void set_precond(rm_plan_t* pl, const rm_solve_opts* o) {
 // When res_partial is given, the residual ||f - A u||^2 of the final iterate is
 // left per tile in res_partial and *res_ranges tells the reduction which slots
 // belong to which instance.  `only_class` >= 0 restricts the launches to one
-// size class (autotuning).
+// size class (autotuning); `tail` selects the classes' tail configurations.
 rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int nsteps, const float* omega,
                 const float* alpha, const float* f, float* const us[2], float* const vs[2], int& cur, int& flips,
-                const int* active, double* res_partial, const int** res_ranges, int only_class = -1) {
+                const int* active, double* res_partial, const int** res_ranges, int only_class = -1,
+                bool tail = false) {
   const PlanDev p = pl->dev();
   if (nsteps <= 0) return RM_OK;
   if (!blocked(pl)) {
@@ -430,7 +519,7 @@ rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int ns
   int L = 0;
   for (size_t ci = 0; ci < pl->classes.size(); ++ci) {
     if (only_class >= 0 && (int)ci != only_class) continue;
-    const int T = pl->classes[ci].T;
+    const int T = tail ? pl->classes[ci].tT : pl->classes[ci].T;
     int lc = (nsteps + T - 1) / T;
     if (nsteps >= 2 && (lc & 1)) ++lc;
     for (int j = 0; j < lc; ++j) chunks[ci].push_back(nsteps / lc + (j < nsteps % lc ? 1 : 0));
@@ -444,16 +533,15 @@ rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int ns
       int s = s0;
       for (int q = 0; q < j; ++q) s += chunks[ci][q];
       const bool last = j + 1 == (int)chunks[ci].size();
-      if (!rmk::launch_block(c.shape, chunks[ci][j], c.cw, method, p, c.tiles.as<rmk::BTile>(), c.ntiles, omega,
-                             alpha, m, s, f, us[rd], vs[rd], us[rd ^ 1], vs[rd ^ 1], active,
-                             last ? res_partial : nullptr, st))
+      if (!launch_class(c, chunks[ci][j], method, p, omega, alpha, m, s, f, us[rd], vs[rd], us[rd ^ 1], vs[rd ^ 1],
+                        active, last ? res_partial : nullptr, st, nullptr, 0, tail))
         return fail(RM_EUNSUPPORTED, "block kernel configuration not built");
     }
   }
   const int lfin = nsteps >= 2 ? 0 : 1;  // parity of every class's launch count
   cur ^= lfin;
   flips += nsteps >= 2 ? 2 : 1;
-  if (res_partial != nullptr) *res_ranges = pl->d_ranges.as<int>();
+  if (res_partial != nullptr) *res_ranges = (tail ? pl->d_tranges : pl->d_ranges).as<int>();
   return RM_OK;
 }
 
@@ -593,8 +681,21 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   rmk::launch_fill_i32(status, 0, B, st);
   RM_HIP(hipMemcpyAsync(mask, mask_h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
   int flips_per_outer = 0;
-  GraphHolder graph;
+  GraphHolder graph[2];  // one captured outer iteration per configuration (main, tail)
   bool use_graph = (o->flags & RM_FLAG_GRAPH) != 0;
+  // Switch to the classes' tail configurations below this many active instances.
+  int tail_below = 0;
+  {
+    bool distinct = false;
+    double frac = 1.0;
+    for (const auto& c : pl->classes)
+      if (c.tshape != c.shape || c.tT != c.T || c.tcw != c.cw) {
+        distinct = true;
+        frac = std::min(frac, c.floor_us > 0.0 && c.tus > 0.0 ? c.floor_us / c.tus : 0.35);
+      }
+    if (pl->tail_frac >= 0.0) frac = pl->tail_frac;
+    if (distinct) tail_below = frac >= 1.0 ? B + 1 : (int)std::ceil(frac * B);
+  }
   for (int j = 0;; ++j) {
     if (j > 0) rmk::launch_refine_update(p, x, ds[0], ds[1], count, flips_per_outer, mask, st);
     rmk::launch_refine_residual(p, b, x, r32, ds[0], vs[0], partial, mask, st);
@@ -648,29 +749,29 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     int cur = 0;
     // one outer iteration: sweep of m steps with the residual fused into its last
     // launch, per-instance reduction, convergence bookkeeping
-    auto outer_iteration = [&]() -> rm_status {
+    auto outer_iteration = [&](bool tail) -> rm_status {
       int flips = 0;
       const int* ranges = nullptr;
-      RM_TRY(sweep(pl, st, method, o->m, 0, o->m, omega, alpha, r32, ds, vs, cur, flips, active, partial, &ranges));
+      RM_TRY(sweep(pl, st, method, o->m, 0, o->m, omega, alpha, r32, ds, vs, cur, flips, active, partial, &ranges, -1,
+                   tail));
       flips_per_outer = flips;
-      rmk::launch_reduce_partials(p, partial, res2, nullptr, 1, nullptr, st, ranges);
-      rmk::launch_fill_i32(n_active, 0, 1, st);
-      rmk::launch_inner_flags(B, res2, rhs2, target2, best2, since, gains, stall_min, stall_max, o->max_outer,
-                              active, count, status, n_active, st);
+      rmk::launch_outer_flags(p, partial, ranges, res2, rhs2, target2, best2, since, gains, stall_min, stall_max,
+                              o->max_outer, active, count, status, n_active, st);
       return RM_OK;
     };
     // The iteration returns to buffer set 0, so one captured iteration can be
-    // replayed; captured once per call and reused by every round.
-    if (use_graph && graph.exec == nullptr) {
+    // replayed; captured on first use per configuration and reused by every round.
+    auto capture = [&](int g) {
       const int cur0 = cur;
+      GraphHolder& gh = graph[g];
       if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        const rm_status sc = outer_iteration();
-        const hipError_t ec = hipStreamEndCapture(st, &graph.graph);
+        const rm_status sc = outer_iteration(g == 1);
+        const hipError_t ec = hipStreamEndCapture(st, &gh.graph);
         if (sc != RM_OK || ec != hipSuccess || cur != cur0 ||
-            hipGraphInstantiate(&graph.exec, graph.graph, nullptr, nullptr, 0) != hipSuccess) {
-          if (graph.graph != nullptr) (void)hipGraphDestroy(graph.graph);
-          graph.graph = nullptr;
-          graph.exec = nullptr;
+            hipGraphInstantiate(&gh.exec, gh.graph, nullptr, nullptr, 0) != hipSuccess) {
+          if (gh.graph != nullptr) (void)hipGraphDestroy(gh.graph);
+          gh.graph = nullptr;
+          gh.exec = nullptr;
           use_graph = false;
         }
       } else {
@@ -678,16 +779,20 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
       }
       (void)hipGetLastError();
       cur = cur0;
-    }
+    };
+    // the configuration follows the active count seen at the last poll
+    int tail = n_round < tail_below ? 1 : 0;
     for (int k = 1;; ++k) {
+      if (use_graph && graph[tail].exec == nullptr) capture(tail);
       if (use_graph)
-        RM_HIP(hipGraphLaunch(graph.exec, st));
+        RM_HIP(hipGraphLaunch(graph[tail].exec, st));
       else
-        RM_TRY(outer_iteration());
+        RM_TRY(outer_iteration(tail == 1));
       if (k % o->check_every == 0 || k >= o->max_outer) {
         RM_HIP(hipMemcpyAsync(ctx->host_flag, n_active, sizeof(int), hipMemcpyDeviceToHost, st));
         RM_HIP(hipStreamSynchronize(st));
         if (*ctx->host_flag == 0) break;
+        tail = *ctx->host_flag < tail_below ? 1 : 0;
       }
     }
     RM_HIP(hipMemcpyAsync(cnt_h.data(), count, B * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1137,9 +1242,8 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
       for (int s0 = 0; s0 < steps;) {
         const int t = std::min(cl.T, steps - s0);
         float* uo = S + (int64_t)(s0 + t) * 2 * P;
-        if (!rmk::launch_block(cl.shape, t, cl.cw, method, p, cl.tiles.as<rmk::BTile>(), cl.ntiles, omega, alpha, m,
-                               c * E + s0, b, su(c, s0), sv(c, s0), uo, uo + P, nullptr, nullptr, st,
-                               S + (int64_t)(s0 + 1) * 2 * P, 2 * P))
+        if (!launch_class(cl, t, method, p, omega, alpha, m, c * E + s0, b, su(c, s0), sv(c, s0), uo, uo + P, nullptr,
+                          nullptr, st, S + (int64_t)(s0 + 1) * 2 * P, 2 * P))
           return fail(RM_EUNSUPPORTED, "block kernel configuration not built");
         s0 += t;
       }
@@ -1277,9 +1381,8 @@ rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
         for (int s0 = 0; s0 < m;) {
           const int t = std::min(cl.T, m - s0);
           float* uo = S + (int64_t)(s0 + t) * 2 * P;
-          if (!rmk::launch_block(cl.shape, t, cl.cw, method, p, cl.tiles.as<rmk::BTile>(), cl.ntiles, omega, alpha,
-                                 m, s0, b, su(s0), sv(s0), uo, uo + P, nullptr, nullptr, st,
-                                 S + (int64_t)(s0 + 1) * 2 * P, 2 * P))
+          if (!launch_class(cl, t, method, p, omega, alpha, m, s0, b, su(s0), sv(s0), uo, uo + P, nullptr, nullptr,
+                            st, S + (int64_t)(s0 + 1) * 2 * P, 2 * P))
             return fail(RM_EUNSUPPORTED, "block kernel configuration not built");
           s0 += t;
         }
@@ -1467,7 +1570,7 @@ rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t 
     plan->use_block = false;
     return RM_OK;
   }
-  if (shape < 0 || shape >= rmk::kNumBlockVariants) return fail(RM_EINVAL, "unknown kernel variant");
+  if (shape < 0 || shape >= kNumShapes) return fail(RM_EINVAL, "unknown kernel variant");
   if (T < 1 || T > 64) return fail(RM_EINVAL, "T must be in 1..64");
   bool hit = false;
   for (auto& c : plan->classes) {
@@ -1476,7 +1579,7 @@ rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t 
     if (w <= 0) {
       double best = 1e301;
       for (int cand : candidate_widths(c.n, shape, T)) {
-        const double cost = model_cost(c.n, shape, T, cand);
+        const double cost = model_cost(c.n, shape, T, cand, (int)c.insts.size());
         if (cost < best) {
           best = cost;
           w = cand;
@@ -1489,11 +1592,61 @@ rm_status rm_plan_set_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t 
     c.shape = shape;
     c.T = T;
     c.cw = w;
+    set_default_tail(c);
     hit = true;
   }
   if (!hit) return fail(RM_EINVAL, "no instance of that size in the plan");
   plan->use_block = true;
   plan->exec_dirty = true;
+  return RM_OK;
+}
+
+rm_status rm_plan_set_tail_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t T, int32_t cw) {
+  if (plan == nullptr) return fail(RM_EINVAL, "null plan");
+  if (shape < 0 || shape >= kNumShapes) return fail(RM_EINVAL, "unknown kernel variant");
+  bool hit = false;
+  for (auto& c : plan->classes) {
+    if (n > 0 && c.n != n) continue;
+    int w = cw;
+    if (w <= 0) {
+      double best = 1e301;
+      for (int cand : candidate_widths(c.n, shape, T)) {
+        const double cost = model_cost(c.n, shape, T, cand, (int)c.insts.size());
+        if (cost < best) {
+          best = cost;
+          w = cand;
+        }
+      }
+    }
+    int tx, ty;
+    if (!class_geometry(c.n, shape, T, w, tx, ty))
+      return fail(RM_EINVAL, "tile width / halo T + 1 does not fit this kernel variant");
+    c.tshape = shape;
+    c.tT = T;
+    c.tcw = w;
+    hit = true;
+  }
+  if (!hit) return fail(RM_EINVAL, "no instance of that size in the plan");
+  plan->exec_dirty = true;
+  return RM_OK;
+}
+
+rm_status rm_plan_get_tail_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, int32_t* T, int32_t* cw) {
+  if (plan == nullptr || shape == nullptr || T == nullptr || cw == nullptr) return fail(RM_EINVAL, "null argument");
+  for (const auto& c : plan->classes)
+    if (c.n == n) {
+      *shape = c.tshape;
+      *T = c.tT;
+      *cw = c.tcw;
+      return RM_OK;
+    }
+  return fail(RM_EINVAL, "no instance of that size in the plan");
+}
+
+rm_status rm_plan_set_tail_switch(rm_plan_t* plan, double frac) {
+  if (plan == nullptr) return fail(RM_EINVAL, "null plan");
+  if (!(frac <= 1.0)) return fail(RM_EINVAL, "frac must be <= 1 (negative: automatic)");
+  plan->tail_frac = frac;
   return RM_OK;
 }
 
@@ -1537,14 +1690,8 @@ rm_status rm_tune(rm_ctx* ctx, rm_plan_t* plan, int32_t method, int32_t m, const
     if (FILE* fh = std::fopen(cache_path, "r")) {
       char line[512];
       while (std::fgets(line, sizeof line, fh)) {
-        char key[300];
-        int sh, T, w;
-        double us;
-        if (std::sscanf(line, " \"%299[^\"]\": [%d, %d, %d, %lf]", key, &sh, &T, &w, &us) == 5) {
-          char val[96];
-          std::snprintf(val, sizeof val, "[%d, %d, %d, %.3f]", sh, T, w, us);
-          cache.emplace_back(key, val);
-        }
+        char key[300], val[200];
+        if (std::sscanf(line, " \"%299[^\"]\": %199[^]]", key, val) == 2) cache.emplace_back(key, std::string(val) + "]");
       }
       std::fclose(fh);
     }
@@ -1572,54 +1719,92 @@ rm_status rm_tune(rm_ctx* ctx, rm_plan_t* plan, int32_t method, int32_t m, const
     bool found = false;
     for (auto& kv : cache)
       if (kv.first == key) {
-        int sh, T, w;
-        double us;
-        if (std::sscanf(kv.second.c_str(), "[%d, %d, %d, %lf]", &sh, &T, &w, &us) == 4) {
-          int tx, ty;
-          if (class_geometry(c.n, sh, T, w, tx, ty)) {
-            c.shape = sh;
-            c.T = T;
-            c.cw = w;
-            total_us += us;
-            found = true;
+        int sh, T, w, tsh, tT, tw;
+        double us, tus, fus;
+        const int got = std::sscanf(kv.second.c_str(), "[%d, %d, %d, %lf, %d, %d, %d, %lf, %lf]", &sh, &T, &w, &us,
+                                    &tsh, &tT, &tw, &tus, &fus);
+        int tx, ty;
+        if (got >= 4 && class_geometry(c.n, sh, T, w, tx, ty)) {
+          c.shape = sh;
+          c.T = T;
+          c.cw = w;
+          set_default_tail(c);
+          c.us = us;
+          if (got == 9 && class_geometry(c.n, tsh, tT, tw, tx, ty)) {
+            c.tshape = tsh;
+            c.tT = tT;
+            c.tcw = tw;
+            c.tus = tus;
+            c.floor_us = fus;
           }
+          total_us += us;
+          found = true;
         }
       }
     if (found) continue;
-    double best = 1e300;
-    int best_s = c.shape, best_T = c.T, best_w = c.cw;
-    for (int sh = 0; sh < rmk::kNumBlockVariants; ++sh)
+    // time 16 steps of the class (best of `reps` after one warm-up), with all of its
+    // instances active or only those marked in `mask`
+    auto time_class = [&](const int* mask, double& t_best) -> rm_status {
+      plan->exec_dirty = true;
+      t_best = 1e300;
+      for (int r = 0; r < reps + 1; ++r) {
+        int cur = 0, flips = 0;
+        RM_HIP(hipEventRecord(e0, st));
+        RM_TRY(sweep(plan, st, method, m, 0, steps, omega, alpha, b, us_, vs_, cur, flips, mask, nullptr, nullptr,
+                     (int)ci));
+        RM_HIP(hipEventRecord(e1, st));
+        RM_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        RM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (r > 0) t_best = std::min(t_best, (double)ms * 1e3 / steps);
+      }
+      return RM_OK;
+    };
+    double best = 1e300, tbest = 1e300;
+    int best_s = c.shape, best_T = c.T, best_w = c.cw, tbest_s = c.tshape, tbest_T = c.tT, tbest_w = c.tcw;
+    for (int sh = 0; sh < kNumShapes; ++sh)
       for (int T : kTs)
         for (int w : candidate_widths(c.n, sh, T)) {
           c.shape = sh;
           c.T = T;
           c.cw = w;
-          plan->exec_dirty = true;
-          double t_best = 1e300;
-          for (int r = 0; r < reps + 1; ++r) {
-            int cur = 0, flips = 0;
-            RM_HIP(hipEventRecord(e0, st));
-            RM_TRY(sweep(plan, st, method, m, 0, steps, omega, alpha, b, us_, vs_, cur, flips, nullptr, nullptr,
-                         nullptr, (int)ci));
-            RM_HIP(hipEventRecord(e1, st));
-            RM_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            RM_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (r > 0) t_best = std::min(t_best, (double)ms * 1e3 / steps);
-          }
+          double t_best;
+          RM_TRY(time_class(nullptr, t_best));
           if (t_best < best) {
             best = t_best;
             best_s = sh;
             best_T = T;
             best_w = w;
           }
+          if (sh != kStreamShape && t_best < tbest) {
+            tbest = t_best;
+            tbest_s = sh;
+            tbest_T = T;
+            tbest_w = w;
+          }
         }
     c.shape = best_s;
     c.T = best_T;
     c.cw = best_w;
+    c.us = best;
+    c.tshape = tbest_s;
+    c.tT = tbest_T;
+    c.tcw = tbest_w;
+    c.tus = tbest;
+    c.floor_us = 0.0;
+    if (best_s == kStreamShape && !c.insts.empty()) {
+      // the main configuration with a single instance of the class active
+      RM_TRY(plan->flags.ensure(((size_t)plan->B * 6 + 16) * sizeof(int), st));
+      int* one = plan->flags.as<int>();
+      rmk::launch_fill_i32(one, 0, plan->B, st);
+      const int on = 1;
+      RM_HIP(hipMemcpyAsync(one + c.insts[0], &on, sizeof(int), hipMemcpyHostToDevice, st));
+      RM_TRY(time_class(one, c.floor_us));
+    }
     total_us += best;
-    char val[96];
-    std::snprintf(val, sizeof val, "[%d, %d, %d, %.3f]", best_s, best_T, best_w, best);
+    char val[200];
+    std::snprintf(val, sizeof val, "[%d, %d, %d, %.3f, %d, %d, %d, %.3f, %.3f]", best_s, best_T, best_w, best, tbest_s,
+                  tbest_T, tbest_w, tbest, c.floor_us);
     cache.emplace_back(key, val);
   }
   (void)hipEventDestroy(e0);

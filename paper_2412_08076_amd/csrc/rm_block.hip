@@ -36,19 +36,6 @@ namespace rmk {
 
 namespace {
 
-// New momentum with the weight folded into the stencil (the same sequence as the
-// one-step kernel): v' = a v + w f - sum_j (w c_j) s_j.
-__device__ __forceinline__ float step_vf(const float wc[5], float w, float a, float f, float v, float C, float W,
-                                         float E, float S, float N, float SW, float NE, float SE, float NW) {
-  float acc = fmadd(a, v, w * f);
-  acc = fmadd(-wc[0], C, acc);
-  acc = fmadd(-wc[1], W + E, acc);
-  acc = fmadd(-wc[2], S + N, acc);
-  acc = fmadd(-wc[3], SW + NE, acc);
-  acc = fmadd(-wc[4], SE + NW, acc);
-  return acc;
-}
-
 // Walk down this thread's strip with a three-row window over the LDS tile B (row
 // stride LW, zero border; strip row k sits at LDS row lr0 + k + 1, column lc + 1)
 // and hand f(k, C, W, E, S, N, SW, NE, SE, NW) the nine inputs of every point.

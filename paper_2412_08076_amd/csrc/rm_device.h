@@ -23,11 +23,26 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
 // the diagonal pairs (1,1)/(-1,-1) and (-1,1)/(1,-1).
 template <typename T>
 __device__ __forceinline__ T stencil9(const T c[5], T C, T W, T E, T S, T N, T SW, T NE, T SE, T NW) {
+#pragma clang fp contract(off)
   T acc = c[0] * C;
   acc = fmadd(c[1], W + E, acc);
   acc = fmadd(c[2], S + N, acc);
   acc = fmadd(c[3], SW + NE, acc);
   acc = fmadd(c[4], SE + NW, acc);
+  return acc;
+}
+
+// New momentum of a Table-1 step with the weight folded into the stencil,
+// v' = a v + w f - sum_j (w c_j) s_j, in the one order every FP32 sweep kernel uses.
+__device__ __forceinline__ float step_vf(const float wc[5], float w, float a, float f, float v, float C, float W,
+                                         float E, float S, float N, float SW, float NE, float SE, float NW) {
+#pragma clang fp contract(off)
+  float acc = fmadd(a, v, w * f);
+  acc = fmadd(-wc[0], C, acc);
+  acc = fmadd(-wc[1], W + E, acc);
+  acc = fmadd(-wc[2], S + N, acc);
+  acc = fmadd(-wc[3], SW + NE, acc);
+  acc = fmadd(-wc[4], SE + NW, acc);
   return acc;
 }
 

@@ -87,10 +87,14 @@ void launch_refine_residual(const PlanDev& p, const double* b, const double* x, 
 // outer_count[b] * flips (the inner solve swaps its two buffers `flips` times per outer iteration)
 void launch_refine_update(const PlanDev& p, double* x, const float* d0, const float* d1,
                           const int* outer_count, int flips, const int* round_mask, hipStream_t st);
-// inner-solve bookkeeping after one outer iteration (one thread per instance)
-void launch_inner_flags(int B, const double* res2, const double* rhs2, const double* target2,
-                        double* best2, int* since, int* gains, int stall_min, int stall_max, int cap,
-                        int* active, int* outer_count, int* status, int* n_active, hipStream_t st);
+// Inner-solve bookkeeping after one outer iteration, one launch: res2[b] = the sum of the
+// instance's residual partials in slot order, then for active
+// instances the outer count, divergence / target / cap / stagnation tests and the new
+// active flag, and *n_active = the number still active.
+void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ranges, double* res2,
+                        const double* rhs2, const double* target2, double* best2, int* since, int* gains,
+                        int stall_min, int stall_max, int cap, int* active, int* outer_count, int* status,
+                        int* n_active, hipStream_t st);
 void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st);
 void launch_fill_f32(float* p, float value, int64_t count, hipStream_t st);
 void launch_fill_f64(double* p, double value, int64_t count, hipStream_t st);
@@ -147,6 +151,19 @@ bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, cons
                   const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,
                   const float* v, float* u_out, float* v_out, const int* active, double* partial2,
                   hipStream_t st, float* states = nullptr, int64_t state_stride = 0);
+
+// ---- row-streaming temporal-blocked steps (rm_stream.hip) ----------------------
+// One workgroup of 64 ceil(n / 64) threads per window of whole rows: tiles carry
+// x0 = 0, ox0 = 0, ox1 = n and the window [y0, min(n, y0 + wlen)) with owned rows
+// [oy0, oy1); windows overlap by at least T rows at cuts (T + 1 with partial2).
+// Same step semantics, partial2 and states layout as launch_block.  Returns false
+// when n or T is outside what is built.
+constexpr int kStreamMaxN = 512;
+constexpr int kStreamMaxT = 8;
+bool launch_stream(int T, int wlen, int n, int method, const PlanDev& p, const BTile* tiles, int ntiles,
+                   const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,
+                   const float* v, float* u_out, float* v_out, const int* active, double* partial2,
+                   hipStream_t st, float* states = nullptr, int64_t state_stride = 0);
 
 // ---- SSOR-preconditioned steps (rm_ssor.hip) ----------------------------------
 // One inner step of a Table-1 scheme with the four-colour SSOR preconditioner of

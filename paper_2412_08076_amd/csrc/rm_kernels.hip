@@ -304,35 +304,57 @@ __global__ __launch_bounds__(WG) void k_refine_update(PlanDev p, double* __restr
 // clamped to [stall_min, stall_max] (stall_max before the first reduction):
 // an instance at its FP32 floor stops quickly, a slowly converging large one is
 // given time.
-__global__ void k_inner_flags(int B, const double* __restrict__ res2, const double* __restrict__ rhs2,
-                              const double* __restrict__ target2, double* __restrict__ best2,
-                              int* __restrict__ since, int* __restrict__ gains, int stall_min, int stall_max,
-                              int cap, int* __restrict__ active, int* __restrict__ outer_count,
-                              int* __restrict__ status, int* __restrict__ n_active) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B || active[b] == 0) return;
-  const int cnt = outer_count[b] + 1;
-  outer_count[b] = cnt;
-  const double r2 = res2[b];
-  int keep = 1;
-  if (!(r2 <= 1e12 * rhs2[b])) {  // NaN, Inf or growth
-    status[b] = 5;                // RM_EDIVERGED
-    keep = 0;
-  } else if (r2 <= target2[b] || cnt >= cap) {
-    keep = 0;
-  } else if (r2 < 0.81 * best2[b]) {
-    best2[b] = r2;
-    since[b] = 0;
-    gains[b] = gains[b] + 1;
-  } else {
-    const int g = gains[b];
-    int w = g == 0 ? stall_max : (6 * cnt) / g;
-    w = w < stall_min ? stall_min : (w > stall_max ? stall_max : w);
-    if (since[b] + 1 >= w) keep = 0;
-    else since[b] = since[b] + 1;
+// Bookkeeping after one outer iteration of the refined solve, in one workgroup with a
+// thread per instance: the residual of the inner iterate (the instance's residual
+// partials summed in slot order), then for active instances the count, divergence,
+// target, cap and stagnation tests; finally the number still active, summed over the
+// threads in a fixed order (no atomics and no counter to clear beforehand).
+__global__ __launch_bounds__(1024) void k_outer_flags(
+    PlanDev p, const double* __restrict__ partial2, const int* __restrict__ ranges, double* __restrict__ res2,
+    const double* __restrict__ rhs2, const double* __restrict__ target2, double* __restrict__ best2,
+    int* __restrict__ since, int* __restrict__ gains, int stall_min, int stall_max, int cap,
+    int* __restrict__ active, int* __restrict__ outer_count, int* __restrict__ status, int* __restrict__ n_active) {
+  __shared__ int kept[16];
+  int mine = 0;
+  for (int b = threadIdx.x; b < p.B; b += blockDim.x) {
+    const Inst in = p.inst[b];
+    const int t0 = ranges != nullptr ? ranges[2 * b] : in.tile_begin;
+    const int t1 = ranges != nullptr ? ranges[2 * b + 1] : in.tile_end;
+    double r2 = 0.0;
+    for (int t = t0; t < t1; ++t) r2 += partial2[2 * t];
+    res2[b] = r2;
+    if (active[b] == 0) continue;
+    const int cnt = outer_count[b] + 1;
+    outer_count[b] = cnt;
+    int keep = 1;
+    if (!(r2 <= 1e12 * rhs2[b])) {  // NaN, Inf or growth
+      status[b] = 5;                // RM_EDIVERGED
+      keep = 0;
+    } else if (r2 <= target2[b] || cnt >= cap) {
+      keep = 0;
+    } else if (r2 < 0.81 * best2[b]) {
+      best2[b] = r2;
+      since[b] = 0;
+      gains[b] = gains[b] + 1;
+    } else {
+      const int g = gains[b];
+      int win = g == 0 ? stall_max : (6 * cnt) / g;
+      win = win < stall_min ? stall_min : (win > stall_max ? stall_max : win);
+      if (since[b] + 1 >= win) keep = 0;
+      else since[b] = since[b] + 1;
+    }
+    active[b] = keep;
+    mine += keep;
   }
-  active[b] = keep;
-  if (keep) atomicAdd(n_active, 1);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o, 64);
+  if ((threadIdx.x & 63) == 0) kept[threadIdx.x >> 6] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int total = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) total += kept[k];
+    *n_active = total;
+  }
 }
 
 template <typename T>
@@ -685,11 +707,12 @@ void launch_refine_update(const PlanDev& p, double* x, const float* d0, const fl
                      round_mask);
 }
 
-void launch_inner_flags(int B, const double* res2, const double* rhs2, const double* target2, double* best2,
-                        int* since, int* gains, int stall_min, int stall_max, int cap, int* active, int* outer_count,
-                        int* status, int* n_active, hipStream_t st) {
-  hipLaunchKernelGGL(k_inner_flags, dim3((B + 255) / 256), dim3(256), 0, st, B, res2, rhs2, target2, best2, since,
-                     gains, stall_min, stall_max, cap, active, outer_count, status, n_active);
+void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ranges, double* res2, const double* rhs2,
+                        const double* target2, double* best2, int* since, int* gains, int stall_min, int stall_max,
+                        int cap, int* active, int* outer_count, int* status, int* n_active, hipStream_t st) {
+  const int threads = 64 * std::min(16, std::max(1, (p.B + 63) / 64));
+  hipLaunchKernelGGL(k_outer_flags, dim3(1), dim3(threads), 0, st, p, partial2, ranges, res2, rhs2, target2, best2,
+                     since, gains, stall_min, stall_max, cap, active, outer_count, status, n_active);
 }
 
 void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st) {

@@ -14,6 +14,8 @@ from . import _lib
 from ._lib import (RM_EDIVERGED, RM_ENOTCONV, RM_F32, RM_F64, RM_FD5_HELMHOLTZ, RM_MOM, RM_NAG, RM_NAGEX,
                    RM_OK, RM_Q1_ANISO, RM_RICHARDSON, RM_TO_TOL, RM_UNROLL)
 
+STREAM_SHAPE = 9  # kernel shape id of the row-streaming sweep (rm_plan_set_kernel)
+
 __all__ = [
     "RMError", "Context", "Plan", "rm_tune", "rm_apply_A", "rm_residual", "rm_solve", "rm_solve_adjoint",
     "rm_twogrid_solve", "rm_twogrid_adjoint", "rm_fgmres",
@@ -111,7 +113,9 @@ class Plan:
 
     def set_kernel(self, shape, T, n=0, cw=0):
         """rm_plan_set_kernel: (variant, T, tile width) for the size class n (n <= 0: all);
-        shape -1 = one launch per inner step; cw <= 0 = the cost model's width."""
+        shape -1 = one launch per inner step; shape STREAM_SHAPE = the row-streaming
+        kernel, whose cw is the height of its row windows; cw <= 0 = the cost model's
+        width."""
         _check(self.lib.rm_plan_set_kernel(self.handle, n, shape, T, cw), "rm_plan_set_kernel")
 
     def get_kernel(self, n):
@@ -119,6 +123,21 @@ class Plan:
         _check(self.lib.rm_plan_get_kernel(self.handle, n, ctypes.byref(sh), ctypes.byref(T), ctypes.byref(cw)),
                "rm_plan_get_kernel")
         return sh.value, T.value, cw.value
+
+    def set_tail_kernel(self, shape, T, n=0, cw=0):
+        """rm_plan_set_tail_kernel: the configuration the refined solve switches to once
+        few instances are still active."""
+        _check(self.lib.rm_plan_set_tail_kernel(self.handle, n, shape, T, cw), "rm_plan_set_tail_kernel")
+
+    def get_tail_kernel(self, n):
+        sh, T, cw = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.rm_plan_get_tail_kernel(self.handle, n, ctypes.byref(sh), ctypes.byref(T),
+                                                ctypes.byref(cw)), "rm_plan_get_tail_kernel")
+        return sh.value, T.value, cw.value
+
+    def set_tail_switch(self, frac):
+        """rm_plan_set_tail_switch: active fraction below which the tails run (< 0: measured)."""
+        _check(self.lib.rm_plan_set_tail_switch(self.handle, float(frac)), "rm_plan_set_tail_switch")
 
     def coarse_points(self):
         """rm_plan_coarse_points: total coarse points of the two-grid cycle (-1 if the

@@ -1,6 +1,7 @@
 """Temporal-blocked FP32 sweeps: bitwise equal to one launch per inner step (the LDS
-race / halo detector), for every kernel variant, steps-per-launch T and several
-tile widths, on ragged sizes; autotuner choices and cache."""
+race / halo detector), for every kernel variant (tiled and row-streaming),
+steps-per-launch T and several tile widths / row windows, on ragged sizes; autotuner
+choices and cache."""
 import json
 import os
 
@@ -57,7 +58,7 @@ def test_blocked_equals_one_step_bitwise(ctx, method_name, jacobi):
     f = dev(batch.f_packed(), torch.float32)
     plan.set_kernel(-1, 1)
     ref, ref_h, _ = _unroll(ctx, plan, method, om, al, f, m, K, hist=True, jacobi=jacobi)
-    for shape in range(9):
+    for shape in range(rm.STREAM_SHAPE + 1):
         for T in (1, 2, 3, 8, 16):
             for cw in (0, 24, 64, 128):
                 try:
@@ -91,6 +92,14 @@ def test_blocked_checkpoints_and_mixed_classes(ctx):
     got, _, got_ck = _unroll(ctx, plan, rm.RM_NAG, om, al, f, m, K, ckpt_every=E)
     assert np.array_equal(got, ref)
     assert np.array_equal(got_ck, ref_ck)
+    # row-streaming classes: whole height, and row windows with cuts
+    plan.set_kernel(rm.STREAM_SHAPE, 5)
+    plan.set_kernel(rm.STREAM_SHAPE, 3, n=127, cw=40)
+    plan.set_kernel(rm.STREAM_SHAPE, 8, n=255, cw=100)
+    say("stream classes", [plan.get_kernel(k) for k in (31, 63, 127, 255)])
+    got, _, got_ck = _unroll(ctx, plan, rm.RM_NAG, om, al, f, m, K, ckpt_every=E)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(got_ck, ref_ck)
 
 
 def test_refined_solve_blocked_matches_one_step(ctx):
@@ -102,12 +111,15 @@ def test_refined_solve_blocked_matches_one_step(ctx):
     om, al = _weights(batch, m, 3)
     b = dev(batch.f_packed())
     reps = []
-    for cfg in ((-1, 1), (2, 4), (4, 8)):
+    # the row-streaming shape with its tail (a tiled variant) never, always, or once
+    # half of the instances have converged
+    for cfg, frac in (((-1, 1), -1), ((2, 4), -1), ((4, 8), -1), ((9, 8), 0.0), ((9, 7), 1.0), ((9, 8), 0.5)):
         plan.set_kernel(*cfg)
+        plan.set_tail_switch(frac)
         x = torch.zeros(plan.P, dtype=torch.float64, device="cuda")
         opts = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=1e-10, tol_inner=1e-3, max_outer=20000, max_rounds=10)
         rep = rm.rm_solve(ctx, plan, rm.RM_NAG, opts, om, al, b, x)
-        say("refined", cfg, rep["outer_iters"], rep["rounds"])
+        say("refined", cfg, frac, [plan.get_tail_kernel(k) for k in ns], rep["outer_iters"], rep["rounds"])
         assert rep["status"] == rm.RM_OK and np.all(rep["relres"] <= 1e-10)
         reps.append((rep, host(x)))
     for rep, x in reps[1:]:
@@ -128,13 +140,17 @@ def test_autotune_and_cache(ctx, tmp_path):
     say("tuned", us, [plan.get_kernel(k) for k in (63, 255)])
     assert us > 0
     table = json.load(open(cache))
-    assert len(table) == 2 and all(len(v) == 4 for v in table.values())
+    # [shape, T, cw, us, tail shape, tail T, tail cw, tail us, one-active us]
+    assert len(table) == 2 and all(len(v) == 9 for v in table.values())
+    for k in (63, 255):
+        assert plan.get_tail_kernel(k)[0] != rm.STREAM_SHAPE
     # a second plan reads the cache (no timing) and lands on the same choices
     plan2 = plan_for(ctx, batch)
     us2 = rm.rm_tune(ctx, plan2, rm.RM_NAG, m, om, al, f, cache_path=cache)
     assert abs(us2 - us) < 1e-2
     for k in (63, 255):
         assert plan2.get_kernel(k) == plan.get_kernel(k)
+        assert plan2.get_tail_kernel(k) == plan.get_tail_kernel(k)
     # tuned plan still computes the same iterates as the one-step kernel
     ref_plan = plan_for(ctx, batch)
     ref_plan.set_kernel(-1, 1)
@@ -144,17 +160,17 @@ def test_autotune_and_cache(ctx, tmp_path):
 
 
 def test_adjoint_blocked_recompute_bitwise(ctx):
-    """The adjoint through blocked launches (forward recompute storing every state, then
-    several reverse steps per launch with ub, vb, fb in registers) gives the same
-    vectors as one launch per step, bit for bit; the gradients of omega and alpha are
-    dot products summed over different tiles, so they agree to rounding order."""
+    """The adjoint whose forward recompute runs blocked launches that store every
+    intermediate state (tiled and row-streaming) gives the same vectors as one launch
+    per step, bit for bit; the gradients of omega and alpha are dot products summed over
+    different tiles, so they agree to rounding order."""
     from paper_2412_08076_amd import rm
     ns = [40, 63, 127, 130]
     batch = random_batch(ns, seed=23)
     m, K, E = 8, 32, 16
     f = dev(batch.f_packed(), torch.float32)
     outs = []
-    for cfg in ((-1, 1), (0, 4), (2, 8)):
+    for cfg in ((-1, 1), (0, 4), (2, 8), (9, 8), (9, 5)):
         plan = plan_for(ctx, batch)
         om, al = _weights(batch, m, 6)
         plan.set_kernel(*cfg)
@@ -179,15 +195,16 @@ def test_adjoint_blocked_recompute_bitwise(ctx):
 
 @pytest.mark.parametrize("method_name", ["nag", "nagex", "mom", "richardson"])
 def test_blocked_reverse_matches_one_step_reverse(ctx, method_name):
-    """Every variant with a blocked reverse, several reverse steps per launch, uneven
-    sizes: ub, vb and d_b bit for bit equal to one reverse step per launch."""
+    """Every Table-1 scheme, forward recompute through several kernel shapes and steps
+    per launch, uneven sizes: d_b and the loss bit for bit equal to the one-step
+    recompute, the weight gradients to rounding order."""
     from paper_2412_08076_amd import rm
     method = {"nag": rm.RM_NAG, "richardson": rm.RM_RICHARDSON, "mom": rm.RM_MOM, "nagex": rm.RM_NAGEX}[method_name]
     batch = random_batch([17, 40, 64, 65, 130], seed=27)
     m, K, E = 8, 24, 12
     f = dev(batch.f_packed(), torch.float32)
     ref = None
-    for cfg in ((-1, 1), (0, 4), (3, 8), (6, 3), (2, 6), (5, 12), (1, 5), (4, 8)):
+    for cfg in ((-1, 1), (0, 4), (3, 8), (6, 3), (2, 6), (5, 12), (1, 5), (4, 8), (9, 6), (9, 8)):
         plan = plan_for(ctx, batch)
         om, al = _weights(batch, m, 7)
         if method_name == "nagex":
@@ -228,6 +245,11 @@ def test_refined_solve_graph_replays_match_eager(ctx, ns, m):
     outs = []
     for graph in (False, True, True):  # eager reference, then two calls with graph replay
         plan = plan_for(ctx, batch)
+        if max(ns) <= 512:
+            # row-streaming main configuration, tiled tail from half the batch on:
+            # two captured iterations, switched between at the polls
+            plan.set_kernel(rm.STREAM_SHAPE, 8)
+            plan.set_tail_switch(0.5)
         x = torch.zeros(plan.P, dtype=torch.float64, device="cuda")
         opts = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=1e-10, tol_inner=1e-3, max_outer=20000, max_rounds=10,
                              check_every=3, graph=graph)
