@@ -248,7 +248,10 @@ rm_status rm_solve(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, const rm_
  * with the same plan, method, opts, omega, alpha, b and its checkpoints ckpt
  * (opts->ckpt_every > 0 required).  Forward states are recomputed one
  * checkpoint segment at a time; A is symmetric, so the backward sweep applies
- * the same stencil.
+ * the same stencil.  When every size class runs the row-streaming kernel the
+ * reverse steps run up to three per launch in its row pipeline, else one per
+ * launch; both give the same d_b and loss bit for bit and the same weight
+ * gradients up to the order of their FP64 sums.
  *   g_uK:  device float [P_tot], the seed dJ/du_K; or NULL for the loss mode
  *          J = sum_b g_loss[b] * ||b - A u_K||^2 / ||b||^2.
  *   g_loss: device float [B] (loss mode only; NULL = all ones).

@@ -1205,11 +1205,14 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   RM_TRY(pl->vecC.ensure(fbytes, st));  // ub1
   RM_TRY(pl->vecD.ensure(fbytes, st));  // vb1
   RM_TRY(pl->vecE.ensure(fbytes, st));  // r_K
-  const int nslot = (int)pl->tiles.size();
+  if (pl->use_block) RM_TRY(build_exec(pl, st));
+  const int nslot = (int)partial_slots(pl);
   RM_TRY(pl->partial.ensure((size_t)nslot * 4 * sizeof(double) * E, st));
   RM_TRY(pl->red.ensure((size_t)B * 4 * sizeof(double), st));
   RM_TRY(pl->acc.ensure((size_t)B * m * (1 + na) * sizeof(double), st));
-  if (pl->use_block) RM_TRY(build_exec(pl, st));
+  // reverse steps in the row pipeline when every size class runs the row-streaming kernel
+  bool stream_rev = blocked(pl) && !pl->classes.empty();
+  for (const auto& cl : pl->classes) stream_rev = stream_rev && cl.shape == kStreamShape;
   float* S = pl->states.as<float>();  // slot t: (u, v) before step c*E + t, t = 1..E; slot 0 unused
                                       // (the checkpoint itself serves as slot 0)
   float* ubs[2] = {pl->vecA.as<float>(), pl->vecC.as<float>()};
@@ -1266,13 +1269,34 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   int cur = 0;
   for (int c = nseg - 1; c >= 0; --c) {
     if (c != nseg - 1) RM_TRY(recompute(c));
-    for (int t = E - 1; t >= 0; --t) {
-      const int i = (c * E + t) % m;
-      adj_one_step(pl, p, method, omega, alpha, m, i, b, su(c, t), sv(c, t), ubs[cur], vbs[cur],
-                           ubs[cur ^ 1], vbs[cur ^ 1], d_b, partial + (size_t)t * 4 * nslot, st);
-      cur ^= 1;
+    if (stream_rev) {
+      // up to kAdjMaxT reverse steps per launch, latest step first
+      for (int t = E - 1; t >= 0;) {
+        const int tn = std::min(rmk::kAdjMaxT, t + 1);
+        rmk::AdjLevels lev{};
+        for (int l = 0; l < tn; ++l) {
+          lev.u[l] = su(c, t - l);
+          lev.v[l] = sv(c, t - l);
+          lev.part[l] = partial + (size_t)(t - l) * 4 * nslot;
+          lev.i[l] = (c * E + t - l) % m;
+        }
+        for (auto& cl : pl->classes)
+          if (!rmk::launch_adj_stream(tn, cl.cw, cl.n, method, p, cl.tiles.as<rmk::BTile>(), cl.ntiles, omega, alpha,
+                                      m, lev, b, ubs[cur], vbs[cur], ubs[cur ^ 1], vbs[cur ^ 1], d_b, st))
+            return fail(RM_EUNSUPPORTED, "reverse kernel configuration not built");
+        cur ^= 1;
+        t -= tn;
+      }
+      rmk::launch_adj_accumulate(method, p, partial, nslot, E, c * E, m, acc_w, acc_a, st, pl->d_ranges.as<int>());
+    } else {
+      for (int t = E - 1; t >= 0; --t) {
+        const int i = (c * E + t) % m;
+        adj_one_step(pl, p, method, omega, alpha, m, i, b, su(c, t), sv(c, t), ubs[cur], vbs[cur], ubs[cur ^ 1],
+                     vbs[cur ^ 1], d_b, partial + (size_t)t * 4 * nslot, st);
+        cur ^= 1;
+      }
+      rmk::launch_adj_accumulate(method, p, partial, nslot, E, c * E, m, acc_w, acc_a, st);
     }
-    rmk::launch_adj_accumulate(method, p, partial, nslot, E, c * E, m, acc_w, acc_a, st);
   }
   rmk::launch_f64_to_f32(acc_w, d_omega, (int64_t)B * m, st);
   rmk::launch_f64_to_f32(acc_a, d_alpha, (int64_t)B * m * na, st);

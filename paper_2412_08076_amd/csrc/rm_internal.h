@@ -114,7 +114,7 @@ void launch_adj_step(int method, const PlanDev& p, const float* omega, const flo
 // (NAG: <g, v> + <ut_bar, v>; MOM, NAGex: <g, v>) and, for NAGex, <ut_bar, v> to
 // acc_a[(B + b)*m + i].
 void launch_adj_accumulate(int method, const PlanDev& p, const double* partial4, int nslot, int E, int s_first,
-                           int m, double* acc_w, double* acc_a, hipStream_t st);
+                           int m, double* acc_w, double* acc_a, hipStream_t st, const int* ranges = nullptr);
 void launch_f64_to_f32(const double* src, float* dst, int64_t count, hipStream_t st);
 // meta network
 void launch_meta_forward(const PlanDev& p, int m, const float* params, float* omega, float* alpha,
@@ -164,6 +164,24 @@ bool launch_stream(int T, int wlen, int n, int method, const PlanDev& p, const B
                    const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,
                    const float* v, float* u_out, float* v_out, const int* active, double* partial2,
                    hipStream_t st, float* states = nullptr, int64_t state_stride = 0);
+
+// Up to kAdjMaxT reverse steps per launch over a row-streaming tile table (windows
+// overlapping by at least T + 1 rows).  Level l = 1..T reverses the forward step whose
+// state (before the step) is u[l - 1], v[l - 1] and whose weight index is i[l - 1]
+// (consecutive levels go back in time); ub, vb are the adjoints after the latest step
+// and ub_out, vb_out receive them before the earliest one; fb (may be null) gets
+// w g added per step in place; part[l - 1] + 4 slot receives the window's
+// <g, r>, <g, v>, <utb, v>, 0 for level l (as launch_adj_step's partial4).
+constexpr int kAdjMaxT = 3;
+struct AdjLevels {
+  const float* u[kAdjMaxT];
+  const float* v[kAdjMaxT];
+  double* part[kAdjMaxT];
+  int i[kAdjMaxT];
+};
+bool launch_adj_stream(int T, int wlen, int n, int method, const PlanDev& p, const BTile* tiles, int ntiles,
+                       const float* omega, const float* alpha, int m, const AdjLevels& lev, const float* f,
+                       const float* ub, const float* vb, float* ub_out, float* vb_out, float* fb, hipStream_t st);
 
 // ---- SSOR-preconditioned steps (rm_ssor.hip) ----------------------------------
 // One inner step of a Table-1 scheme with the four-colour SSOR preconditioner of

@@ -506,14 +506,16 @@ __global__ __launch_bounds__(WG) void k_adj_step(PlanDev p, const float* __restr
 template <int METHOD>
 __global__ __launch_bounds__(64) void k_adj_accumulate(PlanDev p, const double* __restrict__ partial4, int nslot,
                                                        int E, int s_first, int m, double* __restrict__ acc_w,
-                                                       double* __restrict__ acc_a) {
+                                                       double* __restrict__ acc_a, const int* __restrict__ ranges) {
   const int b = blockIdx.x;
   const Inst in = p.inst[b];
   const double dinv = p.jacobi ? p.coef64[b * 8 + 5] : 1.0;
+  const int k0 = ranges != nullptr ? ranges[2 * b] : in.tile_begin;
+  const int k1 = ranges != nullptr ? ranges[2 * b + 1] : in.tile_end;
   for (int t = E - 1; t >= 0; --t) {
     const double* q = partial4 + (size_t)t * 4 * nslot;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int k = in.tile_begin + (int)threadIdx.x; k < in.tile_end; k += 64) {
+    for (int k = k0 + (int)threadIdx.x; k < k1; k += 64) {
       s0 += q[4 * k];
       s1 += q[4 * k + 1];
       s2 += q[4 * k + 2];
@@ -750,9 +752,10 @@ void launch_adj_step(int method, const PlanDev& p, const float* omega, const flo
 }
 
 void launch_adj_accumulate(int method, const PlanDev& p, const double* partial4, int nslot, int E, int s_first,
-                           int m, double* acc_w, double* acc_a, hipStream_t st) {
-#define RM_ACC(MM) \
-  hipLaunchKernelGGL(k_adj_accumulate<MM>, dim3(p.B), dim3(64), 0, st, p, partial4, nslot, E, s_first, m, acc_w, acc_a)
+                           int m, double* acc_w, double* acc_a, hipStream_t st, const int* ranges) {
+#define RM_ACC(MM)                                                                                                \
+  hipLaunchKernelGGL(k_adj_accumulate<MM>, dim3(p.B), dim3(64), 0, st, p, partial4, nslot, E, s_first, m, acc_w, \
+                     acc_a, ranges)
   switch (method) {
     case M_NAG: RM_ACC(M_NAG); break;
     case M_MOM: RM_ACC(M_MOM); break;

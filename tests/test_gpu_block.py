@@ -197,11 +197,13 @@ def test_adjoint_blocked_recompute_bitwise(ctx):
 def test_blocked_reverse_matches_one_step_reverse(ctx, method_name):
     """Every Table-1 scheme, forward recompute through several kernel shapes and steps
     per launch, uneven sizes: d_b and the loss bit for bit equal to the one-step
-    recompute, the weight gradients to rounding order."""
+    recompute and reverse, the weight gradients to rounding order.  With every class on
+    the row-streaming shape the reverse steps run in its row pipeline as well."""
     from paper_2412_08076_amd import rm
     method = {"nag": rm.RM_NAG, "richardson": rm.RM_RICHARDSON, "mom": rm.RM_MOM, "nagex": rm.RM_NAGEX}[method_name]
     batch = random_batch([17, 40, 64, 65, 130], seed=27)
-    m, K, E = 8, 24, 12
+    # E = 8: the row-streaming reverse runs launches of 3, 3 and 2 reverse steps per segment
+    m, K, E = 8, 24, 8
     f = dev(batch.f_packed(), torch.float32)
     ref = None
     for cfg in ((-1, 1), (0, 4), (3, 8), (6, 3), (2, 6), (5, 12), (1, 5), (4, 8), (9, 6), (9, 8)):
