@@ -78,7 +78,7 @@ struct DevBuf {
 struct rm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  int* host_flag = nullptr;  // pinned, polled by the refined solve
+  int* host_count = nullptr;  // pinned and coherent: active count written by the refined solve's kernels
   // the refined solve runs on a stream of its own (graph capture is not
   // possible on a legacy default stream) after waiting for `stream`
   hipStream_t work = nullptr;
@@ -756,7 +756,7 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
                    tail));
       flips_per_outer = flips;
       rmk::launch_outer_flags(p, partial, ranges, res2, rhs2, target2, best2, since, gains, stall_min, stall_max,
-                              o->max_outer, active, count, status, n_active, st);
+                              o->max_outer, active, count, status, n_active, ctx->host_count, st);
       return RM_OK;
     };
     // The iteration returns to buffer set 0, so one captured iteration can be
@@ -789,10 +789,11 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
       else
         RM_TRY(outer_iteration(tail == 1));
       if (k % o->check_every == 0 || k >= o->max_outer) {
-        RM_HIP(hipMemcpyAsync(ctx->host_flag, n_active, sizeof(int), hipMemcpyDeviceToHost, st));
+        // the bookkeeping kernel stored the count into pinned host memory
         RM_HIP(hipStreamSynchronize(st));
-        if (*ctx->host_flag == 0) break;
-        tail = *ctx->host_flag < tail_below ? 1 : 0;
+        const int na = __atomic_load_n(ctx->host_count, __ATOMIC_ACQUIRE);
+        if (na == 0) break;
+        tail = na < tail_below ? 1 : 0;
       }
     }
     RM_HIP(hipMemcpyAsync(cnt_h.data(), count, B * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -983,10 +984,12 @@ rm_status rm_create(rm_ctx** out, int32_t device, void* hip_stream) {
   rm_ctx* c = new rm_ctx;
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
-  if (hipHostMalloc((void**)&c->host_flag, sizeof(int) * 16, hipHostMallocDefault) != hipSuccess) {
+  // coherent, so that a kernel's system-scope store is what the host reads after the stream syncs
+  if (hipHostMalloc((void**)&c->host_count, sizeof(int) * 16, hipHostMallocCoherent) != hipSuccess) {
     delete c;
     return fail(RM_ENOMEM, "pinned host allocation failed");
   }
+  *c->host_count = 0;
   *out = c;
   return RM_OK;
 }
@@ -995,7 +998,7 @@ rm_status rm_destroy(rm_ctx* ctx) {
   if (ctx == nullptr) return RM_OK;
   (void)hipStreamSynchronize(ctx->stream);
   for (rm_plan_s* pl : ctx->plans) pl->ctx = nullptr;
-  if (ctx->host_flag != nullptr) (void)hipHostFree(ctx->host_flag);
+  if (ctx->host_count != nullptr) (void)hipHostFree(ctx->host_count);
   if (ctx->work != nullptr) (void)hipStreamDestroy(ctx->work);
   if (ctx->handoff != nullptr) (void)hipEventDestroy(ctx->handoff);
   delete ctx;
