@@ -118,6 +118,11 @@ struct rm_plan_s {
     int tshape = 0, tT = 1, tcw = 64;
     DevBuf ttiles;
     int tntiles = 0;
+    // Row windows for the reverse steps of the adjoint (n <= kStreamMaxN), whatever the
+    // forward configuration: rcw rows each, overlapping by kAdjMaxT + 1.
+    int rcw = 0;
+    DevBuf rtiles;
+    int rntiles = 0;
     double us = 0.0, tus = 0.0;  // tuned time per inner step, whole class active
     double floor_us = 0.0;       // main configuration with one instance active
   };
@@ -129,6 +134,7 @@ struct rm_plan_s {
   std::vector<ClassExec> classes;
   DevBuf d_ranges;  // int [B][2]: slot range of each instance over all class tables
   DevBuf d_tranges; // the same over the tail tables
+  DevBuf d_rranges; // the same over the reverse-step tables
   int nslots = 0;
   double tail_frac = -1.0;  // active fraction below which the refined solve uses the tails (< 0: measured)
   // two-grid correction: coarse layout, tile and row-group tables, twiddles and
@@ -166,13 +172,14 @@ struct rm_plan_s {
   }
   ~rm_plan_s() {
     for (DevBuf* b : {&d_tiles, &d_inst, &d_coef32, &d_coef64, &d_mu, &d_gersh, &partial, &red, &flags, &vecA,
-                      &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges, &d_tranges, &tg.d_inst,
+                      &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges, &d_tranges, &d_rranges, &tg.d_inst,
                       &tg.d_rtiles, &tg.d_groups, &tg.d_tw, &tg.c0, &tg.c1, &tg.shat, &tg.fine2,
                       &tg.zero, &fg.V, &fg.Z, &fg.w, &fg.t, &fg.b32, &fg.dbl, &fg.ints, &fg.partial})
       b->release();
     for (auto& c : classes) {
       c.tiles.release();
       c.ttiles.release();
+      c.rtiles.release();
     }
   }
 };
@@ -419,15 +426,37 @@ rm_status build_table(const rm_plan_s::ClassExec& c, int shape, int T, int cw, i
   return RM_OK;
 }
 
+// Row-window height of the reverse-step table of a class: enough windows per instance
+// for about two waves per SIMD, each window at least four overlaps high.
+int reverse_window(int n, int count) {
+  const int h = rmk::kAdjMaxT + 1;
+  const int nw = (n + 63) / 64;
+  int want = (2048 + count * nw - 1) / std::max(1, count * nw);
+  want = std::max(1, std::min(16, want));
+  for (int S = want; S > 1; --S) {
+    const int len = (n + 2 * (S - 1) * h + S - 1) / S;
+    if (len >= 4 * h && (int)partition(n, len, h).size() == S) return len;
+  }
+  return n;
+}
+
 rm_status build_exec(rm_plan_t* pl, hipStream_t st) {
   if (!pl->exec_dirty) return RM_OK;
-  std::vector<int> ranges((size_t)pl->B * 2, 0), tranges((size_t)pl->B * 2, 0);
-  int slot = 0, tslot = 0;
+  std::vector<int> ranges((size_t)pl->B * 2, 0), tranges((size_t)pl->B * 2, 0), rranges((size_t)pl->B * 2, 0);
+  int slot = 0, tslot = 0, rslot = 0;
   for (auto& c : pl->classes) {
     RM_TRY(build_table(c, c.shape, c.T, c.cw, slot, ranges, c.tiles, c.ntiles, st));
     RM_TRY(build_table(c, c.tshape, c.tT, c.tcw, tslot, tranges, c.ttiles, c.tntiles, st));
+    c.rcw = 0;
+    c.rntiles = 0;
+    if (c.n <= rmk::kStreamMaxN) {
+      c.rcw = reverse_window(c.n, (int)c.insts.size());
+      RM_TRY(build_table(c, kStreamShape, rmk::kAdjMaxT, c.rcw, rslot, rranges, c.rtiles, c.rntiles, st));
+    }
   }
-  pl->nslots = std::max(slot, tslot);
+  pl->nslots = std::max(slot, std::max(tslot, rslot));
+  RM_TRY(pl->d_rranges.ensure(rranges.size() * sizeof(int), st));
+  RM_HIP(hipMemcpy(pl->d_rranges.ptr, rranges.data(), rranges.size() * sizeof(int), hipMemcpyHostToDevice));
   RM_TRY(pl->d_ranges.ensure(ranges.size() * sizeof(int), st));
   RM_HIP(hipMemcpy(pl->d_ranges.ptr, ranges.data(), ranges.size() * sizeof(int), hipMemcpyHostToDevice));
   RM_TRY(pl->d_tranges.ensure(tranges.size() * sizeof(int), st));
@@ -1213,9 +1242,9 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   RM_TRY(pl->partial.ensure((size_t)nslot * 4 * sizeof(double) * E, st));
   RM_TRY(pl->red.ensure((size_t)B * 4 * sizeof(double), st));
   RM_TRY(pl->acc.ensure((size_t)B * m * (1 + na) * sizeof(double), st));
-  // reverse steps in the row pipeline when every size class runs the row-streaming kernel
+  // reverse steps in the row pipeline when every size class has row windows for them
   bool stream_rev = blocked(pl) && !pl->classes.empty();
-  for (const auto& cl : pl->classes) stream_rev = stream_rev && cl.shape == kStreamShape;
+  for (const auto& cl : pl->classes) stream_rev = stream_rev && cl.rntiles > 0;
   float* S = pl->states.as<float>();  // slot t: (u, v) before step c*E + t, t = 1..E; slot 0 unused
                                       // (the checkpoint itself serves as slot 0)
   float* ubs[2] = {pl->vecA.as<float>(), pl->vecC.as<float>()};
@@ -1284,13 +1313,13 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
           lev.i[l] = (c * E + t - l) % m;
         }
         for (auto& cl : pl->classes)
-          if (!rmk::launch_adj_stream(tn, cl.cw, cl.n, method, p, cl.tiles.as<rmk::BTile>(), cl.ntiles, omega, alpha,
-                                      m, lev, b, ubs[cur], vbs[cur], ubs[cur ^ 1], vbs[cur ^ 1], d_b, st))
+          if (!rmk::launch_adj_stream(tn, cl.rcw, cl.n, method, p, cl.rtiles.as<rmk::BTile>(), cl.rntiles, omega,
+                                      alpha, m, lev, b, ubs[cur], vbs[cur], ubs[cur ^ 1], vbs[cur ^ 1], d_b, st))
             return fail(RM_EUNSUPPORTED, "reverse kernel configuration not built");
         cur ^= 1;
         t -= tn;
       }
-      rmk::launch_adj_accumulate(method, p, partial, nslot, E, c * E, m, acc_w, acc_a, st, pl->d_ranges.as<int>());
+      rmk::launch_adj_accumulate(method, p, partial, nslot, E, c * E, m, acc_w, acc_a, st, pl->d_rranges.as<int>());
     } else {
       for (int t = E - 1; t >= 0; --t) {
         const int i = (c * E + t) % m;

@@ -57,6 +57,13 @@ def test_host_only_entry_points(lib):
         _lib.RM_EINVAL
     assert b"null" in lib.rm_last_error()
     assert lib.rm_plan_points(None) == -1
+    # kernel-configuration calls reject a null plan before touching it
+    sh, T, cw = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert lib.rm_plan_set_kernel(None, 0, 9, 8, 0) == _lib.RM_EINVAL
+    assert lib.rm_plan_set_tail_kernel(None, 0, 0, 8, 0) == _lib.RM_EINVAL
+    assert lib.rm_plan_get_tail_kernel(None, 255, ctypes.byref(sh), ctypes.byref(T), ctypes.byref(cw)) == \
+        _lib.RM_EINVAL
+    assert lib.rm_plan_set_tail_switch(None, 0.5) == _lib.RM_EINVAL
 
 
 def test_struct_layouts_match_the_header(tmp_path):

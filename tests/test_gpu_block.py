@@ -262,3 +262,28 @@ def test_refined_solve_graph_replays_match_eager(ctx, ns, m):
     for o in outs[1:]:
         for a, e in zip(o, outs[0]):
             assert np.array_equal(a, e)
+
+
+def test_tail_configuration_calls(ctx):
+    """The tail follows rm_plan_set_kernel (a tiled variant under a row-streaming main
+    configuration, the main configuration otherwise), can be set on its own, and bad
+    arguments are rejected."""
+    from paper_2412_08076_amd import rm
+    batch = random_batch([63, 255], seed=31)
+    plan = plan_for(ctx, batch)
+    plan.set_kernel(rm.STREAM_SHAPE, 8)
+    for k in (63, 255):
+        assert plan.get_kernel(k)[0] == rm.STREAM_SHAPE
+        assert plan.get_tail_kernel(k)[0] != rm.STREAM_SHAPE
+    plan.set_tail_kernel(rm.STREAM_SHAPE, 4, n=255)
+    assert plan.get_tail_kernel(255)[:2] == (rm.STREAM_SHAPE, 4)
+    with pytest.raises(rm.RMError):
+        plan.set_tail_switch(1.5)
+    with pytest.raises(rm.RMError):
+        plan.set_tail_kernel(rm.STREAM_SHAPE, 16)  # more steps per launch than are built
+    with pytest.raises(rm.RMError):
+        plan.set_tail_kernel(0, 8, n=77)  # no instance of that size
+    with pytest.raises(rm.RMError):
+        plan.set_kernel(rm.STREAM_SHAPE + 1, 8)
+    plan.set_kernel(3, 8)
+    assert plan.get_tail_kernel(255) == plan.get_kernel(255)
