@@ -507,6 +507,53 @@ void adj_one_step(const rm_plan_t* pl, const PlanDev& p, int method, const float
     rmk::launch_adj_step(method, p, omega, alpha, m, i, f, u, v, ub, vb, ub_out, vb_out, fb, partial4, st);
 }
 
+// Reverse steps of the adjoint in the row pipeline: when every size class has row windows
+// for them (and no SSOR step, whose reverse needs its own kernel).
+bool stream_reverse(const rm_plan_t* pl) {
+  bool ok = blocked(pl) && !pl->classes.empty();
+  for (const auto& cl : pl->classes) ok = ok && cl.rntiles > 0;
+  return ok;
+}
+
+// Reverse the forward steps nsteps - 1 .. 0 of one segment (latest first).  su(t), sv(t)
+// give the state before step t, the weight index of step t is (base + t) mod m, and the
+// dot-product partials of step t go to partial + 4 nslot t.  (ubs[cur], vbs[cur]) hold
+// the adjoints after the segment on entry and before it on return.  *ranges receives
+// the per-instance slot ranges the accumulation must use (null: the one-step tiles).
+template <typename SU, typename SV>
+rm_status reverse_segment(rm_plan_t* pl, const PlanDev& p, hipStream_t st, int method, const float* omega,
+                          const float* alpha, int m, int base, int nsteps, SU su, SV sv, const float* b,
+                          float* const ubs[2], float* const vbs[2], int& cur, float* d_b, double* partial, int nslot,
+                          const int** ranges) {
+  if (stream_reverse(pl)) {
+    for (int t = nsteps - 1; t >= 0;) {
+      const int tn = std::min(rmk::kAdjMaxT, t + 1);
+      rmk::AdjLevels lev{};
+      for (int l = 0; l < tn; ++l) {
+        lev.u[l] = su(t - l);
+        lev.v[l] = sv(t - l);
+        lev.part[l] = partial + (size_t)(t - l) * 4 * nslot;
+        lev.i[l] = (base + t - l) % m;
+      }
+      for (auto& cl : pl->classes)
+        if (!rmk::launch_adj_stream(tn, cl.rcw, cl.n, method, p, cl.rtiles.as<rmk::BTile>(), cl.rntiles, omega, alpha,
+                                    m, lev, b, ubs[cur], vbs[cur], ubs[cur ^ 1], vbs[cur ^ 1], d_b, st))
+          return fail(RM_EUNSUPPORTED, "reverse kernel configuration not built");
+      cur ^= 1;
+      t -= tn;
+    }
+    *ranges = pl->d_rranges.as<int>();
+    return RM_OK;
+  }
+  for (int t = nsteps - 1; t >= 0; --t) {
+    adj_one_step(pl, p, method, omega, alpha, m, (base + t) % m, b, su(t), sv(t), ubs[cur], vbs[cur], ubs[cur ^ 1],
+                 vbs[cur ^ 1], d_b, partial + (size_t)t * 4 * nslot, st);
+    cur ^= 1;
+  }
+  *ranges = nullptr;
+  return RM_OK;
+}
+
 // Preconditioner of this call (validated by validate_weights).
 void set_precond(rm_plan_t* pl, const rm_solve_opts* o) {
   pl->jacobi = (o->flags & RM_FLAG_JACOBI) ? 1 : 0;
@@ -1242,9 +1289,6 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   RM_TRY(pl->partial.ensure((size_t)nslot * 4 * sizeof(double) * E, st));
   RM_TRY(pl->red.ensure((size_t)B * 4 * sizeof(double), st));
   RM_TRY(pl->acc.ensure((size_t)B * m * (1 + na) * sizeof(double), st));
-  // reverse steps in the row pipeline when every size class has row windows for them
-  bool stream_rev = blocked(pl) && !pl->classes.empty();
-  for (const auto& cl : pl->classes) stream_rev = stream_rev && cl.rntiles > 0;
   float* S = pl->states.as<float>();  // slot t: (u, v) before step c*E + t, t = 1..E; slot 0 unused
                                       // (the checkpoint itself serves as slot 0)
   float* ubs[2] = {pl->vecA.as<float>(), pl->vecC.as<float>()};
@@ -1301,34 +1345,10 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   int cur = 0;
   for (int c = nseg - 1; c >= 0; --c) {
     if (c != nseg - 1) RM_TRY(recompute(c));
-    if (stream_rev) {
-      // up to kAdjMaxT reverse steps per launch, latest step first
-      for (int t = E - 1; t >= 0;) {
-        const int tn = std::min(rmk::kAdjMaxT, t + 1);
-        rmk::AdjLevels lev{};
-        for (int l = 0; l < tn; ++l) {
-          lev.u[l] = su(c, t - l);
-          lev.v[l] = sv(c, t - l);
-          lev.part[l] = partial + (size_t)(t - l) * 4 * nslot;
-          lev.i[l] = (c * E + t - l) % m;
-        }
-        for (auto& cl : pl->classes)
-          if (!rmk::launch_adj_stream(tn, cl.rcw, cl.n, method, p, cl.rtiles.as<rmk::BTile>(), cl.rntiles, omega,
-                                      alpha, m, lev, b, ubs[cur], vbs[cur], ubs[cur ^ 1], vbs[cur ^ 1], d_b, st))
-            return fail(RM_EUNSUPPORTED, "reverse kernel configuration not built");
-        cur ^= 1;
-        t -= tn;
-      }
-      rmk::launch_adj_accumulate(method, p, partial, nslot, E, c * E, m, acc_w, acc_a, st, pl->d_rranges.as<int>());
-    } else {
-      for (int t = E - 1; t >= 0; --t) {
-        const int i = (c * E + t) % m;
-        adj_one_step(pl, p, method, omega, alpha, m, i, b, su(c, t), sv(c, t), ubs[cur], vbs[cur], ubs[cur ^ 1],
-                     vbs[cur ^ 1], d_b, partial + (size_t)t * 4 * nslot, st);
-        cur ^= 1;
-      }
-      rmk::launch_adj_accumulate(method, p, partial, nslot, E, c * E, m, acc_w, acc_a, st);
-    }
+    const int* ranges = nullptr;
+    RM_TRY(reverse_segment(pl, p, st, method, omega, alpha, m, c * E, E, [&](int t) { return su(c, t); },
+                           [&](int t) { return sv(c, t); }, b, ubs, vbs, cur, d_b, partial, nslot, &ranges));
+    rmk::launch_adj_accumulate(method, p, partial, nslot, E, c * E, m, acc_w, acc_a, st, ranges);
   }
   rmk::launch_f64_to_f32(acc_w, d_omega, (int64_t)B * m, st);
   rmk::launch_f64_to_f32(acc_a, d_alpha, (int64_t)B * m * na, st);
@@ -1397,11 +1417,11 @@ rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
   RM_TRY(tg.fine2.ensure(fbytes, st));
   RM_TRY(tg.zero.ensure(fbytes, st));
   RM_TRY(tg.shat.ensure(cbytes, st));
-  const int nslot = (int)pl->tiles.size();
+  if (pl->use_block) RM_TRY(build_exec(pl, st));
+  const int nslot = (int)partial_slots(pl);
   RM_TRY(pl->partial.ensure((size_t)nslot * 4 * sizeof(double) * m, st));
   RM_TRY(pl->red.ensure((size_t)B * 4 * sizeof(double), st));
   RM_TRY(pl->acc.ensure((size_t)B * m * (1 + na) * sizeof(double), st));
-  if (pl->use_block) RM_TRY(build_exec(pl, st));
   const PlanDev p = pl->dev();
   const rmk::TgDev g = pl->tgdev();
   float* S = pl->states.as<float>();  // slot t = 1..m: (u, v) after t smoothing steps
@@ -1471,12 +1491,10 @@ rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
     cur ^= 1;
     // through the smoothing, which starts from v = 0 (its adjoint is dropped)
     rmk::launch_fill_f32(vbs[cur], 0.f, P, st);
-    for (int t = m - 1; t >= 0; --t) {
-      adj_one_step(pl, p, method, omega, alpha, m, t, b, su(t), sv(t), ubs[cur], vbs[cur], ubs[cur ^ 1],
-                           vbs[cur ^ 1], d_b, partial + (size_t)t * 4 * nslot, st);
-      cur ^= 1;
-    }
-    rmk::launch_adj_accumulate(method, p, partial, nslot, m, 0, m, acc_w, acc_a, st);
+    const int* ranges = nullptr;
+    RM_TRY(reverse_segment(pl, p, st, method, omega, alpha, m, 0, m, su, sv, b, ubs, vbs, cur, d_b, partial, nslot,
+                           &ranges));
+    rmk::launch_adj_accumulate(method, p, partial, nslot, m, 0, m, acc_w, acc_a, st, ranges);
   }
   rmk::launch_f64_to_f32(acc_w, d_omega, (int64_t)B * m, st);
   rmk::launch_f64_to_f32(acc_a, d_alpha, (int64_t)B * m * na, st);
