@@ -564,8 +564,10 @@ void set_precond(rm_plan_t* pl, const rm_solve_opts* o) {
 // Advance `nsteps` FP32 inner steps (global step indices s0 ..) on the pingpong
 // pair (us, vs), starting from set `cur`; `cur` ends on the set holding the
 // result and `flips` counts the swaps (the same for every instance).  Each size
-// class advances in its own chunks of at most its T steps; for nsteps >= 2 every
-// class uses an even number of launches, so all classes end on the same set.
+// class advances in its own chunks of at most its T steps, as few as T allows, but
+// every class, in its main and in its tail configuration alike, makes a number of
+// launches of one common parity, so all classes end on the same set and a solve that
+// switches configurations flips the same way throughout.
 // When res_partial is given, the residual ||f - A u||^2 of the final iterate is
 // left per tile in res_partial and *res_ranges tells the reduction which slots
 // belong to which instance.  `only_class` >= 0 restricts the launches to one
@@ -590,6 +592,19 @@ rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int ns
     return RM_OK;
   }
   RM_TRY(build_exec(pl, st));
+  // common parity of the launch counts: the fewest launches when they agree; else the
+  // parity of a count that cannot grow (one step per launch), else even
+  int par = -1;
+  bool mixed = false;
+  int fixed_par = -1;
+  for (const auto& c : pl->classes)
+    for (const int T : {c.T, c.tT}) {
+      const int lc = (nsteps + T - 1) / T;
+      if (par < 0) par = lc & 1;
+      else if ((lc & 1) != par) mixed = true;
+      if (lc == nsteps) fixed_par = lc & 1;
+    }
+  if (mixed) par = fixed_par >= 0 ? fixed_par : 0;
   // chunk plan per class
   std::vector<std::vector<int>> chunks(pl->classes.size());
   int L = 0;
@@ -597,7 +612,7 @@ rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int ns
     if (only_class >= 0 && (int)ci != only_class) continue;
     const int T = tail ? pl->classes[ci].tT : pl->classes[ci].T;
     int lc = (nsteps + T - 1) / T;
-    if (nsteps >= 2 && (lc & 1)) ++lc;
+    if ((lc & 1) != par) ++lc;
     for (int j = 0; j < lc; ++j) chunks[ci].push_back(nsteps / lc + (j < nsteps % lc ? 1 : 0));
     L = std::max(L, lc);
   }
@@ -614,9 +629,8 @@ rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int ns
         return fail(RM_EUNSUPPORTED, "block kernel configuration not built");
     }
   }
-  const int lfin = nsteps >= 2 ? 0 : 1;  // parity of every class's launch count
-  cur ^= lfin;
-  flips += nsteps >= 2 ? 2 : 1;
+  cur ^= par;
+  flips += par ? 1 : 2;
   if (res_partial != nullptr) *res_ranges = (tail ? pl->d_tranges : pl->d_ranges).as<int>();
   return RM_OK;
 }
