@@ -287,3 +287,40 @@ def test_tail_configuration_calls(ctx):
         plan.set_kernel(rm.STREAM_SHAPE + 1, 8)
     plan.set_kernel(3, 8)
     assert plan.get_tail_kernel(255) == plan.get_kernel(255)
+
+
+@pytest.mark.parametrize("method_name", ["nag", "nagex"])
+def test_stream_wide_instances_bitwise(ctx, method_name):
+    """Row-streaming forward and reverse at the widths where a workgroup holds 4, 5, 7
+    and 8 waves (n = 256, 257, 448, 512, the largest it takes): the unroll with
+    checkpoints and residual history, and the adjoint, equal one launch per step bit for
+    bit (weight gradients to rounding order), over the whole height and over row windows."""
+    from paper_2412_08076_amd import rm
+    method = rm.RM_NAG if method_name == "nag" else rm.RM_NAGEX
+    batch = random_batch([256, 257, 448, 512], seed=37)
+    m, K, E = 8, 16, 8
+    f = dev(batch.f_packed(), torch.float32)
+    outs = []
+    for cfg in ((-1, 1, 0), (rm.STREAM_SHAPE, 8, 0), (rm.STREAM_SHAPE, 5, 120)):
+        plan = plan_for(ctx, batch)
+        om, al = _weights(batch, m, 11)
+        if method_name == "nagex":
+            al = torch.cat([al, 0.5 * al])
+        plan.set_kernel(cfg[0], cfg[1], cw=cfg[2])
+        say("wide stream", method_name, cfg, [plan.get_kernel(k) for k in (256, 512)])
+        x, h, ck = _unroll(ctx, plan, method, om, al, f, m, K, hist=True, ckpt_every=E)
+        opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=K, ckpt_every=E)
+        na = 2 if method_name == "nagex" else 1
+        dw = torch.empty(plan.B * m, dtype=torch.float32, device="cuda")
+        da = torch.empty(na * plan.B * m, dtype=torch.float32, device="cuda")
+        db = torch.empty(plan.P, dtype=torch.float32, device="cuda")
+        loss = torch.empty(plan.B, dtype=torch.float32, device="cuda")
+        rm.rm_solve_adjoint(ctx, plan, method, opts, om, al, f, dev(ck, torch.float32), dw, da, d_b=db, loss=loss)
+        outs.append((x, h, ck, host(db), host(loss), host(dw), host(da)))
+    ref = outs[0]
+    for o in outs[1:]:
+        assert np.array_equal(o[0], ref[0]) and np.array_equal(o[2], ref[2])
+        assert np.allclose(o[1], ref[1], rtol=1e-12, atol=0)
+        assert np.array_equal(o[3], ref[3]) and np.array_equal(o[4], ref[4])
+        for a, b in zip(o[5:], ref[5:]):
+            np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-7 * max(1e-30, np.max(np.abs(b))))
