@@ -12,11 +12,19 @@
 //   backward (c = 2, 1, 0):     w_p = y_p - (a / D) sum_{upper q} A_pq w_q   (colour 3: w = y)
 //   B^{-1} r = a (2 - a) w.
 //
-// One inner step per launch.  A workgroup owns a 64 x 32 tile; the six passes that
-// read neighbours each invalidate one more ring at the edge of the LDS region, so the
-// region carries a halo of 6 (7 for the look-ahead field the residual needs) and is
-// swept in place.  Points outside the domain hold 0 and are never updated (Dirichlet).
-// Temporal blocking would need a halo of 7 per step, so none is attempted.
+// One inner step per launch.  A workgroup owns a 64 x 32 tile.  Each of the six passes
+// that read neighbours needs its inputs one ring further out than its own output, so the
+// passes run on the tile plus a ring that shrinks from 6 (first pass) to 0 (last), and
+// the residual is formed on a halo of 6 from a look-ahead field with a halo of 7.
+// Points outside the domain hold 0 and are never updated (Dirichlet).  Temporal
+// blocking would need a halo of 7 per step, so none is attempted.
+//
+// LDS layout.  The swept field is held as four colour planes: padded point (x, y) lives
+// in plane (x mod 2, y mod 2) at index (y / 2) * QW + x / 2.  In a colour pass every
+// neighbour of a point then sits at a fixed offset in one other plane, so consecutive
+// lanes read and write consecutive words.  The look-ahead field and the residual share
+// one buffer: the residual is held in registers across a barrier and then scattered
+// into the planes, which keeps one workgroup at 14 KB of LDS in FP32.
 #include "rm_device.h"
 
 #pragma clang fp contract(off)
@@ -25,62 +33,85 @@ namespace rmk {
 
 namespace {
 
-constexpr int HR = 6;               // halo of the swept region
+constexpr int HR = 6;               // halo of the residual and of the first colour pass
 constexpr int HU = HR + 1;          // halo of the field the residual is formed from
-constexpr int RW = TX + 2 * HR;     // swept region 76 x 44
+constexpr int RW = TX + 2 * HR;     // residual region 76 x 44
 constexpr int RH = TY + 2 * HR;
-constexpr int PW = RW + 2;          // plus a zero ring, so every neighbour read is in bounds
+constexpr int PW = RW + 2;          // plus one ring: 78 x 46, the look-ahead region
 constexpr int PH = RH + 2;
-constexpr int UW = TX + 2 * HU;     // 78 x 46 (= PW x PH)
+constexpr int UW = TX + 2 * HU;
 constexpr int UH = TY + 2 * HU;
 constexpr int NW = WG / 64;
-static_assert(UW == PW && UH == PH, "the padded region and the residual input coincide");
+static_assert(UW == PW && UH == PH, "the padded region and the look-ahead region coincide");
 
-// In-place SSOR sweeps on a padded LDS field s: a W x H region (W, H even) at offset
-// (1, 1) of a (W + 2)-wide array whose outer ring is 0; region origin (ox, oy) in
-// instance coordinates.  On entry the region holds r (0 outside the domain), on exit
-// w with B^{-1} r = a (2 - a) w.  Colours are taken from instance coordinates.
-template <typename T, int W, int H>
-__device__ __forceinline__ void ssor_lds(T* s, int ox, int oy, int n, const T c[5], T relax, T dinv) {
-  constexpr int S = W + 2, AW = W / 2, AH = H / 2;
-  for (int col = 0; col < 4; ++col) {
-    const int lx0 = (col & 1) ^ (ox & 1), ly0 = (col >> 1) ^ (oy & 1);
-    for (int k = threadIdx.x; k < AW * AH; k += WG) {
-      const int b = k / AW, a = k - b * AW;
-      const int lx = 2 * a + lx0, ly = 2 * b + ly0;
-      const int gx = ox + lx, gy = oy + ly;
-      if (gx < 0 || gx >= n || gy < 0 || gy >= n) continue;
-      T* q = s + (ly + 1) * S + (lx + 1);
-      T acc = T(0);
-      if (col & 1) acc = fmadd(c[1], q[-1] + q[1], acc);      // x-neighbours, colour col - 1
-      if (col >= 2) {
-        acc = fmadd(c[2], q[-S] + q[S], acc);                 // y-neighbours, colour col - 2
-        acc = fmadd(c[3], q[-S - 1] + q[S + 1], acc);         // diagonals, colour col ^ 3
-        acc = fmadd(c[4], q[-S + 1] + q[S - 1], acc);
-      }
-      q[0] = (q[0] - relax * acc) * dinv;
-    }
-    __syncthreads();
+// Colour planes of a padded (W + 2) x (H + 2) region (W, H even).
+template <int W, int H>
+struct Planes {
+  static constexpr int QW = W / 2 + 1, QH = H / 2 + 1, QS = QW * QH, SIZE = 4 * QS;
+  static __device__ __forceinline__ int at(int x, int y) {
+    return ((y & 1) * 2 + (x & 1)) * QS + (y >> 1) * QW + (x >> 1);
   }
-  for (int col = 2; col >= 0; --col) {
-    const int lx0 = (col & 1) ^ (ox & 1), ly0 = (col >> 1) ^ (oy & 1);
-    for (int k = threadIdx.x; k < AW * AH; k += WG) {
-      const int b = k / AW, a = k - b * AW;
-      const int lx = 2 * a + lx0, ly = 2 * b + ly0;
-      const int gx = ox + lx, gy = oy + ly;
-      if (gx < 0 || gx >= n || gy < 0 || gy >= n) continue;
-      T* q = s + (ly + 1) * S + (lx + 1);
-      T acc = T(0);
-      if (!(col & 1)) acc = fmadd(c[1], q[-1] + q[1], acc);   // x-neighbours, colour col + 1
-      if (col < 2) {
-        acc = fmadd(c[2], q[-S] + q[S], acc);                 // y-neighbours, colour col + 2
-        acc = fmadd(c[3], q[-S - 1] + q[S + 1], acc);         // diagonals, colour col ^ 3
-        acc = fmadd(c[4], q[-S + 1] + q[S - 1], acc);
-      }
-      q[0] = fmadd(-(relax * dinv), acc, q[0]);
+};
+
+// One colour pass of the SSOR sweeps (FWD: the forward solve with D - aL, else the
+// backward solve with D - aU) over the points of colour col within h of the tile.  s
+// holds the colour planes Q of a region whose padded point (x, y) is instance point
+// (px0 + x, py0 + y); the tile starts at padded (G, G).
+template <typename T, typename Q, int G, int h, bool FWD>
+__device__ __forceinline__ void ssor_pass(T* s, int col, int px0, int py0, int n, const T c[5], T relax, T dinv) {
+  constexpr int NX = TX / 2 + h, NY = TY / 2 + h;   // points of one colour per row, rows
+  static_assert(G - h >= 1 && G + TX + h <= 2 * Q::QW - 1 && G + TY + h <= 2 * Q::QH - 1,
+                "a pass and its neighbour reads stay inside the padded region");
+  const int a = (col ^ px0) & 1, b = ((col >> 1) ^ py0) & 1;   // plane of colour col
+  const int lo = G - h;
+  const int i0 = (lo + ((lo ^ a) & 1)) >> 1, j0 = (lo + ((lo ^ b) & 1)) >> 1;
+  T* q0 = s + (2 * b + a) * Q::QS;
+  const T* qx = s + (2 * b + (a ^ 1)) * Q::QS;          // x-neighbours
+  const T* qy = s + (2 * (b ^ 1) + a) * Q::QS;          // y-neighbours
+  const T* qd = s + (2 * (b ^ 1) + (a ^ 1)) * Q::QS;    // diagonal neighbours
+  const int xm = a - 1, xp = a;                         // plane offsets of x - 1, x + 1
+  const int ym = (b - 1) * Q::QW, yp = b * Q::QW;       // and of y - 1, y + 1
+  const bool xn = FWD ? (col & 1) != 0 : (col & 1) == 0;
+  const bool yn = FWD ? col >= 2 : col < 2;
+  for (int k = threadIdx.x; k < NX * NY; k += WG) {
+    const int jj = k / NX, ii = k - jj * NX;
+    const int i = i0 + ii, j = j0 + jj;
+    const int gx = px0 + 2 * i + a, gy = py0 + 2 * j + b;
+    if (gx < 0 || gx >= n || gy < 0 || gy >= n) continue;
+    const int e = j * Q::QW + i;
+    T acc = T(0);
+    if (xn) acc = fmadd(c[1], qx[e + xm] + qx[e + xp], acc);
+    if (yn) {
+      acc = fmadd(c[2], qy[e + ym] + qy[e + yp], acc);
+      acc = fmadd(c[3], qd[e + ym + xm] + qd[e + yp + xp], acc);   // (-1, -1) and (+1, +1)
+      acc = fmadd(c[4], qd[e + ym + xp] + qd[e + yp + xm], acc);   // (+1, -1) and (-1, +1)
     }
-    __syncthreads();
+    if (FWD)
+      q0[e] = (q0[e] - relax * acc) * dinv;
+    else
+      q0[e] = fmadd(-(relax * dinv), acc, q0[e]);
   }
+}
+
+// The seven colour passes: forward colours 0..3, backward colours 2..0.  On entry s
+// holds r on the tile plus a ring of h0 + 6; on exit it holds w (B^{-1} r = a (2 - a) w)
+// on the tile plus a ring of h0.
+template <typename T, typename Q, int G, int h0>
+__device__ __forceinline__ void ssor_sweeps(T* s, int px0, int py0, int n, const T c[5], T relax, T dinv) {
+  ssor_pass<T, Q, G, h0 + 6, true>(s, 0, px0, py0, n, c, relax, dinv);
+  __syncthreads();
+  ssor_pass<T, Q, G, h0 + 5, true>(s, 1, px0, py0, n, c, relax, dinv);
+  __syncthreads();
+  ssor_pass<T, Q, G, h0 + 4, true>(s, 2, px0, py0, n, c, relax, dinv);
+  __syncthreads();
+  ssor_pass<T, Q, G, h0 + 3, true>(s, 3, px0, py0, n, c, relax, dinv);
+  __syncthreads();
+  ssor_pass<T, Q, G, h0 + 2, false>(s, 2, px0, py0, n, c, relax, dinv);
+  __syncthreads();
+  ssor_pass<T, Q, G, h0 + 1, false>(s, 1, px0, py0, n, c, relax, dinv);
+  __syncthreads();
+  ssor_pass<T, Q, G, h0, false>(s, 0, px0, py0, n, c, relax, dinv);
+  __syncthreads();
 }
 
 // 9-point stencil at padded position q (row stride W), fixed order.
@@ -94,6 +125,33 @@ __device__ __forceinline__ T stencil_at(const T* q, int W, const T c[5]) {
   return acc;
 }
 
+// Residual r = f - A u~ on the padded region (0 on its outer ring and outside the
+// domain), read from the look-ahead field s (row-major, UW wide), then written over s
+// as colour planes Q.  Ends with a barrier.
+template <typename T, typename Q>
+__device__ __forceinline__ void residual_to_planes(T* s, const T* fi, int ox, int oy, int n, const T c[5]) {
+  constexpr int NR = (PH * PW + WG - 1) / WG;
+  T rr[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    const int k = threadIdx.x + j * WG;
+    const int py = k / PW, px = k - py * PW;
+    const int gx = ox + px, gy = oy + py;
+    T r = T(0);
+    const bool ring = px == 0 || py == 0 || px == PW - 1 || py >= PH - 1;
+    if (!ring && gx >= 0 && gx < n && gy >= 0 && gy < n) r = fi[(int64_t)gy * n + gx] - stencil_at(s + k, UW, c);
+    rr[j] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    const int k = threadIdx.x + j * WG;
+    const int py = k / PW, px = k - py * PW;
+    if (k < PH * PW) s[Q::at(px, py)] = rr[j];
+  }
+  __syncthreads();
+}
+
 // One SSOR-preconditioned inner step (NAGex form):
 //   u~ = u + at v;  r = f - A u~;  v' = a v + w B^{-1} r;  u' = u + v'.
 template <typename T, int METHOD>
@@ -103,8 +161,9 @@ __global__ __launch_bounds__(WG) void k_ssor_step(PlanDev p, const Tile* __restr
                                                   const T* __restrict__ u, const T* __restrict__ v,
                                                   T* __restrict__ u_out, T* __restrict__ v_out,
                                                   const int* __restrict__ active) {
-  __shared__ T su[UH * UW];
-  __shared__ T sr[PH * PW];
+  using Q = Planes<RW, RH>;
+  static_assert(Q::SIZE == UH * UW, "the planes and the look-ahead field share one buffer");
+  __shared__ T s[UH * UW];
   const Tile tl = tiles[xcd_remap(blockIdx.x, gridDim.x)];
   if (tl.inst < 0) return;
   if (active != nullptr && active[tl.inst] == 0) return;
@@ -119,29 +178,20 @@ __global__ __launch_bounds__(WG) void k_ssor_step(PlanDev p, const Tile* __restr
   const T* ui = u + in.off;
   const T* vi = v + in.off;
   const T* fi = f + in.off;
+  const int ox = tl.x0 - HU, oy = tl.y0 - HU;   // instance point of padded (0, 0)
   for (int k = threadIdx.x; k < UH * UW; k += WG) {
     const int ly = k / UW, lx = k - ly * UW;
-    const int gx = tl.x0 - HU + lx, gy = tl.y0 - HU + ly;
+    const int gx = ox + lx, gy = oy + ly;
     T val = T(0);
     if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
       const int64_t idx = (int64_t)gy * n + gx;
       val = uses_lookahead(METHOD) ? fmadd(at, vi[idx], ui[idx]) : ui[idx];
     }
-    su[k] = val;
+    s[k] = val;
   }
   __syncthreads();
-  // residual on the swept region (its padded ring and the outside of the domain stay 0)
-  for (int k = threadIdx.x; k < PH * PW; k += WG) {
-    const int py = k / PW, px = k - py * PW;
-    const int gx = tl.x0 - HR - 1 + px, gy = tl.y0 - HR - 1 + py;
-    T r = T(0);
-    const bool ring = px == 0 || py == 0 || px == PW - 1 || py == PH - 1;
-    if (!ring && gx >= 0 && gx < n && gy >= 0 && gy < n)
-      r = fi[(int64_t)gy * n + gx] - stencil_at(su + k, UW, c);
-    sr[k] = r;
-  }
-  __syncthreads();
-  ssor_lds<T, RW, RH>(sr, tl.x0 - HR, tl.y0 - HR, n, c, relax, dinv);
+  residual_to_planes<T, Q>(s, fi, ox, oy, n, c);
+  ssor_sweeps<T, Q, HU, 0>(s, ox, oy, n, c, relax, dinv);
   const T s2 = relax * (T(2) - relax);
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = tl.x0 + tx;
@@ -150,7 +200,7 @@ __global__ __launch_bounds__(WG) void k_ssor_step(PlanDev p, const Tile* __restr
     const int ly = ty0 + NW * k, gy = tl.y0 + ly;
     if (gy >= n) break;
     const int64_t idx = in.off + (int64_t)gy * n + gx;
-    const T z = s2 * sr[(ly + HR + 1) * PW + (tx + HR + 1)];
+    const T z = s2 * s[Q::at(tx + HU, ly + HU)];
     const T vv = uses_momentum(METHOD) ? v[idx] : T(0);
     const T vn = uses_momentum(METHOD) ? fmadd(a, vv, w * z) : w * z;
     v_out[idx] = vn;
@@ -162,7 +212,8 @@ __global__ __launch_bounds__(WG) void k_ssor_step(PlanDev p, const Tile* __restr
 //   g = vb + ub;  r = f - A u~;  z = B^{-1} r;  rb = w B^{-1} g;  fb += rb;
 //   ut_bar = -A rb;  ub' = ub + ut_bar;  vb' = a g + at ut_bar (NAG: a (g + ut_bar)).
 // Per tile: <g, z>, <g, v>, <ut_bar, v>.  rb is needed on the tile and a one-point
-// ring, so g is staged with a halo of HR + 1.
+// ring, so g is staged with a halo of HR + 1 and its sweeps end on a ring of 1.  The
+// passes of the two SSOR applications share their barriers.
 template <int METHOD>
 __global__ __launch_bounds__(WG) void k_adj_ssor_step(PlanDev p, const float* __restrict__ omega,
                                                       const float* __restrict__ alpha, int m, int i, float relax,
@@ -171,11 +222,12 @@ __global__ __launch_bounds__(WG) void k_adj_ssor_step(PlanDev p, const float* __
                                                       const float* __restrict__ vb, float* __restrict__ ub_out,
                                                       float* __restrict__ vb_out, float* __restrict__ fb,
                                                       double* __restrict__ partial4) {
-  constexpr int GW = TX + 2 * (HR + 1), GH = TY + 2 * (HR + 1);  // g region (halo 7)
-  constexpr int GPW = GW + 2, GPH = GH + 2;
-  __shared__ float su[UH * UW];
-  __shared__ float sr[PH * PW];
-  __shared__ float sg[GPH * GPW];
+  using Q = Planes<RW, RH>;
+  using QG = Planes<TX + 2 * (HR + 1), TY + 2 * (HR + 1)>;   // g region (halo 7) and its ring
+  constexpr int GPW = 2 * QG::QW, GPH = 2 * QG::QH;
+  constexpr int GG = HR + 2;                                  // tile origin in the padded g region
+  __shared__ float s[UH * UW];
+  __shared__ float sg[QG::SIZE];
   __shared__ double sh[NW];
   const Tile tl = p.tiles[xcd_remap(blockIdx.x, gridDim.x)];
   if (tl.inst < 0) return;
@@ -192,40 +244,52 @@ __global__ __launch_bounds__(WG) void k_adj_ssor_step(PlanDev p, const float* __
   const float* ubi = ub + in.off;
   const float* vbi = vb + in.off;
   const float* fi = f + in.off;
+  const int ox = tl.x0 - HU, oy = tl.y0 - HU;
+  const int gox = tl.x0 - GG, goy = tl.y0 - GG;
   for (int k = threadIdx.x; k < UH * UW; k += WG) {
     const int ly = k / UW, lx = k - ly * UW;
-    const int gx = tl.x0 - HU + lx, gy = tl.y0 - HU + ly;
+    const int gx = ox + lx, gy = oy + ly;
     float val = 0.f;
     if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
       const int64_t idx = (int64_t)gy * n + gx;
       val = uses_lookahead(METHOD) ? fmadd(at, vi[idx], ui[idx]) : ui[idx];
     }
-    su[k] = val;
+    s[k] = val;
   }
   for (int k = threadIdx.x; k < GPH * GPW; k += WG) {
     const int py = k / GPW, px = k - py * GPW;
-    const int gx = tl.x0 - HR - 2 + px, gy = tl.y0 - HR - 2 + py;
+    const int gx = gox + px, gy = goy + py;
     float val = 0.f;
     const bool ring = px == 0 || py == 0 || px == GPW - 1 || py == GPH - 1;
     if (!ring && gx >= 0 && gx < n && gy >= 0 && gy < n) {
       const int64_t idx = (int64_t)gy * n + gx;
       val = uses_momentum(METHOD) ? vbi[idx] + ubi[idx] : ubi[idx];
     }
-    sg[k] = val;
+    sg[QG::at(px, py)] = val;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < PH * PW; k += WG) {
-    const int py = k / PW, px = k - py * PW;
-    const int gx = tl.x0 - HR - 1 + px, gy = tl.y0 - HR - 1 + py;
-    float r = 0.f;
-    const bool ring = px == 0 || py == 0 || px == PW - 1 || py == PH - 1;
-    if (!ring && gx >= 0 && gx < n && gy >= 0 && gy < n)
-      r = fi[(int64_t)gy * n + gx] - stencil_at(su + k, UW, c);
-    sr[k] = r;
-  }
+  residual_to_planes<float, Q>(s, fi, ox, oy, n, c);
+  ssor_pass<float, Q, HU, 6, true>(s, 0, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 7, true>(sg, 0, gox, goy, n, c, relax, dinv);
   __syncthreads();
-  ssor_lds<float, RW, RH>(sr, tl.x0 - HR, tl.y0 - HR, n, c, relax, dinv);
-  ssor_lds<float, GW, GH>(sg, tl.x0 - HR - 1, tl.y0 - HR - 1, n, c, relax, dinv);
+  ssor_pass<float, Q, HU, 5, true>(s, 1, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 6, true>(sg, 1, gox, goy, n, c, relax, dinv);
+  __syncthreads();
+  ssor_pass<float, Q, HU, 4, true>(s, 2, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 5, true>(sg, 2, gox, goy, n, c, relax, dinv);
+  __syncthreads();
+  ssor_pass<float, Q, HU, 3, true>(s, 3, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 4, true>(sg, 3, gox, goy, n, c, relax, dinv);
+  __syncthreads();
+  ssor_pass<float, Q, HU, 2, false>(s, 2, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 3, false>(sg, 2, gox, goy, n, c, relax, dinv);
+  __syncthreads();
+  ssor_pass<float, Q, HU, 1, false>(s, 1, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 2, false>(sg, 1, gox, goy, n, c, relax, dinv);
+  __syncthreads();
+  ssor_pass<float, Q, HU, 0, false>(s, 0, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 1, false>(sg, 0, gox, goy, n, c, relax, dinv);
+  __syncthreads();
   const float s2 = relax * (2.f - relax);
   double pw = 0.0, pg = 0.0, pl = 0.0;
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
@@ -235,15 +299,16 @@ __global__ __launch_bounds__(WG) void k_adj_ssor_step(PlanDev p, const float* __
       const int ly = ty0 + NW * k, gy = tl.y0 + ly;
       if (gy >= n) break;
       const int64_t idx = in.off + (int64_t)gy * n + gx;
-      const float z = s2 * sr[(ly + HR + 1) * PW + (tx + HR + 1)];
-      const float* qg = sg + (ly + HR + 2) * GPW + (tx + HR + 2);  // w_g at this point
+      const float z = s2 * s[Q::at(tx + HU, ly + HU)];
+      const int x = tx + GG, y = ly + GG;   // w_g at this point and its ring
       // rb = w s2 w_g at the point and its ring; ut_bar = -A rb
       const float wsc = w * s2;
-      float acc = c[0] * (wsc * qg[0]);
-      acc = fmadd(c[1], wsc * qg[-1] + wsc * qg[1], acc);
-      acc = fmadd(c[2], wsc * qg[-GPW] + wsc * qg[GPW], acc);
-      acc = fmadd(c[3], wsc * qg[-GPW - 1] + wsc * qg[GPW + 1], acc);
-      acc = fmadd(c[4], wsc * qg[-GPW + 1] + wsc * qg[GPW - 1], acc);
+      const float g0 = sg[QG::at(x, y)];
+      float acc = c[0] * (wsc * g0);
+      acc = fmadd(c[1], wsc * sg[QG::at(x - 1, y)] + wsc * sg[QG::at(x + 1, y)], acc);
+      acc = fmadd(c[2], wsc * sg[QG::at(x, y - 1)] + wsc * sg[QG::at(x, y + 1)], acc);
+      acc = fmadd(c[3], wsc * sg[QG::at(x - 1, y - 1)] + wsc * sg[QG::at(x + 1, y + 1)], acc);
+      acc = fmadd(c[4], wsc * sg[QG::at(x + 1, y - 1)] + wsc * sg[QG::at(x - 1, y + 1)], acc);
       const float utb = -acc;
       const float ubv = ubi[idx - in.off];
       const float vv = uses_momentum(METHOD) ? vi[idx - in.off] : 0.f;
@@ -255,7 +320,7 @@ __global__ __launch_bounds__(WG) void k_adj_ssor_step(PlanDev p, const float* __
       if (METHOD == M_NAG) vb_out[idx] = a * (g + utb);
       if (METHOD == M_MOM) vb_out[idx] = a * g;
       if (METHOD == M_NAGEX) vb_out[idx] = fmadd(at, utb, a * g);
-      if (fb != nullptr) fb[idx] += wsc * qg[0];
+      if (fb != nullptr) fb[idx] += wsc * g0;
     }
   }
   const double t0 = block_sum(pw, sh);
