@@ -43,6 +43,7 @@ constexpr int UW = TX + 2 * HU;
 constexpr int UH = TY + 2 * HU;
 constexpr int NW = WG / 64;
 static_assert(UW == PW && UH == PH, "the padded region and the look-ahead region coincide");
+static_assert(TX % 2 == 0 && TY % 2 == 0, "tile origins are even: the colour of a padded point is fixed");
 
 // Colour planes of a padded (W + 2) x (H + 2) region (W, H even).
 template <int W, int H>
@@ -54,30 +55,32 @@ struct Planes {
 };
 
 // One colour pass of the SSOR sweeps (FWD: the forward solve with D - aL, else the
-// backward solve with D - aU) over the points of colour col within h of the tile.  s
+// backward solve with D - aU) over the points of colour COL within h of the tile.  s
 // holds the colour planes Q of a region whose padded point (x, y) is instance point
-// (px0 + x, py0 + y); the tile starts at padded (G, G).
-template <typename T, typename Q, int G, int h, bool FWD>
-__device__ __forceinline__ void ssor_pass(T* s, int col, int px0, int py0, int n, const T c[5], T relax, T dinv) {
+// (px0 + x, py0 + y), with px0 and py0 of parity OP (tile origins are even, so the
+// parity is fixed per field and every plane offset below is a constant); the tile
+// starts at padded (G, G).
+template <typename T, typename Q, int G, int h, bool FWD, int COL, int OP>
+__device__ __forceinline__ void ssor_pass(T* s, int px0, int py0, int n, const T c[5], T relax, T dinv) {
   constexpr int NX = TX / 2 + h, NY = TY / 2 + h;   // points of one colour per row, rows
   static_assert(G - h >= 1 && G + TX + h <= 2 * Q::QW - 1 && G + TY + h <= 2 * Q::QH - 1,
                 "a pass and its neighbour reads stay inside the padded region");
-  const int a = (col ^ px0) & 1, b = ((col >> 1) ^ py0) & 1;   // plane of colour col
-  const int lo = G - h;
-  const int i0 = (lo + ((lo ^ a) & 1)) >> 1, j0 = (lo + ((lo ^ b) & 1)) >> 1;
+  constexpr int a = (COL ^ OP) & 1, b = ((COL >> 1) ^ OP) & 1;   // plane of colour COL
+  constexpr int lo = G - h;
+  constexpr int i0 = (lo + ((lo ^ a) & 1)) >> 1, j0 = (lo + ((lo ^ b) & 1)) >> 1;
+  constexpr int xm = a - 1, xp = a;                         // plane offsets of x - 1, x + 1
+  constexpr int ym = (b - 1) * Q::QW, yp = b * Q::QW;       // and of y - 1, y + 1
+  constexpr bool xn = FWD ? (COL & 1) != 0 : (COL & 1) == 0;
+  constexpr bool yn = FWD ? COL >= 2 : COL < 2;
   T* q0 = s + (2 * b + a) * Q::QS;
   const T* qx = s + (2 * b + (a ^ 1)) * Q::QS;          // x-neighbours
   const T* qy = s + (2 * (b ^ 1) + a) * Q::QS;          // y-neighbours
   const T* qd = s + (2 * (b ^ 1) + (a ^ 1)) * Q::QS;    // diagonal neighbours
-  const int xm = a - 1, xp = a;                         // plane offsets of x - 1, x + 1
-  const int ym = (b - 1) * Q::QW, yp = b * Q::QW;       // and of y - 1, y + 1
-  const bool xn = FWD ? (col & 1) != 0 : (col & 1) == 0;
-  const bool yn = FWD ? col >= 2 : col < 2;
   for (int k = threadIdx.x; k < NX * NY; k += WG) {
     const int jj = k / NX, ii = k - jj * NX;
     const int i = i0 + ii, j = j0 + jj;
     const int gx = px0 + 2 * i + a, gy = py0 + 2 * j + b;
-    if (gx < 0 || gx >= n || gy < 0 || gy >= n) continue;
+    if ((unsigned)gx >= (unsigned)n || (unsigned)gy >= (unsigned)n) continue;
     const int e = j * Q::QW + i;
     T acc = T(0);
     if (xn) acc = fmadd(c[1], qx[e + xm] + qx[e + xp], acc);
@@ -96,21 +99,21 @@ __device__ __forceinline__ void ssor_pass(T* s, int col, int px0, int py0, int n
 // The seven colour passes: forward colours 0..3, backward colours 2..0.  On entry s
 // holds r on the tile plus a ring of h0 + 6; on exit it holds w (B^{-1} r = a (2 - a) w)
 // on the tile plus a ring of h0.
-template <typename T, typename Q, int G, int h0>
+template <typename T, typename Q, int G, int h0, int OP>
 __device__ __forceinline__ void ssor_sweeps(T* s, int px0, int py0, int n, const T c[5], T relax, T dinv) {
-  ssor_pass<T, Q, G, h0 + 6, true>(s, 0, px0, py0, n, c, relax, dinv);
+  ssor_pass<T, Q, G, h0 + 6, true, 0, OP>(s, px0, py0, n, c, relax, dinv);
   __syncthreads();
-  ssor_pass<T, Q, G, h0 + 5, true>(s, 1, px0, py0, n, c, relax, dinv);
+  ssor_pass<T, Q, G, h0 + 5, true, 1, OP>(s, px0, py0, n, c, relax, dinv);
   __syncthreads();
-  ssor_pass<T, Q, G, h0 + 4, true>(s, 2, px0, py0, n, c, relax, dinv);
+  ssor_pass<T, Q, G, h0 + 4, true, 2, OP>(s, px0, py0, n, c, relax, dinv);
   __syncthreads();
-  ssor_pass<T, Q, G, h0 + 3, true>(s, 3, px0, py0, n, c, relax, dinv);
+  ssor_pass<T, Q, G, h0 + 3, true, 3, OP>(s, px0, py0, n, c, relax, dinv);
   __syncthreads();
-  ssor_pass<T, Q, G, h0 + 2, false>(s, 2, px0, py0, n, c, relax, dinv);
+  ssor_pass<T, Q, G, h0 + 2, false, 2, OP>(s, px0, py0, n, c, relax, dinv);
   __syncthreads();
-  ssor_pass<T, Q, G, h0 + 1, false>(s, 1, px0, py0, n, c, relax, dinv);
+  ssor_pass<T, Q, G, h0 + 1, false, 1, OP>(s, px0, py0, n, c, relax, dinv);
   __syncthreads();
-  ssor_pass<T, Q, G, h0, false>(s, 0, px0, py0, n, c, relax, dinv);
+  ssor_pass<T, Q, G, h0, false, 0, OP>(s, px0, py0, n, c, relax, dinv);
   __syncthreads();
 }
 
@@ -125,27 +128,114 @@ __device__ __forceinline__ T stencil_at(const T* q, int W, const T c[5]) {
   return acc;
 }
 
+// An instance field read through a buffer resource: a 32-bit offset from a uniform
+// base, so an address costs one register.
+template <typename T>
+struct Field {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ Field(const T* base, int count)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, count * (int)sizeof(T), 0x00020000)) {}
+  __device__ __forceinline__ T operator[](unsigned idx) const {
+    if constexpr (sizeof(T) == 4) {
+      return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)(idx * 4u), 0, 0));
+    } else {
+      const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(idx * 8u), 0, 0);
+      return __hiloint2double((int)w[1], (int)w[0]);
+    }
+  }
+  // A store at idx >= count is dropped by the hardware.
+  __device__ __forceinline__ void store(unsigned idx, T x) const {
+    if constexpr (sizeof(T) == 4) {
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)(idx * 4u), 0, 0);
+    } else {
+      typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+      const long long b = __double_as_longlong(x);
+      const u32x2 w = {(unsigned)b, (unsigned)(b >> 32)};
+      __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)(idx * 8u), 0, 0);
+    }
+  }
+};
+
+// Global loads a thread keeps in flight while staging.
+constexpr int kLoadBatch = 8;
+
+// The thread index through an opaque copy: index arithmetic derived from it is not
+// merged with the same arithmetic of an earlier phase, whose results would otherwise
+// stay live (in registers) from one phase to the next.
+__device__ __forceinline__ int opaque_tid() {
+  int t;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+  return t;
+}
+
+// Stages a W x H region whose point (x, y) is instance point (ox + x, oy + y) into
+// LDS: put(k, x, y, load(idx)) at flat position k = y W + x, with the value 0 outside
+// the domain (and, with RING, on the region's outer ring).  Every global load takes an
+// in-bounds index (0 stands in for points that are not loaded) and sits behind no
+// branch, so the loads of a batch are all in flight before the first is used.
+template <typename T, int W, int H, bool RING, typename Load, typename Put>
+__device__ __forceinline__ void stage(int ox, int oy, int n, Load load, Put put) {
+  constexpr int NK = W * H, NU = (NK + WG - 1) / WG;
+#pragma unroll
+  for (int j0 = 0; j0 < NU; j0 += kLoadBatch) {
+    T val[kLoadBatch];
+    const int t0 = opaque_tid();
+#pragma unroll
+    for (int j = 0; j < kLoadBatch && j0 + j < NU; ++j) {
+      const int k = t0 + (j0 + j) * WG;
+      const int y = k / W, x = k - y * W;
+      const int gx = ox + x, gy = oy + y;
+      bool ok = (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
+      if (RING) ok = ok && x > 0 && y > 0 && x < W - 1 && y < H - 1;
+      const T t = load(ok ? (unsigned)(gy * n + gx) : 0u);
+      val[j] = ok ? t : T(0);
+    }
+    const int t1 = opaque_tid();
+#pragma unroll
+    for (int j = 0; j < kLoadBatch && j0 + j < NU; ++j) {
+      const int k = t1 + (j0 + j) * WG;
+      const int y = k / W, x = k - y * W;
+      if (k < NK) put(k, x, y, val[j]);
+    }
+  }
+}
+
 // Residual r = f - A u~ on the padded region (0 on its outer ring and outside the
 // domain), read from the look-ahead field s (row-major, UW wide), then written over s
 // as colour planes Q.  Ends with a barrier.
 template <typename T, typename Q>
-__device__ __forceinline__ void residual_to_planes(T* s, const T* fi, int ox, int oy, int n, const T c[5]) {
+__device__ __forceinline__ void residual_to_planes(T* s, const Field<T>& fi, int ox, int oy, int n, const T c[5]) {
   constexpr int NR = (PH * PW + WG - 1) / WG;
-  T rr[NR];
+  T fv[NR], rr[NR];
+  const int t0 = opaque_tid();
 #pragma unroll
-  for (int j = 0; j < NR; ++j) {
-    const int k = threadIdx.x + j * WG;
+  for (int j = 0; j < NR; ++j) {   // points not formed read f at 0
+    const int k = t0 + j * WG;
     const int py = k / PW, px = k - py * PW;
     const int gx = ox + px, gy = oy + py;
-    T r = T(0);
-    const bool ring = px == 0 || py == 0 || px == PW - 1 || py >= PH - 1;
-    if (!ring && gx >= 0 && gx < n && gy >= 0 && gy < n) r = fi[(int64_t)gy * n + gx] - stencil_at(s + k, UW, c);
-    rr[j] = r;
+    const bool ok = (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
+    fv[j] = fi[ok ? (unsigned)(gy * n + gx) : 0u];
   }
-  __syncthreads();
+  const int t1 = opaque_tid();
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
-    const int k = threadIdx.x + j * WG;
+    const int k = t1 + j * WG;
+    const int py = k / PW, px = k - py * PW;
+    const int gx = ox + px, gy = oy + py;
+    const bool ring = px == 0 || py == 0 || px == PW - 1 || py >= PH - 1;
+    const bool ok = !ring && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
+    // points not formed read the stencil at an interior point
+    T st = stencil_at(s + (ok ? k : PW + 1), UW, c);
+    // the stencil is complete before the next one's LDS reads are issued, so the
+    // reads of one stencil at a time occupy registers
+    asm volatile("" : "+v"(st)::"memory");
+    rr[j] = ok ? fv[j] - st : T(0);
+  }
+  __syncthreads();
+  const int t2 = opaque_tid();
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    const int k = t2 + j * WG;
     const int py = k / PW, px = k - py * PW;
     if (k < PH * PW) s[Q::at(px, py)] = rr[j];
   }
@@ -175,36 +265,37 @@ __global__ __launch_bounds__(WG) void k_ssor_step(PlanDev p, const Tile* __restr
   const T dinv = sizeof(T) == 4 ? (T)p.coef32[bi * 8 + 5] : (T)p.coef64[bi * 8 + 5];
   T w, a, at;
   step_factors<T, METHOD>(p, omega, alpha, m, bi, i, w, a, at);
-  const T* ui = u + in.off;
-  const T* vi = v + in.off;
-  const T* fi = f + in.off;
+  const int nn = n * n;
+  const Field<T> uf(u + in.off, nn), vf(v + in.off, nn), fi(f + in.off, nn);
   const int ox = tl.x0 - HU, oy = tl.y0 - HU;   // instance point of padded (0, 0)
-  for (int k = threadIdx.x; k < UH * UW; k += WG) {
-    const int ly = k / UW, lx = k - ly * UW;
-    const int gx = ox + lx, gy = oy + ly;
-    T val = T(0);
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
-      const int64_t idx = (int64_t)gy * n + gx;
-      val = uses_lookahead(METHOD) ? fmadd(at, vi[idx], ui[idx]) : ui[idx];
-    }
-    s[k] = val;
-  }
+  stage<T, UW, UH, false>(
+      ox, oy, n,
+      [&](unsigned idx) { return uses_lookahead(METHOD) ? fmadd(at, vf[idx], uf[idx]) : uf[idx]; },
+      [&](int k, int, int, T val) { s[k] = val; });
   __syncthreads();
   residual_to_planes<T, Q>(s, fi, ox, oy, n, c);
-  ssor_sweeps<T, Q, HU, 0>(s, ox, oy, n, c, relax, dinv);
+  ssor_sweeps<T, Q, HU, 0, HU & 1>(s, ox, oy, n, c, relax, dinv);
   const T s2 = relax * (T(2) - relax);
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = tl.x0 + tx;
   if (gx >= n) return;
-  for (int k = 0; k < TY / NW; ++k) {
-    const int ly = ty0 + NW * k, gy = tl.y0 + ly;
-    if (gy >= n) break;
-    const int64_t idx = in.off + (int64_t)gy * n + gx;
+  constexpr int NY = TY / NW;
+  T uu[NY], vv[NY];
+#pragma unroll
+  for (int k = 0; k < NY; ++k) {   // rows below the domain load its last row
+    const unsigned idx = (unsigned)(min(tl.y0 + ty0 + NW * k, n - 1) * n + gx);
+    uu[k] = uf[idx];
+    vv[k] = uses_momentum(METHOD) ? vf[idx] : T(0);
+  }
+  const Field<T> uo(u_out + in.off, nn), vo(v_out + in.off, nn);
+#pragma unroll
+  for (int k = 0; k < NY; ++k) {   // rows below the domain are dropped by the stores
+    const int ly = ty0 + NW * k;
+    const unsigned idx = (unsigned)((tl.y0 + ly) * n + gx);
     const T z = s2 * s[Q::at(tx + HU, ly + HU)];
-    const T vv = uses_momentum(METHOD) ? v[idx] : T(0);
-    const T vn = uses_momentum(METHOD) ? fmadd(a, vv, w * z) : w * z;
-    v_out[idx] = vn;
-    u_out[idx] = u[idx] + vn;
+    const T vn = uses_momentum(METHOD) ? fmadd(a, vv[k], w * z) : w * z;
+    vo.store(idx, vn);
+    uo.store(idx, uu[k] + vn);
   }
 }
 
@@ -239,63 +330,58 @@ __global__ __launch_bounds__(WG) void k_adj_ssor_step(PlanDev p, const float* __
   const float dinv = p.coef32[bi * 8 + 5];
   float w, a, at;
   step_factors<float, METHOD>(p, omega, alpha, m, bi, i, w, a, at);
-  const float* ui = u + in.off;
-  const float* vi = v + in.off;
-  const float* ubi = ub + in.off;
-  const float* vbi = vb + in.off;
-  const float* fi = f + in.off;
+  const int nn = n * n;
+  const Field<float> uf(u + in.off, nn), vf(v + in.off, nn), ubf(ub + in.off, nn), vbf(vb + in.off, nn);
+  const Field<float> fi(f + in.off, nn), fbf(fb != nullptr ? fb + in.off : ub + in.off, nn);
   const int ox = tl.x0 - HU, oy = tl.y0 - HU;
   const int gox = tl.x0 - GG, goy = tl.y0 - GG;
-  for (int k = threadIdx.x; k < UH * UW; k += WG) {
-    const int ly = k / UW, lx = k - ly * UW;
-    const int gx = ox + lx, gy = oy + ly;
-    float val = 0.f;
-    if (gx >= 0 && gx < n && gy >= 0 && gy < n) {
-      const int64_t idx = (int64_t)gy * n + gx;
-      val = uses_lookahead(METHOD) ? fmadd(at, vi[idx], ui[idx]) : ui[idx];
-    }
-    s[k] = val;
-  }
-  for (int k = threadIdx.x; k < GPH * GPW; k += WG) {
-    const int py = k / GPW, px = k - py * GPW;
-    const int gx = gox + px, gy = goy + py;
-    float val = 0.f;
-    const bool ring = px == 0 || py == 0 || px == GPW - 1 || py == GPH - 1;
-    if (!ring && gx >= 0 && gx < n && gy >= 0 && gy < n) {
-      const int64_t idx = (int64_t)gy * n + gx;
-      val = uses_momentum(METHOD) ? vbi[idx] + ubi[idx] : ubi[idx];
-    }
-    sg[QG::at(px, py)] = val;
-  }
+  stage<float, UW, UH, false>(
+      ox, oy, n,
+      [&](unsigned idx) { return uses_lookahead(METHOD) ? fmadd(at, vf[idx], uf[idx]) : uf[idx]; },
+      [&](int k, int, int, float val) { s[k] = val; });
+  stage<float, GPW, GPH, true>(
+      gox, goy, n, [&](unsigned idx) { return uses_momentum(METHOD) ? vbf[idx] + ubf[idx] : ubf[idx]; },
+      [&](int, int x, int y, float val) { sg[QG::at(x, y)] = val; });
   __syncthreads();
   residual_to_planes<float, Q>(s, fi, ox, oy, n, c);
-  ssor_pass<float, Q, HU, 6, true>(s, 0, ox, oy, n, c, relax, dinv);
-  ssor_pass<float, QG, GG, 7, true>(sg, 0, gox, goy, n, c, relax, dinv);
+  ssor_pass<float, Q, HU, 6, true, 0, HU & 1>(s, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 7, true, 0, GG & 1>(sg, gox, goy, n, c, relax, dinv);
   __syncthreads();
-  ssor_pass<float, Q, HU, 5, true>(s, 1, ox, oy, n, c, relax, dinv);
-  ssor_pass<float, QG, GG, 6, true>(sg, 1, gox, goy, n, c, relax, dinv);
+  ssor_pass<float, Q, HU, 5, true, 1, HU & 1>(s, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 6, true, 1, GG & 1>(sg, gox, goy, n, c, relax, dinv);
   __syncthreads();
-  ssor_pass<float, Q, HU, 4, true>(s, 2, ox, oy, n, c, relax, dinv);
-  ssor_pass<float, QG, GG, 5, true>(sg, 2, gox, goy, n, c, relax, dinv);
+  ssor_pass<float, Q, HU, 4, true, 2, HU & 1>(s, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 5, true, 2, GG & 1>(sg, gox, goy, n, c, relax, dinv);
   __syncthreads();
-  ssor_pass<float, Q, HU, 3, true>(s, 3, ox, oy, n, c, relax, dinv);
-  ssor_pass<float, QG, GG, 4, true>(sg, 3, gox, goy, n, c, relax, dinv);
+  ssor_pass<float, Q, HU, 3, true, 3, HU & 1>(s, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 4, true, 3, GG & 1>(sg, gox, goy, n, c, relax, dinv);
   __syncthreads();
-  ssor_pass<float, Q, HU, 2, false>(s, 2, ox, oy, n, c, relax, dinv);
-  ssor_pass<float, QG, GG, 3, false>(sg, 2, gox, goy, n, c, relax, dinv);
+  ssor_pass<float, Q, HU, 2, false, 2, HU & 1>(s, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 3, false, 2, GG & 1>(sg, gox, goy, n, c, relax, dinv);
   __syncthreads();
-  ssor_pass<float, Q, HU, 1, false>(s, 1, ox, oy, n, c, relax, dinv);
-  ssor_pass<float, QG, GG, 2, false>(sg, 1, gox, goy, n, c, relax, dinv);
+  ssor_pass<float, Q, HU, 1, false, 1, HU & 1>(s, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 2, false, 1, GG & 1>(sg, gox, goy, n, c, relax, dinv);
   __syncthreads();
-  ssor_pass<float, Q, HU, 0, false>(s, 0, ox, oy, n, c, relax, dinv);
-  ssor_pass<float, QG, GG, 1, false>(sg, 0, gox, goy, n, c, relax, dinv);
+  ssor_pass<float, Q, HU, 0, false, 0, HU & 1>(s, ox, oy, n, c, relax, dinv);
+  ssor_pass<float, QG, GG, 1, false, 0, GG & 1>(sg, gox, goy, n, c, relax, dinv);
   __syncthreads();
   const float s2 = relax * (2.f - relax);
   double pw = 0.0, pg = 0.0, pl = 0.0;
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = tl.x0 + tx;
   if (gx < n) {
-    for (int k = 0; k < TY / NW; ++k) {
+    constexpr int NY = TY / NW;
+    float ubr[NY], vr[NY], vbr[NY], fbr[NY];
+#pragma unroll
+    for (int k = 0; k < NY; ++k) {   // rows below the domain load its last row
+      const unsigned idx = (unsigned)(min(tl.y0 + ty0 + NW * k, n - 1) * n + gx);
+      ubr[k] = ubf[idx];
+      vr[k] = uses_momentum(METHOD) ? vf[idx] : 0.f;
+      vbr[k] = uses_momentum(METHOD) ? vbf[idx] : 0.f;
+      fbr[k] = fb != nullptr ? fbf[idx] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < NY; ++k) {
       const int ly = ty0 + NW * k, gy = tl.y0 + ly;
       if (gy >= n) break;
       const int64_t idx = in.off + (int64_t)gy * n + gx;
@@ -310,9 +396,9 @@ __global__ __launch_bounds__(WG) void k_adj_ssor_step(PlanDev p, const float* __
       acc = fmadd(c[3], wsc * sg[QG::at(x - 1, y - 1)] + wsc * sg[QG::at(x + 1, y + 1)], acc);
       acc = fmadd(c[4], wsc * sg[QG::at(x + 1, y - 1)] + wsc * sg[QG::at(x - 1, y + 1)], acc);
       const float utb = -acc;
-      const float ubv = ubi[idx - in.off];
-      const float vv = uses_momentum(METHOD) ? vi[idx - in.off] : 0.f;
-      const float g = uses_momentum(METHOD) ? vbi[idx - in.off] + ubv : ubv;
+      const float ubv = ubr[k];
+      const float vv = vr[k];
+      const float g = uses_momentum(METHOD) ? vbr[k] + ubv : ubv;
       pw += (double)g * (double)z;
       pg += (double)g * (double)vv;
       pl += (double)utb * (double)vv;
@@ -320,7 +406,7 @@ __global__ __launch_bounds__(WG) void k_adj_ssor_step(PlanDev p, const float* __
       if (METHOD == M_NAG) vb_out[idx] = a * (g + utb);
       if (METHOD == M_MOM) vb_out[idx] = a * g;
       if (METHOD == M_NAGEX) vb_out[idx] = fmadd(at, utb, a * g);
-      if (fb != nullptr) fb[idx] += wsc * g0;
+      if (fb != nullptr) fb[idx] = fbr[k] + wsc * g0;
     }
   }
   const double t0 = block_sum(pw, sh);
