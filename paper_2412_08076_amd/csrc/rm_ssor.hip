@@ -128,78 +128,6 @@ __device__ __forceinline__ T stencil_at(const T* q, int W, const T c[5]) {
   return acc;
 }
 
-// An instance field read through a buffer resource: a 32-bit offset from a uniform
-// base, so an address costs one register.
-template <typename T>
-struct Field {
-  __amdgpu_buffer_rsrc_t r;
-  __device__ __forceinline__ Field(const T* base, int count)
-      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, count * (int)sizeof(T), 0x00020000)) {}
-  __device__ __forceinline__ T operator[](unsigned idx) const {
-    if constexpr (sizeof(T) == 4) {
-      return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)(idx * 4u), 0, 0));
-    } else {
-      const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(idx * 8u), 0, 0);
-      return __hiloint2double((int)w[1], (int)w[0]);
-    }
-  }
-  // A store at idx >= count is dropped by the hardware.
-  __device__ __forceinline__ void store(unsigned idx, T x) const {
-    if constexpr (sizeof(T) == 4) {
-      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)(idx * 4u), 0, 0);
-    } else {
-      typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-      const long long b = __double_as_longlong(x);
-      const u32x2 w = {(unsigned)b, (unsigned)(b >> 32)};
-      __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)(idx * 8u), 0, 0);
-    }
-  }
-};
-
-// Global loads a thread keeps in flight while staging.
-constexpr int kLoadBatch = 8;
-
-// The thread index through an opaque copy: index arithmetic derived from it is not
-// merged with the same arithmetic of an earlier phase, whose results would otherwise
-// stay live (in registers) from one phase to the next.
-__device__ __forceinline__ int opaque_tid() {
-  int t;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
-  return t;
-}
-
-// Stages a W x H region whose point (x, y) is instance point (ox + x, oy + y) into
-// LDS: put(k, x, y, load(idx)) at flat position k = y W + x, with the value 0 outside
-// the domain (and, with RING, on the region's outer ring).  Every global load takes an
-// in-bounds index (0 stands in for points that are not loaded) and sits behind no
-// branch, so the loads of a batch are all in flight before the first is used.
-template <typename T, int W, int H, bool RING, typename Load, typename Put>
-__device__ __forceinline__ void stage(int ox, int oy, int n, Load load, Put put) {
-  constexpr int NK = W * H, NU = (NK + WG - 1) / WG;
-#pragma unroll
-  for (int j0 = 0; j0 < NU; j0 += kLoadBatch) {
-    T val[kLoadBatch];
-    const int t0 = opaque_tid();
-#pragma unroll
-    for (int j = 0; j < kLoadBatch && j0 + j < NU; ++j) {
-      const int k = t0 + (j0 + j) * WG;
-      const int y = k / W, x = k - y * W;
-      const int gx = ox + x, gy = oy + y;
-      bool ok = (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
-      if (RING) ok = ok && x > 0 && y > 0 && x < W - 1 && y < H - 1;
-      const T t = load(ok ? (unsigned)(gy * n + gx) : 0u);
-      val[j] = ok ? t : T(0);
-    }
-    const int t1 = opaque_tid();
-#pragma unroll
-    for (int j = 0; j < kLoadBatch && j0 + j < NU; ++j) {
-      const int k = t1 + (j0 + j) * WG;
-      const int y = k / W, x = k - y * W;
-      if (k < NK) put(k, x, y, val[j]);
-    }
-  }
-}
-
 // Residual r = f - A u~ on the padded region (0 on its outer ring and outside the
 // domain), read from the look-ahead field s (row-major, UW wide), then written over s
 // as colour planes Q.  Ends with a barrier.

@@ -53,39 +53,45 @@ __global__ __launch_bounds__(WG) void k_tg_restrict(PlanDev p, TgDev g, const Ti
   const TgInst gi = g.inst[t.inst];
   const int n = in.n, nc = gi.nc;
   const int fx0 = 2 * t.x0, fy0 = 2 * t.y0;  // fine origin of the residual window
-  const float* ui = u + in.off;
+  const Field<float> uf(u + in.off, n * n);
   if (MODE == 0) {
     double c[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) c[k] = p.coef64[t.inst * 8 + k];
-    for (int k = threadIdx.x; k < RU_H * RU_W; k += WG) {
-      const int ly = k / RU_W, lx = k - ly * RU_W;
-      const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly;
-      su[k] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? ui[(int64_t)gy * n + gx] : 0.f;
-    }
+    stage<float, RU_W, RU_H, false>(
+        fx0 - 1, fy0 - 1, n, [&](unsigned idx) { return uf[idx]; }, [&](int k, int, int, float v) { su[k] = v; });
     __syncthreads();
-    const float* fi = f + in.off;
-    for (int k = threadIdx.x; k < RR_H * RR_W; k += WG) {
+    const Field<float> fi(f + in.off, n * n);
+    constexpr int NR = (RR_H * RR_W + WG - 1) / WG;
+    float fv[NR];
+    const int t0 = opaque_tid();
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {   // points off the field read f at 0
+      const int k = t0 + j * WG;
       const int ly = k / RR_W, lx = k - ly * RR_W;
       const int gx = fx0 + lx, gy = fy0 + ly;
-      float r = 0.f;
-      if (gx < n && gy < n) {
-        const float* s = su + (ly + 1) * RU_W + (lx + 1);
-        double acc = c[0] * (double)s[0];
-        acc = __builtin_fma(c[1], (double)s[-1] + (double)s[1], acc);
-        acc = __builtin_fma(c[2], (double)s[-RU_W] + (double)s[RU_W], acc);
-        acc = __builtin_fma(c[3], (double)s[-RU_W - 1] + (double)s[RU_W + 1], acc);
-        acc = __builtin_fma(c[4], (double)s[-RU_W + 1] + (double)s[RU_W - 1], acc);
-        r = (float)((double)fi[(int64_t)gy * n + gx] - acc);
-      }
-      sr[k] = r;
+      fv[j] = fi[(gx < n && gy < n) ? (unsigned)(gy * n + gx) : 0u];
+    }
+    const int t1 = opaque_tid();
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      const int k = t1 + j * WG;
+      const int ly = k / RR_W, lx = k - ly * RR_W;
+      const int gx = fx0 + lx, gy = fy0 + ly;
+      const bool ok = k < RR_H * RR_W && gx < n && gy < n;
+      // points not formed read the stencil at the window's first interior point
+      const float* s = su + (ok ? (ly + 1) * RU_W + (lx + 1) : RU_W + 1);
+      double acc = c[0] * (double)s[0];
+      acc = __builtin_fma(c[1], (double)s[-1] + (double)s[1], acc);
+      acc = __builtin_fma(c[2], (double)s[-RU_W] + (double)s[RU_W], acc);
+      acc = __builtin_fma(c[3], (double)s[-RU_W - 1] + (double)s[RU_W + 1], acc);
+      acc = __builtin_fma(c[4], (double)s[-RU_W + 1] + (double)s[RU_W - 1], acc);
+      asm volatile("" : "+v"(acc)::"memory");   // one stencil's LDS reads in flight at a time
+      if (k < RR_H * RR_W) sr[k] = ok ? (float)((double)fv[j] - acc) : 0.f;
     }
   } else {
-    for (int k = threadIdx.x; k < RR_H * RR_W; k += WG) {
-      const int ly = k / RR_W, lx = k - ly * RR_W;
-      const int gx = fx0 + lx, gy = fy0 + ly;
-      sr[k] = (gx < n && gy < n) ? ui[(int64_t)gy * n + gx] : 0.f;
-    }
+    stage<float, RR_W, RR_H, false>(
+        fx0, fy0, n, [&](unsigned idx) { return uf[idx]; }, [&](int k, int, int, float v) { sr[k] = v; });
   }
   __syncthreads();
   const float w = scale * 0.0625f;  // (1/16) [1 2 1; 2 4 2; 1 2 1]
@@ -291,12 +297,9 @@ __global__ __launch_bounds__(WG) void k_tg_dst(TgDev g, const Tile* __restrict__
 constexpr int CW_W = TX / 2 + 4, CW_H = TY / 2 + 4;
 
 __device__ __forceinline__ void stage_coarse(float* cw, const float* e, int nc, int x0, int y0) {
-  const int I0 = x0 / 2 - 2, J0 = y0 / 2 - 2;
-  for (int k = threadIdx.x; k < CW_W * CW_H; k += WG) {
-    const int JJ = k / CW_W, II = k - JJ * CW_W;
-    const int I = I0 + II, J = J0 + JJ;
-    cw[k] = (I >= 0 && I < nc && J >= 0 && J < nc) ? e[(int64_t)J * nc + I] : 0.f;
-  }
+  const Field<float> ef(e, nc * nc);
+  stage<float, CW_W, CW_H, false>(
+      x0 / 2 - 2, y0 / 2 - 2, nc, [&](unsigned idx) { return ef[idx]; }, [&](int k, int, int, float v) { cw[k] = v; });
 }
 
 // Bilinear interpolation at fine point (i, j) from the window: along each axis an
@@ -326,12 +329,15 @@ __global__ __launch_bounds__(WG) void k_tg_prolong(PlanDev p, TgDev g, const flo
   const int i = tl.x0 + (threadIdx.x & 63);
   if (i >= n) return;
   const int ty0 = threadIdx.x >> 6;
+  constexpr int NY = TY / (WG / 64);
+  const Field<float> uif(ui + in.off, n * n), uof(uo + in.off, n * n);
+  float uv[NY];
 #pragma unroll
-  for (int k = 0; k < TY / (WG / 64); ++k) {
+  for (int k = 0; k < NY; ++k) uv[k] = uif[(unsigned)(min(tl.y0 + ty0 + 4 * k, n - 1) * n + i)];
+#pragma unroll
+  for (int k = 0; k < NY; ++k) {   // rows below the field are dropped by the store
     const int j = tl.y0 + ty0 + 4 * k;
-    if (j >= n) break;
-    const int64_t idx = in.off + (int64_t)j * n + i;
-    uo[idx] = ui[idx] + interp(cw, tl.x0, tl.y0, i, j);
+    uof.store((unsigned)(j * n + i), uv[k] + interp(cw, tl.x0, tl.y0, i, min(j, n - 1)));
   }
 }
 
@@ -364,8 +370,17 @@ __global__ __launch_bounds__(WG) void k_tg_adj_correct(PlanDev p, TgDev g, const
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = tl.x0 + tx;
   if (gx >= n) return;
+  constexpr int NY = TY / (WG / 64);
+  const Field<float> ubf(ub + in.off, n * n), fbf(fb != nullptr ? fb + in.off : ub + in.off, n * n);
+  float ubv[NY], fbv[NY];
 #pragma unroll
-  for (int k = 0; k < TY / (WG / 64); ++k) {
+  for (int k = 0; k < NY; ++k) {   // rows below the field load its last row
+    const unsigned idx = (unsigned)(min(tl.y0 + ty0 + 4 * k, n - 1) * n + gx);
+    ubv[k] = ubf[idx];
+    fbv[k] = fb != nullptr ? fbf[idx] : 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < NY; ++k) {
     const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
     if (gy >= n) break;
     const float* q = s + (ly + 1) * AW + tx + 1;
@@ -375,8 +390,8 @@ __global__ __launch_bounds__(WG) void k_tg_adj_correct(PlanDev p, TgDev g, const
     acc = __builtin_fma(c[3], (double)q[-AW - 1] + (double)q[AW + 1], acc);
     acc = __builtin_fma(c[4], (double)q[-AW + 1] + (double)q[AW - 1], acc);
     const int64_t idx = in.off + (int64_t)gy * n + gx;
-    ub_out[idx] = (float)((double)ub[idx] - acc);
-    if (fb != nullptr) fb[idx] += q[0];
+    ub_out[idx] = (float)((double)ubv[k] - acc);
+    if (fb != nullptr) fb[idx] = fbv[k] + q[0];
   }
 }
 
