@@ -318,31 +318,32 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
   __shared__ int kept[16];
   int mine = 0;
   for (int b = threadIdx.x; b < p.B; b += blockDim.x) {
-    const Inst in = p.inst[b];
-    const int t0 = ranges != nullptr ? ranges[2 * b] : in.tile_begin;
-    const int t1 = ranges != nullptr ? ranges[2 * b + 1] : in.tile_end;
+    const int t0 = ranges != nullptr ? ranges[2 * b] : p.inst[b].tile_begin;
+    const int t1 = ranges != nullptr ? ranges[2 * b + 1] : p.inst[b].tile_end;
+    // the instance's state is read before the partial sums are waited for
+    const int act = active[b], cnt = outer_count[b] + 1, sn = since[b], g = gains[b];
+    const double rh = rhs2[b], tg = target2[b], best = best2[b];
     double r2 = 0.0;
+#pragma unroll 8
     for (int t = t0; t < t1; ++t) r2 += partial2[2 * t];
     res2[b] = r2;
-    if (active[b] == 0) continue;
-    const int cnt = outer_count[b] + 1;
+    if (act == 0) continue;
     outer_count[b] = cnt;
     int keep = 1;
-    if (!(r2 <= 1e12 * rhs2[b])) {  // NaN, Inf or growth
-      status[b] = 5;                // RM_EDIVERGED
+    if (!(r2 <= 1e12 * rh)) {  // NaN, Inf or growth
+      status[b] = 5;           // RM_EDIVERGED
       keep = 0;
-    } else if (r2 <= target2[b] || cnt >= cap) {
+    } else if (r2 <= tg || cnt >= cap) {
       keep = 0;
-    } else if (r2 < 0.81 * best2[b]) {
+    } else if (r2 < 0.81 * best) {
       best2[b] = r2;
       since[b] = 0;
-      gains[b] = gains[b] + 1;
+      gains[b] = g + 1;
     } else {
-      const int g = gains[b];
       int win = g == 0 ? stall_max : (6 * cnt) / g;
       win = win < stall_min ? stall_min : (win > stall_max ? stall_max : win);
-      if (since[b] + 1 >= win) keep = 0;
-      else since[b] = since[b] + 1;
+      if (sn + 1 >= win) keep = 0;
+      else since[b] = sn + 1;
     }
     active[b] = keep;
     mine += keep;
