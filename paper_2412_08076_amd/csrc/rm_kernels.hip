@@ -60,7 +60,7 @@ __device__ __forceinline__ T stencil_lds(const T* s, int lx, int ly, const T c[5
 }
 
 // Fill the one-point halo ring of the LDS tile with val(gx, gy), or 0 outside the
-// n x n interior.
+// n x n interior (val is called at (0, 0) there, so it must not fault on it).
 template <typename T, typename F>
 __device__ __forceinline__ void stage_halo(T* s, int x0, int y0, int n, F&& val) {
   constexpr int NH = 2 * LDS_W + 2 * TY;
@@ -77,7 +77,8 @@ __device__ __forceinline__ void stage_halo(T* s, int x0, int y0, int n, F&& val)
     }
     const int gx = x0 + hx - 1, gy = y0 + hy - 1;
     const bool in = (gx >= 0) && (gx < n) && (gy >= 0) && (gy < n);
-    s[hy * LDS_W + hx] = in ? val(gx, gy) : T(0);
+    const T x = val(in ? gx : 0, in ? gy : 0);   // an in-bounds load behind no branch
+    s[hy * LDS_W + hx] = in ? x : T(0);
   }
 }
 
@@ -98,16 +99,23 @@ __global__ __launch_bounds__(WG) void k_apply(PlanDev p, const Tile* tiles, cons
   const int n = in.n;
   T c[5];
   load_coef<T>(p, tl.inst, c);
-  const T* xi = x + in.off;
+  const Field<T> xf(x + in.off, n * n), bf(MODE == 1 ? b + in.off : x + in.off, n * n);
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = tl.x0 + tx;
+  // every load on an in-bounds index (0 for points off the grid) and behind no branch
+  T rx[RPT], rb[RPT];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
+    const int gy = tl.y0 + ty0 + 4 * k;
     const bool in_ = gx < n && gy < n;
-    s[(ly + 1) * LDS_W + tx + 1] = in_ ? xi[gy * n + gx] : T(0);
+    const unsigned idx = in_ ? (unsigned)(gy * n + gx) : 0u;
+    rx[k] = xf[idx];
+    rb[k] = MODE == 1 ? bf[idx] : T(0);
+    rx[k] = in_ ? rx[k] : T(0);
   }
-  stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return xi[Y * n + X]; });
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) s[(ty0 + 4 * k + 1) * LDS_W + tx + 1] = rx[k];
+  stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return xf[(unsigned)(Y * n + X)]; });
   __syncthreads();
   double r2 = 0.0, b2 = 0.0;
 #pragma unroll
@@ -119,7 +127,7 @@ __global__ __launch_bounds__(WG) void k_apply(PlanDev p, const Tile* tiles, cons
       if (MODE == 0) {
         y[idx] = ax;
       } else {
-        const T bv = b[idx];
+        const T bv = rb[k];
         const T r = bv - ax;
         if (y != nullptr) y[idx] = r;
         r2 += (double)r * (double)r;
@@ -160,26 +168,32 @@ __global__ __launch_bounds__(WG) void k_step(PlanDev p, const Tile* tiles, const
   load_coef<T>(p, tl.inst, c);
   T w, a, at;
   step_factors<T, METHOD>(p, omega, alpha, m, tl.inst, i, w, a, at);
-  const T* ui = u + in.off;
-  const T* vi = v + in.off;
-  const T* fi = f + in.off;
+  const int nn = n * n;
+  const Field<T> uf(u + in.off, nn), vf(v + in.off, nn), ff(f + in.off, nn);
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = tl.x0 + tx;
+  // every load on an in-bounds index (0 for points off the grid) and behind no branch
   T ru[RPT], rv[RPT], rf[RPT];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
+    const int gy = tl.y0 + ty0 + 4 * k;
     const bool in_ = gx < n && gy < n;
-    const int idx = gy * n + gx;
-    ru[k] = in_ ? ui[idx] : T(0);
-    rv[k] = (uses_momentum(METHOD) && in_) ? vi[idx] : T(0);
-    rf[k] = in_ ? fi[idx] : T(0);
-    s[(ly + 1) * LDS_W + tx + 1] = uses_lookahead(METHOD) ? fmadd(at, rv[k], ru[k]) : ru[k];
+    const unsigned idx = in_ ? (unsigned)(gy * n + gx) : 0u;
+    const T lu = uf[idx], lv = uses_momentum(METHOD) ? vf[idx] : T(0), lf = ff[idx];
+    ru[k] = in_ ? lu : T(0);
+    rv[k] = in_ ? lv : T(0);
+    rf[k] = in_ ? lf : T(0);
   }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k)
+    s[(ty0 + 4 * k + 1) * LDS_W + tx + 1] = uses_lookahead(METHOD) ? fmadd(at, rv[k], ru[k]) : ru[k];
   if (uses_lookahead(METHOD))
-    stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return fmadd(at, vi[Y * n + X], ui[Y * n + X]); });
+    stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) {
+      const unsigned e = (unsigned)(Y * n + X);
+      return fmadd(at, vf[e], uf[e]);
+    });
   else
-    stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return ui[Y * n + X]; });
+    stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return uf[(unsigned)(Y * n + X)]; });
   __syncthreads();
   T wc[5];
 #pragma unroll
@@ -446,34 +460,47 @@ __global__ __launch_bounds__(WG) void k_adj_step(PlanDev p, const float* __restr
   load_coef<float>(p, bi, c);
   float w, a, at;
   step_factors<float, METHOD>(p, omega, alpha, m, bi, i, w, a, at);
-  const float* ui = u + in.off;
-  const float* vi = v + in.off;
-  const float* ubi = ub + in.off;
-  const float* vbi = vb + in.off;
+  const int nn = n * n;
+  const Field<float> uf(u + in.off, nn), vf(v + in.off, nn), ubf(ub + in.off, nn), vbf(vb + in.off, nn);
+  const Field<float> ff(f + in.off, nn), fbf(fb != nullptr ? fb + in.off : ub + in.off, nn);
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = tl.x0 + tx;
-  float rv[RPT], rg[RPT], rub[RPT];
+  // every load on an in-bounds index (0 for points off the grid) and behind no branch
+  float rv[RPT], rg[RPT], rub[RPT], rut[RPT], rf[RPT], rfb[RPT];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
+    const int gy = tl.y0 + ty0 + 4 * k;
     const bool in_ = gx < n && gy < n;
-    const int idx = gy * n + gx;
-    const float uu = in_ ? ui[idx] : 0.0f;
-    rv[k] = (uses_momentum(METHOD) && in_) ? vi[idx] : 0.0f;
-    rub[k] = in_ ? ubi[idx] : 0.0f;
-    const float vbb = (uses_momentum(METHOD) && in_) ? vbi[idx] : 0.0f;
-    rg[k] = vbb + rub[k];
-    su[(ly + 1) * LDS_W + tx + 1] = uses_lookahead(METHOD) ? fmadd(at, rv[k], uu) : uu;
-    sg[(ly + 1) * LDS_W + tx + 1] = rg[k];
+    const unsigned idx = in_ ? (unsigned)(gy * n + gx) : 0u;
+    const float uu = uf[idx], lv = uses_momentum(METHOD) ? vf[idx] : 0.0f, lub = ubf[idx];
+    const float vbb = uses_momentum(METHOD) ? vbf[idx] : 0.0f;
+    rf[k] = ff[idx];
+    rfb[k] = fb != nullptr ? fbf[idx] : 0.0f;
+    rv[k] = in_ ? lv : 0.0f;
+    rub[k] = in_ ? lub : 0.0f;
+    rg[k] = (in_ ? vbb : 0.0f) + rub[k];
+    const float u0 = in_ ? uu : 0.0f;
+    rut[k] = uses_lookahead(METHOD) ? fmadd(at, rv[k], u0) : u0;
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    su[(ty0 + 4 * k + 1) * LDS_W + tx + 1] = rut[k];
+    sg[(ty0 + 4 * k + 1) * LDS_W + tx + 1] = rg[k];
   }
   if (uses_lookahead(METHOD))
-    stage_halo(su, tl.x0, tl.y0, n, [&](int X, int Y) { return fmadd(at, vi[Y * n + X], ui[Y * n + X]); });
+    stage_halo(su, tl.x0, tl.y0, n, [&](int X, int Y) {
+      const unsigned e = (unsigned)(Y * n + X);
+      return fmadd(at, vf[e], uf[e]);
+    });
   else
-    stage_halo(su, tl.x0, tl.y0, n, [&](int X, int Y) { return ui[Y * n + X]; });
+    stage_halo(su, tl.x0, tl.y0, n, [&](int X, int Y) { return uf[(unsigned)(Y * n + X)]; });
   if (uses_momentum(METHOD))
-    stage_halo(sg, tl.x0, tl.y0, n, [&](int X, int Y) { return vbi[Y * n + X] + ubi[Y * n + X]; });
+    stage_halo(sg, tl.x0, tl.y0, n, [&](int X, int Y) {
+      const unsigned e = (unsigned)(Y * n + X);
+      return vbf[e] + ubf[e];
+    });
   else
-    stage_halo(sg, tl.x0, tl.y0, n, [&](int X, int Y) { return ubi[Y * n + X]; });
+    stage_halo(sg, tl.x0, tl.y0, n, [&](int X, int Y) { return ubf[(unsigned)(Y * n + X)]; });
   __syncthreads();
   double pw = 0.0, pg = 0.0, pl = 0.0;
 #pragma unroll
@@ -481,7 +508,7 @@ __global__ __launch_bounds__(WG) void k_adj_step(PlanDev p, const float* __restr
     const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
     if (gx < n && gy < n) {
       const int64_t idx = in.off + (int64_t)gy * n + gx;
-      const float r = f[idx] - stencil_lds(su, tx + 1, ly + 1, c);
+      const float r = rf[k] - stencil_lds(su, tx + 1, ly + 1, c);
       const float g = rg[k];
       const float utb = -(w * stencil_lds(sg, tx + 1, ly + 1, c));
       pw += (double)g * (double)r;
@@ -491,7 +518,7 @@ __global__ __launch_bounds__(WG) void k_adj_step(PlanDev p, const float* __restr
       if (METHOD == M_NAG) vb_out[idx] = a * (g + utb);
       if (METHOD == M_MOM) vb_out[idx] = a * g;
       if (METHOD == M_NAGEX) vb_out[idx] = fmadd(at, utb, a * g);
-      if (fb != nullptr) fb[idx] = fmadd(w, g, fb[idx]);
+      if (fb != nullptr) fb[idx] = fmadd(w, g, rfb[k]);
     }
   }
   const double t0 = block_sum(pw, sh);
