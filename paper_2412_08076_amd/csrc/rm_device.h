@@ -84,12 +84,15 @@ __device__ __forceinline__ double wave_sum(double x) {
 }
 
 // An instance field read through a buffer resource: a 32-bit offset from a uniform
-// base, so an address costs one register.
+// base, so an address costs one register.  The byte size (at most 2^31 for an FP64
+// field of the largest instance) is formed unsigned; the hardware reads the record
+// count and the offsets as unsigned 32-bit values.
 template <typename T>
 struct Field {
   __amdgpu_buffer_rsrc_t r;
   __device__ __forceinline__ Field(const T* base, int count)
-      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, count * (int)sizeof(T), 0x00020000)) {}
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0,
+                                            (int)((unsigned)count * (unsigned)sizeof(T)), 0x00020000)) {}
   __device__ __forceinline__ T operator[](unsigned idx) const {
     if constexpr (sizeof(T) == 4) {
       return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)(idx * 4u), 0, 0));
