@@ -126,46 +126,56 @@ __device__ __forceinline__ float2 cmul(float2 w, float2 x) {
   return make_float2(fmadd(w.x, x.x, -(w.y * x.y)), fmadd(w.x, x.y, w.y * x.x));
 }
 
+// S consecutive radix-2 stages l .. l + S - 1 of an in-place decimation-in-time FFT,
+// each thread taking 2^S points (stride h = 2^(l-1)) through all S stages in
+// registers.  Stage l + s joins pairs at distance 2^s h with the twiddle
+// exp(-2 pi i p / 2^(l+s)) of the pair's position p; the first stage of the
+// transform (twiddle 1) adds and subtracts without a product.
+template <int S>
+__device__ __forceinline__ void fft_stages(float2* z, int M, int lg, int l, const float2* tws) {
+  constexpr int R = 1 << S;
+  const int h = 1 << (l - 1);
+  for (int bi = threadIdx.x; bi < DPAIR * (M >> S); bi += WG) {
+    const int q = bi >> (lg - S);
+    const int b = bi & ((M >> S) - 1);
+    const int pos = b & (h - 1);
+    const int i0 = q * M + ((b >> (l - 1)) << (l - 1 + S)) + pos;
+    float2 a[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) a[j] = z[i0 + j * h];
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+      const int hs = 1 << st;
+#pragma unroll
+      for (int j0 = 0; j0 < R; j0 += 2 * hs)
+#pragma unroll
+        for (int mm = 0; mm < hs; ++mm) {
+          const float2 e = a[j0 + mm], o = a[j0 + mm + hs];
+          const float2 t = (l + st == 1) ? o : cmul(tws[(pos + mm * h) * (M >> (l + st))], o);
+          a[j0 + mm] = make_float2(e.x + t.x, e.y + t.y);
+          a[j0 + mm + hs] = make_float2(e.x - t.x, e.y - t.y);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) z[i0 + j * h] = a[j];
+  }
+  __syncthreads();
+}
+
 // In-place decimation-in-time FFT of DPAIR sequences of length M = 2^lg stored back
-// to back in z, input in bit-reversed order, output in natural order.  Radix-2
-// stages are fused in pairs (each thread takes four points through two stages in
-// registers); an odd lg starts with one plain radix-2 stage.  tws[k] = exp(-2 pi i k / M).
+// to back in z, input in bit-reversed order, output in natural order, tws[k] =
+// exp(-2 pi i k / M).  The stages go three at a time through registers (one LDS round
+// trip per three stages), after one or two first stages when 3 does not divide lg.
 __device__ __forceinline__ void fft_pairs(float2* z, int M, int lg, const float2* tws) {
   int l = 1;
-  if (lg & 1) {
-    for (int bi = threadIdx.x; bi < DPAIR * (M >> 1); bi += WG) {
-      const int i0 = 2 * bi;  // pairs (2b, 2b + 1) of every sequence, twiddle 1
-      const float2 x0 = z[i0], x1 = z[i0 + 1];
-      z[i0] = make_float2(x0.x + x1.x, x0.y + x1.y);
-      z[i0 + 1] = make_float2(x0.x - x1.x, x0.y - x1.y);
-    }
-    __syncthreads();
-    l = 2;
+  if (lg % 3 == 1) {
+    fft_stages<1>(z, M, lg, l, tws);
+    l += 1;
+  } else if (lg % 3 == 2) {
+    fft_stages<2>(z, M, lg, l, tws);
+    l += 2;
   }
-  for (; l < lg; l += 2) {
-    const int h = 1 << (l - 1);
-    for (int bi = threadIdx.x; bi < DPAIR * (M >> 2); bi += WG) {
-      const int q = bi >> (lg - 2);
-      const int b = bi & ((M >> 2) - 1);
-      const int pos = b & (h - 1);
-      const int i0 = q * M + ((b >> (l - 1)) << (l + 1)) + pos;
-      const float2 a0 = z[i0], a1 = z[i0 + h], a2 = z[i0 + 2 * h], a3 = z[i0 + 3 * h];
-      // stage l (length 2h): (a0, a1) and (a2, a3) with exp(-2 pi i pos / 2h)
-      const float2 w1 = tws[pos * (M >> l)];
-      float2 t = cmul(w1, a1);
-      const float2 b0 = make_float2(a0.x + t.x, a0.y + t.y), b1 = make_float2(a0.x - t.x, a0.y - t.y);
-      t = cmul(w1, a3);
-      const float2 b2 = make_float2(a2.x + t.x, a2.y + t.y), b3 = make_float2(a2.x - t.x, a2.y - t.y);
-      // stage l + 1 (length 4h): (b0, b2) with exp(-2 pi i pos / 4h), (b1, b3) with pos + h
-      t = cmul(tws[pos * (M >> (l + 1))], b2);
-      z[i0] = make_float2(b0.x + t.x, b0.y + t.y);
-      z[i0 + 2 * h] = make_float2(b0.x - t.x, b0.y - t.y);
-      t = cmul(tws[(pos + h) * (M >> (l + 1))], b3);
-      z[i0 + h] = make_float2(b1.x + t.x, b1.y + t.y);
-      z[i0 + 3 * h] = make_float2(b1.x - t.x, b1.y - t.y);
-    }
-    __syncthreads();
-  }
+  for (; l < lg; l += 3) fft_stages<3>(z, M, lg, l, tws);
 }
 
 // Place value x of row rr (0..DG-1), position t (1..nc) into the odd extension
