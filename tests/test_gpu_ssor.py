@@ -11,7 +11,7 @@ from tests.gpu_helpers import dev, host, need_gpu, oracle_coef, plan_for, say
 
 pytestmark = pytest.mark.gpu
 
-NS = [5, 17, 40, 64, 65, 97, 130]
+NS = [1, 2, 3, 5, 17, 40, 64, 65, 97, 130]
 
 
 @pytest.fixture(scope="module")
