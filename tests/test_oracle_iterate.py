@@ -36,6 +36,24 @@ def test_chebyshev_residual_polynomial(m):
     assert np.all((1 / w > lmin) & (1 / w < lmax))
 
 
+@pytest.mark.parametrize("m", [4, 8, 16])
+def test_semi_iteration_weights_equioscillate_on_the_assumed_interval(m):
+    # with lmin := lmax / 30 the cycle polynomial is the Chebyshev minimax polynomial on
+    # [lmax / 30, lmax]: it takes the values (-1)^k / T_m(31 / 29) at the m + 1 mapped
+    # extrema x_k = cos(k pi / m) and never exceeds that magnitude in between
+    lmax = 3.9968
+    lmin = lmax / 30.0
+    w = weights.semi_iteration_weights(lmax, m)
+    bound = 1.0 / cheb_T(m, np.array([31.0 / 29.0]))[0]
+    k = np.arange(m + 1)
+    lam_k = (lmax + lmin - np.cos(k * np.pi / m) * (lmax - lmin)) / 2.0
+    assert np.allclose(weights.cycle_polynomial(w, lam_k), bound * (-1.0) ** k, rtol=1e-10, atol=0.0)
+    lam = np.linspace(lmin, lmax, 4001)
+    assert np.max(np.abs(weights.cycle_polynomial(w, lam))) <= bound * (1 + 1e-10)
+    # outside the assumed interval, below lmin, the polynomial exceeds the bound
+    assert weights.cycle_polynomial(w, np.array([lmin / 4]))[0] > bound
+
+
 def test_lowest_mode_decays_at_chebyshev_rate():
     # f = phi_11 (lowest mode): every cycle multiplies the residual by exactly 1/T_8(sigma)
     n, m = 63, 8
