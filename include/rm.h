@@ -88,7 +88,7 @@ typedef struct {
   int32_t ckpt_every;  /* RM_UNROLL: checkpoint spacing (divides K), 0 = none     */
   int32_t max_outer;   /* RM_TO_TOL: outer iterations per refinement round, cap   */
   int32_t max_rounds;  /* RM_TO_TOL: refinement rounds, cap                       */
-  int32_t check_every; /* RM_TO_TOL: outer iterations between host polls (>= 1)   */
+  int32_t check_every; /* RM_TO_TOL + RM_FLAG_GRAPH: iterations between polls >= 1 */
   int32_t flags;       /* RM_FLAG_* bits                                          */
   int32_t reserved;    /* must be 0                                               */
   double tol;          /* RM_TO_TOL: target ||b - A x|| / ||b|| (FP64)            */
@@ -237,7 +237,11 @@ rm_status rm_residual(rm_ctx* ctx, const rm_plan_t* plan, int32_t dtype, const v
  *   b, x: device double [P_tot]; x holds the initial guess and receives the
  *   result.  ckpt and hist must be NULL.  rep (host) receives per-instance
  *   counts, final FP64 relative residuals and status; the call returns the
- *   worst per-instance status.
+ *   worst per-instance status.  The host learns how many instances are still
+ *   active from a word the GPU writes into pinned memory after every outer
+ *   iteration; it reads each iteration's word while the next iteration is
+ *   already queued (without RM_FLAG_GRAPH), or synchronises every check_every
+ *   replays (with it).
  * omega: device float [B][m]; alpha: device float [B][m] ([2][B][m] for RM_NAGEX;
  * ignored, may be NULL, for RM_RICHARDSON). */
 rm_status rm_solve(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, const rm_solve_opts* opts,

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <array>
 #include <cmath>
 #include <cstdio>
@@ -78,7 +79,10 @@ struct DevBuf {
 struct rm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  int* host_count = nullptr;  // pinned and coherent: active count written by the refined solve's kernels
+  // pinned and coherent: (seq << 32) | active count, written by the refined solve's
+  // bookkeeping launches; seq numbers those launches over the context's lifetime
+  unsigned long long* host_word = nullptr;
+  unsigned seq = 0;
   // the refined solve runs on a stream of its own (graph capture is not
   // possible on a legacy default stream) after waiting for `stream`
   hipStream_t work = nullptr;
@@ -722,6 +726,31 @@ struct GraphHolder {
   }
 };
 
+// Waits until the bookkeeping launch numbered want (or a later one) has published its
+// word, spinning on the pinned copy.  After every 20 ms of waiting the stream is
+// queried, so that an error or a drained stream without the word ends the wait; the
+// query is kept that rare because it can place a marker in the queue, which stalls
+// the GPU between launches.
+rm_status wait_word(rm_ctx* ctx, hipStream_t st, unsigned want, unsigned long long& w) {
+  using clock = std::chrono::steady_clock;
+  auto next_query = clock::now() + std::chrono::milliseconds(20);
+  for (unsigned spin = 1;; ++spin) {
+    w = __atomic_load_n(ctx->host_word, __ATOMIC_ACQUIRE);
+    if ((int)((unsigned)(w >> 32) - want) >= 0) return RM_OK;
+    if ((spin & 4095u) == 0 && clock::now() >= next_query) {
+      const hipError_t e = hipStreamQuery(st);
+      if (e == hipSuccess) {
+        w = __atomic_load_n(ctx->host_word, __ATOMIC_ACQUIRE);
+        if ((int)((unsigned)(w >> 32) - want) >= 0) return RM_OK;
+        return fail(RM_EHIP, "the active count was not published");
+      }
+      if (e != hipErrorNotReady) return fail(RM_EHIP, std::string("hipStreamQuery: ") + hipGetErrorString(e));
+      next_query = clock::now() + std::chrono::milliseconds(20);
+    }
+    __builtin_ia32_pause();
+  }
+}
+
 rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_opts* o, const float* omega,
                        const float* alpha, const double* b, double* x, rm_report* rep) {
   if (ctx->work == nullptr) {
@@ -839,14 +868,14 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     int cur = 0;
     // one outer iteration: sweep of m steps with the residual fused into its last
     // launch, per-instance reduction, convergence bookkeeping
-    auto outer_iteration = [&](bool tail) -> rm_status {
+    auto outer_iteration = [&](bool tail, unsigned seq) -> rm_status {
       int flips = 0;
       const int* ranges = nullptr;
       RM_TRY(sweep(pl, st, method, o->m, 0, o->m, omega, alpha, r32, ds, vs, cur, flips, active, partial, &ranges, -1,
                    tail));
       flips_per_outer = flips;
       rmk::launch_outer_flags(p, partial, ranges, res2, rhs2, target2, best2, since, gains, stall_min, stall_max,
-                              o->max_outer, active, count, status, n_active, ctx->host_count, st);
+                              o->max_outer, active, count, status, n_active, ctx->host_word, seq, st);
       return RM_OK;
     };
     // The iteration returns to buffer set 0, so one captured iteration can be
@@ -855,7 +884,7 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
       const int cur0 = cur;
       GraphHolder& gh = graph[g];
       if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        const rm_status sc = outer_iteration(g == 1);
+        const rm_status sc = outer_iteration(g == 1, 0u);
         const hipError_t ec = hipStreamEndCapture(st, &gh.graph);
         if (sc != RM_OK || ec != hipSuccess || cur != cur0 ||
             hipGraphInstantiate(&gh.exec, gh.graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -872,17 +901,41 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     };
     // the configuration follows the active count seen at the last poll
     int tail = n_round < tail_below ? 1 : 0;
-    for (int k = 1;; ++k) {
-      if (use_graph && graph[tail].exec == nullptr) capture(tail);
-      if (use_graph)
-        RM_HIP(hipGraphLaunch(graph[tail].exec, st));
-      else
-        RM_TRY(outer_iteration(tail == 1));
-      if (k % o->check_every == 0 || k >= o->max_outer) {
-        // the bookkeeping kernel stored the count into pinned host memory
-        RM_HIP(hipStreamSynchronize(st));
-        const int na = __atomic_load_n(ctx->host_count, __ATOMIC_ACQUIRE);
-        if (na == 0) break;
+    if (use_graph && graph[tail].exec == nullptr) capture(tail);
+    if (use_graph) {
+      // captured iterations: synchronise every check_every of them and read the count
+      for (int k = 1;; ++k) {
+        if (use_graph && graph[tail].exec == nullptr) capture(tail);
+        if (use_graph)
+          RM_HIP(hipGraphLaunch(graph[tail].exec, st));
+        else
+          RM_TRY(outer_iteration(tail == 1, 0u));  // the capture failed: launch directly
+        if (k % o->check_every == 0 || k >= o->max_outer) {
+          RM_HIP(hipStreamSynchronize(st));
+          const int na = (int)(__atomic_load_n(ctx->host_word, __ATOMIC_ACQUIRE) & 0xffffffffull);
+          if (na == 0 || k >= o->max_outer) break;
+          tail = na < tail_below ? 1 : 0;
+        }
+      }
+    } else {
+      // One outer iteration stays queued while the host waits for the count of the
+      // iteration before it, so the GPU does not idle for the host's round trip; the
+      // configuration of each iteration follows the count two iterations back.
+      // The context's launch number advances before each launch, so a later solve never
+      // mistakes a word of this one for its own.
+      int issued = 0;
+      auto issue = [&]() -> rm_status {
+        ++issued;
+        return outer_iteration(tail == 1, ++ctx->seq);
+      };
+      RM_TRY(issue());
+      for (;;) {
+        const bool more = issued < o->max_outer;
+        if (more) RM_TRY(issue());
+        unsigned long long w = 0;
+        RM_TRY(wait_word(ctx, st, more ? ctx->seq - 1u : ctx->seq, w));
+        const int na = (int)(w & 0xffffffffull);
+        if (na == 0 || !more) break;
         tail = na < tail_below ? 1 : 0;
       }
     }
@@ -1074,12 +1127,12 @@ rm_status rm_create(rm_ctx** out, int32_t device, void* hip_stream) {
   rm_ctx* c = new rm_ctx;
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
-  // coherent, so that a kernel's system-scope store is what the host reads after the stream syncs
-  if (hipHostMalloc((void**)&c->host_count, sizeof(int) * 16, hipHostMallocCoherent) != hipSuccess) {
+  // coherent, so that a kernel's system-scope store is what the host reads
+  if (hipHostMalloc((void**)&c->host_word, 64, hipHostMallocCoherent) != hipSuccess) {
     delete c;
     return fail(RM_ENOMEM, "pinned host allocation failed");
   }
-  *c->host_count = 0;
+  __atomic_store_n(c->host_word, 0ull, __ATOMIC_RELEASE);
   *out = c;
   return RM_OK;
 }
@@ -1088,7 +1141,7 @@ rm_status rm_destroy(rm_ctx* ctx) {
   if (ctx == nullptr) return RM_OK;
   (void)hipStreamSynchronize(ctx->stream);
   for (rm_plan_s* pl : ctx->plans) pl->ctx = nullptr;
-  if (ctx->host_count != nullptr) (void)hipHostFree(ctx->host_count);
+  if (ctx->host_word != nullptr) (void)hipHostFree(ctx->host_word);
   if (ctx->work != nullptr) (void)hipStreamDestroy(ctx->work);
   if (ctx->handoff != nullptr) (void)hipEventDestroy(ctx->handoff);
   delete ctx;

@@ -90,12 +90,13 @@ void launch_refine_update(const PlanDev& p, double* x, const float* d0, const fl
 // Inner-solve bookkeeping after one outer iteration, one launch: res2[b] = the sum of the
 // instance's residual partials in slot order, then for active
 // instances the outer count, divergence / target / cap / stagnation tests and the new
-// active flag, and *n_active = the number still active, also stored to *host_n_active
-// (pinned host memory, may be null).
+// active flag, and *n_active = the number still active.  With host_word (pinned
+// host memory, may be null) the count is also published there as one 64-bit word,
+// (seq << 32) | count, so a host thread that reads the word knows which launch wrote it.
 void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ranges, double* res2,
                         const double* rhs2, const double* target2, double* best2, int* since, int* gains,
                         int stall_min, int stall_max, int cap, int* active, int* outer_count, int* status,
-                        int* n_active, int* host_n_active, hipStream_t st);
+                        int* n_active, unsigned long long* host_word, unsigned seq, hipStream_t st);
 void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st);
 void launch_fill_f32(float* p, float value, int64_t count, hipStream_t st);
 void launch_fill_f64(double* p, double value, int64_t count, hipStream_t st);

@@ -328,7 +328,7 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
     const double* __restrict__ rhs2, const double* __restrict__ target2, double* __restrict__ best2,
     int* __restrict__ since, int* __restrict__ gains, int stall_min, int stall_max, int cap,
     int* __restrict__ active, int* __restrict__ outer_count, int* __restrict__ status, int* __restrict__ n_active,
-    int* __restrict__ host_n_active) {
+    unsigned long long* __restrict__ host_word, unsigned seq) {
   __shared__ int kept[16];
   int mine = 0;
   for (int b = threadIdx.x; b < p.B; b += blockDim.x) {
@@ -371,7 +371,9 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
     for (int k = 0; k < (int)(blockDim.x >> 6); ++k) total += kept[k];
     *n_active = total;
     // straight to the host's pinned copy (system scope, a vector store)
-    if (host_n_active != nullptr) __hip_atomic_store(host_n_active, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (host_word != nullptr)
+      __hip_atomic_store(host_word, ((unsigned long long)seq << 32) | (unsigned)total, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -742,11 +744,11 @@ void launch_refine_update(const PlanDev& p, double* x, const float* d0, const fl
 
 void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ranges, double* res2, const double* rhs2,
                         const double* target2, double* best2, int* since, int* gains, int stall_min, int stall_max,
-                        int cap, int* active, int* outer_count, int* status, int* n_active, int* host_n_active,
-                        hipStream_t st) {
+                        int cap, int* active, int* outer_count, int* status, int* n_active,
+                        unsigned long long* host_word, unsigned seq, hipStream_t st) {
   const int threads = 64 * std::min(16, std::max(1, (p.B + 63) / 64));
   hipLaunchKernelGGL(k_outer_flags, dim3(1), dim3(threads), 0, st, p, partial2, ranges, res2, rhs2, target2, best2,
-                     since, gains, stall_min, stall_max, cap, active, outer_count, status, n_active, host_n_active);
+                     since, gains, stall_min, stall_max, cap, active, outer_count, status, n_active, host_word, seq);
 }
 
 void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st) {
