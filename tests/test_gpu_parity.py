@@ -241,6 +241,38 @@ def test_refined_solve_richardson_and_statuses(ctx):
     assert rep["inst_status"][0] == rm.RM_OK and rep["inst_status"][1] == rm.RM_OK
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_refined_solve_iteration_cap_and_repeat(ctx, graph):
+    # An unreachable tolerance with a small per-round cap: every round runs exactly
+    # max_outer outer iterations (the stagnation window is longer), the report says
+    # RM_ENOTCONV, and repeating the call in the same context, whose bookkeeping words
+    # are numbered across calls, reproduces the result bit for bit.
+    rm = _rm()
+    batch = random_batch([17, 40, 65], seed=43, eps_range=(0.1, 1.0))
+    plan = plan_for(ctx, batch)
+    m = 4
+    G = np.array([problem.gershgorin(oracle_coef(batch, b)) for b in range(batch.B)])
+    om = dev(np.tile((0.9 / G)[:, None], (1, m)), torch.float32)
+    al = dev(np.full((batch.B, m), 0.5), torch.float32)
+    f = dev(batch.f_packed())
+    for max_outer in (1, 2, 5):
+        say("refined solve cap", max_outer, "graph", graph)
+        opts = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=1e-15, tol_inner=1e-14, max_outer=max_outer, max_rounds=2,
+                             check_every=3, graph=graph)
+        xs, reps = [], []
+        for _ in range(2):
+            x = torch.zeros(plan.P, dtype=torch.float64, device="cuda")
+            reps.append(rm.rm_solve(ctx, plan, rm.RM_NAG, opts, om, al, f, x))
+            xs.append(host(x))
+        for rep in reps:
+            assert rep["status"] == rm.RM_ENOTCONV
+            assert np.all(rep["inst_status"] == rm.RM_ENOTCONV)
+            assert np.all(rep["rounds"] == 2)
+            assert np.all(rep["outer_iters"] == 2 * max_outer)
+        assert np.array_equal(xs[0], xs[1])
+        assert np.array_equal(reps[0]["relres"], reps[1]["relres"])
+
+
 @pytest.mark.parametrize("method,E", [("nag", 4), ("nag", 8), ("richardson", 4)])
 def test_adjoint_parity(ctx, method, E):
     rm = _rm()
