@@ -21,8 +21,9 @@
 //   k_tg_adj_correct  the adjoint on the fine grid: R^T ybar = P ybar / 4 formed in
 //                  LDS, ub - A R^T ybar with the stencil summed in FP64, and the
 //                  right-hand-side gradient.
-// The coarse fields are a few percent of the fine traffic; the FFT stages are
-// LDS-bound at these lengths.
+// The coarse fields are a few percent of the fine traffic.  A transform pass runs
+// about four workgroups per CU, all resident at once, so it lasts one workgroup's
+// chain of dependent steps (row loads, FFT stages between barriers, stores).
 #include "rm_device.h"
 
 #pragma clang fp contract(off)
