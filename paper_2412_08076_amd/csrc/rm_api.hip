@@ -83,6 +83,9 @@ struct rm_ctx {
   // bookkeeping launches; seq numbers those launches over the context's lifetime
   unsigned long long* host_word = nullptr;
   unsigned seq = 0;
+  // pinned host staging for the refined solve's per-round reads (grown on demand)
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
   // the refined solve runs on a stream of its own (graph capture is not
   // possible on a legacy default stream) after waiting for `stream`
   hipStream_t work = nullptr;
@@ -769,8 +772,18 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   RM_TRY(pl->vecE.ensure(fb, st));  // v1
   RM_TRY(build_exec(pl, st));
   RM_TRY(pl->partial.ensure(partial_slots(pl) * 2 * sizeof(double), st));
-  RM_TRY(pl->red.ensure((size_t)B * 6 * sizeof(double), st));
-  RM_TRY(pl->flags.ensure(((size_t)B * 6 + 16) * sizeof(int), st));
+  RM_TRY(pl->red.ensure((size_t)B * 8 * sizeof(double), st));
+  RM_TRY(pl->flags.ensure(((size_t)B * 7 + 16) * sizeof(int), st));
+  // pinned host copies of the per-round reads: r2, b2 (double), then status, tot, count (int)
+  const size_t pin_need = 2 * (size_t)B * sizeof(double) + 3 * (size_t)B * sizeof(int);
+  if (ctx->pin_bytes < pin_need) {
+    RM_HIP(hipStreamSynchronize(st));
+    if (ctx->pin != nullptr) (void)hipHostFree(ctx->pin);
+    ctx->pin = nullptr;
+    ctx->pin_bytes = 0;
+    RM_HIP(hipHostMalloc(&ctx->pin, pin_need, 0));
+    ctx->pin_bytes = pin_need;
+  }
   float* r32 = pl->vecA.as<float>();
   float* ds[2] = {pl->vecB.as<float>(), pl->vecD.as<float>()};
   float* vs[2] = {pl->vecC.as<float>(), pl->vecE.as<float>()};
@@ -780,6 +793,7 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   double* res2 = r2 + 3 * B;              // [B]  inner residual^2 after an outer iteration
   double* target2 = r2 + 4 * B;           // [B]  inner residual^2 that ends the round
   double* best2 = r2 + 5 * B;             // [B]  smallest inner residual^2 so far (stagnation)
+  double* staged = r2 + 6 * B;            // [B] targets + [B] int mask, copied in once per round
   int* active = pl->flags.as<int>();      // [B]
   int* count = active + B;                // [B]
   int* status = active + 2 * B;           // [B]
@@ -787,17 +801,28 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   int* since = active + 4 * B;            // [B]  outer iterations since the last 10 % gain
   int* gains = active + 5 * B;            // [B]  10 % gains so far in this round
   int* n_active = active + 6 * B;         // [1]
+  int* tot = active + 6 * B + 16;         // [B]  outer iterations of the rounds before the current one
   double* partial = pl->partial.as<double>();
   const PlanDev p = pl->dev();
 
-  std::vector<int> done(B, 0), st_h(B, RM_OK), dst_h(B, 0), rounds(B, 0), mask_h(B, 1), cnt_h(B, 0);
-  std::vector<long long> outer_tot(B, 0);
-  std::vector<double> r2_h(B), b2_h(B), relres(B, 0.0), prev_rho(B, 0.0), target2_h(B, 0.0);
+  std::vector<int> done(B, 0), st_h(B, RM_OK), rounds(B, 0), mask_h(B, 1);
+  std::vector<double> relres(B, 0.0), prev_rho(B, 0.0);
+  std::vector<double> staged_h(2 * (size_t)B, 0.0);  // inner targets, then the round mask as int
+  double* rb_h = static_cast<double*>(ctx->pin);     // r2, b2
+  const double* r2_h = rb_h;
+  const double* b2_h = rb_h + B;
+  int* dst_h = reinterpret_cast<int*>(rb_h + 2 * (size_t)B);
+  int* tot_h = dst_h + B;
+  int* cnt_h = tot_h + B;
+  double* target2_h = staged_h.data();
+  int* smask_h = reinterpret_cast<int*>(staged_h.data() + B);
   std::vector<int> strikes(B, 0);
   // stagnation window bounds in outer iterations (about 256 and 4096 inner steps)
   const int stall_min = std::max(16, (256 + o->m - 1) / o->m);
   const int stall_max = std::max(16, (4096 + o->m - 1) / o->m);
   rmk::launch_fill_i32(status, 0, B, st);
+  rmk::launch_fill_i32(count, 0, B, st);
+  rmk::launch_fill_i32(tot, 0, B, st);
   RM_HIP(hipMemcpyAsync(mask, mask_h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
   int flips_per_outer = 0;
   GraphHolder graph[2];  // one captured outer iteration per configuration (main, tail)
@@ -819,9 +844,8 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     if (j > 0) rmk::launch_refine_update(p, x, ds[0], ds[1], count, flips_per_outer, mask, st);
     rmk::launch_refine_residual(p, b, x, r32, ds[0], vs[0], partial, mask, st);
     rmk::launch_reduce_partials(p, partial, r2, b2, 1, nullptr, st);
-    RM_HIP(hipMemcpyAsync(r2_h.data(), r2, B * sizeof(double), hipMemcpyDeviceToHost, st));
-    RM_HIP(hipMemcpyAsync(b2_h.data(), b2, B * sizeof(double), hipMemcpyDeviceToHost, st));
-    RM_HIP(hipMemcpyAsync(dst_h.data(), status, B * sizeof(int), hipMemcpyDeviceToHost, st));
+    RM_HIP(hipMemcpyAsync(rb_h, r2, 2 * (size_t)B * sizeof(double), hipMemcpyDeviceToHost, st));  // r2, b2
+    RM_HIP(hipMemcpyAsync(dst_h, status, B * sizeof(int), hipMemcpyDeviceToHost, st));
     RM_HIP(hipStreamSynchronize(st));
     RM_TRY(last_launch());
     int n_round = 0;
@@ -857,14 +881,9 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     }
     if (n_round == 0) break;
     // inner solve A d = r32 on the instances of this round
-    RM_HIP(hipMemcpyAsync(mask, mask_h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
-    RM_HIP(hipMemcpyAsync(active, mask, B * sizeof(int), hipMemcpyDeviceToDevice, st));
-    RM_HIP(hipMemcpyAsync(rhs2, r2, B * sizeof(double), hipMemcpyDeviceToDevice, st));
-    RM_HIP(hipMemcpyAsync(best2, r2, B * sizeof(double), hipMemcpyDeviceToDevice, st));
-    RM_HIP(hipMemcpyAsync(target2, target2_h.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
-    rmk::launch_fill_i32(count, 0, B, st);
-    rmk::launch_fill_i32(since, 0, B, st);
-    rmk::launch_fill_i32(gains, 0, B, st);
+    for (int bi = 0; bi < B; ++bi) smask_h[bi] = mask_h[bi];
+    RM_HIP(hipMemcpyAsync(staged, staged_h.data(), 2 * (size_t)B * sizeof(double), hipMemcpyHostToDevice, st));
+    rmk::launch_round_start(B, staged, r2, rhs2, best2, target2, mask, active, count, tot, since, gains, st);
     int cur = 0;
     // one outer iteration: sweep of m steps with the residual fused into its last
     // launch, per-instance reduction, convergence bookkeeping
@@ -939,11 +958,14 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
         tail = na < tail_below ? 1 : 0;
       }
     }
-    RM_HIP(hipMemcpyAsync(cnt_h.data(), count, B * sizeof(int), hipMemcpyDeviceToHost, st));
-    RM_HIP(hipStreamSynchronize(st));
-    for (int bi = 0; bi < B; ++bi)
-      if (mask_h[bi]) outer_tot[bi] += cnt_h[bi];
+    // no synchronisation here: the next round's update and residual queue behind the
+    // inner solve, and its count is added to tot when that round starts
   }
+  RM_HIP(hipMemcpyAsync(tot_h, tot, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  RM_HIP(hipMemcpyAsync(cnt_h, count, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  RM_HIP(hipStreamSynchronize(st));
+  std::vector<long long> outer_tot(B, 0);
+  for (int bi = 0; bi < B; ++bi) outer_tot[bi] = (long long)tot_h[bi] + cnt_h[bi];
   rm_status worst = RM_OK;
   for (int bi = 0; bi < B; ++bi) {
     if (st_h[bi] == RM_EDIVERGED) worst = RM_EDIVERGED;
@@ -1142,6 +1164,7 @@ rm_status rm_destroy(rm_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (rm_plan_s* pl : ctx->plans) pl->ctx = nullptr;
   if (ctx->host_word != nullptr) (void)hipHostFree(ctx->host_word);
+  if (ctx->pin != nullptr) (void)hipHostFree(ctx->pin);
   if (ctx->work != nullptr) (void)hipStreamDestroy(ctx->work);
   if (ctx->handoff != nullptr) (void)hipEventDestroy(ctx->handoff);
   delete ctx;

@@ -97,6 +97,11 @@ void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ran
                         const double* rhs2, const double* target2, double* best2, int* since, int* gains,
                         int stall_min, int stall_max, int cap, int* active, int* outer_count, int* status,
                         int* n_active, unsigned long long* host_word, unsigned seq, hipStream_t st);
+// Start of a refinement round from staged[0, B) = inner targets (double) and
+// staged[B, 1.5 B) = the round mask (int): target2, mask, active, rhs2 = best2 = r2,
+// tot += count, and zero outer counts and stagnation counters.
+void launch_round_start(int B, const double* staged, const double* r2, double* rhs2, double* best2, double* target2,
+                        int* mask, int* active, int* count, int* tot, int* since, int* gains, hipStream_t st);
 void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st);
 void launch_fill_f32(float* p, float value, int64_t count, hipStream_t st);
 void launch_fill_f64(double* p, double value, int64_t count, hipStream_t st);

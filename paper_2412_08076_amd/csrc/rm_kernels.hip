@@ -377,6 +377,30 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
   }
 }
 
+// Start of a refinement round, one launch: from the staged host values (per instance
+// the inner target and the round mask) set target2 and the mask, activate the masked
+// instances, take the round's right-hand-side norm as the reference and the best
+// residual so far, add the last round's outer count to tot and clear the outer count
+// and the stagnation counters.
+__global__ void k_round_start(int B, const double* __restrict__ staged, const double* __restrict__ r2,
+                              double* __restrict__ rhs2, double* __restrict__ best2, double* __restrict__ target2,
+                              int* __restrict__ mask, int* __restrict__ active, int* __restrict__ count,
+                              int* __restrict__ tot, int* __restrict__ since, int* __restrict__ gains) {
+  const int* staged_mask = reinterpret_cast<const int*>(staged + B);
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+    target2[b] = staged[b];
+    const int mk = staged_mask[b];
+    mask[b] = mk;
+    active[b] = mk;
+    rhs2[b] = r2[b];
+    best2[b] = r2[b];
+    tot[b] += count[b];
+    count[b] = 0;
+    since[b] = 0;
+    gains[b] = 0;
+  }
+}
+
 template <typename T>
 __global__ void k_fill(T* __restrict__ p, T value, int64_t count) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
@@ -751,6 +775,11 @@ void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ran
                      since, gains, stall_min, stall_max, cap, active, outer_count, status, n_active, host_word, seq);
 }
 
+void launch_round_start(int B, const double* staged, const double* r2, double* rhs2, double* best2, double* target2,
+                        int* mask, int* active, int* count, int* tot, int* since, int* gains, hipStream_t st) {
+  hipLaunchKernelGGL(k_round_start, dim3((B + 255) / 256), dim3(256), 0, st, B, staged, r2, rhs2, best2, target2, mask,
+                     active, count, tot, since, gains);
+}
 void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st) {
   if (count > 0) hipLaunchKernelGGL(k_fill<int>, dim3(fill_grid(count)), dim3(256), 0, st, p, value, count);
 }
