@@ -1,20 +1,20 @@
 """Benchmark of the batched long-step Richardson(m) hot path on one MI355X.
 
-Workload (synthetic, seeded): 256 anisotropic Q1 problems, n = 255 interior nodes
-per direction, eps = 10**U(-4, 0), theta = U(0, pi), f ~ N(0, I); NAG-Richardson(16)
-with per-instance weights and momentum from the meta network.
+Headline step (synthetic, seeded inputs, resident on the device before timing):
+  (1) the uneven batch: 512 anisotropic Q1 problems with n drawn from
+      {63, 127, 255, 511, 1023} in proportions 40/25/20/10/5 %, eps = 10**U(-4, 0),
+      theta = U(0, pi), f ~ N(0, I); NAG-Richardson(16) with per-instance weights and
+      momentum from the meta network (forward included); FP32 sweeps inside FP64
+      refinement until every ||b - A x|| / ||b|| <= 1e-10;
+  (2) one training step on 64 problems of n = 127 (same distributions): meta forward,
+      K = 64 unrolled FP32 NAG-Richardson(16) steps from x = 0 with checkpoints every
+      16 steps, the squared relative residual loss, the hand-written adjoint
+      (recompute included) and the meta-network backward.
+value = (inner-step point updates of (1), as reported per instance, + forward and
+adjoint point updates of (2)) / step time, in GLUP/s.  time_to_tol_s is (1) alone;
+train.glups_fwd_adjoint is (2) alone.
 
-One step =
-  meta-network forward (weights and momentum for every instance)
-  + FP32-sweep / FP64-refined solve of all 256 problems to ||b - A x|| / ||b|| <= 1e-10
-  + one training pass on the same batch: K = 64 unrolled FP32 steps from x = 0 with
-    checkpoints every 16 steps, the squared relative residual loss, the adjoint
-    sweep (recompute included) and the meta-network backward.
-value = (inner-step point updates of the solve + forward and adjoint updates of
-the training pass) / step time, in GLUP/s.  Inputs are resident on the device
-before timing starts.
-
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 import argparse
 import json
@@ -28,22 +28,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GLUP/s (stencil updates/s) fwd+adjoint, batched; time to 1e-10 rel residual"
-B, N, M, K_TRAIN, CKPT, TOL = 256, 255, 16, 64, 16, 1e-10
+M, K_TRAIN, CKPT, TOL = 16, 64, 16, 1e-10
+B_TRAIN, N_TRAIN = 64, 127
 HBM_PEAK_GBS = 8000.0
-# FP32 arithmetic rate without packed FP32 (disabled at compile time for this GPU):
+# published MI355X vector FP32 peak (counts packed FP32 FMAs)
+FP32_PEAK_TFLOPS = 157.3
+# the FP32 rate without packed FP32 instructions, which this build disables:
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flop per FMA x 2.4 GHz
-FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# flops of one NAG-Richardson point update as the kernels evaluate it: v' = a v + w f
-# - sum_j (w c_j) s_j over the four symmetric pairs and the centre (1 mul + 1 FMA,
-# 4 pair adds, 5 FMAs), u' = u + v' (1 add), next look-ahead u + a' v' (1 FMA)
-FLOPS_PER_LUP_NAG = 20.0
+FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# algorithmic flops of one point update: the 9-point stencil (9 multiply-adds), the
+# scheme's update (about 6 operations) and the residual-norm accumulation (1 FMA)
+FLOPS_PER_LUP = 24.0
+BYTES_PER_LUP_NAG = 20.0  # read u, v, f; write u, v (FP32): a sweep that keeps nothing on chip
 STREAM_SHAPE = 9
-# kernel choices of the autotuner for this workload (written by rm_tune on an MI355X)
+# kernel choices of the autotuner for these workloads (written by rm_tune on an MI355X)
 TUNE_CACHE = os.path.join(ROOT, "paper_2412_08076_amd", "tune_gfx950.json")
-BYTES_PER_LUP_NAG = 20.0  # read u, v, f; write u, v (FP32)
 
 
 # ----------------------------------------------------------------------------- CPU oracle leg
+def _host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "affinity": share, "model": model}
+
+
 def _oracle_worker(args):
     eps, theta, seed, n, steps = args
     from oracle import iterate, problem
@@ -58,32 +77,41 @@ def _oracle_worker(args):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(steps=1024):
-    """The FP64 oracle's NAG-Richardson(16) sweep on host cores: one n = 255 instance per
-    worker process, `steps` inner steps each."""
+def cpu_baseline(steps=512, per_class=None):
+    """The FP64 NumPy oracle's NAG-Richardson(16) sweep on the host: a bounded sample of
+    the uneven batch (the first `per_class` instances of each size class), one instance
+    per task, largest first, over worker processes with one BLAS thread each, on the host
+    cores given to this GPU (the process's CPU affinity, at most 16)."""
     import multiprocessing as mp
-    cores = min(16, os.cpu_count() or 1)
-    from synthetic import aniso_batch  # noqa: F401  (same distributions as the GPU batch)
-    rng = np.random.default_rng(2)
-    eps = 10.0 ** rng.uniform(-4, 0, cores)
-    theta = rng.uniform(0, np.pi, cores)
-    jobs = [(eps[k], theta[k], 100 + k, N, steps) for k in range(cores)]
+    from synthetic import uneven_batch
+    info = _host_info()
+    cores = max(1, min(16, info["affinity"]))
+    batch = uneven_batch(seed=4)
+    ns = np.array(batch.n)
+    if per_class is None:  # enough instances to give every core one
+        per_class = max(2, -(-cores // len(set(batch.n))))
+    pick = []
+    for n in sorted(set(batch.n), reverse=True):
+        pick += [int(k) for k in np.flatnonzero(ns == n)[:per_class]]
+    jobs = [(batch.eps[k], batch.theta[k], 100 + k, batch.n[k], steps) for k in pick]
     env_keep = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
     for k in env_keep:
         os.environ[k] = "1"
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(cores) as pool:
-        pool.map(_oracle_worker, jobs)
+    with mp.get_context("fork").Pool(min(cores, len(jobs))) as pool:
+        pool.map(_oracle_worker, jobs, chunksize=1)
     wall = time.perf_counter() - t0
     for k, v in env_keep.items():
         if v is None:
             os.environ.pop(k, None)
         else:
             os.environ[k] = v
-    lups = cores * steps * N * N
-    return {"value": lups / wall / 1e9, "unit": "GLUP/s", "cores": cores, "kind": "oracle",
-            "sample": f"{cores} instances of n={N}, {steps} NAG-Richardson(16) inner steps each, "
-                      f"one FP64 NumPy process per core; wall {wall:.2f} s"}
+    lups = float(sum(batch.n[k] ** 2 for k in pick)) * steps
+    return {"value": lups / wall / 1e9, "unit": "GLUP/s", "cores": min(cores, len(jobs)), "kind": "oracle",
+            "sample": f"the first {per_class} instances of each size class of the uneven batch ({len(pick)} "
+                      f"instances, n = {sorted(set(batch.n))}), {steps} NAG-Richardson(16) inner steps each, "
+                      f"FP64 NumPy, one process per instance; wall {wall:.2f} s",
+            "host": info}
 
 
 # ----------------------------------------------------------------------------- comparator leg
@@ -92,7 +120,8 @@ def plain_fp64_loop(batch, omega, alpha, sample, tol=TOL, max_outer=20000):
     one instance at a time, NAG-Richardson(16) written as separate PyTorch FP64 device
     operations per inner step (look-ahead, 3x3 convolution for A, momentum and iterate
     updates), the residual norm after every outer iteration read back to the host, and
-    the same weights and tolerance.  Returns (seconds for the sample, outer iterations)."""
+    the same weights and tolerance.  Returns (seconds per sampled instance, outer
+    iterations)."""
     import torch
     from paper_2412_08076_amd import rm
     times, iters = [], []
@@ -125,160 +154,200 @@ def plain_fp64_loop(batch, omega, alpha, sample, tol=TOL, max_outer=20000):
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         iters.append(k)
+        print(f"[bench] comparator instance {b} n={n}: {times[-1]:.2f} s, {k} outer", file=sys.stderr, flush=True)
     return times, iters
 
 
 # ----------------------------------------------------------------------------- roofline
-TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
-                 ("k_stream_nag_n255_B256_traffic.json", "k_block_nag_n255_B256_traffic.json")]
-
-
-def kernel_name(kcfg):
+def kernel_name(kcfg, n, count):
     sh, T, cw = kcfg
     if sh == STREAM_SHAPE:
-        return f"k_stream T={T} window={cw} n={N} B={B}"
-    return f"k_block variant {sh} T={T} width={cw} n={N} B={B}"
+        return f"k_stream T={T} window={cw} n={n} B={count}"
+    return f"k_block variant {sh} T={T} width={cw} n={n} B={count}"
 
 
-def roofline(kstr, kcfg, t_step, P, copy_gbs):
-    """Roofline entry of the dominant kernel (the temporal-blocked NAG sweep).
+def roofline(kstr, T, units, t_launch, copy_gbs):
+    """Roofline entry of the dominant kernel (the temporal-blocked NAG sweep of the size
+    class that sets the time to tolerance).
 
-    The sweep keeps T steps on chip and moves one sweep's data per launch, so it is
-    bound by FP32 arithmetic, not HBM: achieved = algorithmic flops per launch (20 per
-    point update, T updates per point) / launch time, against the non-packed FP32 rate
-    derived from the unit counts and clock.  traffic: DRAM bytes per launch from the
-    FETCH_SIZE / WRITE_SIZE counters scaled by a copy-kernel calibration, when a
-    committed profile exists for this exact kernel configuration, else null.  The HBM
-    view is kept alongside: 20 B per point per step (the traffic of a sweep that keeps
-    nothing on chip) over the launch time, which exceeds the HBM peak by design."""
-    T = kcfg[1]
-    t_launch = t_step * T
-    alg_bytes = BYTES_PER_LUP_NAG * P * T
-    flops = FLOPS_PER_LUP_NAG * P * T
+    One launch advances `units` points by T inner steps and keeps them on chip in
+    between, so it moves one sweep's data per launch and is bound by FP32 arithmetic:
+    achieved = 24 algorithmic flops per point update x units x T / launch time, against
+    the published FP32 peak.  The same rate against the FP32 peak without packed
+    instructions (which this build disables) is kept as a separate field.  traffic: DRAM
+    bytes per launch from the FETCH_SIZE / WRITE_SIZE counters scaled by a copy-kernel
+    calibration, when a committed profile exists for this exact kernel configuration,
+    else null; dram_frac is that traffic over the launch time against 8 TB/s."""
+    flops = FLOPS_PER_LUP * units * T
     traffic = None
-    for path in TRAFFIC_FILES:
-        if os.path.exists(path):
-            with open(path) as fh:
+    for name in sorted(os.listdir(os.path.join(ROOT, "profiles"))):
+        if name.endswith("_traffic.json"):
+            with open(os.path.join(ROOT, "profiles", name)) as fh:
                 prof = json.load(fh)
             if prof.get("kernel") == kstr:
                 traffic = prof["dram_bytes_per_launch"]
     achieved = flops / t_launch / 1e12
-    hbm_eff = alg_bytes / t_launch / 1e9
+    dram = (traffic / t_launch / 1e9) if traffic else None
     return {"bound": "alu", "kernel": kstr, "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic, "launch_us": t_launch * 1e6,
-            "algorithmic_flops_per_launch": flops, "steps_per_launch": T,
-            "dram_GBs_at_traffic": (traffic / t_launch / 1e9) if traffic else None,
-            "hbm_effective": {"achieved": hbm_eff, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": hbm_eff / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg_bytes},
-            "min_dram_bytes_per_launch": BYTES_PER_LUP_NAG * P, "measured_copy_GBs": copy_gbs}
+            "flops_per_lup": FLOPS_PER_LUP, "points_per_launch": units, "steps_per_launch": T,
+            "algorithmic_flops_per_launch": flops,
+            "nonpacked_fp32": {"peak": FP32_NONPACKED_TFLOPS, "frac": achieved / FP32_NONPACKED_TFLOPS},
+            "dram_GBs": dram, "dram_frac": (dram / HBM_PEAK_GBS) if dram else None,
+            "min_dram_bytes_per_launch": BYTES_PER_LUP_NAG * units, "measured_copy_GBs": copy_gbs}
 
 
-# ----------------------------------------------------------------------------- GPU leg
-class Workload:
-    def __init__(self):
-        import torch
-        from paper_2412_08076_amd import rm
-        from synthetic import aniso_batch, meta_params
-        self.torch, self.rm = torch, rm
-        batch = aniso_batch(B, N, seed=2)
-        self.batch = batch
-        self.ctx = rm.Context(0)
-        self.plan = rm.Plan(self.ctx, batch.n, eps=batch.eps, theta=batch.theta)
-        P = self.plan.P
-        f = batch.f_packed()
-        dev = "cuda"
-        self.b64 = torch.as_tensor(f).to(dev)
-        self.b32 = self.b64.float().contiguous()
-        self.params = torch.as_tensor(meta_params(m=M, seed=0), dtype=torch.float32).to(dev)
-        self.om = torch.empty(B * M, dtype=torch.float32, device=dev)
-        self.al = torch.empty_like(self.om)
-        self.x64 = torch.zeros(P, dtype=torch.float64, device=dev)
-        self.x32 = torch.zeros(P, dtype=torch.float32, device=dev)
-        self.ckpt = torch.empty(K_TRAIN // CKPT * 2 * P, dtype=torch.float32, device=dev)
-        self.loss = torch.empty(B, dtype=torch.float32, device=dev)
-        self.g_loss = torch.full((B,), 1.0 / B, dtype=torch.float32, device=dev)
-        self.dw = torch.empty_like(self.om)
-        self.da = torch.empty_like(self.om)
-        self.dparams = torch.empty_like(self.params)
-        self.P = P
-        self.opts_tol = rm.solve_opts(mode=rm.RM_TO_TOL, m=M, tol=TOL, tol_inner=1e-3, max_outer=20000,
-                                      max_rounds=10, check_every=4)
-        self.opts_unroll = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=M, K=K_TRAIN, ckpt_every=CKPT)
-
-    def tune(self, cache_path=None):
-        """Autotune the kernel configuration on this batch (outside the timed region)."""
-        rm = self.rm
-        rm.rm_meta_forward(self.ctx, self.plan, M, self.params, self.om, self.al)
-        us = rm.rm_tune(self.ctx, self.plan, rm.RM_NAG, M, self.om, self.al, self.b32, cache_path=cache_path)
-        return us, self.plan.get_kernel(N)
-
-    def copy_bandwidth(self, nbytes=1 << 30):
-        torch = self.torch
-        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        best = None
-        for _ in range(5):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            b.copy_(a)
-            e1.record()
-            torch.cuda.synchronize()
-            t = e0.elapsed_time(e1) / 1e3
-            best = t if best is None else min(best, t)
-        del a, b
-        return 2.0 * nbytes / best / 1e9
-
-    def step(self):
-        rm, torch = self.rm, self.torch
-        rm.rm_meta_forward(self.ctx, self.plan, M, self.params, self.om, self.al)
-        self.x64.zero_()
+def copy_bandwidth(nbytes=1 << 30):
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(5):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        rep = rm.rm_solve(self.ctx, self.plan, rm.RM_NAG, self.opts_tol, self.om, self.al, self.b64, self.x64)
+        b.copy_(a)
         e1.record()
-        # training pass
-        self.x32.zero_()
-        rm.rm_solve(self.ctx, self.plan, rm.RM_NAG, self.opts_unroll, self.om, self.al, self.b32, self.x32,
-                    ckpt=self.ckpt)
-        rm.rm_residual(self.ctx, self.plan, self.b32, self.x32, rel2=self.loss)
-        rm.rm_solve_adjoint(self.ctx, self.plan, rm.RM_NAG, self.opts_unroll, self.om, self.al, self.b32,
-                            self.ckpt, self.dw, self.da, g_loss=self.g_loss)
-        rm.rm_meta_backward(self.ctx, self.plan, M, self.params, self.dw, self.da, self.dparams)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3
+        best = t if best is None else min(best, t)
+    del a, b
+    return 2.0 * nbytes / best / 1e9
+
+
+# ----------------------------------------------------------------------------- GPU leg
+class Headline:
+    """The uneven batch refined to 1e-10 plus the n = 127 training step, one plan each."""
+
+    def __init__(self, tune_cache):
+        import torch
+        from paper_2412_08076_amd import rm
+        from synthetic import aniso_batch, meta_params, uneven_batch
+        self.torch, self.rm = torch, rm
+        self.ctx = rm.Context(0)
+        dev = "cuda"
+        self.params = torch.as_tensor(meta_params(m=M, seed=0), dtype=torch.float32).to(dev)
+        # (1) the uneven batch
+        self.ub = uneven_batch(seed=4)
+        self.uplan = rm.Plan(self.ctx, self.ub.n, eps=self.ub.eps, theta=self.ub.theta)
+        self.ns = np.array(self.ub.n)
+        self.ub64 = torch.as_tensor(self.ub.f_packed()).to(dev)
+        self.ub32 = self.ub64.float().contiguous()
+        Bu = self.uplan.B
+        self.uom = torch.empty(Bu * M, dtype=torch.float32, device=dev)
+        self.ual = torch.empty_like(self.uom)
+        self.ux = torch.zeros(self.uplan.P, dtype=torch.float64, device=dev)
+        self.opts_tol = rm.solve_opts(mode=rm.RM_TO_TOL, m=M, tol=TOL, tol_inner=1e-3, max_outer=20000,
+                                      max_rounds=10, check_every=8)
+        # (2) the training batch
+        self.tb = aniso_batch(B_TRAIN, N_TRAIN, seed=3)
+        self.tplan = rm.Plan(self.ctx, self.tb.n, eps=self.tb.eps, theta=self.tb.theta)
+        P = self.tplan.P
+        self.tb32 = torch.as_tensor(self.tb.f_packed(), dtype=torch.float32).to(dev)
+        self.tom = torch.empty(B_TRAIN * M, dtype=torch.float32, device=dev)
+        self.tal = torch.empty_like(self.tom)
+        self.tx = torch.zeros(P, dtype=torch.float32, device=dev)
+        self.ckpt = torch.empty(K_TRAIN // CKPT * 2 * P, dtype=torch.float32, device=dev)
+        self.loss = torch.empty(B_TRAIN, dtype=torch.float32, device=dev)
+        self.g_loss = torch.full((B_TRAIN,), 1.0 / B_TRAIN, dtype=torch.float32, device=dev)
+        self.dw = torch.empty_like(self.tom)
+        self.da = torch.empty_like(self.tom)
+        self.dparams = torch.empty_like(self.params)
+        self.opts_unroll = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=M, K=K_TRAIN, ckpt_every=CKPT)
+        # autotune both plans (outside the timed region; a committed cache makes it a lookup)
+        rm.rm_meta_forward(self.ctx, self.uplan, M, self.params, self.uom, self.ual)
+        self.tuned_us = rm.rm_tune(self.ctx, self.uplan, rm.RM_NAG, M, self.uom, self.ual, self.ub32,
+                                   cache_path=tune_cache)
+        rm.rm_meta_forward(self.ctx, self.tplan, M, self.params, self.tom, self.tal)
+        self.tuned_train_us = rm.rm_tune(self.ctx, self.tplan, rm.RM_NAG, M, self.tom, self.tal, self.tb32,
+                                         cache_path=tune_cache)
+
+    def kernels(self):
+        return {int(n): list(self.uplan.get_kernel(int(n))) for n in sorted(set(self.ub.n))}
+
+    def solve(self):
+        rm, torch = self.rm, self.torch
+        rm.rm_meta_forward(self.ctx, self.uplan, M, self.params, self.uom, self.ual)
+        self.ux.zero_()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rep = rm.rm_solve(self.ctx, self.uplan, rm.RM_NAG, self.opts_tol, self.uom, self.ual, self.ub64, self.ux)
+        e1.record()
         return rep, (e0, e1)
 
-    def lups(self, rep):
-        n2 = float(N * N)
-        fwd_tol = float(np.sum(rep["outer_iters"].astype(np.float64))) * M * n2
-        train = 2.0 * K_TRAIN * self.P
-        return fwd_tol + train
+    def train_step(self):
+        rm = self.rm
+        rm.rm_meta_forward(self.ctx, self.tplan, M, self.params, self.tom, self.tal)
+        self.tx.zero_()
+        rm.rm_solve(self.ctx, self.tplan, rm.RM_NAG, self.opts_unroll, self.tom, self.tal, self.tb32, self.tx,
+                    ckpt=self.ckpt)
+        rm.rm_solve_adjoint(self.ctx, self.tplan, rm.RM_NAG, self.opts_unroll, self.tom, self.tal, self.tb32,
+                            self.ckpt, self.dw, self.da, g_loss=self.g_loss, loss=self.loss)
+        rm.rm_meta_backward(self.ctx, self.tplan, M, self.params, self.dw, self.da, self.dparams)
 
-    def step_kernel_time(self, K=256, reps=3):
-        """Time per inner step of the fused NAG sweep kernel: an unrolled FP32 solve of K
-        steps launches nothing else (K / T back-to-back launches), timed with events on
-        the library's stream."""
+    def step(self):
+        rep, ev = self.solve()
+        self.train_step()
+        return rep, ev
+
+    def solve_lups(self, rep):
+        return float(np.sum(rep["outer_iters"].astype(np.float64) * M * self.ns.astype(np.float64) ** 2))
+
+    def train_lups(self):
+        return 2.0 * K_TRAIN * self.tplan.P
+
+    def time_train(self, reps=20):
+        torch = self.torch
+        self.train_step()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            self.train_step()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    def dominant_kernel(self, K=128, reps=3):
+        """Per-launch time of the sweep kernel of the largest size class, all its instances
+        active: a plan of that class alone, its tuned configuration, an unrolled solve of K
+        steps (K / T back-to-back launches after two fills), HIP events on the library's
+        stream."""
         rm, torch = self.rm, self.torch
+        n = int(self.ns.max())
+        idx = [b for b in range(len(self.ns)) if self.ns[b] == n]
+        kc = self.uplan.get_kernel(n)
+        plan = rm.Plan(self.ctx, [n] * len(idx), eps=self.ub.eps[idx], theta=self.ub.theta[idx])
+        plan.set_kernel(kc[0], kc[1], n=n, cw=kc[2])
+        sel = torch.as_tensor(np.concatenate([np.arange(b * M, (b + 1) * M) for b in idx])).cuda()
+        om = self.uom[sel].contiguous()
+        al = self.ual[sel].contiguous()
+        f = torch.cat([self.ub32[self.uplan.offsets[b]:self.uplan.offsets[b + 1]] for b in idx]).contiguous()
+        x = torch.zeros(plan.P, dtype=torch.float32, device="cuda")
         opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=M, K=K)
+        rm.rm_solve(self.ctx, plan, rm.RM_NAG, opts, om, al, f, x)
         best = None
         for _ in range(reps):
-            self.x32.zero_()
+            x.zero_()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            rm.rm_solve(self.ctx, self.plan, rm.RM_NAG, opts, self.om, self.al, self.b32, self.x32)
+            rm.rm_solve(self.ctx, plan, rm.RM_NAG, opts, om, al, f, x)
             e1.record()
             torch.cuda.synchronize()
-            t = e0.elapsed_time(e1) / 1e3 / K
+            t = e0.elapsed_time(e1) / 1e3 / (K / kc[1])
             best = t if best is None else min(best, t)
-        return best
+        return kernel_name(kc, n, len(idx)), kc[1], plan.P, best
 
 
 def secondary_workload(name, tune_cache):
-    """The other measured shapes (one JSON line each; the headline line is the default
-    workload): 'uneven' -- 512 instances of mixed size, one plan; 'train' -- the training
-    step on 64 problems of n = 127; 'single' -- one isotropic n = 63 problem."""
+    """The other measured shapes (one JSON line each): 'aniso' -- 256 problems of n = 255
+    refined to 1e-10; 'uneven' -- the uneven batch's unrolled throughput and refined
+    solve per size class; 'train' -- the n = 127 training step alone; 'single' -- one
+    isotropic n = 63 problem; 'twogrid', 'ssor', 'fgmres' -- the multilevel,
+    preconditioned and Krylov variants."""
     import torch
     from paper_2412_08076_amd import rm
     from synthetic import aniso_batch, meta_params, single_isotropic, uneven_batch
@@ -288,7 +357,6 @@ def secondary_workload(name, tune_cache):
     if name == "single":
         batch = single_isotropic(63, seed=0)
         plan = rm.Plan(ctx, batch.n, eps=batch.eps, theta=batch.theta)
-        coef, _ = plan.coefficients()
         # Chebyshev(8) weights from the closed-form extreme eigenvalues of the eps = 1 stencil
         c = np.cos(np.pi / 64)
         lmin, lmax = (4.0 / 3.0) * (2 - c - c * c), (8 + 4 * c * c) / 3.0
@@ -319,7 +387,9 @@ def secondary_workload(name, tune_cache):
         return fgmres_workload(ctx, tune_cache)
     m = 16
     if name == "train":
-        batch = aniso_batch(64, 127, seed=3)
+        batch = aniso_batch(B_TRAIN, N_TRAIN, seed=3)
+    elif name == "aniso":
+        batch = aniso_batch(256, 255, seed=2)
     else:
         batch = uneven_batch(seed=4)
     plan = rm.Plan(ctx, batch.n, eps=batch.eps, theta=batch.theta)
@@ -343,8 +413,7 @@ def secondary_workload(name, tune_cache):
             rm.rm_meta_forward(ctx, plan, m, params, om, al)
             x.zero_()
             rm.rm_solve(ctx, plan, rm.RM_NAG, opts, om, al, b32, x, ckpt=ck)
-            rm.rm_residual(ctx, plan, b32, x, rel2=loss)
-            rm.rm_solve_adjoint(ctx, plan, rm.RM_NAG, opts, om, al, b32, ck, dw, da, g_loss=gl)
+            rm.rm_solve_adjoint(ctx, plan, rm.RM_NAG, opts, om, al, b32, ck, dw, da, g_loss=gl, loss=loss)
             rm.rm_meta_backward(ctx, plan, m, params, dw, da, dp)
         step(); torch.cuda.synchronize()
         e0, e1 = ev(), ev()
@@ -356,7 +425,7 @@ def secondary_workload(name, tune_cache):
         out.update({"ms_per_training_step": t * 1e3, "glups_fwd_adjoint": 2 * K * P / t / 1e9,
                     "loss_mean": float(loss.mean())})
         return out
-    # uneven: unrolled throughput and the refined solve with caps
+    # unrolled throughput and the refined solve with caps
     opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=K)
     rm.rm_solve(ctx, plan, rm.RM_NAG, opts, om, al, b32, x); torch.cuda.synchronize()
     e0, e1 = ev(), ev()
@@ -530,48 +599,37 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--kernel-only", action="store_true",
-                    help="time only the fused sweep kernel and a 1 GiB device copy (for counter runs)")
     ap.add_argument("--no-comparator", action="store_true", help="skip the plain FP64 loop comparator")
-    ap.add_argument("--kernel-config", default=None,
-                    help="variant,T,width of the sweep kernel instead of autotuning (e.g. 3,8,64)")
-    ap.add_argument("--workload", default="aniso", choices=["aniso", "uneven", "train", "single", "twogrid", "ssor", "fgmres"],
-                    help="aniso (default, the headline line) or one of the secondary shapes")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="time only the dominant sweep kernel and a 1 GiB device copy (for counter runs)")
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "aniso", "uneven", "train", "single", "twogrid", "ssor", "fgmres"],
+                    help="headline (default) or one of the secondary shapes")
     args = ap.parse_args()
-    if args.workload != "aniso":
-        print(json.dumps(secondary_workload(args.workload, os.environ.get("RM_TUNE_CACHE", TUNE_CACHE))),
-              flush=True)
-        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the batch shards by instance "
                                    "across GPUs by design, but no multi-GPU path is built"}))
         sys.exit(2)
+    cache = os.environ.get("RM_TUNE_CACHE", TUNE_CACHE)
+    if args.workload != "headline":
+        print(json.dumps(secondary_workload(args.workload, cache)), flush=True)
+        return
 
     cpu = None if (args.no_cpu or args.kernel_only) else cpu_baseline()  # before any GPU use (forks workers)
     print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
 
     import torch
-    w = Workload()
-    if args.kernel_config:
-        v, T, cw = (int(x) for x in args.kernel_config.split(","))
-        w.plan.set_kernel(v, T, cw=cw)
-        kcfg = w.plan.get_kernel(N)
-        rm_ = w.rm
-        rm_.rm_meta_forward(w.ctx, w.plan, M, w.params, w.om, w.al)
-    else:
-        tuned_us, kcfg = w.tune(os.environ.get("RM_TUNE_CACHE", TUNE_CACHE))
-        print(f"[bench] tuned kernel (variant, T, width) = {kcfg}, {tuned_us:.1f} us per inner step",
-              file=sys.stderr, flush=True)
+    h = Headline(cache)
+    print(f"[bench] kernels per size class {h.kernels()}, tuned {h.tuned_us:.1f} us per inner step "
+          f"(uneven), {h.tuned_train_us:.1f} (train)", file=sys.stderr, flush=True)
     if args.kernel_only:
-        kt = w.step_kernel_time()
-        copy_gbs = w.copy_bandwidth()
-        kstr = kernel_name(kcfg)
-        print(json.dumps({"kernel": kstr, "us_per_inner_step": kt * 1e6, "us_per_launch": kt * 1e6 * kcfg[1],
-                          "algorithmic_bytes_per_launch": BYTES_PER_LUP_NAG * w.P * kcfg[1],
-                          "copy_bytes": 2 * (1 << 30), "measured_copy_GBs": copy_gbs}), flush=True)
+        kstr, T, units, tl = h.dominant_kernel()
+        print(json.dumps({"kernel": kstr, "us_per_launch": tl * 1e6, "steps_per_launch": T,
+                          "points_per_launch": units, "algorithmic_bytes_per_launch": BYTES_PER_LUP_NAG * units,
+                          "copy_bytes": 2 * (1 << 30), "measured_copy_GBs": copy_bandwidth()}), flush=True)
         return
     for k in range(args.warmup):
-        rep, _ = w.step()
+        rep, _ = h.step()
         torch.cuda.synchronize()
         print(f"[bench] warmup {k} status {rep['status']} outer max {rep['outer_iters'].max()}", file=sys.stderr,
               flush=True)
@@ -579,34 +637,42 @@ def main():
     t0 = time.perf_counter()
     lups, tol_times, reps = 0.0, [], []
     for k in range(args.steps):
-        rep, (e0, e1) = w.step()
-        lups += w.lups(rep)
+        rep, (e0, e1) = h.step()
+        lups += h.solve_lups(rep) + h.train_lups()
         reps.append(rep)
         tol_times.append((e0, e1))
         print(f"[bench] step {k} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     ttol = float(np.mean([a.elapsed_time(b) / 1e3 for a, b in tol_times]))
-    kt = w.step_kernel_time()
-    copy_gbs = w.copy_bandwidth()
-    kstr = kernel_name(kcfg)
+    t_train = h.time_train()
+    print(f"[bench] training step {t_train * 1e3:.3f} ms", file=sys.stderr, flush=True)
+    kstr, T, units, t_launch = h.dominant_kernel()
+    print(f"[bench] dominant kernel {kstr}: {t_launch * 1e6:.1f} us per launch", file=sys.stderr, flush=True)
+    copy_gbs = copy_bandwidth()
+    rep = reps[-1]
+    ns = h.ns
     comparator = None
     if not args.no_comparator:
-        sample = [0, 85, 170, 255]
-        omh = w.om.view(B, M).cpu().numpy()
-        alh = w.al.view(B, M).cpu().numpy()
-        ptimes, piters = plain_fp64_loop(w.batch, omh, alh, sample)
-        fused_iters = reps[-1]["outer_iters"]
-        est = float(np.mean(ptimes)) * B
+        sample = [int(np.flatnonzero(ns == n)[0]) for n in sorted(set(ns.tolist()))]
+        omh = h.uom.view(-1, M).cpu().numpy()
+        alh = h.ual.view(-1, M).cpu().numpy()
+        ptimes, piters = plain_fp64_loop(h.ub, omh, alh, sample)
+        est = float(sum(ptimes[k] * int(np.sum(ns == ns[b])) for k, b in enumerate(sample)))
         comparator = {"kind": "plain per-instance FP64 GPU loop (PyTorch ops, host residual check per outer "
                               "iteration)",
-                      "sample": f"instances {sample} of {B}, run to 1e-10; batch time extrapolated as "
-                                f"mean x {B}",
+                      "sample": f"instances {sample} (the first of each size class), run to 1e-10; batch time "
+                                f"extrapolated as the sum over classes of the sampled time x the class size",
                       "seconds_per_instance": [round(x, 4) for x in ptimes], "outer_iters": piters,
-                      "fused_outer_iters_same_instances": [int(fused_iters[i]) for i in sample],
+                      "fused_outer_iters_same_instances": [int(rep["outer_iters"][i]) for i in sample],
                       "time_to_tol_s_extrapolated": est, "speedup_time_to_tol": est / ttol}
         print(f"[bench] comparator {comparator}", file=sys.stderr, flush=True)
-    rep = reps[-1]
+    per = {}
+    for n in sorted(set(ns.tolist())):
+        sel = ns == n
+        per[int(n)] = {"count": int(sel.sum()), "outer_median": float(np.median(rep["outer_iters"][sel])),
+                       "outer_max": int(rep["outer_iters"][sel].max()),
+                       "relres_max": float(rep["relres"][sel].max())}
     out = {
         "metric": METRIC,
         "value": lups / t / 1e9,
@@ -620,15 +686,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 sweeps, f64 refinement",
         "data": "synthetic",
-        "config": {"workload": "aniso-Q1 batch B=256 n=255, NAG-Richardson(16), meta-MLP weights; "
-                               "refined solve to 1e-10 + K=64 unrolled fwd/adjoint training pass",
-                   "batch": B, "n": N, "m": M, "tol": TOL, "K_train": K_TRAIN, "ckpt_every": CKPT},
+        "config": {"workload": "uneven batch of 512 aniso-Q1 problems (n in {63,127,255,511,1023}, "
+                               "40/25/20/10/5 %) refined to 1e-10 with NAG-Richardson(16) and meta-MLP weights, "
+                               "+ training step B=64 n=127 (K=64 unroll, ckpt 16, hand-written adjoint, "
+                               "meta backward)",
+                   "batch": int(h.uplan.B), "points": int(h.uplan.P), "m": M, "tol": TOL,
+                   "train_batch": B_TRAIN, "train_n": N_TRAIN, "K_train": K_TRAIN, "ckpt_every": CKPT},
         "time_to_tol_s": ttol,
-        "solve": {"status": int(rep["status"]), "outer_iters_median": float(np.median(rep["outer_iters"])),
-                  "outer_iters_max": int(rep["outer_iters"].max()), "rounds_max": int(rep["rounds"].max()),
-                  "relres_max": float(rep["relres"].max()), "kernel": kstr,
-                  "tail_kernel": kernel_name(w.plan.get_tail_kernel(N))},
-        "roofline": roofline(kstr, kcfg, kt, w.P, copy_gbs),
+        "solve": {"status": int(rep["status"]), "rounds_max": int(rep["rounds"].max()),
+                  "relres_max": float(rep["relres"].max()), "per_size": per, "kernels": h.kernels(),
+                  "glups": h.solve_lups(rep) / ttol / 1e9},
+        "train": {"ms_per_step": t_train * 1e3, "glups_fwd_adjoint": h.train_lups() / t_train / 1e9,
+                  "loss_mean": float(h.loss.mean())},
+        "roofline": roofline(kstr, T, units, t_launch, copy_gbs),
         "cpu_baseline": cpu,
         "plain_fp64_gpu_loop": comparator,
     }

@@ -20,10 +20,12 @@
  *   - Every vector, weight array and gradient is a DEVICE pointer owned by the
  *     caller.  Host pointers are marked "host".  The library owns only its
  *     context, plans and internal scratch.
- *   - A batch of B instances is packed back to back in instance order; instance
- *     b has n_b x n_b interior unknowns stored row-major as u[j][i] with i (the
- *     x index) fastest and y increasing with j; h = 1/(n_b + 1).  P_tot is the
- *     sum of n_b^2.  Boundary values are never stored (they are zero).
+ *   - A batch of B instances is placed in instance order at the plan's offsets
+ *     (back to back unless rm_plan is given offsets); instance b has n_b x n_b
+ *     interior unknowns stored row-major as u[j][i] with i (the x index) fastest
+ *     and y increasing with j; h = 1/(n_b + 1).  P_tot is the length of every
+ *     vector (the sum of n_b^2 when packed).  Boundary values are never stored
+ *     (they are zero).
  *   - Weight arrays omega[B][m], alpha[B][m] are row-major; inner step s of a
  *     solve uses index i = s mod m, so omega[b][0] is applied first (the order
  *     T_m = (I - omega_m A) ... (I - omega_1 A) of eq. Chebyshev(m)T).  The
@@ -90,7 +92,7 @@ typedef struct {
   int32_t max_rounds;  /* RM_TO_TOL: refinement rounds, cap                       */
   int32_t check_every; /* RM_TO_TOL + RM_FLAG_GRAPH: iterations between polls >= 1 */
   int32_t flags;       /* RM_FLAG_* bits                                          */
-  int32_t reserved;    /* must be 0                                               */
+  int32_t hist_len;    /* RM_TO_TOL: rows of hist (outer iterations recorded)     */
   double tol;          /* RM_TO_TOL: target ||b - A x|| / ||b|| (FP64)            */
   double tol_inner;    /* RM_TO_TOL: inner relative residual that ends a round    */
   double relax;        /* RM_FLAG_SSOR: relaxation factor a, 0 < a < 2           */
@@ -119,12 +121,17 @@ typedef struct {
  * RM_EINVAL unless 0 < relax < 2. */
 #define RM_FLAG_SSOR 4
 
-/* Per-instance results of RM_TO_TOL (host arrays of length B, any may be NULL). */
+/* Per-instance results of RM_TO_TOL (host arrays, any may be NULL; length B unless
+ * stated).  history has max_rounds + 1 rows of B: row j holds
+ * rho_j = ||b - A x_j|| / ||b|| (FP64) of the refinement round j (row 0: the initial
+ * guess), the quantity the stopping rule of §2.3 tests; rows an instance did not reach
+ * hold -1. */
 typedef struct {
   int32_t* outer_iters;  /* outer iterations summed over all rounds          */
   int32_t* rounds;       /* refinement rounds used                           */
   double* relres;        /* final ||b - A x|| / ||b|| computed in FP64       */
   int32_t* status;       /* RM_OK, RM_ENOTCONV or RM_EDIVERGED per instance  */
+  double* history;       /* [max_rounds + 1][B] rho_j per round, see above   */
 } rm_report;
 
 typedef struct rm_ctx rm_ctx;
@@ -138,14 +145,20 @@ rm_status rm_create(rm_ctx** out, int32_t device, void* hip_stream);
 rm_status rm_destroy(rm_ctx* ctx);
 
 /* Build a plan for a batch (host array inst[B]).  Computes the stencil
- * coefficients of every instance in FP64 (§2.3 / §3.2), the packed offsets and
- * the tile table, and uploads them.  Rejects n < 1, n > 16384, eps outside
- * (0, 1], non-finite parameters, unknown op. */
-rm_status rm_plan(rm_ctx* ctx, int32_t B, const rm_instance* inst, rm_plan_t** out);
+ * coefficients of every instance in FP64 (§2.3 / §3.2), the offsets and the tile
+ * tables, and uploads them.  Rejects n < 1, n > 16384, eps outside (0, 1],
+ * non-finite parameters, unknown op.
+ * offsets (host int64 [B + 1], copied; NULL = packed back to back from 0): instance b
+ * occupies elements [offsets[b], offsets[b] + n_b^2) of every vector, and P_tot =
+ * offsets[B] is the length of every vector.  Needs offsets[0] >= 0 and
+ * offsets[b + 1] - offsets[b] >= n_b^2 (RM_EINVAL otherwise).  Elements outside the
+ * instances (gaps) are never read; the library may overwrite the gaps of its output
+ * vectors (x, ckpt, gradients) with unspecified values. */
+rm_status rm_plan(rm_ctx* ctx, int32_t B, const rm_instance* inst, const int64_t* offsets, rm_plan_t** out);
 rm_status rm_plan_free(rm_plan_t* plan);
 
-/* Host queries: number of instances, P_tot, and the packed offsets
- * (host array off[B + 1], off[0] = 0, off[B] = P_tot). */
+/* Host queries: number of instances, P_tot, and the offsets
+ * (host array off[B + 1], off[B] = P_tot). */
 int32_t rm_plan_batch(const rm_plan_t* plan);
 int64_t rm_plan_points(const rm_plan_t* plan);
 rm_status rm_plan_offsets(const rm_plan_t* plan, int64_t* off);
@@ -235,9 +248,15 @@ rm_status rm_residual(rm_ctx* ctx, const rm_plan_t* plan, int32_t dtype, const v
  *   run in whole outer iterations until its relative residual is <= tol_inner
  *   or max_outer is reached; x += d in FP64; stop when ||b - A x|| / ||b|| <= tol.
  *   b, x: device double [P_tot]; x holds the initial guess and receives the
- *   result.  ckpt and hist must be NULL.  rep (host) receives per-instance
- *   counts, final FP64 relative residuals and status; the call returns the
- *   worst per-instance status.  The host learns how many instances are still
+ *   result.  ckpt must be NULL.  hist: device double [opts->hist_len][B] or
+ *   NULL; row k receives ||r_j - A d||^2 of the inner solve after the instance's
+ *   k-th outer iteration counted over all rounds from 0 (r_j the round's FP32
+ *   right-hand side, so hist / ||b||^2 follows ||b - A x||^2 / ||b||^2 through
+ *   the rounds), -1 in rows it did not reach; later iterations are not
+ *   recorded.  rep (host) receives per-instance counts, final FP64 relative
+ *   residuals, status and the per-round history; the call returns the worst
+ *   per-instance status.  After an error other than RM_ENOTCONV / RM_EDIVERGED
+ *   the call still waits for what it had queued.  The host learns how many instances are still
  *   active from a word the GPU writes into pinned memory after every outer
  *   iteration; it reads each iteration's word while the next iteration is
  *   already queued (without RM_FLAG_GRAPH), or synchronises every check_every
@@ -328,8 +347,8 @@ rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
  * restart, estimated by the rotations in between) or after max_iter Arnoldi steps.
  * b, x: device double [P_tot]; x is the initial guess and receives the result.
  * rep (host, may be NULL): Arnoldi steps (outer_iters), cycles (rounds), the last true
- * relative residual and RM_OK / RM_ENOTCONV / RM_EDIVERGED per instance.  Blocks; the
- * call returns the worst per-instance status. */
+ * relative residual and RM_OK / RM_ENOTCONV / RM_EDIVERGED per instance (history is not
+ * written).  Blocks; the call returns the worst per-instance status. */
 typedef struct {
   int32_t restart;   /* Krylov dimension per cycle, 1..64 */
   int32_t max_iter;  /* Arnoldi steps per instance        */

@@ -36,7 +36,7 @@ class rm_solve_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("dtype", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("K", ctypes.c_int32), ("ckpt_every", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("hist_len", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("tol_inner", ctypes.c_double), ("relax", ctypes.c_double)]
 
 
@@ -46,7 +46,8 @@ class rm_fgmres_opts(ctypes.Structure):
 
 class rm_report(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.POINTER(ctypes.c_int32)), ("rounds", ctypes.POINTER(ctypes.c_int32)),
-                ("relres", ctypes.POINTER(ctypes.c_double)), ("status", ctypes.POINTER(ctypes.c_int32))]
+                ("relres", ctypes.POINTER(ctypes.c_double)), ("status", ctypes.POINTER(ctypes.c_int32)),
+                ("history", ctypes.POINTER(ctypes.c_double))]
 
 
 _lib = None
@@ -65,7 +66,7 @@ def load():
     sig = {
         "rm_create": (st, [ctypes.POINTER(P), I32, P]),
         "rm_destroy": (st, [P]),
-        "rm_plan": (st, [P, I32, ctypes.POINTER(rm_instance), ctypes.POINTER(P)]),
+        "rm_plan": (st, [P, I32, ctypes.POINTER(rm_instance), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(P)]),
         "rm_plan_free": (st, [P]),
         "rm_plan_batch": (I32, [P]),
         "rm_plan_points": (I64, [P]),

@@ -9,6 +9,7 @@ that it does not know that target feature, which is harmless.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -32,17 +33,21 @@ def flags():
     ]
 
 
-def build(verbose=False):
-    objs = []
+def build(verbose=False, jobs=None):
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(build_dir, src.replace(".hip", ".o"))
-        cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+    objs = [os.path.join(build_dir, src.replace(".hip", ".o")) for src in SOURCES]
+
+    def compile_one(k):
+        cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, SOURCES[k]), "-o", objs[k]]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    # one hipcc per source, at most one per host core (each takes one core)
+    jobs = jobs or max(1, min(len(SOURCES), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        list(pool.map(compile_one, range(len(SOURCES))))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

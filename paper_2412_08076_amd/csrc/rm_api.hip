@@ -755,7 +755,7 @@ rm_status wait_word(rm_ctx* ctx, hipStream_t st, unsigned want, unsigned long lo
 }
 
 rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_opts* o, const float* omega,
-                       const float* alpha, const double* b, double* x, rm_report* rep) {
+                       const float* alpha, const double* b, double* x, double* hist, rm_report* rep) {
   if (ctx->work == nullptr) {
     RM_HIP(hipStreamCreateWithFlags(&ctx->work, hipStreamNonBlocking));
     RM_HIP(hipEventCreateWithFlags(&ctx->handoff, hipEventDisableTiming));
@@ -823,6 +823,9 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   rmk::launch_fill_i32(status, 0, B, st);
   rmk::launch_fill_i32(count, 0, B, st);
   rmk::launch_fill_i32(tot, 0, B, st);
+  if (hist != nullptr) rmk::launch_fill_f64(hist, -1.0, (int64_t)o->hist_len * B, st);
+  if (rep != nullptr && rep->history != nullptr)
+    std::fill(rep->history, rep->history + (size_t)(o->max_rounds + 1) * B, -1.0);
   RM_HIP(hipMemcpyAsync(mask, mask_h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
   int flips_per_outer = 0;
   GraphHolder graph[2];  // one captured outer iteration per configuration (main, tail)
@@ -856,6 +859,7 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
       }
       const double rho = b2_h[bi] > 0.0 ? std::sqrt(r2_h[bi] / b2_h[bi]) : std::sqrt(r2_h[bi]);
       relres[bi] = rho;
+      if (rep != nullptr && rep->history != nullptr) rep->history[(size_t)j * B + bi] = rho;
       if (!std::isfinite(rho) || dst_h[bi] == RM_EDIVERGED) {
         done[bi] = 1;
         st_h[bi] = RM_EDIVERGED;
@@ -894,7 +898,8 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
                    tail));
       flips_per_outer = flips;
       rmk::launch_outer_flags(p, partial, ranges, res2, rhs2, target2, best2, since, gains, stall_min, stall_max,
-                              o->max_outer, active, count, status, n_active, ctx->host_word, seq, st);
+                              o->max_outer, active, count, status, n_active, ctx->host_word, seq, tot, hist,
+                              o->hist_len, st);
       return RM_OK;
     };
     // The iteration returns to buffer set 0, so one captured iteration can be
@@ -1162,6 +1167,7 @@ rm_status rm_create(rm_ctx** out, int32_t device, void* hip_stream) {
 rm_status rm_destroy(rm_ctx* ctx) {
   if (ctx == nullptr) return RM_OK;
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->work != nullptr) (void)hipStreamSynchronize(ctx->work);
   for (rm_plan_s* pl : ctx->plans) pl->ctx = nullptr;
   if (ctx->host_word != nullptr) (void)hipHostFree(ctx->host_word);
   if (ctx->pin != nullptr) (void)hipHostFree(ctx->pin);
@@ -1171,7 +1177,7 @@ rm_status rm_destroy(rm_ctx* ctx) {
   return RM_OK;
 }
 
-rm_status rm_plan(rm_ctx* ctx, int32_t B, const rm_instance* inst, rm_plan_t** out) {
+rm_status rm_plan(rm_ctx* ctx, int32_t B, const rm_instance* inst, const int64_t* offsets, rm_plan_t** out) {
   if (ctx == nullptr || out == nullptr) return fail(RM_EINVAL, "null context or output handle");
   if (B < 1 || inst == nullptr) return fail(RM_EINVAL, "need B >= 1 instances");
   for (int b = 0; b < B; ++b) {
@@ -1187,19 +1193,27 @@ rm_status rm_plan(rm_ctx* ctx, int32_t B, const rm_instance* inst, rm_plan_t** o
       return fail(RM_EINVAL, "instance " + std::to_string(b) + ": unknown op");
     }
   }
+  if (offsets != nullptr) {
+    // caller-chosen placement: increasing starts, each instance's n^2 points before the next
+    if (offsets[0] < 0) return fail(RM_EINVAL, "offsets[0] must be >= 0");
+    for (int b = 0; b < B; ++b)
+      if (offsets[b + 1] - offsets[b] < (int64_t)inst[b].n * inst[b].n)
+        return fail(RM_EINVAL, "offsets leave instance " + std::to_string(b) + " fewer than n^2 points");
+    if (offsets[B] > ((int64_t)1 << 40)) return fail(RM_EINVAL, "offsets beyond 2^40 points");
+  }
   RM_HIP(hipSetDevice(ctx->device));
   rm_plan_t* pl = new rm_plan_t;
   pl->ctx = ctx;
   pl->B = B;
   pl->inst.assign(inst, inst + B);
-  pl->off.assign(B + 1, 0);
+  pl->off.assign(B + 1, offsets != nullptr ? offsets[0] : 0);
   pl->coef.assign((size_t)B * 8, 0.0);
   pl->gersh.assign(B, 0.0);
   std::vector<float> coef32((size_t)B * 8, 0.f), mu((size_t)B * 2), g32(B);
   pl->insts.resize(B);
   for (int b = 0; b < B; ++b) {
     const int n = inst[b].n;
-    pl->off[b + 1] = pl->off[b] + (int64_t)n * n;
+    pl->off[b + 1] = offsets != nullptr ? offsets[b + 1] : pl->off[b] + (int64_t)n * n;
     double* c = &pl->coef[(size_t)b * 8];
     stencil_coefficients(inst[b], c);
     c[5] = c[0] != 0.0 ? 1.0 / c[0] : 0.0;  // 1/D for weighted-Jacobi preconditioning
@@ -1252,6 +1266,7 @@ rm_status rm_plan_free(rm_plan_t* plan) {
   if (plan == nullptr) return RM_OK;
   if (plan->ctx != nullptr) {
     (void)hipStreamSynchronize(plan->ctx->stream);
+    if (plan->ctx->work != nullptr) (void)hipStreamSynchronize(plan->ctx->work);
     auto& v = plan->ctx->plans;
     v.erase(std::remove(v.begin(), v.end(), plan), v.end());
   }
@@ -1337,12 +1352,22 @@ rm_status rm_solve(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, const rm_
     return fail(RM_EINVAL, "unknown dtype");
   }
   if (opts->mode == RM_TO_TOL) {
-    if (ckpt != nullptr || hist != nullptr) return fail(RM_EINVAL, "RM_TO_TOL takes no ckpt or hist");
+    if (ckpt != nullptr) return fail(RM_EINVAL, "RM_TO_TOL takes no ckpt");
+    if (opts->hist_len < 0 || (hist != nullptr && opts->hist_len == 0))
+      return fail(RM_EINVAL, "RM_TO_TOL with hist needs hist_len >= 1 (and hist_len >= 0 always)");
     if (!(opts->tol > 0.0) || !(opts->tol_inner > 0.0 && opts->tol_inner < 1.0))
       return fail(RM_EINVAL, "need tol > 0 and 0 < tol_inner < 1");
     if (opts->max_outer < 1 || opts->max_rounds < 1 || opts->check_every < 1)
       return fail(RM_EINVAL, "max_outer, max_rounds and check_every must be >= 1");
-    return solve_to_tol(ctx, pl, method, opts, omega, alpha, (const double*)b, (double*)x, rep);
+    const rm_status s = solve_to_tol(ctx, pl, method, opts, omega, alpha, (const double*)b, (double*)x, hist, rep);
+    if (s != RM_OK && s != RM_ENOTCONV && s != RM_EDIVERGED && ctx->work != nullptr) {
+      // an error left the round loop early: wait for what it had queued on the solve's
+      // stream, so that the caller may free x and b, or the context, once this returns
+      const std::string keep = g_last_error;
+      (void)hipStreamSynchronize(ctx->work);
+      g_last_error = keep;
+    }
+    return s;
   }
   return fail(RM_EINVAL, "unknown mode");
 }

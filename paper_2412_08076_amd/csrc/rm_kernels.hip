@@ -328,7 +328,8 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
     const double* __restrict__ rhs2, const double* __restrict__ target2, double* __restrict__ best2,
     int* __restrict__ since, int* __restrict__ gains, int stall_min, int stall_max, int cap,
     int* __restrict__ active, int* __restrict__ outer_count, int* __restrict__ status, int* __restrict__ n_active,
-    unsigned long long* __restrict__ host_word, unsigned seq) {
+    unsigned long long* __restrict__ host_word, unsigned seq, const int* __restrict__ tot, double* __restrict__ hist,
+    int hist_len) {
   __shared__ int kept[16];
   int mine = 0;
   for (int b = threadIdx.x; b < p.B; b += blockDim.x) {
@@ -343,6 +344,10 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
     res2[b] = r2;
     if (act == 0) continue;
     outer_count[b] = cnt;
+    if (hist != nullptr) {
+      const int k = tot[b] + cnt - 1;  // outer iterations of this instance over all rounds, from 0
+      if (k < hist_len) hist[(int64_t)k * p.B + b] = r2;
+    }
     int keep = 1;
     if (!(r2 <= 1e12 * rh)) {  // NaN, Inf or growth
       status[b] = 5;           // RM_EDIVERGED
@@ -769,10 +774,12 @@ void launch_refine_update(const PlanDev& p, double* x, const float* d0, const fl
 void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ranges, double* res2, const double* rhs2,
                         const double* target2, double* best2, int* since, int* gains, int stall_min, int stall_max,
                         int cap, int* active, int* outer_count, int* status, int* n_active,
-                        unsigned long long* host_word, unsigned seq, hipStream_t st) {
+                        unsigned long long* host_word, unsigned seq, const int* tot, double* hist, int hist_len,
+                        hipStream_t st) {
   const int threads = 64 * std::min(16, std::max(1, (p.B + 63) / 64));
   hipLaunchKernelGGL(k_outer_flags, dim3(1), dim3(threads), 0, st, p, partial2, ranges, res2, rhs2, target2, best2,
-                     since, gains, stall_min, stall_max, cap, active, outer_count, status, n_active, host_word, seq);
+                     since, gains, stall_min, stall_max, cap, active, outer_count, status, n_active, host_word, seq,
+                     tot, hist, hist_len);
 }
 
 void launch_round_start(int B, const double* staged, const double* r2, double* rhs2, double* best2, double* target2,

@@ -89,7 +89,9 @@ class Plan:
     """rm_plan: a batch of instances.  ``n`` list of sizes; Q1 instances take eps and
     theta, Helmholtz instances take kappa."""
 
-    def __init__(self, ctx, n, eps=None, theta=None, kappa=None, op=RM_Q1_ANISO):
+    def __init__(self, ctx, n, eps=None, theta=None, kappa=None, op=RM_Q1_ANISO, offsets=None):
+        """offsets: optional B + 1 element offsets of the instances in every vector
+        (rm_plan; None = packed back to back)."""
         self.ctx = ctx
         self.lib = ctx.lib
         B = len(n)
@@ -100,8 +102,13 @@ class Plan:
             arr[b].eps = float(eps[b]) if eps is not None else 1.0
             arr[b].theta = float(theta[b]) if theta is not None else 0.0
             arr[b].kappa = float(kappa[b]) if kappa is not None else 0.0
+        off_in = None
+        if offsets is not None:
+            if len(offsets) != B + 1:
+                raise ValueError(f"offsets must have {B + 1} entries")
+            off_in = (ctypes.c_int64 * (B + 1))(*[int(o) for o in offsets])
         h = ctypes.c_void_p()
-        _check(self.lib.rm_plan(ctx.handle, B, arr, ctypes.byref(h)), "rm_plan")
+        _check(self.lib.rm_plan(ctx.handle, B, arr, off_in, ctypes.byref(h)), "rm_plan")
         self.handle = h
         ctx._plans.add(self)
         self.B = B
@@ -168,14 +175,15 @@ class Plan:
 
 
 def solve_opts(mode=RM_UNROLL, dtype=RM_F32, m=16, K=0, ckpt_every=0, max_outer=100000, max_rounds=8,
-               check_every=4, tol=1e-10, tol_inner=1e-3, graph=False, jacobi=False, ssor=None):
-    """rm_solve_opts; ssor = the SSOR relaxation factor (None: no SSOR preconditioning)."""
+               check_every=4, tol=1e-10, tol_inner=1e-3, graph=False, jacobi=False, ssor=None, hist_len=0):
+    """rm_solve_opts; ssor = the SSOR relaxation factor (None: no SSOR preconditioning);
+    hist_len = rows of the refined solve's per-outer-iteration history."""
     o = _lib.rm_solve_opts()
     o.mode, o.dtype, o.m, o.K, o.ckpt_every = mode, dtype, m, K, ckpt_every
     o.max_outer, o.max_rounds, o.check_every = max_outer, max_rounds, check_every
     o.flags = ((_lib.RM_FLAG_GRAPH if graph else 0) | (_lib.RM_FLAG_JACOBI if jacobi else 0)
                | (_lib.RM_FLAG_SSOR if ssor is not None else 0))
-    o.reserved = 0
+    o.hist_len = hist_len
     o.tol, o.tol_inner = tol, tol_inner
     o.relax = 1.0 if ssor is None else float(ssor)
     return o
@@ -209,7 +217,9 @@ def rm_residual(ctx, plan, b, x, r=None, r2=None, b2=None, rel2=None):
 
 def rm_solve(ctx, plan, method, opts, omega, alpha, b, x, ckpt=None, hist=None):
     """UNROLL: returns None (asynchronous).  TO_TOL: blocks and returns a dict of
-    per-instance numpy arrays (outer_iters, rounds, relres, status) plus 'status'."""
+    per-instance numpy arrays (outer_iters, rounds, relres, inst_status and history
+    [max_rounds + 1, B]) plus 'status'; hist (TO_TOL) is a device double tensor of
+    opts.hist_len * B elements."""
     m = opts.m
     na = 2 if method == RM_NAGEX else 1
     om = _ptr(omega, torch.float32, plan.B * m, "omega")
@@ -229,10 +239,13 @@ def rm_solve(ctx, plan, method, opts, omega, alpha, b, x, ckpt=None, hist=None):
     rounds = (ctypes.c_int32 * B)()
     relres = (ctypes.c_double * B)()
     status = (ctypes.c_int32 * B)()
-    rep = _lib.rm_report(outer, rounds, relres, status)
+    nh = (opts.max_rounds + 1) * B
+    history = (ctypes.c_double * nh)()
+    rep = _lib.rm_report(outer, rounds, relres, status, history)
+    hs = _ptr(hist, torch.float64, opts.hist_len * B, "hist") if hist is not None else None
     st = ctx.lib.rm_solve(ctx.handle, plan.handle, method, ctypes.byref(opts), om, al,
                           _ptr(b, torch.float64, plan.P, "b"), _ptr(x, torch.float64, plan.P, "x"),
-                          None, None, ctypes.byref(rep))
+                          None, hs, ctypes.byref(rep))
     if st not in (RM_OK, RM_ENOTCONV, RM_EDIVERGED):
         _check(st, "rm_solve")
     return {
@@ -241,6 +254,7 @@ def rm_solve(ctx, plan, method, opts, omega, alpha, b, x, ckpt=None, hist=None):
         "rounds": np.frombuffer(rounds, dtype=np.int32).copy(),
         "relres": np.frombuffer(relres, dtype=np.float64).copy(),
         "inst_status": np.frombuffer(status, dtype=np.int32).copy(),
+        "history": np.frombuffer(history, dtype=np.float64).reshape(opts.max_rounds + 1, B).copy(),
     }
 
 
@@ -309,7 +323,7 @@ def rm_fgmres(ctx, plan, b, x, restart=20, max_iter=200, tol=1e-6, method=RM_NAG
     rounds = (ctypes.c_int32 * B)()
     relres = (ctypes.c_double * B)()
     status = (ctypes.c_int32 * B)()
-    rep = _lib.rm_report(outer, rounds, relres, status)
+    rep = _lib.rm_report(outer, rounds, relres, status, None)
     st = ctx.lib.rm_fgmres(ctx.handle, plan.handle, ctypes.byref(fo), method,
                            ctypes.byref(inner) if inner is not None else None, om, al, sy,
                            _ptr(b, torch.float64, plan.P, "b"), _ptr(x, torch.float64, plan.P, "x"),

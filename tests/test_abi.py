@@ -50,7 +50,7 @@ def test_host_only_entry_points(lib):
     h = ctypes.c_void_p()
     inst = (_lib.rm_instance * 1)()
     inst[0].n, inst[0].op, inst[0].eps = 8, 0, 0.5
-    assert lib.rm_plan(None, 1, inst, ctypes.byref(h)) == _lib.RM_EINVAL
+    assert lib.rm_plan(None, 1, inst, None, ctypes.byref(h)) == _lib.RM_EINVAL
     assert lib.rm_create(None, 0, None) == _lib.RM_EINVAL
     opts = _lib.rm_solve_opts()
     assert lib.rm_solve(None, None, 1, ctypes.byref(opts), None, None, None, None, None, None, None) == \

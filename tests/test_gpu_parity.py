@@ -3,11 +3,14 @@
 Tolerances
   FP64 sweeps       a few ulp per step times the cycle's rounding amplification:
                     relative 1e-9 on iterates after 50 cycles of Chebyshev(8).
-  FP32 sweeps       ||A (x_gpu - x_oracle)|| / ||f|| <= 1e-5 after K steps (same weights).
+  FP32 sweeps       element-wise max|x_gpu - u_oracle| <= 2 eps32 K max|u_oracle| after K
+                    steps with the same weights (tests.gpu_helpers.FP32_C), and
+                    ||A (x_gpu - x_oracle)|| / ||f|| <= 1e-5.
   Refined (FP64)    reported relres <= tol; the oracle's FP64 residual of the GPU's x
                     agrees with the reported one to 1e-12 (absolute, relative to ||b||);
                     ||x - x*|| / ||x*|| <= kappa * tol.
-  Adjoint (FP32)    loss to 1e-5 relative, gradients to 1e-4 of their max magnitude.
+  Adjoint (FP32)    loss to 1e-5 relative, gradients (also those of the meta network's
+                    parameters) element-wise to 1e-4 of their max magnitude.
 """
 import numpy as np
 import pytest
@@ -15,7 +18,7 @@ import torch
 
 from oracle import adjoint, iterate, meta, problem, refine, spectra, weights
 from synthetic import Batch, meta_params, pack, random_batch, single_isotropic, unpack_vec
-from tests.gpu_helpers import dev, host, need_gpu, oracle_coef, plan_for, say
+from tests.gpu_helpers import assert_fp32_close, dev, host, need_gpu, oracle_coef, plan_for, say
 
 pytestmark = pytest.mark.gpu
 
@@ -149,6 +152,7 @@ def test_fp32_unroll_parity(ctx, method):
         fn = np.linalg.norm(f32)
         err = np.linalg.norm(problem.apply_A(c, xs[b] - u)) / fn
         assert err <= 1e-5, (b, ns[b], err)
+        assert_fp32_close(xs[b], u, K, (method, ns[b]))
         assert np.allclose(np.sqrt(hs[:, b]) / fn, h, rtol=1e-4, atol=1e-6)
 
 
@@ -388,7 +392,7 @@ def test_training_step_gradient(ctx):
     assert abs(J.item() - np.mean(Ls)) <= 1e-5 * np.mean(Ls)
     want = meta.backward(params.astype(np.float64), m, cache, gw, ga)
     got = host(pt.grad)
-    assert np.linalg.norm(got - want) <= 1e-3 * np.linalg.norm(want)
+    assert np.max(np.abs(got - want)) <= 1e-4 * np.max(np.abs(want))
 
 
 def test_determinism(ctx):
@@ -466,6 +470,7 @@ def test_config2_full_size_sampled(ctx):
         u, _ = iterate.run(iterate.NAG, c, f32, omh[b], K, alpha=alh[b])
         got = xh[batch.offsets[b]:batch.offsets[b + 1]].reshape(255, 255)
         assert np.linalg.norm(problem.apply_A(c, got - u)) / np.linalg.norm(f32) <= 1e-5
+        assert_fp32_close(got, u, K, ("n=255 meta weights", b))
     x64 = torch.zeros(plan.P, dtype=torch.float64, device="cuda")
     opts = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=1e-10, tol_inner=1e-4, max_outer=20000, max_rounds=10,
                          check_every=4)
@@ -507,6 +512,7 @@ def test_uneven_batch_sampled(ctx):
         fn = np.linalg.norm(f32)
         err = np.linalg.norm(problem.apply_A(c, xs[b] - u)) / fn
         assert err <= 1e-5, (b, ns[b], err)
+        assert_fp32_close(xs[b], u, K, ("uneven", ns[b]))
         assert np.allclose(np.sqrt(hs[:, b]) / fn, h, rtol=1e-4)
 
 
@@ -577,6 +583,7 @@ def test_fp32_unroll_all_schemes(ctx, name, jacobi):
         u, _ = iterate.run(name, c, f32, om[b].astype(np.float64), K, binv=binv, **kw)
         err = np.linalg.norm(problem.apply_A(c, xs[b] - u)) / np.linalg.norm(f32)
         assert err <= 1e-5, (name, jacobi, b, err)
+        assert_fp32_close(xs[b], u, K, (name, jacobi, ns[b]))
 
 
 @pytest.mark.parametrize("name,jacobi", SCHEMES)
@@ -668,7 +675,7 @@ def test_context_destroyed_before_its_plans():
     plans = []
     for _ in range(2):
         p = ctypes.c_void_p()
-        assert lib.rm_plan(h, 2, inst, ctypes.byref(p)) == rm.RM_OK
+        assert lib.rm_plan(h, 2, inst, None, ctypes.byref(p)) == rm.RM_OK
         plans.append(p)
     assert lib.rm_plan_free(plans[0]) == rm.RM_OK
     assert lib.rm_destroy(h) == rm.RM_OK

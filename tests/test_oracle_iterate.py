@@ -249,3 +249,33 @@ def test_amplification_diagnostic():
     assert nat >= abs(1 - w[-1] * lmax) - 1e-12
     assert lej < nat
     assert weights.amplification([0.5 / lmax], lmin, lmax) == 1.0
+
+
+def test_amplification_closed_form_two_weights():
+    # m = 2: the tail after step 1 is |1 - w2 lam|, linear in lam, so its maximum over
+    # [lmin, lmax] sits at an end; after step 2 the tail is empty (factor 1).  With w2 = 0.5
+    # on [1, 10] that is |1 - 5| = 4.  The whole product (1 - 0.3 lam)(1 - 0.5 lam) reaches
+    # 8 at lam = 10, so a tail that wrongly starts at step j instead of j + 1 reads 8.
+    assert abs(weights.amplification([0.3, 0.5], 1.0, 10.0) - 4.0) < 1e-12
+
+
+def test_amplification_closed_form_three_weights():
+    # m = 3, w = (0.5, 1.0, 0.1) on [0.2, 9]:
+    #   tail after step 1: q(lam) = (1 - lam)(1 - 0.1 lam), vertex at lam = 1.1 / 0.2 = 5.5
+    #     where |q| = 4.5 * 0.45 = 2.025; at the ends 0.784 and 0.8;
+    #   tail after step 2: |1 - 0.1 lam| <= 0.98;  after step 3: 1.
+    # The full product (one step too many) reaches 3.5 * 8 * 0.1 = 2.8 at lam = 9.
+    got = weights.amplification([0.5, 1.0, 0.1], 0.2, 9.0)
+    assert abs(got - 2.025) < 1e-7
+
+
+def test_leja_order_hand_computed():
+    # nodes 1/w = {1, 2, 4, 8}: start at 8; then the farthest from 8 is 1 (distance 7);
+    # then products |x - 8||x - 1|: 2 -> 6, 4 -> 12, so 4; then 2.
+    got = weights.leja_order([0.5, 0.125, 1.0, 0.25])
+    assert np.array_equal(1.0 / np.asarray(got), [8.0, 1.0, 4.0, 2.0])
+    # nodes {0.5, 1.5, 2, 7, 9}: 9; 0.5 (8.5); products with {9, 0.5}: 1.5 -> 7.5,
+    # 2 -> 10.5, 7 -> 13, so 7; with {9, 0.5, 7}: 1.5 -> 41.25, 2 -> 52.5, so 2; then 1.5.
+    nodes = np.array([2.0, 9.0, 0.5, 1.5, 7.0])
+    got = weights.leja_order(1.0 / nodes)
+    assert np.allclose(1.0 / np.asarray(got), [9.0, 0.5, 7.0, 2.0, 1.5], rtol=0, atol=1e-12)
