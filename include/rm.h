@@ -232,6 +232,22 @@ rm_status rm_apply_A(rm_ctx* ctx, const rm_plan_t* plan, int32_t dtype, const vo
 rm_status rm_residual(rm_ctx* ctx, const rm_plan_t* plan, int32_t dtype, const void* b,
                       const void* x, void* r, double* r2, double* b2, float* rel2);
 
+/* rm_residual without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results (bit for bit) and asynchrony as rm_residual;
+ * the plan must already exist (rm_plan allocates its tables).  Its per-tile partial
+ * sums go to a file-scope device array of RM_NOALLOC_MAX_TILES * 2 doubles (1 MiB)
+ * that each GPU the library runs on holds until the process ends; its address is
+ * looked up once per device by rm_create.  A plan has one tile per 64 x 32 block of
+ * every instance (ceil(n / 64) * ceil(n / 32) for instance n) plus padding to a
+ * multiple of 8: a plan with more than RM_NOALLOC_MAX_TILES tiles gives RM_EINVAL
+ * before anything is launched.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's partials: calls that overlap on one GPU (other streams,
+ * other contexts, other host threads) race and must be serialised by the caller. */
+#define RM_NOALLOC_MAX_TILES 65536
+rm_status rm_residual_noalloc(rm_ctx* ctx, const rm_plan_t* plan, int32_t dtype, const void* b,
+                              const void* x, void* r, double* r2, double* b2, float* rel2);
+
 /* Batched Richardson(m) / NAG-Richardson(m) (Table 1, last column; §2.3 evaluation).
  *
  * RM_UNROLL (asynchronous): K inner steps from u = x (in), v = 0, in opts->dtype.

@@ -20,7 +20,7 @@ EXPORTS = [
     "rm_create", "rm_destroy", "rm_plan", "rm_plan_free", "rm_plan_batch", "rm_plan_points",
     "rm_plan_offsets", "rm_plan_coefficients", "rm_plan_set_kernel", "rm_plan_get_kernel",
     "rm_plan_set_tail_kernel", "rm_plan_get_tail_kernel", "rm_plan_set_tail_switch", "rm_tune",
-    "rm_apply_A", "rm_residual", "rm_solve",
+    "rm_apply_A", "rm_residual", "rm_residual_noalloc", "rm_solve",
     "rm_solve_adjoint", "rm_plan_coarse_points", "rm_plan_coarse_offsets", "rm_twogrid_solve",
     "rm_twogrid_adjoint", "rm_fgmres", "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count",
     "rm_status_string", "rm_last_error",
@@ -80,6 +80,7 @@ def load():
         "rm_tune": (st, [P, P, I32, I32, P, P, P, ctypes.c_char_p, ctypes.POINTER(D)]),
         "rm_apply_A": (st, [P, P, I32, P, P]),
         "rm_residual": (st, [P, P, I32, P, P, P, P, P, P]),
+        "rm_residual_noalloc": (st, [P, P, I32, P, P, P, P, P, P]),
         "rm_solve": (st, [P, P, I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P, P,
                           ctypes.POINTER(rm_report)]),
         "rm_solve_adjoint": (st, [P, P, I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P, P, P, P, P, P]),

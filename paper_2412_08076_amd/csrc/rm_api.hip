@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -93,6 +94,8 @@ struct rm_ctx {
   // plans built on this context; rm_destroy detaches them so that a later
   // rm_plan_free does not reach the freed context
   std::vector<rm_plan_s*> plans;
+  // this device's address of the file-scope scratch array of rm_residual_noalloc
+  double* noalloc_scratch = nullptr;
 };
 
 struct rm_plan_s {
@@ -1130,6 +1133,39 @@ std::string tune_key(const char* arch, const rm_plan_s::ClassExec& c, int m, int
 
 extern "C" {
 
+// ---------------------------------------------------------------------------
+// Scratch of rm_residual_noalloc: the per-tile partial sums live in a file-scope device
+// array (one copy per GPU, held until the process ends) instead of plan scratch.  In
+// host code `scratch` names a host-side stand-in, never the device memory: its device
+// address is taken once per device with hipGetSymbolAddress and kept in
+// g_noalloc_addr, and only that address is passed to kernels.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) double scratch[RM_NOALLOC_MAX_TILES * 2];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_addr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (which must be current), looked up on
+// the first call for that device.
+rm_status noalloc_address(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(RM_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_addr[device] == nullptr) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      (void)hipGetLastError();
+      return fail(RM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_noalloc_addr[device] = static_cast<double*>(ptr);
+  }
+  *out = g_noalloc_addr[device];
+  return RM_OK;
+}
+}  // namespace
+
 const char* rm_status_string(rm_status s) {
   switch (s) {
     case RM_OK: return "ok";
@@ -1160,6 +1196,12 @@ rm_status rm_create(rm_ctx** out, int32_t device, void* hip_stream) {
     return fail(RM_ENOMEM, "pinned host allocation failed");
   }
   __atomic_store_n(c->host_word, 0ull, __ATOMIC_RELEASE);
+  const rm_status sa = noalloc_address(device, &c->noalloc_scratch);
+  if (sa != RM_OK) {
+    (void)hipHostFree(c->host_word);
+    delete c;
+    return sa;
+  }
   *out = c;
   return RM_OK;
 }
@@ -1324,6 +1366,29 @@ rm_status rm_residual(rm_ctx* ctx, const rm_plan_t* plan, int32_t dtype, const v
                                  nullptr, ctx->stream);
   else
     return fail(RM_EINVAL, "unknown dtype");
+  if (r2 != nullptr || b2 != nullptr || rel2 != nullptr)
+    rmk::launch_reduce_partials(p, part, r2, b2, 1, rel2, ctx->stream);
+  return last_launch();
+}
+
+rm_status rm_residual_noalloc(rm_ctx* ctx, const rm_plan_t* plan, int32_t dtype, const void* b, const void* x,
+                              void* r, double* r2, double* b2, float* rel2) {
+  RM_TRY(check_ctx_plan(ctx, plan));
+  if (b == nullptr || x == nullptr) return fail(RM_EINVAL, "null vector");
+  if (r != nullptr && r == x) return fail(RM_EINVAL, "r and x must not overlap");
+  if (dtype != RM_F32 && dtype != RM_F64) return fail(RM_EINVAL, "unknown dtype");
+  if (plan->tiles.size() > (size_t)RM_NOALLOC_MAX_TILES)
+    return fail(RM_EINVAL, "plan has " + std::to_string(plan->tiles.size()) + " tiles; rm_residual_noalloc holds " +
+                               std::to_string(RM_NOALLOC_MAX_TILES));
+  if (ctx->noalloc_scratch == nullptr) return fail(RM_EHIP, "no scratch address for this context's device");
+  const PlanDev p = plan->dev();
+  double* part = ctx->noalloc_scratch;  // every used slot is written by the residual launch before it is read
+  if (dtype == RM_F32)
+    rmk::launch_residual<float>(p, p.tiles, p.ntiles, (const float*)b, (const float*)x, (float*)r, part, nullptr,
+                                ctx->stream);
+  else
+    rmk::launch_residual<double>(p, p.tiles, p.ntiles, (const double*)b, (const double*)x, (double*)r, part,
+                                 nullptr, ctx->stream);
   if (r2 != nullptr || b2 != nullptr || rel2 != nullptr)
     rmk::launch_reduce_partials(p, part, r2, b2, 1, rel2, ctx->stream);
   return last_launch();
