@@ -29,6 +29,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GLUP/s (stencil updates/s) fwd+adjoint, batched; time to 1e-10 rel residual"
 M, K_TRAIN, CKPT, TOL = 16, 64, 16, 1e-10
+# refined solve: each round's FP32 inner solve stops at 5 % of its right-hand side (it
+# drifts from the FP64 trajectory a little below that at n >= 511), at most 16 rounds
+TOL_INNER, MAX_ROUNDS = 0.05, 16
 B_TRAIN, N_TRAIN = 64, 127
 HBM_PEAK_GBS = 8000.0
 # published MI355X vector FP32 peak (counts packed FP32 FMAs)
@@ -238,8 +241,8 @@ class Headline:
         self.uom = torch.empty(Bu * M, dtype=torch.float32, device=dev)
         self.ual = torch.empty_like(self.uom)
         self.ux = torch.zeros(self.uplan.P, dtype=torch.float64, device=dev)
-        self.opts_tol = rm.solve_opts(mode=rm.RM_TO_TOL, m=M, tol=TOL, tol_inner=1e-3, max_outer=20000,
-                                      max_rounds=10, check_every=8)
+        self.opts_tol = rm.solve_opts(mode=rm.RM_TO_TOL, m=M, tol=TOL, tol_inner=TOL_INNER, max_outer=20000,
+                                      max_rounds=MAX_ROUNDS, check_every=8)
         # (2) the training batch
         self.tb = aniso_batch(B_TRAIN, N_TRAIN, seed=3)
         self.tplan = rm.Plan(self.ctx, self.tb.n, eps=self.tb.eps, theta=self.tb.theta)
@@ -435,7 +438,7 @@ def secondary_workload(name, tune_cache):
     out.update({"points": P, "unroll_glups": K * P / t / 1e9, "unroll_us_per_step": t / K * 1e6})
     b64 = torch.as_tensor(batch.f_packed()).cuda()
     x64 = torch.zeros_like(b64)
-    o = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=TOL, tol_inner=1e-3, max_outer=20000, max_rounds=10,
+    o = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=TOL, tol_inner=TOL_INNER, max_outer=20000, max_rounds=MAX_ROUNDS,
                       check_every=8)
     t0 = time.perf_counter(); rep = rm.rm_solve(ctx, plan, rm.RM_NAG, o, om, al, b64, x64)
     tt = time.perf_counter() - t0
@@ -476,7 +479,7 @@ def ssor_workload(ctx, m=3, relax=1.0, w=1.2, a=0.96):
     t_step = e0.elapsed_time(e1) / 1e3 / K
     b64 = torch.as_tensor(batch.f_packed()).cuda()
     x64 = torch.zeros_like(b64)
-    o = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=TOL, tol_inner=1e-3, max_outer=20000, max_rounds=10, check_every=8,
+    o = rm.solve_opts(mode=rm.RM_TO_TOL, m=m, tol=TOL, tol_inner=TOL_INNER, max_outer=20000, max_rounds=MAX_ROUNDS, check_every=8,
                       ssor=relax)
     t0 = time.perf_counter(); rep = rm.rm_solve(ctx, plan, rm.RM_NAGEX, o, om, al, b64, x64)
     tt = time.perf_counter() - t0

@@ -197,11 +197,12 @@ rm_status rm_plan_get_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, i
  * them, a tiled launch costs in proportion, so after rm_plan_set_kernel the tail is
  * the main configuration, or the cost model's best tiled variant when the main one
  * is row-streaming.  Same arguments and errors as rm_plan_set_kernel (shape >= 0).
- * rm_plan_set_tail_switch: active fraction below which the tails run (frac <= 1;
- * 0: never; 1: always; < 0, the default: the ratio rm_tune measured between the
- * main configuration's launch with one instance active and the tail's with all
- * active, or 0.35 before tuning).  Results do not depend on the switch: every
- * configuration computes the same iterates. */
+ * Each size class switches on its own, from the count of its instances still active.
+ * rm_plan_set_tail_switch: fraction of a class's instances still active below which
+ * its tail runs, for every class (frac <= 1; 0: never; 1: always; < 0, the default:
+ * per class, the ratio rm_tune measured between the main configuration's launch with
+ * one instance active and the tail's with all active, or 0.35 before tuning).  Results
+ * do not depend on the switch: every configuration computes the same iterates. */
 rm_status rm_plan_set_tail_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int32_t T, int32_t cw);
 rm_status rm_plan_get_tail_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, int32_t* T,
                                   int32_t* cw);

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -96,6 +97,10 @@ struct rm_ctx {
   std::vector<rm_plan_s*> plans;
   // this device's address of the file-scope scratch array of rm_residual_noalloc
   double* noalloc_scratch = nullptr;
+  // pinned and coherent: active instances per size class, written by the refined solve's
+  // bookkeeping launches before the word above (grown on demand)
+  int* host_cnt = nullptr;
+  size_t host_cnt_n = 0;
 };
 
 struct rm_plan_s {
@@ -128,7 +133,7 @@ struct rm_plan_s {
     int tshape = 0, tT = 1, tcw = 64;
     DevBuf ttiles;
     int tntiles = 0;
-    // Row windows for the reverse steps of the adjoint (n <= kStreamMaxN), whatever the
+    // Row windows for the reverse steps of the adjoint (n <= kAdjStreamMaxN), whatever the
     // forward configuration: rcw rows each, overlapping by kAdjMaxT + 1.
     int rcw = 0;
     DevBuf rtiles;
@@ -143,7 +148,8 @@ struct rm_plan_s {
   double relax = 1.0;
   std::vector<ClassExec> classes;
   DevBuf d_ranges;  // int [B][2]: slot range of each instance over all class tables
-  DevBuf d_tranges; // the same over the tail tables
+  DevBuf d_tranges; // the same over the tail tables (slots after those of the main tables)
+  DevBuf d_cls;     // int [B]: size class of each instance
   DevBuf d_rranges; // the same over the reverse-step tables
   int nslots = 0;
   double tail_frac = -1.0;  // active fraction below which the refined solve uses the tails (< 0: measured)
@@ -182,7 +188,7 @@ struct rm_plan_s {
   }
   ~rm_plan_s() {
     for (DevBuf* b : {&d_tiles, &d_inst, &d_coef32, &d_coef64, &d_mu, &d_gersh, &partial, &red, &flags, &vecA,
-                      &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges, &d_tranges, &d_rranges, &tg.d_inst,
+                      &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges, &d_tranges, &d_rranges, &d_cls, &tg.d_inst,
                       &tg.d_rtiles, &tg.d_groups, &tg.d_tw, &tg.c0, &tg.c1, &tg.shat, &tg.fine2,
                       &tg.zero, &fg.V, &fg.Z, &fg.w, &fg.t, &fg.b32, &fg.dbl, &fg.ints, &fg.partial})
       b->release();
@@ -330,9 +336,9 @@ constexpr int kTs[] = {2, 4, 8, 16, 32};
 std::vector<int> candidate_widths(int n, int v, int T) {
   std::vector<int> out;
   if (v == kStreamShape) {
-    // windows for 1, 2, 3, 4, 6 or 8 row segments per instance
+    // windows for 1 to 10, 12 or 16 row segments per instance
     const int h = T + 1;
-    for (int S : {1, 2, 3, 4, 6, 8}) {
+    for (int S : {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16}) {
       const int len = S == 1 ? n : (n + 2 * (S - 1) * h + S - 1) / S;
       int tx, ty;
       if (class_geometry(n, v, T, len, tx, ty) && ty == S && std::find(out.begin(), out.end(), len) == out.end())
@@ -453,13 +459,19 @@ int reverse_window(int n, int count) {
 rm_status build_exec(rm_plan_t* pl, hipStream_t st) {
   if (!pl->exec_dirty) return RM_OK;
   std::vector<int> ranges((size_t)pl->B * 2, 0), tranges((size_t)pl->B * 2, 0), rranges((size_t)pl->B * 2, 0);
-  int slot = 0, tslot = 0, rslot = 0;
-  for (auto& c : pl->classes) {
-    RM_TRY(build_table(c, c.shape, c.T, c.cw, slot, ranges, c.tiles, c.ntiles, st));
+  // main and tail tables number their residual slots in one sequence, so that one outer
+  // iteration may run some classes in their main and others in their tail configuration
+  int slot = 0, rslot = 0;
+  for (auto& c : pl->classes) RM_TRY(build_table(c, c.shape, c.T, c.cw, slot, ranges, c.tiles, c.ntiles, st));
+  int tslot = slot;
+  std::vector<int> cls((size_t)pl->B, 0);
+  for (size_t ci = 0; ci < pl->classes.size(); ++ci) {
+    auto& c = pl->classes[ci];
+    for (int b : c.insts) cls[b] = (int)ci;
     RM_TRY(build_table(c, c.tshape, c.tT, c.tcw, tslot, tranges, c.ttiles, c.tntiles, st));
     c.rcw = 0;
     c.rntiles = 0;
-    if (c.n <= rmk::kStreamMaxN) {
+    if (c.n <= rmk::kAdjStreamMaxN) {
       c.rcw = reverse_window(c.n, (int)c.insts.size());
       RM_TRY(build_table(c, kStreamShape, rmk::kAdjMaxT, c.rcw, rslot, rranges, c.rtiles, c.rntiles, st));
     }
@@ -471,6 +483,8 @@ rm_status build_exec(rm_plan_t* pl, hipStream_t st) {
   RM_HIP(hipMemcpy(pl->d_ranges.ptr, ranges.data(), ranges.size() * sizeof(int), hipMemcpyHostToDevice));
   RM_TRY(pl->d_tranges.ensure(tranges.size() * sizeof(int), st));
   RM_HIP(hipMemcpy(pl->d_tranges.ptr, tranges.data(), tranges.size() * sizeof(int), hipMemcpyHostToDevice));
+  RM_TRY(pl->d_cls.ensure(cls.size() * sizeof(int), st));
+  RM_HIP(hipMemcpy(pl->d_cls.ptr, cls.data(), cls.size() * sizeof(int), hipMemcpyHostToDevice));
   pl->exec_dirty = false;
   return RM_OK;
 }
@@ -580,12 +594,16 @@ void set_precond(rm_plan_t* pl, const rm_solve_opts* o) {
 // switches configurations flips the same way throughout.
 // When res_partial is given, the residual ||f - A u||^2 of the final iterate is
 // left per tile in res_partial and *res_ranges tells the reduction which slots
-// belong to which instance.  `only_class` >= 0 restricts the launches to one
-// size class (autotuning); `tail` selects the classes' tail configurations.
+// belong to which instance (the main tables' ranges; classes in their tail
+// configuration use the tail tables' ranges, see uses_tail).  `only_class` >= 0
+// restricts the launches to one size class (autotuning); bit c of `tail` selects the
+// tail configuration of class c (classes from 64 on always run their main one).
+bool uses_tail(unsigned long long tail, size_t ci) { return ci < 64 && ((tail >> ci) & 1ull) != 0; }
+
 rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int nsteps, const float* omega,
                 const float* alpha, const float* f, float* const us[2], float* const vs[2], int& cur, int& flips,
                 const int* active, double* res_partial, const int** res_ranges, int only_class = -1,
-                bool tail = false) {
+                unsigned long long tail = 0) {
   const PlanDev p = pl->dev();
   if (nsteps <= 0) return RM_OK;
   if (!blocked(pl)) {
@@ -620,7 +638,7 @@ rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int ns
   int L = 0;
   for (size_t ci = 0; ci < pl->classes.size(); ++ci) {
     if (only_class >= 0 && (int)ci != only_class) continue;
-    const int T = tail ? pl->classes[ci].tT : pl->classes[ci].T;
+    const int T = uses_tail(tail, ci) ? pl->classes[ci].tT : pl->classes[ci].T;
     int lc = (nsteps + T - 1) / T;
     if ((lc & 1) != par) ++lc;
     for (int j = 0; j < lc; ++j) chunks[ci].push_back(nsteps / lc + (j < nsteps % lc ? 1 : 0));
@@ -635,13 +653,13 @@ rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int ns
       for (int q = 0; q < j; ++q) s += chunks[ci][q];
       const bool last = j + 1 == (int)chunks[ci].size();
       if (!launch_class(c, chunks[ci][j], method, p, omega, alpha, m, s, f, us[rd], vs[rd], us[rd ^ 1], vs[rd ^ 1],
-                        active, last ? res_partial : nullptr, st, nullptr, 0, tail))
+                        active, last ? res_partial : nullptr, st, nullptr, 0, uses_tail(tail, ci)))
         return fail(RM_EUNSUPPORTED, "block kernel configuration not built");
     }
   }
   cur ^= par;
   flips += par ? 1 : 2;
-  if (res_partial != nullptr) *res_ranges = (tail ? pl->d_tranges : pl->d_ranges).as<int>();
+  if (res_partial != nullptr) *res_ranges = pl->d_ranges.as<int>();
   return RM_OK;
 }
 
@@ -777,6 +795,15 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   RM_TRY(pl->partial.ensure(partial_slots(pl) * 2 * sizeof(double), st));
   RM_TRY(pl->red.ensure((size_t)B * 8 * sizeof(double), st));
   RM_TRY(pl->flags.ensure(((size_t)B * 7 + 16) * sizeof(int), st));
+  const int ncls = (int)pl->classes.size();
+  if (ctx->host_cnt_n < (size_t)ncls) {
+    RM_HIP(hipStreamSynchronize(st));
+    if (ctx->host_cnt != nullptr) (void)hipHostFree(ctx->host_cnt);
+    ctx->host_cnt = nullptr;
+    ctx->host_cnt_n = 0;
+    RM_HIP(hipHostMalloc((void**)&ctx->host_cnt, (size_t)ncls * sizeof(int), hipHostMallocCoherent));
+    ctx->host_cnt_n = (size_t)ncls;
+  }
   // pinned host copies of the per-round reads: r2, b2 (double), then status, tot, count (int)
   const size_t pin_need = 2 * (size_t)B * sizeof(double) + 3 * (size_t)B * sizeof(int);
   if (ctx->pin_bytes < pin_need) {
@@ -831,21 +858,27 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     std::fill(rep->history, rep->history + (size_t)(o->max_rounds + 1) * B, -1.0);
   RM_HIP(hipMemcpyAsync(mask, mask_h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
   int flips_per_outer = 0;
-  GraphHolder graph[2];  // one captured outer iteration per configuration (main, tail)
+  // one captured outer iteration per combination of main and tail configurations
+  std::map<unsigned long long, GraphHolder> graphs;
   bool use_graph = (o->flags & RM_FLAG_GRAPH) != 0;
-  // Switch to the classes' tail configurations below this many active instances.
-  int tail_below = 0;
-  {
-    bool distinct = false;
-    double frac = 1.0;
-    for (const auto& c : pl->classes)
-      if (c.tshape != c.shape || c.tT != c.T || c.tcw != c.cw) {
-        distinct = true;
-        frac = std::min(frac, c.floor_us > 0.0 && c.tus > 0.0 ? c.floor_us / c.tus : 0.35);
-      }
+  // Per size class: its tail configuration runs once fewer than thr[c] of its
+  // instances are active (0: never; the first 64 classes can switch).
+  std::vector<int> thr(ncls, 0);
+  for (int ci = 0; ci < ncls && ci < 64; ++ci) {
+    const auto& c = pl->classes[ci];
+    if (c.tshape == c.shape && c.tT == c.T && c.tcw == c.cw) continue;
+    double frac = c.floor_us > 0.0 && c.tus > 0.0 ? c.floor_us / c.tus : 0.35;
     if (pl->tail_frac >= 0.0) frac = pl->tail_frac;
-    if (distinct) tail_below = frac >= 1.0 ? B + 1 : (int)std::ceil(frac * B);
+    const int size = (int)c.insts.size();
+    thr[ci] = frac >= 1.0 ? size + 1 : (int)std::ceil(frac * size);
   }
+  auto tail_mask = [&](auto active_in) {
+    unsigned long long mk = 0;
+    for (int ci = 0; ci < ncls && ci < 64; ++ci)
+      if (active_in(ci) < thr[ci]) mk |= 1ull << ci;
+    return mk;
+  };
+  std::vector<int> round_cnt(ncls, 0);
   for (int j = 0;; ++j) {
     if (j > 0) rmk::launch_refine_update(p, x, ds[0], ds[1], count, flips_per_outer, mask, st);
     rmk::launch_refine_residual(p, b, x, r32, ds[0], vs[0], partial, mask, st);
@@ -887,6 +920,9 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
       }
     }
     if (n_round == 0) break;
+    std::fill(round_cnt.begin(), round_cnt.end(), 0);
+    for (int ci = 0; ci < ncls; ++ci)
+      for (int bi : pl->classes[ci].insts) round_cnt[ci] += mask_h[bi];
     // inner solve A d = r32 on the instances of this round
     for (int bi = 0; bi < B; ++bi) smask_h[bi] = mask_h[bi];
     RM_HIP(hipMemcpyAsync(staged, staged_h.data(), 2 * (size_t)B * sizeof(double), hipMemcpyHostToDevice, st));
@@ -894,24 +930,25 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     int cur = 0;
     // one outer iteration: sweep of m steps with the residual fused into its last
     // launch, per-instance reduction, convergence bookkeeping
-    auto outer_iteration = [&](bool tail, unsigned seq) -> rm_status {
+    auto outer_iteration = [&](unsigned long long tail, unsigned seq) -> rm_status {
       int flips = 0;
       const int* ranges = nullptr;
       RM_TRY(sweep(pl, st, method, o->m, 0, o->m, omega, alpha, r32, ds, vs, cur, flips, active, partial, &ranges, -1,
                    tail));
       flips_per_outer = flips;
-      rmk::launch_outer_flags(p, partial, ranges, res2, rhs2, target2, best2, since, gains, stall_min, stall_max,
-                              o->max_outer, active, count, status, n_active, ctx->host_word, seq, tot, hist,
-                              o->hist_len, st);
+      rmk::launch_outer_flags(p, partial, ranges, ranges != nullptr ? pl->d_tranges.as<int>() : nullptr,
+                              pl->d_cls.as<int>(), tail, ncls, res2, rhs2, target2, best2, since, gains, stall_min,
+                              stall_max, o->max_outer, active, count, status, n_active, ctx->host_word,
+                              ctx->host_cnt, seq, tot, hist, o->hist_len, st);
       return RM_OK;
     };
     // The iteration returns to buffer set 0, so one captured iteration can be
     // replayed; captured on first use per configuration and reused by every round.
-    auto capture = [&](int g) {
+    auto capture = [&](unsigned long long g) {
       const int cur0 = cur;
-      GraphHolder& gh = graph[g];
+      GraphHolder& gh = graphs[g];
       if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        const rm_status sc = outer_iteration(g == 1, 0u);
+        const rm_status sc = outer_iteration(g, 0u);
         const hipError_t ec = hipStreamEndCapture(st, &gh.graph);
         if (sc != RM_OK || ec != hipSuccess || cur != cur0 ||
             hipGraphInstantiate(&gh.exec, gh.graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -926,34 +963,34 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
       (void)hipGetLastError();
       cur = cur0;
     };
-    // the configuration follows the active count seen at the last poll
-    int tail = n_round < tail_below ? 1 : 0;
-    if (use_graph && graph[tail].exec == nullptr) capture(tail);
+    // the configuration of every class follows its active count seen at the last poll
+    auto counts_seen = [&](int ci) { return __atomic_load_n(ctx->host_cnt + ci, __ATOMIC_ACQUIRE); };
+    unsigned long long tail = tail_mask([&](int ci) { return round_cnt[ci]; });
     if (use_graph) {
       // captured iterations: synchronise every check_every of them and read the count
       for (int k = 1;; ++k) {
-        if (use_graph && graph[tail].exec == nullptr) capture(tail);
+        if (use_graph && (graphs.count(tail) == 0 || graphs[tail].exec == nullptr)) capture(tail);
         if (use_graph)
-          RM_HIP(hipGraphLaunch(graph[tail].exec, st));
+          RM_HIP(hipGraphLaunch(graphs[tail].exec, st));
         else
-          RM_TRY(outer_iteration(tail == 1, 0u));  // the capture failed: launch directly
+          RM_TRY(outer_iteration(tail, 0u));  // the capture failed: launch directly
         if (k % o->check_every == 0 || k >= o->max_outer) {
           RM_HIP(hipStreamSynchronize(st));
           const int na = (int)(__atomic_load_n(ctx->host_word, __ATOMIC_ACQUIRE) & 0xffffffffull);
           if (na == 0 || k >= o->max_outer) break;
-          tail = na < tail_below ? 1 : 0;
+          tail = tail_mask(counts_seen);
         }
       }
     } else {
       // One outer iteration stays queued while the host waits for the count of the
       // iteration before it, so the GPU does not idle for the host's round trip; the
-      // configuration of each iteration follows the count two iterations back.
+      // configuration of each iteration follows the counts two iterations back.
       // The context's launch number advances before each launch, so a later solve never
       // mistakes a word of this one for its own.
       int issued = 0;
       auto issue = [&]() -> rm_status {
         ++issued;
-        return outer_iteration(tail == 1, ++ctx->seq);
+        return outer_iteration(tail, ++ctx->seq);
       };
       RM_TRY(issue());
       for (;;) {
@@ -963,7 +1000,7 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
         RM_TRY(wait_word(ctx, st, more ? ctx->seq - 1u : ctx->seq, w));
         const int na = (int)(w & 0xffffffffull);
         if (na == 0 || !more) break;
-        tail = na < tail_below ? 1 : 0;
+        tail = tail_mask(counts_seen);
       }
     }
     // no synchronisation here: the next round's update and residual queue behind the
@@ -1212,6 +1249,7 @@ rm_status rm_destroy(rm_ctx* ctx) {
   if (ctx->work != nullptr) (void)hipStreamSynchronize(ctx->work);
   for (rm_plan_s* pl : ctx->plans) pl->ctx = nullptr;
   if (ctx->host_word != nullptr) (void)hipHostFree(ctx->host_word);
+  if (ctx->host_cnt != nullptr) (void)hipHostFree(ctx->host_cnt);
   if (ctx->pin != nullptr) (void)hipHostFree(ctx->pin);
   if (ctx->work != nullptr) (void)hipStreamDestroy(ctx->work);
   if (ctx->handoff != nullptr) (void)hipEventDestroy(ctx->handoff);

@@ -117,9 +117,6 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 8 * (LW - 2)), amdgpu_
     const int i = (s0 + t) % m;
     float w, a, at;
     step_factors<float, METHOD>(p, omega, alpha, m, tl.inst, i, w, a, at);
-    float wc[5];
-#pragma unroll
-    for (int j = 0; j < 5; ++j) wc[j] = w * c[j];
     if (t > 0) __syncthreads();  // every read of the previous step is done
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -133,7 +130,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 8 * (LW - 2)), amdgpu_
     __syncthreads();
     strip_walk<R, LW>(B, lc, lr0, [&](int k, float C, float W, float E, float S, float N, float SW, float NE,
                                       float SE, float NW) {
-      const float vn = step_vf(wc, w, a, rf[k], rv[k], C, W, E, S, N, SW, NE, SE, NW);
+      const float vn = step_vf(c, w, a, rf[k], rv[k], C, W, E, S, N, SW, NE, SE, NW);
       ru[k] = ru[k] + vn;
       rv[k] = vn;
     });
@@ -165,7 +162,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 8 * (LW - 2)), amdgpu_
                                       float SE, float NW) {
       const int gy = gy0 + k;
       if (colown && gy >= tl.oy0 && gy < tl.oy1) {
-        const float r = rf[k] - stencil9<float>(c, C, W, E, S, N, SW, NE, SE, NW);
+        const float r = residual9<float>(c, rf[k], C, W, E, S, N, SW, NE, SE, NW);
         r2 += (double)r * (double)r;
       }
     });

@@ -32,18 +32,38 @@ __device__ __forceinline__ T stencil9(const T c[5], T C, T W, T E, T S, T N, T S
   return acc;
 }
 
-// New momentum of a Table-1 step with the weight folded into the stencil,
-// v' = a v + w f - sum_j (w c_j) s_j, in the one order every FP32 sweep kernel uses.
-__device__ __forceinline__ float step_vf(const float wc[5], float w, float a, float f, float v, float C, float W,
+// f - sum_j c_j s_j, the residual of a 9-point stencil, in the one order every FP32
+// sweep kernel and the residual kernels use: starting from f, subtract the south row
+// (S, SW, SE), then the centre row (C, then the pair W + E), then the north row (N, NE,
+// NW) -- the order in which a row pipeline receives the rows -- each as a fused
+// multiply-add.  Coefficients as in stencil9: c2 for S and N, c3 for SW and NE, c4 for
+// SE and NW.  Kernels that form the same residual in this order agree bit for bit.
+template <typename T>
+__device__ __forceinline__ T residual9(const T c[5], T f, T C, T W, T E, T S, T N, T SW, T NE, T SE, T NW) {
+#pragma clang fp contract(off)
+  T acc = fmadd(-c[2], S, f);
+  acc = fmadd(-c[3], SW, acc);
+  acc = fmadd(-c[4], SE, acc);
+  acc = fmadd(-c[0], C, acc);
+  acc = fmadd(-c[1], W + E, acc);
+  acc = fmadd(-c[2], N, acc);
+  acc = fmadd(-c[3], NE, acc);
+  return fmadd(-c[4], NW, acc);
+}
+
+// New momentum of a Table-1 step, v' = a v + w (f - A s) with the residual of
+// residual9; c, w and a are the same for every point of a workgroup, so they stay in
+// scalar registers.
+__device__ __forceinline__ float step_vf(const float c[5], float w, float a, float f, float v, float C, float W,
                                          float E, float S, float N, float SW, float NE, float SE, float NW) {
 #pragma clang fp contract(off)
-  float acc = fmadd(a, v, w * f);
-  acc = fmadd(-wc[0], C, acc);
-  acc = fmadd(-wc[1], W + E, acc);
-  acc = fmadd(-wc[2], S + N, acc);
-  acc = fmadd(-wc[3], SW + NE, acc);
-  acc = fmadd(-wc[4], SE + NW, acc);
-  return acc;
+  return fmadd(a, v, w * residual9<float>(c, f, C, W, E, S, N, SW, NE, SE, NW));
+}
+
+// A value the whole workgroup shares, moved to a scalar register (for values formed by
+// vector arithmetic on scalar inputs, which would otherwise occupy a vector register).
+__device__ __forceinline__ float uniform_f32(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
 // The five stencil coefficients of instance b in the precision of T.

@@ -90,15 +90,20 @@ void launch_refine_update(const PlanDev& p, double* x, const float* d0, const fl
 // Inner-solve bookkeeping after one outer iteration, one launch: res2[b] = the sum of the
 // instance's residual partials in slot order, then for active
 // instances the outer count, divergence / target / cap / stagnation tests and the new
-// active flag, and *n_active = the number still active.  With host_word (pinned
-// host memory, may be null) the count is also published there as one 64-bit word,
-// (seq << 32) | count, so a host thread that reads the word knows which launch wrote it.
+// active flag, and *n_active = the number still active.  The partial slots of instance b
+// are [r[2b], r[2b+1]) with r = tranges when bit cls[b] of tailmask is set (its class ran
+// its tail configuration), else ranges; with ranges null, its range in the plan's tile
+// table.  With host_word (pinned host memory, may be null) the count is also published
+// there as one 64-bit word, (seq << 32) | count, so a host thread that reads the word
+// knows which launch wrote it; host_cnt (pinned, may be null) receives the active
+// instances of each of the ncls classes first (cls may be null when ncls <= 1).
 // With hist given, an active instance also stores res2 at hist[k * B + b], k = tot[b] + (its
 // outer count in this round) - 1, when k < hist_len.
-void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ranges, double* res2,
-                        const double* rhs2, const double* target2, double* best2, int* since, int* gains,
-                        int stall_min, int stall_max, int cap, int* active, int* outer_count, int* status,
-                        int* n_active, unsigned long long* host_word, unsigned seq, const int* tot, double* hist,
+void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ranges, const int* tranges,
+                        const int* cls, unsigned long long tailmask, int ncls, double* res2, const double* rhs2,
+                        const double* target2, double* best2, int* since, int* gains, int stall_min, int stall_max,
+                        int cap, int* active, int* outer_count, int* status, int* n_active,
+                        unsigned long long* host_word, int* host_cnt, unsigned seq, const int* tot, double* hist,
                         int hist_len, hipStream_t st);
 // Start of a refinement round from staged[0, B) = inner targets (double) and
 // staged[B, 1.5 B) = the round mask (int): target2, mask, active, rhs2 = best2 = r2,
@@ -167,8 +172,10 @@ bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, cons
 // x0 = 0, ox0 = 0, ox1 = n and the window [y0, min(n, y0 + wlen)) with owned rows
 // [oy0, oy1); windows overlap by at least T rows at cuts (T + 1 with partial2).
 // Same step semantics, partial2 and states layout as launch_block.  Returns false
-// when n or T is outside what is built.
-constexpr int kStreamMaxN = 512;
+// when n or T is outside what is built.  The reverse steps (launch_adj_stream) are
+// built for n <= kAdjStreamMaxN.
+constexpr int kStreamMaxN = 1024;
+constexpr int kAdjStreamMaxN = 512;
 constexpr int kStreamMaxT = 8;
 bool launch_stream(int T, int wlen, int n, int method, const PlanDev& p, const BTile* tiles, int ntiles,
                    const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,

@@ -33,21 +33,13 @@ constexpr int LDS_W = TX + 2;
 constexpr int RPT = TY / (WG / TX);  // rows per thread
 constexpr int NWAVE = WG / 64;
 
-// One inner step's new momentum at a point, with the weight folded into the
-// stencil: v' = a v + w f - sum_j (w c_j) s_j, where wc[j] = w c_j and the s_j are
-// the centre and the symmetric neighbour pairs of the look-ahead field (same
-// pairing and order as stencil9).  Every kernel that advances the iteration uses
-// exactly this sequence, so they agree bit for bit.
+// One inner step's new momentum at a point, v' = a v + w (f - A s) with the residual
+// of residual9, the sequence of step_vf, which every kernel that advances the iteration
+// uses, so they agree bit for bit.
 template <typename T>
-__device__ __forceinline__ T step_v(const T wc[5], T w, T a, T f, T v, T C, T W, T E, T S, T N, T SW, T NE, T SE,
+__device__ __forceinline__ T step_v(const T c[5], T w, T a, T f, T v, T C, T W, T E, T S, T N, T SW, T NE, T SE,
                                     T NW) {
-  T acc = fmadd(a, v, w * f);
-  acc = fmadd(-wc[0], C, acc);
-  acc = fmadd(-wc[1], W + E, acc);
-  acc = fmadd(-wc[2], S + N, acc);
-  acc = fmadd(-wc[3], SW + NE, acc);
-  acc = fmadd(-wc[4], SE + NW, acc);
-  return acc;
+  return fmadd(a, v, w * residual9<T>(c, f, C, W, E, S, N, SW, NE, SE, NW));
 }
 
 // Stencil at LDS position (lx, ly) of a (TY+2) x LDS_W tile.
@@ -57,6 +49,15 @@ __device__ __forceinline__ T stencil_lds(const T* s, int lx, int ly, const T c[5
   const T* rc = s + ly * LDS_W + lx;
   const T* rn = s + (ly + 1) * LDS_W + lx;
   return stencil9(c, rc[0], rc[-1], rc[1], rs[0], rn[0], rs[-1], rn[1], rs[1], rn[-1]);
+}
+
+// f - A s at LDS position (lx, ly), in the order of residual9.
+template <typename T>
+__device__ __forceinline__ T residual_lds(const T* s, int lx, int ly, const T c[5], T f) {
+  const T* rs = s + (ly - 1) * LDS_W + lx;
+  const T* rc = s + ly * LDS_W + lx;
+  const T* rn = s + (ly + 1) * LDS_W + lx;
+  return residual9(c, f, rc[0], rc[-1], rc[1], rs[0], rn[0], rs[-1], rn[1], rs[1], rn[-1]);
 }
 
 // Fill the one-point halo ring of the LDS tile with val(gx, gy), or 0 outside the
@@ -122,13 +123,12 @@ __global__ __launch_bounds__(WG) void k_apply(PlanDev p, const Tile* tiles, cons
   for (int k = 0; k < RPT; ++k) {
     const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
     if (gx < n && gy < n) {
-      const T ax = stencil_lds(s, tx + 1, ly + 1, c);
       const int64_t idx = in.off + (int64_t)gy * n + gx;
       if (MODE == 0) {
-        y[idx] = ax;
+        y[idx] = stencil_lds(s, tx + 1, ly + 1, c);
       } else {
         const T bv = rb[k];
-        const T r = bv - ax;
+        const T r = residual_lds(s, tx + 1, ly + 1, c, bv);
         if (y != nullptr) y[idx] = r;
         r2 += (double)r * (double)r;
         b2 += (double)bv * (double)bv;
@@ -195,9 +195,6 @@ __global__ __launch_bounds__(WG) void k_step(PlanDev p, const Tile* tiles, const
   else
     stage_halo(s, tl.x0, tl.y0, n, [&](int X, int Y) { return uf[(unsigned)(Y * n + X)]; });
   __syncthreads();
-  T wc[5];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) wc[k] = w * c[k];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int ly = ty0 + 4 * k, gy = tl.y0 + ly;
@@ -205,7 +202,7 @@ __global__ __launch_bounds__(WG) void k_step(PlanDev p, const Tile* tiles, const
       const T* rs = s + ly * LDS_W + tx + 1;
       const T* rc = rs + LDS_W;
       const T* rn = rc + LDS_W;
-      const T vn = step_v(wc, w, a, rf[k], rv[k], rc[0], rc[-1], rc[1], rs[0], rn[0], rs[-1], rn[1], rs[1], rn[-1]);
+      const T vn = step_v(c, w, a, rf[k], rv[k], rc[0], rc[-1], rc[1], rs[0], rn[0], rs[-1], rn[1], rs[1], rn[-1]);
       const int64_t idx = in.off + (int64_t)gy * n + gx;
       u_out[idx] = ru[k] + vn;
       if (uses_momentum(METHOD)) v_out[idx] = vn;
@@ -324,17 +321,24 @@ __global__ __launch_bounds__(WG) void k_refine_update(PlanDev p, double* __restr
 // target, cap and stagnation tests; finally the number still active, summed over the
 // threads in a fixed order (no atomics and no counter to clear beforehand).
 __global__ __launch_bounds__(1024) void k_outer_flags(
-    PlanDev p, const double* __restrict__ partial2, const int* __restrict__ ranges, double* __restrict__ res2,
-    const double* __restrict__ rhs2, const double* __restrict__ target2, double* __restrict__ best2,
-    int* __restrict__ since, int* __restrict__ gains, int stall_min, int stall_max, int cap,
-    int* __restrict__ active, int* __restrict__ outer_count, int* __restrict__ status, int* __restrict__ n_active,
-    unsigned long long* __restrict__ host_word, unsigned seq, const int* __restrict__ tot, double* __restrict__ hist,
-    int hist_len) {
+    PlanDev p, const double* __restrict__ partial2, const int* __restrict__ ranges,
+    const int* __restrict__ tranges, const int* __restrict__ cls, unsigned long long tailmask, int ncls,
+    double* __restrict__ res2, const double* __restrict__ rhs2, const double* __restrict__ target2,
+    double* __restrict__ best2, int* __restrict__ since, int* __restrict__ gains, int stall_min, int stall_max,
+    int cap, int* __restrict__ active, int* __restrict__ outer_count, int* __restrict__ status,
+    int* __restrict__ n_active, unsigned long long* __restrict__ host_word, int* __restrict__ host_cnt, unsigned seq,
+    const int* __restrict__ tot, double* __restrict__ hist, int hist_len) {
   __shared__ int kept[16];
+  extern __shared__ int per_class[];  // [ncls] active instances per size class
+  for (int c = threadIdx.x; c < ncls; c += blockDim.x) per_class[c] = 0;
+  __syncthreads();
   int mine = 0;
   for (int b = threadIdx.x; b < p.B; b += blockDim.x) {
-    const int t0 = ranges != nullptr ? ranges[2 * b] : p.inst[b].tile_begin;
-    const int t1 = ranges != nullptr ? ranges[2 * b + 1] : p.inst[b].tile_end;
+    // slot range of the configuration the instance's class ran
+    const int ci = cls != nullptr ? cls[b] : 0;
+    const int* rg = (tranges != nullptr && ci < 64 && ((tailmask >> ci) & 1ull)) ? tranges : ranges;
+    const int t0 = rg != nullptr ? rg[2 * b] : p.inst[b].tile_begin;
+    const int t1 = rg != nullptr ? rg[2 * b + 1] : p.inst[b].tile_end;
     // the instance's state is read before the partial sums are waited for
     const int act = active[b], cnt = outer_count[b] + 1, sn = since[b], g = gains[b];
     const double rh = rhs2[b], tg = target2[b], best = best2[b];
@@ -366,6 +370,7 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
     }
     active[b] = keep;
     mine += keep;
+    if (keep && ci < ncls) atomicAdd(&per_class[ci], 1);
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o, 64);
@@ -375,10 +380,16 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
     int total = 0;
     for (int k = 0; k < (int)(blockDim.x >> 6); ++k) total += kept[k];
     *n_active = total;
-    // straight to the host's pinned copy (system scope, a vector store)
-    if (host_word != nullptr)
-      __hip_atomic_store(host_word, ((unsigned long long)seq << 32) | (unsigned)total, __ATOMIC_RELAXED,
+    // straight to the host's pinned copies (system scope, vector stores): the per-class
+    // counts first, then the sequence-stamped total with release ordering, so a host
+    // thread that sees the new stamp also sees the counts
+    if (host_word != nullptr) {
+      if (host_cnt != nullptr)
+        for (int c = 0; c < ncls; ++c)
+          __hip_atomic_store(host_cnt + c, per_class[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(host_word, ((unsigned long long)seq << 32) | (unsigned)total, __ATOMIC_RELEASE,
                          __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
@@ -771,15 +782,17 @@ void launch_refine_update(const PlanDev& p, double* x, const float* d0, const fl
                      round_mask);
 }
 
-void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ranges, double* res2, const double* rhs2,
+void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ranges, const int* tranges,
+                        const int* cls, unsigned long long tailmask, int ncls, double* res2, const double* rhs2,
                         const double* target2, double* best2, int* since, int* gains, int stall_min, int stall_max,
                         int cap, int* active, int* outer_count, int* status, int* n_active,
-                        unsigned long long* host_word, unsigned seq, const int* tot, double* hist, int hist_len,
-                        hipStream_t st) {
+                        unsigned long long* host_word, int* host_cnt, unsigned seq, const int* tot, double* hist,
+                        int hist_len, hipStream_t st) {
   const int threads = 64 * std::min(16, std::max(1, (p.B + 63) / 64));
-  hipLaunchKernelGGL(k_outer_flags, dim3(1), dim3(threads), 0, st, p, partial2, ranges, res2, rhs2, target2, best2,
-                     since, gains, stall_min, stall_max, cap, active, outer_count, status, n_active, host_word, seq,
-                     tot, hist, hist_len);
+  hipLaunchKernelGGL(k_outer_flags, dim3(1), dim3(threads), (size_t)std::max(1, ncls) * sizeof(int), st, p,
+                     partial2, ranges, tranges, cls, tailmask, ncls, res2, rhs2, target2, best2, since, gains,
+                     stall_min, stall_max, cap, active, outer_count, status, n_active, host_word, host_cnt, seq, tot,
+                     hist, hist_len);
 }
 
 void launch_round_start(int B, const double* staged, const double* r2, double* rhs2, double* best2, double* target2,

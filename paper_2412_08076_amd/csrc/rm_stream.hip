@@ -1,29 +1,33 @@
 // Row-streaming temporal-blocked steps for gfx950.
 //
-// One workgroup of 64 ceil(n / 64) threads holds whole grid rows of one instance
-// (thread = column), so no column halo is needed, and streams down a window of rows
-// (the whole height, or one of several overlapping row windows when the batch alone
-// does not fill the chip).  The TL inner steps of a launch of a Table-1 scheme
+// One workgroup of 64 ceil(n / 64) threads (up to 1024) holds whole grid rows of one
+// instance (thread = column), so no column halo is needed, and streams down a window
+// of rows (the whole height, or one of several overlapping row windows when the batch
+// alone does not fill the chip).  The TL inner steps of a launch of a Table-1 scheme
 // (Richardson(m), MOM-, NAG- or NAGex-Richardson(m), optionally Jacobi-preconditioned)
 // run as a pipeline over the rows: at iteration s the loader brings in row s, and
-// step t (1..TL) updates row s - 2t from what step t - 1 produced for rows s - 2t - 1,
-// s - 2t and s - 2t + 1 in the three iterations before.  Since no step needs a row
-// produced in the same iteration, the TL updates of an iteration are independent.
+// step t (1..TL) receives row s - 2t + 1 of what step t - 1 produced in the iteration
+// before and completes row s - 2t.  Since no step needs a row produced in the same
+// iteration, the TL updates of an iteration are independent and one barrier per
+// iteration suffices.
 //
-// Per step, every thread keeps in registers the last three published rows of its own
-// column and of its two neighbours (u~ = u + at v, the input of the stencil) and the
-// (u, v, f) it is about to update.  A step publishes each row it produces to LDS once,
-// and the neighbours' values are read back one iteration later, after the iteration's
-// single barrier.  Global memory sees one read of (u, v, f) and one write of (u, v)
-// per point and launch.
+// Each step accumulates the stencil of a row as its three input rows arrive: the row
+// below (the south row, y - 1) starts the sum, the row itself adds the centre row and
+// the row above (y + 1) completes it.  A step therefore keeps only two partial sums
+// (rows y + 1 and y + 2) and the (u, v, f) of the two rows it is about to update in
+// registers, nine values per column, and the neighbour columns of an arriving row are
+// read from LDS once and used at once.  A step publishes each row it produces to LDS
+// once (two row slots per step).  Global memory sees one read of (u, v, f) and one
+// write of (u, v) per point and launch.
 //
-// The update uses the same fused multiply-add sequence as the one-step kernel, so a
-// launch of TL steps reproduces TL one-step launches bit for bit.  Rows outside the
-// window publish zeros: at the domain edge that is the Dirichlet condition; at a cut
-// between windows the error moves inward one row per step, so windows overlap by a
-// halo h >= TL (h >= TL + 1 with the residual) and each stores only its owned rows.
-// With partial2 given, ||f - A u||^2 of the final u over the owned rows is formed by
-// one more pipeline stage.
+// The sum is formed in the order of step_vf (south row, centre row, north row, then
+// the weight and the momentum), the order every FP32 sweep kernel uses, so a launch of
+// TL steps reproduces TL one-step launches bit for bit.  Rows outside the window
+// publish zeros: at the domain edge that is the Dirichlet condition; at a cut between
+// windows the error moves inward one row per step, so windows overlap by a halo
+// h >= TL (h >= TL + 1 with the residual) and each stores only its owned rows.  With
+// partial2 given, ||f - A u||^2 of the final u over the owned rows is formed by one
+// more pipeline stage.
 #include <type_traits>
 
 #include "rm_device.h"
@@ -54,23 +58,23 @@ __device__ __forceinline__ float fresh(float x) {
   return y;
 }
 
-// Iterations per unrolled loop body: a multiple of the register rings' lengths
-// (3 rows of published values, 2 rows of queued inputs) and of the prefetch depth.
+// Iterations per unrolled loop body of the reverse pipeline: a multiple of its
+// register rings' lengths (3 rows of published values, 2 rows of queued inputs) and
+// of the prefetch depth.
 constexpr int kUnroll = 6;
 
-// Per-thread registers of the pipeline.  Level t = 1..TL is step t; level TL + 1 forms
-// the residual.  Row r of level t lives in ring slot r mod 3 (published values) or
-// r mod 2 (queued inputs).
-template <int TL>
+// Per-thread registers of the forward pipeline.  Level t = 1..TL is step t; level
+// TL + 1 forms the residual.  Partial sums and queued inputs of row r live in slot
+// r mod 2; PF rows are prefetched.
+template <int TL, int PF>
 struct StreamRegs {
   static constexpr int NL = TL + 1;
-  float c[NL + 1][3];    // published input of level t: own column
-  float mw[NL + 1][3];   // ... of the west neighbour (column - 1)
-  float pe[NL + 1][3];   // ... of the east neighbour (column + 1)
+  float in[NL + 1];      // the row arriving at level t (own column), published by level t - 1
+  float acc[NL + 1][2];  // partial stencil sums of level t
   float qu[NL + 1][2];   // u, v, f waiting to be updated by level t
   float qv[NL + 1][2];
   float qf[NL + 1][2];
-  float pu[kUnroll], pv[kUnroll], pf[kUnroll];  // prefetched rows
+  float pu[PF], pv[PF], pf[PF];  // prefetched rows
 };
 
 // Bounds-checked stores: a raw buffer store whose byte offset is at or beyond the
@@ -79,19 +83,25 @@ struct StreamRegs {
 constexpr int kBufWord3 = 0x00020000;  // 32-bit data, raw (unswizzled) buffer
 constexpr int kDropOffset = 0x7ffffff0;
 
-template <int TL, int METHOD, bool STORE, bool RES>
-__global__ __attribute__((amdgpu_flat_work_group_size(64, 512))) void k_stream(
+// MAXT: the largest workgroup of the instantiation (512, or 1024 for n > 512, which
+// limits a thread to 128 registers); PF: prefetch depth = iterations per unrolled body.
+template <int TL, int METHOD, bool STORE, bool RES, int MAXT, int PF>
+__global__ __attribute__((amdgpu_flat_work_group_size(64, MAXT))) void k_stream(
     PlanDev p, const BTile* __restrict__ tiles, int ntiles, int wlen, const float* __restrict__ omega,
     const float* __restrict__ alpha, int m, int s0, const float* __restrict__ f, const float* __restrict__ u,
     const float* __restrict__ v, float* __restrict__ u_out, float* __restrict__ v_out,
     const int* __restrict__ active, double* __restrict__ partial2, float* __restrict__ states,
     int64_t state_stride) {
   constexpr int NL = TL + 1;
-  // LDS: per column, two row slots per level (odd stride: conflict-free across lanes);
-  // column 0 and the column after the last thread are the zero Dirichlet border
+  constexpr int NLV = RES ? NL : TL;  // levels that run
+  // LDS: per column, two row slots per level (odd stride: conflict-free across lanes).
+  // Block k holds grid column k - 1: block 0 and block n + 1 (never written) are the
+  // zero Dirichlet border.  Threads beyond the grid use blocks NT + 2 .. NT + 4 as their
+  // west, own and east columns: they read zeros and write where no other thread reads,
+  // so what they compute never reaches the grid.
   constexpr int LS = 2 * NL + 1;
   extern __shared__ float lds[];
-  __shared__ double sh[8];
+  __shared__ double sh[MAXT / 64];
   const BTile tl = tiles[xcd_remap(blockIdx.x, ntiles)];
   if (tl.inst < 0) return;
   if (active != nullptr && active[tl.inst] == 0) return;
@@ -107,25 +117,23 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 512))) void k_stream(
   float c[5];
   load_coef<float>(p, tl.inst, c);
   // factors of the TL steps: fat[t] is the look-ahead of step t, applied by its producer
-  float fw[NL], fa[NL], fat[NL + 1], fwc[NL][5];
+  float fw[NL], fa[NL], fat[NL + 1];
   static_for<1, NL>([&](auto T_) {
     constexpr int t = decltype(T_)::value;
     step_factors<float, METHOD>(p, omega, alpha, m, tl.inst, (s0 + t - 1) % m, fw[t], fa[t], fat[t]);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) fwc[t][j] = fw[t] * c[j];
+    fw[t] = uniform_f32(fw[t]);  // scaled by 1 / D under Jacobi preconditioning
   });
-  for (int e = threadIdx.x; e < (NT + 2) * LS; e += NT) lds[e] = 0.0f;
-  float* lb = lds + gx * LS;  // column gx - 1; own column at + LS, east at + 2 LS
+  for (int e = threadIdx.x; e < (NT + 5) * LS; e += NT) lds[e] = 0.0f;
+  float* lb = lds + (colin ? gx : NT + 2) * LS;  // west column; own column at + LS, east at + 2 LS
   const float* fi = f + in.off;
   const float* ui = u + in.off;
   const float* vi = v + in.off;
-  StreamRegs<TL> R;
+  StreamRegs<TL, PF> R;
   static_for<0, NL + 1>([&](auto T_) {
     constexpr int t = decltype(T_)::value;
+    R.in[t] = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) R.c[t][k] = R.mw[t][k] = R.pe[t][k] = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) R.qu[t][k] = R.qv[t][k] = R.qf[t][k] = 0.0f;
+    for (int k = 0; k < 2; ++k) R.acc[t][k] = R.qu[t][k] = R.qv[t][k] = R.qf[t][k] = 0.0f;
   });
   auto load_row = [&](int r, float& lu, float& lv, float& lf) {
     const int idx = (ys + r) * n + gxc;
@@ -133,96 +141,122 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 512))) void k_stream(
     lv = uses_momentum(METHOD) ? vi[idx] : 0.0f;
     lf = fi[idx];
   };
-  static_for<0, kUnroll>([&](auto K_) {
+  static_for<0, PF>([&](auto K_) {
     constexpr int k = decltype(K_)::value;
     load_row(min(k, L - 1), R.pu[k], R.pv[k], R.pf[k]);
   });
   __syncthreads();
   double r2 = 0.0;
-  const int S = L + 2 * (RES ? NL : TL);
+  const int S = L + 2 * NLV;
   const int nn4 = n * n * (int)sizeof(float);
   const __amdgpu_buffer_rsrc_t ub_out = __builtin_amdgcn_make_buffer_rsrc(u_out + in.off, (short)0, nn4, kBufWord3);
   const __amdgpu_buffer_rsrc_t vb_out = __builtin_amdgcn_make_buffer_rsrc(v_out + in.off, (short)0, nn4, kBufWord3);
-  auto iter = [&](auto PH_, int s) {
+  // One iteration.  Phase A, levels from the last to the first (each consumes its
+  // arriving row and queue slot before the level below refills them): level t
+  // completes row y = s - 2t with the north row (its arriving row y + 1), updates it
+  // and passes it on, and adds the centre row of y + 1.  Phase B: level t starts the
+  // residual of row y + 2 from its f (queued by level t - 1 in phase A) with the south
+  // row.  STEADY: every level's row lies in the window, so nothing is masked.
+  auto iter = [&](auto PH_, auto STEADY_, int s) {
     constexpr int PH = decltype(PH_)::value;
-    // neighbours of the newest row of every level (produced in the previous iteration)
-    static_for<1, NL + 1>([&](auto T_) {
+    constexpr bool STEADY = decltype(STEADY_)::value;
+    constexpr int y2 = pmod(PH, 2);       // slot of row s - 2t (and of row s - 2t + 2)
+    constexpr int y2n = pmod(PH + 1, 2);  // slot of row s - 2t + 1 (the arriving row)
+    float Cv[NL + 2], Wv[NL + 2], Ev[NL + 2];
+    // phase B of level t: the south row (the arriving row y + 1) starts row y + 2 from the
+    // f that level t - 1 queued in its phase A
+    auto phase_b = [&](auto T_) {
       constexpr int t = decltype(T_)::value;
-      if (t == NL && !RES) return;
-      constexpr int r3 = pmod(PH - 2 * t + 1, 3), q = pmod(PH + 1, 2);
-      R.mw[t][r3] = lb[(t - 1) * 2 + q];
-      R.pe[t][r3] = lb[2 * LS + (t - 1) * 2 + q];
-    });
-    // levels from the last to the first: each consumes its ring slots before the level
-    // below refills them
+      if constexpr (t >= 1 && t <= NLV) {
+        float a0 = fmadd(-c[2], Cv[t], R.qf[t][y2]);
+        a0 = fmadd(-c[3], Wv[t], a0);
+        R.acc[t][y2] = fmadd(-c[4], Ev[t], a0);
+      }
+    };
     static_for<0, NL>([&](auto K_) {
       constexpr int t = NL - decltype(K_)::value;
-      constexpr int y3 = pmod(PH - 2 * t, 3), ym3 = pmod(PH - 2 * t - 1, 3), yp3 = pmod(PH - 2 * t + 1, 3);
-      constexpr int y2 = pmod(PH, 2);  // = (s - 2 t) mod 2
-      const int y = s - 2 * t;
-      const bool rowok = (unsigned)y < (unsigned)L;
-      const bool mine = y >= own0 && y < own1 && colin;
-      if constexpr (t == NL) {
-        if constexpr (RES) {
-          const float r = R.qf[t][y2] - stencil9<float>(c, R.c[t][y3], R.mw[t][y3], R.pe[t][y3], R.c[t][ym3],
-                                                        R.c[t][yp3], R.mw[t][ym3], R.pe[t][yp3], R.pe[t][ym3],
-                                                        R.mw[t][yp3]);
-          const double rr = (double)r * (double)r;
-          r2 += mine ? rr : 0.0;
-        }
-      } else {
-        const float vn = step_vf(fwc[t], fw[t], fa[t], R.qf[t][y2], R.qv[t][y2], R.c[t][y3], R.mw[t][y3],
-                                 R.pe[t][y3], R.c[t][ym3], R.c[t][yp3], R.mw[t][ym3], R.pe[t][yp3], R.pe[t][ym3],
-                                 R.mw[t][yp3]);
-        const float un = R.qu[t][y2] + vn;
-        if constexpr (t < TL) {
-          const float x = uses_lookahead(METHOD) ? fmadd(fat[t + 1], vn, un) : un;
-          const float pub = rowok && colin ? x : 0.0f;
-          R.c[t + 1][y3] = pub;
-          lb[LS + t * 2 + y2] = pub;
-          R.qf[t + 1][y2] = R.qf[t][y2];
-          R.qu[t + 1][y2] = un;
-          R.qv[t + 1][y2] = vn;
-          if (STORE && mine) {
-            const int64_t gidx = in.off + (int64_t)(ys + y) * n + gx;
-            float* su = states + (int64_t)(t - 1) * state_stride;
-            su[gidx] = un;
-            if (uses_momentum(METHOD)) su[gidx + state_stride / 2] = vn;
-          }
+      if constexpr (t <= NLV) {
+        const int y = s - 2 * t;
+        const bool rowok = STEADY || (unsigned)y < (unsigned)L;
+        const bool mine = y >= own0 && y < own1 && colin;
+        // row y + 1: own column from the register, neighbours from the producer's LDS slot
+        const float C = R.in[t];
+        const float W = lb[(t - 1) * 2 + y2n];
+        const float E = lb[2 * LS + (t - 1) * 2 + y2n];
+        Cv[t] = C;
+        Wv[t] = W;
+        Ev[t] = E;
+        float r = fmadd(-c[2], C, R.acc[t][y2]);
+        r = fmadd(-c[3], E, r);
+        r = fmadd(-c[4], W, r);
+        R.acc[t][y2n] = fmadd(-c[1], W + E, fmadd(-c[0], C, R.acc[t][y2n]));
+        if constexpr (t == NL) {
+          const float rm = mine ? r : 0.0f;
+          r2 = __builtin_fma((double)rm, (double)rm, r2);
         } else {
-          const int boff = mine ? ((ys + y) * n + gx) * (int)sizeof(float) : kDropOffset;
-          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), ub_out, boff, 0, 0);
-          if (uses_momentum(METHOD)) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(vn), vb_out, boff, 0, 0);
-          if constexpr (RES) {
-            const float pub = rowok && colin ? un : 0.0f;
-            R.c[NL][y3] = pub;
-            lb[LS + TL * 2 + y2] = pub;
-            R.qf[NL][y2] = R.qf[t][y2];
+          const float vn = fmadd(fa[t], R.qv[t][y2], fw[t] * r);
+          const float un = R.qu[t][y2] + vn;
+          if constexpr (t < TL) {
+            const float x = uses_lookahead(METHOD) ? fmadd(fat[t + 1], vn, un) : un;
+            const float pub = rowok ? x : 0.0f;
+            R.in[t + 1] = pub;
+            lb[LS + t * 2 + y2] = pub;
+            R.qf[t + 1][y2] = R.qf[t][y2];
+            R.qu[t + 1][y2] = un;
+            R.qv[t + 1][y2] = vn;
+            if (STORE && mine) {
+              const int64_t gidx = in.off + (int64_t)(ys + y) * n + gx;
+              float* su = states + (int64_t)(t - 1) * state_stride;
+              su[gidx] = un;
+              if (uses_momentum(METHOD)) su[gidx + state_stride / 2] = vn;
+            }
+          } else {
+            const int boff = mine ? ((ys + y) * n + gx) * (int)sizeof(float) : kDropOffset;
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), ub_out, boff, 0, 0);
+            if (uses_momentum(METHOD))
+              __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(vn), vb_out, boff, 0, 0);
+            if constexpr (RES) {
+              const float pub = rowok ? un : 0.0f;
+              R.in[NL] = pub;
+              lb[LS + TL * 2 + y2] = pub;
+              R.qf[NL][y2] = R.qf[t][y2];
+            }
           }
         }
       }
+      // level t has queued f for level t + 1: its phase B can run
+      phase_b(std::integral_constant<int, t + 1>{});
     });
     // loader: row s enters level 1
     {
-      constexpr int y3 = pmod(PH, 3), y2 = pmod(PH, 2);
-      const bool rowok = (unsigned)s < (unsigned)L;
+      const bool rowok = STEADY || (unsigned)s < (unsigned)L;
       const float lu = fresh(R.pu[PH]), lv = fresh(R.pv[PH]), lf = fresh(R.pf[PH]);
       const float x = uses_lookahead(METHOD) ? fmadd(fat[1], lv, lu) : lu;
-      const float pub = rowok && colin ? x : 0.0f;
-      R.c[1][y3] = pub;
+      const float pub = rowok ? x : 0.0f;
+      R.in[1] = pub;
       lb[LS + y2] = pub;
       R.qu[1][y2] = lu;
       R.qv[1][y2] = lv;
       R.qf[1][y2] = lf;
       // unconditional (clamped) so that the loaded registers are not merged with old ones
-      load_row(min(s + kUnroll, L - 1), R.pu[PH], R.pv[PH], R.pf[PH]);
+      load_row(min(s + PF, L - 1), R.pu[PH], R.pv[PH], R.pf[PH]);
     }
+    phase_b(std::integral_constant<int, 1>{});
     __syncthreads();
   };
+  // fill and drain iterations mask rows outside the window; in between none is
+  const int F = min(S, ((2 * NLV + PF - 1) / PF) * PF);
+  const int D = F + max(0, (L - F) / PF) * PF;
+  int s = 0;
 #pragma unroll 1
-  for (int s = 0; s < S; s += kUnroll) {
-    static_for<0, kUnroll>([&](auto PH_) { iter(PH_, s + decltype(PH_)::value); });
-  }
+  for (; s < F; s += PF)
+    static_for<0, PF>([&](auto PH_) { iter(PH_, std::false_type{}, s + decltype(PH_)::value); });
+#pragma unroll 1
+  for (; s < D; s += PF)
+    static_for<0, PF>([&](auto PH_) { iter(PH_, std::true_type{}, s + decltype(PH_)::value); });
+#pragma unroll 1
+  for (; s < S; s += PF)
+    static_for<0, PF>([&](auto PH_) { iter(PH_, std::false_type{}, s + decltype(PH_)::value); });
   if constexpr (RES) {
     r2 = wave_sum(r2);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = r2;
@@ -236,16 +270,16 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 512))) void k_stream(
   }
 }
 
-template <int TL>
+template <int TL, int MAXT, int PF>
 bool launch_stream_tl(int nw, int wlen, int method, const PlanDev& p, const BTile* tiles, int ntiles,
                       const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,
                       const float* v, float* u_out, float* v_out, const int* active, double* partial2,
                       float* states, int64_t state_stride, hipStream_t st) {
   const dim3 grid(ntiles), block(64 * nw);
-  const size_t lds = (size_t)(64 * nw + 2) * (2 * (TL + 1) + 1) * sizeof(float);
+  const size_t lds = (size_t)(64 * nw + 5) * (2 * (TL + 1) + 1) * sizeof(float);
 #define RM_LAUNCH(MM, SS, RR)                                                                                       \
-  hipLaunchKernelGGL((k_stream<TL, MM, SS, RR>), grid, block, lds, st, p, tiles, ntiles, wlen, omega, alpha, m, s0, \
-                     f, u, v, u_out, v_out, active, partial2, states, state_stride)
+  hipLaunchKernelGGL((k_stream<TL, MM, SS, RR, MAXT, PF>), grid, block, lds, st, p, tiles, ntiles, wlen, omega,   \
+                     alpha, m, s0, f, u, v, u_out, v_out, active, partial2, states, state_stride)
 #define RM_METHOD(MM)                          \
   if (states != nullptr) RM_LAUNCH(MM, true, false);  \
   else if (partial2 != nullptr) RM_LAUNCH(MM, false, true); \
@@ -507,10 +541,12 @@ bool launch_stream(int T, int wlen, int n, int method, const PlanDev& p, const B
                    hipStream_t st, float* states, int64_t state_stride) {
   if (n < 1 || n > kStreamMaxN || wlen < 1 || T < 1 || T > kStreamMaxT) return false;
   const int nw = (n + 63) / 64;
-#define RM_T_CASE(TT)                                                                                             \
-  case TT:                                                                                                        \
-    return launch_stream_tl<TT>(nw, wlen, method, p, tiles, ntiles, omega, alpha, m, s0, f, u, v, u_out, v_out, \
-                                active, partial2, states, state_stride, st);
+#define RM_T_CASE(TT)                                                                                              \
+  case TT:                                                                                                         \
+    return nw > 8 ? launch_stream_tl<TT, 1024, 2>(nw, wlen, method, p, tiles, ntiles, omega, alpha, m, s0, f, u, v, \
+                                                  u_out, v_out, active, partial2, states, state_stride, st)        \
+                  : launch_stream_tl<TT, 512, 4>(nw, wlen, method, p, tiles, ntiles, omega, alpha, m, s0, f, u, v,  \
+                                                 u_out, v_out, active, partial2, states, state_stride, st);
   switch (T) {
     RM_T_CASE(1)
     RM_T_CASE(2)
@@ -529,7 +565,7 @@ bool launch_stream(int T, int wlen, int n, int method, const PlanDev& p, const B
 bool launch_adj_stream(int T, int wlen, int n, int method, const PlanDev& p, const BTile* tiles, int ntiles,
                        const float* omega, const float* alpha, int m, const AdjLevels& lev, const float* f,
                        const float* ub, const float* vb, float* ub_out, float* vb_out, float* fb, hipStream_t st) {
-  if (n < 1 || n > kStreamMaxN || wlen < 1 || T < 1 || T > kAdjMaxT) return false;
+  if (n < 1 || n > kAdjStreamMaxN || wlen < 1 || T < 1 || T > kAdjMaxT) return false;
   const int nw = (n + 63) / 64;
   // three levels need 253 registers; a fourth would spill
   switch (T) {

@@ -324,3 +324,38 @@ def test_stream_wide_instances_bitwise(ctx, method_name):
         assert np.array_equal(o[3], ref[3]) and np.array_equal(o[4], ref[4])
         for a, b in zip(o[5:], ref[5:]):
             np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-7 * max(1e-30, np.max(np.abs(b))))
+
+
+@pytest.mark.parametrize("method_name", ["nag", "richardson"])
+def test_stream_widest_instances_bitwise(ctx, method_name):
+    """Row-streaming forward on 1024-thread workgroups (n = 513 .. 1024: 9 to 16 waves
+    holding whole rows): the unroll with checkpoints and residual history equals one
+    launch per step bit for bit, over the whole height and over row windows, with
+    several steps per launch; the adjoint (one reverse step per launch at these widths)
+    agrees too."""
+    from paper_2412_08076_amd import rm
+    method = rm.RM_NAG if method_name == "nag" else rm.RM_RICHARDSON
+    batch = random_batch([513, 700, 1023, 1024], seed=41)
+    m, K, E = 8, 16, 8
+    f = dev(batch.f_packed(), torch.float32)
+    outs = []
+    for cfg in ((-1, 1, 0), (rm.STREAM_SHAPE, 8, 0), (rm.STREAM_SHAPE, 7, 300), (rm.STREAM_SHAPE, 4, 130)):
+        plan = plan_for(ctx, batch)
+        om, al = _weights(batch, m, 13)
+        plan.set_kernel(cfg[0], cfg[1], cw=cfg[2])
+        say("widest stream", method_name, cfg, [plan.get_kernel(k) for k in (513, 1024)])
+        x, h, ck = _unroll(ctx, plan, method, om, al, f, m, K, hist=True, ckpt_every=E)
+        opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=m, K=K, ckpt_every=E)
+        dw = torch.empty(plan.B * m, dtype=torch.float32, device="cuda")
+        da = torch.empty(plan.B * m, dtype=torch.float32, device="cuda")
+        db = torch.empty(plan.P, dtype=torch.float32, device="cuda")
+        loss = torch.empty(plan.B, dtype=torch.float32, device="cuda")
+        rm.rm_solve_adjoint(ctx, plan, method, opts, om, al, f, dev(ck, torch.float32), dw, da, d_b=db, loss=loss)
+        outs.append((x, h, ck, host(db), host(loss), host(dw), host(da)))
+    ref = outs[0]
+    for o in outs[1:]:
+        assert np.array_equal(o[0], ref[0]) and np.array_equal(o[2], ref[2])
+        assert np.allclose(o[1], ref[1], rtol=1e-12, atol=0)
+        assert np.array_equal(o[3], ref[3]) and np.array_equal(o[4], ref[4])
+        for a, b in zip(o[5:], ref[5:]):
+            np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-7 * max(1e-30, np.max(np.abs(b))))

@@ -244,9 +244,17 @@ def test_twogrid_full_size_sampled(ctx):
             rr = problem.relres(c, fs[b], u)
             rr_gpu = problem.relres(c, fs[b], xs[b])
             err = np.linalg.norm(xs[b] - u) / np.linalg.norm(u)
-            say("  instance", b, "kappa", round(batch.kappa[b], 2), "relres", rr, rr_gpu, "err", err)
+            # how far an FP32 rounding of the iterate alone moves the relative residual
+            # (large near resonance, where the symbol amplifies the high modes): the GPU
+            # rounds once per smoothing step, so its residual may differ by m K times that
+            e32 = float(np.finfo(np.float32).eps)
+            prng = np.random.default_rng(b)
+            drr = max(abs(problem.relres(c, fs[b], u * (1.0 + e32 * prng.choice([-1.0, 1.0], u.shape))) - rr)
+                      for _ in range(2))
+            say("  instance", b, "kappa", round(batch.kappa[b], 2), "relres", rr, rr_gpu, "err", err,
+                "fp32 residual sensitivity", drr)
             assert err <= 1e-5
-            assert abs(rr_gpu - rr) <= 1e-5 * max(1.0, rr)
+            assert abs(rr_gpu - rr) <= 1e-5 * max(1.0, rr) + m * K * drr
 
 
 def test_twogrid_autograd_function(ctx):
