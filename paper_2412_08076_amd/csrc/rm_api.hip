@@ -97,9 +97,9 @@ struct rm_ctx {
   std::vector<rm_plan_s*> plans;
   // this device's address of the file-scope scratch array of rm_residual_noalloc
   double* noalloc_scratch = nullptr;
-  // pinned and coherent: active instances per size class, written by the refined solve's
-  // bookkeeping launches before the word above (grown on demand)
-  int* host_cnt = nullptr;
+  // pinned and coherent: (seq << 32) | active instances, per size class, written by the
+  // refined solve's bookkeeping launches like the word above (grown on demand)
+  unsigned long long* host_cnt = nullptr;
   size_t host_cnt_n = 0;
 };
 
@@ -597,13 +597,14 @@ void set_precond(rm_plan_t* pl, const rm_solve_opts* o) {
 // belong to which instance (the main tables' ranges; classes in their tail
 // configuration use the tail tables' ranges, see uses_tail).  `only_class` >= 0
 // restricts the launches to one size class (autotuning); bit c of `tail` selects the
-// tail configuration of class c (classes from 64 on always run their main one).
+// tail configuration of class c (classes from 64 on always run their main one); bit c
+// of `skip` leaves class c out (all of its instances are inactive).
 bool uses_tail(unsigned long long tail, size_t ci) { return ci < 64 && ((tail >> ci) & 1ull) != 0; }
 
 rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int nsteps, const float* omega,
                 const float* alpha, const float* f, float* const us[2], float* const vs[2], int& cur, int& flips,
                 const int* active, double* res_partial, const int** res_ranges, int only_class = -1,
-                unsigned long long tail = 0) {
+                unsigned long long tail = 0, unsigned long long skip = 0) {
   const PlanDev p = pl->dev();
   if (nsteps <= 0) return RM_OK;
   if (!blocked(pl)) {
@@ -638,6 +639,7 @@ rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int ns
   int L = 0;
   for (size_t ci = 0; ci < pl->classes.size(); ++ci) {
     if (only_class >= 0 && (int)ci != only_class) continue;
+    if (uses_tail(skip, ci)) continue;
     const int T = uses_tail(tail, ci) ? pl->classes[ci].tT : pl->classes[ci].T;
     int lc = (nsteps + T - 1) / T;
     if ((lc & 1) != par) ++lc;
@@ -801,7 +803,8 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     if (ctx->host_cnt != nullptr) (void)hipHostFree(ctx->host_cnt);
     ctx->host_cnt = nullptr;
     ctx->host_cnt_n = 0;
-    RM_HIP(hipHostMalloc((void**)&ctx->host_cnt, (size_t)ncls * sizeof(int), hipHostMallocCoherent));
+    RM_HIP(hipHostMalloc((void**)&ctx->host_cnt, (size_t)ncls * sizeof(unsigned long long), hipHostMallocCoherent));
+    for (int ci = 0; ci < ncls; ++ci) __atomic_store_n(ctx->host_cnt + ci, 0ull, __ATOMIC_RELEASE);
     ctx->host_cnt_n = (size_t)ncls;
   }
   // pinned host copies of the per-round reads: r2, b2 (double), then status, tot, count (int)
@@ -859,7 +862,7 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   RM_HIP(hipMemcpyAsync(mask, mask_h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
   int flips_per_outer = 0;
   // one captured outer iteration per combination of main and tail configurations
-  std::map<unsigned long long, GraphHolder> graphs;
+  std::map<std::pair<unsigned long long, unsigned long long>, GraphHolder> graphs;
   bool use_graph = (o->flags & RM_FLAG_GRAPH) != 0;
   // Per size class: its tail configuration runs once fewer than thr[c] of its
   // instances are active (0: never; the first 64 classes can switch).
@@ -930,21 +933,22 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     int cur = 0;
     // one outer iteration: sweep of m steps with the residual fused into its last
     // launch, per-instance reduction, convergence bookkeeping
-    auto outer_iteration = [&](unsigned long long tail, unsigned seq) -> rm_status {
+    using Config = std::pair<unsigned long long, unsigned long long>;  // (tail mask, skip mask)
+    auto outer_iteration = [&](Config cf, unsigned seq) -> rm_status {
       int flips = 0;
       const int* ranges = nullptr;
       RM_TRY(sweep(pl, st, method, o->m, 0, o->m, omega, alpha, r32, ds, vs, cur, flips, active, partial, &ranges, -1,
-                   tail));
+                   cf.first, cf.second));
       flips_per_outer = flips;
       rmk::launch_outer_flags(p, partial, ranges, ranges != nullptr ? pl->d_tranges.as<int>() : nullptr,
-                              pl->d_cls.as<int>(), tail, ncls, res2, rhs2, target2, best2, since, gains, stall_min,
-                              stall_max, o->max_outer, active, count, status, n_active, ctx->host_word,
+                              pl->d_cls.as<int>(), cf.first, ncls, res2, rhs2, target2, best2, since, gains,
+                              stall_min, stall_max, o->max_outer, active, count, status, n_active, ctx->host_word,
                               ctx->host_cnt, seq, tot, hist, o->hist_len, st);
       return RM_OK;
     };
     // The iteration returns to buffer set 0, so one captured iteration can be
     // replayed; captured on first use per configuration and reused by every round.
-    auto capture = [&](unsigned long long g) {
+    auto capture = [&](Config g) {
       const int cur0 = cur;
       GraphHolder& gh = graphs[g];
       if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
@@ -963,22 +967,39 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
       (void)hipGetLastError();
       cur = cur0;
     };
-    // the configuration of every class follows its active count seen at the last poll
-    auto counts_seen = [&](int ci) { return __atomic_load_n(ctx->host_cnt + ci, __ATOMIC_ACQUIRE); };
-    unsigned long long tail = tail_mask([&](int ci) { return round_cnt[ci]; });
+    // Every class's configuration follows its active count seen at the last poll, and a
+    // class with no active instance left is not launched (instances become active again
+    // only when a round starts).  A count is taken only if a launch of this round wrote
+    // it (its stamp is at least the round's first launch number), or, after a
+    // synchronisation, whatever the stamp (captured launches carry none).
+    const unsigned seq0 = ctx->seq + 1u;
+    auto read_counts = [&](bool synced) {
+      for (int ci = 0; ci < ncls; ++ci) {
+        const unsigned long long w = __atomic_load_n(ctx->host_cnt + ci, __ATOMIC_ACQUIRE);
+        if (synced || (int)((unsigned)(w >> 32) - seq0) >= 0) round_cnt[ci] = (int)(w & 0xffffffffull);
+      }
+    };
+    auto config = [&]() {
+      Config cf{tail_mask([&](int ci) { return round_cnt[ci]; }), 0ull};
+      for (int ci = 0; ci < ncls && ci < 64; ++ci)
+        if (round_cnt[ci] == 0) cf.second |= 1ull << ci;
+      return cf;
+    };
+    Config cfg = config();
     if (use_graph) {
-      // captured iterations: synchronise every check_every of them and read the count
+      // captured iterations: synchronise every check_every of them and read the counts
       for (int k = 1;; ++k) {
-        if (use_graph && (graphs.count(tail) == 0 || graphs[tail].exec == nullptr)) capture(tail);
+        if (use_graph && (graphs.count(cfg) == 0 || graphs[cfg].exec == nullptr)) capture(cfg);
         if (use_graph)
-          RM_HIP(hipGraphLaunch(graphs[tail].exec, st));
+          RM_HIP(hipGraphLaunch(graphs[cfg].exec, st));
         else
-          RM_TRY(outer_iteration(tail, 0u));  // the capture failed: launch directly
+          RM_TRY(outer_iteration(cfg, 0u));  // the capture failed: launch directly
         if (k % o->check_every == 0 || k >= o->max_outer) {
           RM_HIP(hipStreamSynchronize(st));
           const int na = (int)(__atomic_load_n(ctx->host_word, __ATOMIC_ACQUIRE) & 0xffffffffull);
           if (na == 0 || k >= o->max_outer) break;
-          tail = tail_mask(counts_seen);
+          read_counts(true);
+          cfg = config();
         }
       }
     } else {
@@ -990,7 +1011,7 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
       int issued = 0;
       auto issue = [&]() -> rm_status {
         ++issued;
-        return outer_iteration(tail, ++ctx->seq);
+        return outer_iteration(cfg, ++ctx->seq);
       };
       RM_TRY(issue());
       for (;;) {
@@ -1000,7 +1021,8 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
         RM_TRY(wait_word(ctx, st, more ? ctx->seq - 1u : ctx->seq, w));
         const int na = (int)(w & 0xffffffffull);
         if (na == 0 || !more) break;
-        tail = tail_mask(counts_seen);
+        read_counts(false);
+        cfg = config();
       }
     }
     // no synchronisation here: the next round's update and residual queue behind the

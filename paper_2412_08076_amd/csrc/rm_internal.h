@@ -96,15 +96,16 @@ void launch_refine_update(const PlanDev& p, double* x, const float* d0, const fl
 // table.  With host_word (pinned host memory, may be null) the count is also published
 // there as one 64-bit word, (seq << 32) | count, so a host thread that reads the word
 // knows which launch wrote it; host_cnt (pinned, may be null) receives the active
-// instances of each of the ncls classes first (cls may be null when ncls <= 1).
+// instances of each of the ncls classes as words of the same form (cls may be null when
+// ncls <= 1).
 // With hist given, an active instance also stores res2 at hist[k * B + b], k = tot[b] + (its
 // outer count in this round) - 1, when k < hist_len.
 void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ranges, const int* tranges,
                         const int* cls, unsigned long long tailmask, int ncls, double* res2, const double* rhs2,
                         const double* target2, double* best2, int* since, int* gains, int stall_min, int stall_max,
                         int cap, int* active, int* outer_count, int* status, int* n_active,
-                        unsigned long long* host_word, int* host_cnt, unsigned seq, const int* tot, double* hist,
-                        int hist_len, hipStream_t st);
+                        unsigned long long* host_word, unsigned long long* host_cnt, unsigned seq,
+                        const int* tot, double* hist, int hist_len, hipStream_t st);
 // Start of a refinement round from staged[0, B) = inner targets (double) and
 // staged[B, 1.5 B) = the round mask (int): target2, mask, active, rhs2 = best2 = r2,
 // tot += count, and zero outer counts and stagnation counters.

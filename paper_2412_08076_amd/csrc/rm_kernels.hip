@@ -326,7 +326,8 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
     double* __restrict__ res2, const double* __restrict__ rhs2, const double* __restrict__ target2,
     double* __restrict__ best2, int* __restrict__ since, int* __restrict__ gains, int stall_min, int stall_max,
     int cap, int* __restrict__ active, int* __restrict__ outer_count, int* __restrict__ status,
-    int* __restrict__ n_active, unsigned long long* __restrict__ host_word, int* __restrict__ host_cnt, unsigned seq,
+    int* __restrict__ n_active, unsigned long long* __restrict__ host_word,
+    unsigned long long* __restrict__ host_cnt, unsigned seq,
     const int* __restrict__ tot, double* __restrict__ hist, int hist_len) {
   __shared__ int kept[16];
   extern __shared__ int per_class[];  // [ncls] active instances per size class
@@ -380,14 +381,16 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
     int total = 0;
     for (int k = 0; k < (int)(blockDim.x >> 6); ++k) total += kept[k];
     *n_active = total;
-    // straight to the host's pinned copies (system scope, vector stores): the per-class
-    // counts first, then the sequence-stamped total with release ordering, so a host
-    // thread that sees the new stamp also sees the counts
+    // straight to the host's pinned copies (system scope, vector stores), each one
+    // 64-bit word stamped with the launch number, so the host can tell which launch
+    // wrote it without any ordering between the words: the per-class counts, then the
+    // total
     if (host_word != nullptr) {
       if (host_cnt != nullptr)
         for (int c = 0; c < ncls; ++c)
-          __hip_atomic_store(host_cnt + c, per_class[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_store(host_word, ((unsigned long long)seq << 32) | (unsigned)total, __ATOMIC_RELEASE,
+          __hip_atomic_store(host_cnt + c, ((unsigned long long)seq << 32) | (unsigned)per_class[c],
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(host_word, ((unsigned long long)seq << 32) | (unsigned)total, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
@@ -786,8 +789,8 @@ void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ran
                         const int* cls, unsigned long long tailmask, int ncls, double* res2, const double* rhs2,
                         const double* target2, double* best2, int* since, int* gains, int stall_min, int stall_max,
                         int cap, int* active, int* outer_count, int* status, int* n_active,
-                        unsigned long long* host_word, int* host_cnt, unsigned seq, const int* tot, double* hist,
-                        int hist_len, hipStream_t st) {
+                        unsigned long long* host_word, unsigned long long* host_cnt, unsigned seq,
+                        const int* tot, double* hist, int hist_len, hipStream_t st) {
   const int threads = 64 * std::min(16, std::max(1, (p.B + 63) / 64));
   hipLaunchKernelGGL(k_outer_flags, dim3(1), dim3(threads), (size_t)std::max(1, ncls) * sizeof(int), st, p,
                      partial2, ranges, tranges, cls, tailmask, ncls, res2, rhs2, target2, best2, since, gains,
