@@ -787,6 +787,7 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   RM_HIP(hipStreamWaitEvent(ctx->work, ctx->handoff, 0));
   hipStream_t st = ctx->work;
   const int B = pl->B;
+  const int H = o->max_rounds + 1;  // rows of the per-round history
   const size_t fb = vec_bytes<float>(pl);
   RM_TRY(pl->vecA.ensure(fb, st));  // r32
   RM_TRY(pl->vecB.ensure(fb, st));  // d0
@@ -795,8 +796,8 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   RM_TRY(pl->vecE.ensure(fb, st));  // v1
   RM_TRY(build_exec(pl, st));
   RM_TRY(pl->partial.ensure(partial_slots(pl) * 2 * sizeof(double), st));
-  RM_TRY(pl->red.ensure((size_t)B * 8 * sizeof(double), st));
-  RM_TRY(pl->flags.ensure(((size_t)B * 7 + 16) * sizeof(int), st));
+  RM_TRY(pl->red.ensure(((size_t)B * 8 + (size_t)H * B) * sizeof(double), st));
+  RM_TRY(pl->flags.ensure(((size_t)B * 13 + 16) * sizeof(int), st));
   const int ncls = (int)pl->classes.size();
   if (ctx->host_cnt_n < (size_t)ncls) {
     RM_HIP(hipStreamSynchronize(st));
@@ -807,8 +808,9 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     for (int ci = 0; ci < ncls; ++ci) __atomic_store_n(ctx->host_cnt + ci, 0ull, __ATOMIC_RELEASE);
     ctx->host_cnt_n = (size_t)ncls;
   }
-  // pinned host copies of the per-round reads: r2, b2 (double), then status, tot, count (int)
-  const size_t pin_need = 2 * (size_t)B * sizeof(double) + 3 * (size_t)B * sizeof(int);
+  // pinned host copies of the final per-instance results: history [H][B], relres (double),
+  // then status, rounds, tot, count (int)
+  const size_t pin_need = ((size_t)H + 1) * B * sizeof(double) + 4 * (size_t)B * sizeof(int);
   if (ctx->pin_bytes < pin_need) {
     RM_HIP(hipStreamSynchronize(st));
     if (ctx->pin != nullptr) (void)hipHostFree(ctx->pin);
@@ -820,52 +822,56 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
   float* r32 = pl->vecA.as<float>();
   float* ds[2] = {pl->vecB.as<float>(), pl->vecD.as<float>()};
   float* vs[2] = {pl->vecC.as<float>(), pl->vecE.as<float>()};
-  double* r2 = pl->red.as<double>();      // [B]  ||b - A x||^2 (FP64)
-  double* b2 = r2 + B;                    // [B]  ||b||^2
-  double* rhs2 = r2 + 2 * B;              // [B]  ||r_j||^2 of the current round
-  double* res2 = r2 + 3 * B;              // [B]  inner residual^2 after an outer iteration
-  double* target2 = r2 + 4 * B;           // [B]  inner residual^2 that ends the round
-  double* best2 = r2 + 5 * B;             // [B]  smallest inner residual^2 so far (stagnation)
-  double* staged = r2 + 6 * B;            // [B] targets + [B] int mask, copied in once per round
-  int* active = pl->flags.as<int>();      // [B]
-  int* count = active + B;                // [B]
-  int* status = active + 2 * B;           // [B]
-  int* mask = active + 3 * B;             // [B]
-  int* since = active + 4 * B;            // [B]  outer iterations since the last 10 % gain
-  int* gains = active + 5 * B;            // [B]  10 % gains so far in this round
-  int* n_active = active + 6 * B;         // [1]
-  int* tot = active + 6 * B + 16;         // [B]  outer iterations of the rounds before the current one
+  double* dd = pl->red.as<double>();
+  rmk::RoundState rs;
+  double* res2 = dd;            // [B]  inner residual^2 after an outer iteration
+  rs.rhs2 = dd + B;             // [B]  ||r_j||^2 of the instance's current round
+  rs.target2 = dd + 2 * B;      // [B]  inner residual^2 that ends the round
+  rs.best2 = dd + 3 * B;        // [B]  smallest inner residual^2 of the round (stagnation)
+  rs.prev_rho = dd + 4 * B;     // [B]  rho of the previous round
+  rs.relres = dd + 5 * B;       // [B]  the last rho
+  rs.history = dd + 8 * B;      // [H][B]
+  int* ii = pl->flags.as<int>();
+  rs.active = ii;               // [B]  in an inner solve
+  rs.count = ii + B;            // [B]  outer iterations of the current round
+  rs.status = ii + 2 * B;       // [B]
+  rs.pending = ii + 3 * B;      // [B]  round ended, refinement step not yet taken
+  rs.since = ii + 4 * B;        // [B]  outer iterations since the last 10 % gain
+  rs.gains = ii + 5 * B;        // [B]  10 % gains so far in this round
+  rs.tot = ii + 6 * B;          // [B]  outer iterations of the instance's earlier rounds
+  rs.round = ii + 7 * B;        // [B]  rounds started
+  rs.strikes = ii + 8 * B;      // [B]  rounds that did not halve rho
+  rs.start = ii + 9 * B;        // [B]  outer iteration of the solve at which the round began
+  int* n_active = ii + 13 * B;  // [1]
   double* partial = pl->partial.as<double>();
   const PlanDev p = pl->dev();
-
-  std::vector<int> done(B, 0), st_h(B, RM_OK), rounds(B, 0), mask_h(B, 1);
-  std::vector<double> relres(B, 0.0), prev_rho(B, 0.0);
-  std::vector<double> staged_h(2 * (size_t)B, 0.0);  // inner targets, then the round mask as int
-  double* rb_h = static_cast<double*>(ctx->pin);     // r2, b2
-  const double* r2_h = rb_h;
-  const double* b2_h = rb_h + B;
-  int* dst_h = reinterpret_cast<int*>(rb_h + 2 * (size_t)B);
-  int* tot_h = dst_h + B;
-  int* cnt_h = tot_h + B;
-  double* target2_h = staged_h.data();
-  int* smask_h = reinterpret_cast<int*>(staged_h.data() + B);
-  std::vector<int> strikes(B, 0);
   // stagnation window bounds in outer iterations (about 256 and 4096 inner steps)
   const int stall_min = std::max(16, (256 + o->m - 1) / o->m);
   const int stall_max = std::max(16, (4096 + o->m - 1) / o->m);
-  rmk::launch_fill_i32(status, 0, B, st);
-  rmk::launch_fill_i32(count, 0, B, st);
-  rmk::launch_fill_i32(tot, 0, B, st);
+  rmk::launch_fill_i32(ii, 0, (int64_t)B * 10, st);
+  rmk::launch_fill_i32(rs.pending, 1, B, st);  // every instance starts with a refinement step
+  rmk::launch_fill_f64(rs.history, -1.0, (int64_t)H * B, st);
   if (hist != nullptr) rmk::launch_fill_f64(hist, -1.0, (int64_t)o->hist_len * B, st);
-  if (rep != nullptr && rep->history != nullptr)
-    std::fill(rep->history, rep->history + (size_t)(o->max_rounds + 1) * B, -1.0);
-  RM_HIP(hipMemcpyAsync(mask, mask_h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+  rmk::RoundParams rp{o->tol, o->tol_inner, o->max_rounds, 0};
   int flips_per_outer = 0;
+  // Refinement step of every waiting instance before outer iteration g of the solve:
+  // x += d of the ended round, r = b - A x in FP64, r32 = fl32(r), d = v = 0 in the buffer
+  // set iteration g reads, then the decision.  Each instance runs its rounds on its own:
+  // one that ends a round starts the next while the others go on.
+  auto refine_step = [&](long long g, bool first) {
+    if (!first) rmk::launch_refine_update(p, x, ds[0], ds[1], rs.start, rs.count, flips_per_outer, rs.pending, st);
+    const int set = (int)((g * flips_per_outer) & 1);
+    rmk::launch_refine_residual(p, b, x, r32, ds[set], vs[set], partial, rs.pending, st);
+    rp.start = (int)g;
+    rmk::launch_round_decide(p, partial, rp, rs, st);
+  };
+  refine_step(0, true);
+
   // one captured outer iteration per combination of main and tail configurations
   std::map<std::pair<unsigned long long, unsigned long long>, GraphHolder> graphs;
   bool use_graph = (o->flags & RM_FLAG_GRAPH) != 0;
   // Per size class: its tail configuration runs once fewer than thr[c] of its
-  // instances are active (0: never; the first 64 classes can switch).
+  // instances are not done (0: never; the first 64 classes can switch).
   std::vector<int> thr(ncls, 0);
   for (int ci = 0; ci < ncls && ci < 64; ++ci) {
     const auto& c = pl->classes[ci];
@@ -875,79 +881,51 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
     const int size = (int)c.insts.size();
     thr[ci] = frac >= 1.0 ? size + 1 : (int)std::ceil(frac * size);
   }
-  auto tail_mask = [&](auto active_in) {
-    unsigned long long mk = 0;
-    for (int ci = 0; ci < ncls && ci < 64; ++ci)
-      if (active_in(ci) < thr[ci]) mk |= 1ull << ci;
-    return mk;
-  };
-  std::vector<int> round_cnt(ncls, 0);
-  for (int j = 0;; ++j) {
-    if (j > 0) rmk::launch_refine_update(p, x, ds[0], ds[1], count, flips_per_outer, mask, st);
-    rmk::launch_refine_residual(p, b, x, r32, ds[0], vs[0], partial, mask, st);
-    rmk::launch_reduce_partials(p, partial, r2, b2, 1, nullptr, st);
-    RM_HIP(hipMemcpyAsync(rb_h, r2, 2 * (size_t)B * sizeof(double), hipMemcpyDeviceToHost, st));  // r2, b2
-    RM_HIP(hipMemcpyAsync(dst_h, status, B * sizeof(int), hipMemcpyDeviceToHost, st));
-    RM_HIP(hipStreamSynchronize(st));
-    RM_TRY(last_launch());
-    int n_round = 0;
-    for (int bi = 0; bi < B; ++bi) {
-      if (done[bi]) {
-        mask_h[bi] = 0;
-        continue;
-      }
-      const double rho = b2_h[bi] > 0.0 ? std::sqrt(r2_h[bi] / b2_h[bi]) : std::sqrt(r2_h[bi]);
-      relres[bi] = rho;
-      if (rep != nullptr && rep->history != nullptr) rep->history[(size_t)j * B + bi] = rho;
-      if (!std::isfinite(rho) || dst_h[bi] == RM_EDIVERGED) {
-        done[bi] = 1;
-        st_h[bi] = RM_EDIVERGED;
-      } else if (rho <= o->tol || r2_h[bi] == 0.0) {
-        done[bi] = 1;
-        st_h[bi] = RM_OK;
-      } else if (j >= o->max_rounds) {
-        done[bi] = 1;
-        st_h[bi] = RM_ENOTCONV;
-      } else if (j > 0 && rho > 0.5 * prev_rho[bi] && ++strikes[bi] >= 2) {
-        done[bi] = 1;  // two rounds without halving the residual: give up
-        st_h[bi] = RM_ENOTCONV;
-      }
-      prev_rho[bi] = rho;
-      mask_h[bi] = done[bi] ? 0 : 1;
-      if (!done[bi]) {
-        ++n_round;
-        ++rounds[bi];
-        // inner target: tol_inner, relaxed in the last round to what reaching tol needs
-        const double tau = std::max(o->tol_inner, 0.5 * o->tol / rho);
-        target2_h[bi] = tau * tau * r2_h[bi];
-      }
+  // instances per class not yet done, as last seen (all of them before the first poll)
+  std::vector<int> live(ncls, 0);
+  for (int ci = 0; ci < ncls; ++ci) live[ci] = (int)pl->classes[ci].insts.size();
+  using Config = std::pair<unsigned long long, unsigned long long>;  // (tail mask, skip mask)
+  auto config = [&]() {
+    Config cf{0ull, 0ull};
+    for (int ci = 0; ci < ncls && ci < 64; ++ci) {
+      if (live[ci] < thr[ci]) cf.first |= 1ull << ci;
+      if (live[ci] == 0) cf.second |= 1ull << ci;
     }
-    if (n_round == 0) break;
-    std::fill(round_cnt.begin(), round_cnt.end(), 0);
-    for (int ci = 0; ci < ncls; ++ci)
-      for (int bi : pl->classes[ci].insts) round_cnt[ci] += mask_h[bi];
-    // inner solve A d = r32 on the instances of this round
-    for (int bi = 0; bi < B; ++bi) smask_h[bi] = mask_h[bi];
-    RM_HIP(hipMemcpyAsync(staged, staged_h.data(), 2 * (size_t)B * sizeof(double), hipMemcpyHostToDevice, st));
-    rmk::launch_round_start(B, staged, r2, rhs2, best2, target2, mask, active, count, tot, since, gains, st);
-    int cur = 0;
-    // one outer iteration: sweep of m steps with the residual fused into its last
-    // launch, per-instance reduction, convergence bookkeeping
-    using Config = std::pair<unsigned long long, unsigned long long>;  // (tail mask, skip mask)
-    auto outer_iteration = [&](Config cf, unsigned seq) -> rm_status {
-      int flips = 0;
-      const int* ranges = nullptr;
-      RM_TRY(sweep(pl, st, method, o->m, 0, o->m, omega, alpha, r32, ds, vs, cur, flips, active, partial, &ranges, -1,
-                   cf.first, cf.second));
-      flips_per_outer = flips;
-      rmk::launch_outer_flags(p, partial, ranges, ranges != nullptr ? pl->d_tranges.as<int>() : nullptr,
-                              pl->d_cls.as<int>(), cf.first, ncls, res2, rhs2, target2, best2, since, gains,
-                              stall_min, stall_max, o->max_outer, active, count, status, n_active, ctx->host_word,
-                              ctx->host_cnt, seq, tot, hist, o->hist_len, st);
-      return RM_OK;
-    };
-    // The iteration returns to buffer set 0, so one captured iteration can be
-    // replayed; captured on first use per configuration and reused by every round.
+    return cf;
+  };
+  int cur = 0;
+  // one outer iteration: sweep of m steps with the residual fused into its last
+  // launch, per-instance reduction, convergence bookkeeping
+  auto outer_iteration = [&](Config cf, unsigned seq) -> rm_status {
+    int flips = 0;
+    const int* ranges = nullptr;
+    RM_TRY(sweep(pl, st, method, o->m, 0, o->m, omega, alpha, r32, ds, vs, cur, flips, rs.active, partial, &ranges,
+                 -1, cf.first, cf.second));
+    flips_per_outer = flips;
+    rmk::launch_outer_flags(p, partial, ranges, ranges != nullptr ? pl->d_tranges.as<int>() : nullptr,
+                            pl->d_cls.as<int>(), cf.first, ncls, res2, rs.rhs2, rs.target2, rs.best2, rs.since,
+                            rs.gains, stall_min, stall_max, o->max_outer, rs.active, rs.count, rs.status, rs.pending,
+                            n_active, ctx->host_word, ctx->host_cnt, seq, rs.tot, hist, o->hist_len, st);
+    return RM_OK;
+  };
+  // A class word counts only if a launch of this solve wrote it (its stamp is at least
+  // the solve's first launch number), or, after a synchronisation, whatever the stamp
+  // (captured launches carry none).
+  const unsigned seq0 = ctx->seq + 1u;
+  auto read_counts = [&](bool synced) {
+    for (int ci = 0; ci < ncls; ++ci) {
+      const unsigned long long w = __atomic_load_n(ctx->host_cnt + ci, __ATOMIC_ACQUIRE);
+      if (synced || (int)((unsigned)(w >> 32) - seq0) >= 0) live[ci] = (int)(w & 0xffffffffull);
+    }
+  };
+  // every instance's rounds together are capped, so the solve is too
+  const long long cap = (long long)(o->max_rounds + 1) * ((long long)o->max_outer + 1) + 2;
+  long long issued = 0;  // outer iterations enqueued
+  Config cfg = config();
+  if (use_graph) {
+    // The iteration returns to buffer set 0, so one captured iteration can be replayed;
+    // captured on first use per configuration.  Synchronise every check_every replays,
+    // read the counts and take the refinement steps of the rounds that ended.
     auto capture = [&](Config g) {
       const int cur0 = cur;
       GraphHolder& gh = graphs[g];
@@ -967,84 +945,87 @@ rm_status solve_to_tol(rm_ctx* ctx, rm_plan_t* pl, int method, const rm_solve_op
       (void)hipGetLastError();
       cur = cur0;
     };
-    // Every class's configuration follows its active count seen at the last poll, and a
-    // class with no active instance left is not launched (instances become active again
-    // only when a round starts).  A count is taken only if a launch of this round wrote
-    // it (its stamp is at least the round's first launch number), or, after a
-    // synchronisation, whatever the stamp (captured launches carry none).
-    const unsigned seq0 = ctx->seq + 1u;
-    auto read_counts = [&](bool synced) {
-      for (int ci = 0; ci < ncls; ++ci) {
-        const unsigned long long w = __atomic_load_n(ctx->host_cnt + ci, __ATOMIC_ACQUIRE);
-        if (synced || (int)((unsigned)(w >> 32) - seq0) >= 0) round_cnt[ci] = (int)(w & 0xffffffffull);
-      }
-    };
-    auto config = [&]() {
-      Config cf{tail_mask([&](int ci) { return round_cnt[ci]; }), 0ull};
-      for (int ci = 0; ci < ncls && ci < 64; ++ci)
-        if (round_cnt[ci] == 0) cf.second |= 1ull << ci;
-      return cf;
-    };
-    Config cfg = config();
-    if (use_graph) {
-      // captured iterations: synchronise every check_every of them and read the counts
-      for (int k = 1;; ++k) {
-        if (use_graph && (graphs.count(cfg) == 0 || graphs[cfg].exec == nullptr)) capture(cfg);
-        if (use_graph)
-          RM_HIP(hipGraphLaunch(graphs[cfg].exec, st));
-        else
-          RM_TRY(outer_iteration(cfg, 0u));  // the capture failed: launch directly
-        if (k % o->check_every == 0 || k >= o->max_outer) {
-          RM_HIP(hipStreamSynchronize(st));
-          const int na = (int)(__atomic_load_n(ctx->host_word, __ATOMIC_ACQUIRE) & 0xffffffffull);
-          if (na == 0 || k >= o->max_outer) break;
-          read_counts(true);
-          cfg = config();
-        }
-      }
-    } else {
-      // One outer iteration stays queued while the host waits for the count of the
-      // iteration before it, so the GPU does not idle for the host's round trip; the
-      // configuration of each iteration follows the counts two iterations back.
-      // The context's launch number advances before each launch, so a later solve never
-      // mistakes a word of this one for its own.
-      int issued = 0;
-      auto issue = [&]() -> rm_status {
-        ++issued;
-        return outer_iteration(cfg, ++ctx->seq);
-      };
-      RM_TRY(issue());
-      for (;;) {
-        const bool more = issued < o->max_outer;
-        if (more) RM_TRY(issue());
-        unsigned long long w = 0;
-        RM_TRY(wait_word(ctx, st, more ? ctx->seq - 1u : ctx->seq, w));
-        const int na = (int)(w & 0xffffffffull);
-        if (na == 0 || !more) break;
-        read_counts(false);
+    for (;;) {
+      if (use_graph && (graphs.count(cfg) == 0 || graphs[cfg].exec == nullptr)) capture(cfg);
+      if (use_graph)
+        RM_HIP(hipGraphLaunch(graphs[cfg].exec, st));
+      else
+        RM_TRY(outer_iteration(cfg, 0u));  // the capture failed: launch directly
+      ++issued;
+      if (issued % o->check_every == 0 || issued >= cap) {
+        RM_HIP(hipStreamSynchronize(st));
+        const int left = (int)(__atomic_load_n(ctx->host_word, __ATOMIC_ACQUIRE) & 0xffffffffull);
+        const int waiting = (int)(__atomic_load_n(ctx->host_word + 1, __ATOMIC_ACQUIRE) & 0xffffffffull);
+        if (left == 0 || issued >= cap) break;
+        if (waiting > 0) refine_step(issued, false);
+        read_counts(true);
         cfg = config();
       }
     }
-    // no synchronisation here: the next round's update and residual queue behind the
-    // inner solve, and its count is added to tot when that round starts
+  } else {
+    // One outer iteration stays queued while the host waits for the words of the
+    // iteration before it, so the GPU does not idle for the host's round trip; the
+    // configuration of each iteration follows the counts two iterations back.  When that
+    // iteration reports rounds waiting for their refinement step, the step is queued
+    // before the next iteration (words older than the last step are not taken for it).
+    // The context's launch number advances before each launch, so a later solve never
+    // mistakes a word of this one for its own.
+    long long refined_after = -1;  // the last refinement step ran after this iteration
+    auto issue = [&]() -> rm_status {
+      ++issued;
+      return outer_iteration(cfg, ++ctx->seq);
+    };
+    RM_TRY(issue());
+    for (;;) {
+      const bool more = issued < cap;
+      if (more) RM_TRY(issue());
+      const long long k = more ? issued - 2 : issued - 1;  // the iteration whose words are read
+      unsigned long long w = 0;
+      RM_TRY(wait_word(ctx, st, more ? ctx->seq - 1u : ctx->seq, w));
+      const int left = (int)(w & 0xffffffffull);
+      if (left == 0 || !more) break;
+      const unsigned long long wp = __atomic_load_n(ctx->host_word + 1, __ATOMIC_ACQUIRE);
+      const bool fresh = (int)((unsigned)(wp >> 32) - (unsigned)(seq0 + k)) >= 0;
+      if (fresh && (wp & 0xffffffffull) > 0 && k > refined_after) {
+        refine_step(issued, false);
+        refined_after = issued - 1;
+      }
+      read_counts(false);
+      cfg = config();
+    }
   }
-  RM_HIP(hipMemcpyAsync(tot_h, tot, B * sizeof(int), hipMemcpyDeviceToHost, st));
-  RM_HIP(hipMemcpyAsync(cnt_h, count, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  // instances still in a solve or waiting at the cap: mark them as not converged
+  double* hist_h = static_cast<double*>(ctx->pin);
+  double* relres_h = hist_h + (size_t)H * B;
+  int* status_h = reinterpret_cast<int*>(relres_h + B);
+  int* rounds_h = status_h + B;
+  int* tot_h = rounds_h + B;
+  int* cnt_h = tot_h + B;
+  RM_HIP(hipMemcpyAsync(hist_h, rs.history, (size_t)H * B * sizeof(double), hipMemcpyDeviceToHost, st));
+  RM_HIP(hipMemcpyAsync(relres_h, rs.relres, B * sizeof(double), hipMemcpyDeviceToHost, st));
+  RM_HIP(hipMemcpyAsync(status_h, rs.status, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  RM_HIP(hipMemcpyAsync(rounds_h, rs.round, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  RM_HIP(hipMemcpyAsync(tot_h, rs.tot, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  RM_HIP(hipMemcpyAsync(cnt_h, rs.count, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  std::vector<int> act_h(B, 0), pend_h(B, 0);
+  RM_HIP(hipMemcpyAsync(act_h.data(), rs.active, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  RM_HIP(hipMemcpyAsync(pend_h.data(), rs.pending, B * sizeof(int), hipMemcpyDeviceToHost, st));
   RM_HIP(hipStreamSynchronize(st));
-  std::vector<long long> outer_tot(B, 0);
-  for (int bi = 0; bi < B; ++bi) outer_tot[bi] = (long long)tot_h[bi] + cnt_h[bi];
   rm_status worst = RM_OK;
   for (int bi = 0; bi < B; ++bi) {
-    if (st_h[bi] == RM_EDIVERGED) worst = RM_EDIVERGED;
-    else if (st_h[bi] == RM_ENOTCONV && worst == RM_OK) worst = RM_ENOTCONV;
+    if ((act_h[bi] || pend_h[bi]) && status_h[bi] == 0) status_h[bi] = RM_ENOTCONV;
+    if (status_h[bi] == RM_EDIVERGED) worst = RM_EDIVERGED;
+    else if (status_h[bi] == RM_ENOTCONV && worst == RM_OK) worst = RM_ENOTCONV;
   }
   if (rep != nullptr) {
     for (int bi = 0; bi < B; ++bi) {
-      if (rep->outer_iters) rep->outer_iters[bi] = (int32_t)std::min<long long>(outer_tot[bi], INT32_MAX);
-      if (rep->rounds) rep->rounds[bi] = rounds[bi];
-      if (rep->relres) rep->relres[bi] = relres[bi];
-      if (rep->status) rep->status[bi] = st_h[bi];
+      if (rep->outer_iters)
+        rep->outer_iters[bi] = (int32_t)std::min<long long>((long long)tot_h[bi] + cnt_h[bi], INT32_MAX);
+      if (rep->rounds) rep->rounds[bi] = rounds_h[bi];
+      if (rep->relres) rep->relres[bi] = relres_h[bi];
+      if (rep->status) rep->status[bi] = status_h[bi];
     }
+    if (rep->history != nullptr) std::memcpy(rep->history, hist_h, (size_t)H * B * sizeof(double));
   }
   RM_TRY(last_launch());
   if (worst != RM_OK) g_last_error = worst == RM_EDIVERGED ? "an instance diverged" : "an instance hit a cap";

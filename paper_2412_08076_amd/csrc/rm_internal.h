@@ -84,9 +84,26 @@ void launch_refine_residual(const PlanDev& p, const double* b, const double* x, 
                             float* d, float* v, double* partial2, const int* round_mask,
                             hipStream_t st);
 // x += d for instances with round_mask[b] != 0; d is d0 or d1 depending on the parity of
-// outer_count[b] * flips (the inner solve swaps its two buffers `flips` times per outer iteration)
-void launch_refine_update(const PlanDev& p, double* x, const float* d0, const float* d1,
+// (start[b] + outer_count[b]) * flips (the solve swaps its two buffers `flips` times per
+// outer iteration, and the instance's round began at outer iteration start[b] of the solve;
+// start may be null: 0)
+void launch_refine_update(const PlanDev& p, double* x, const float* d0, const float* d1, const int* start,
                           const int* outer_count, int flips, const int* round_mask, hipStream_t st);
+// Per-instance refinement state of the refined solve (device arrays of length B; history
+// [max_rounds + 1][B]).
+struct RoundState {
+  int *pending, *active, *status, *round, *strikes, *start, *tot, *count, *since, *gains;
+  double *prev_rho, *relres, *history, *target2, *rhs2, *best2;
+};
+struct RoundParams {
+  double tol, tol_inner;
+  int max_rounds, start;
+};
+// The decision at the end of each waiting instance's round (k_round_decide): from the
+// refinement residual's partials (one-step tile table), record rho, finish the instance or
+// start its next inner solve at outer iteration rp.start.
+void launch_round_decide(const PlanDev& p, const double* partial2, const RoundParams& rp, RoundState rs,
+                         hipStream_t st);
 // Inner-solve bookkeeping after one outer iteration, one launch: res2[b] = the sum of the
 // instance's residual partials in slot order, then for active
 // instances the outer count, divergence / target / cap / stagnation tests and the new
@@ -97,20 +114,17 @@ void launch_refine_update(const PlanDev& p, double* x, const float* d0, const fl
 // there as one 64-bit word, (seq << 32) | count, so a host thread that reads the word
 // knows which launch wrote it; host_cnt (pinned, may be null) receives the active
 // instances of each of the ncls classes as words of the same form (cls may be null when
-// ncls <= 1).
+// ncls <= 1).  With pending given, an instance whose inner solve ends sets pending[b] and
+// counts as not done (so do instances already waiting); host_word[1] then receives the
+// count of waiting instances, and the counts above include them.
 // With hist given, an active instance also stores res2 at hist[k * B + b], k = tot[b] + (its
 // outer count in this round) - 1, when k < hist_len.
 void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ranges, const int* tranges,
                         const int* cls, unsigned long long tailmask, int ncls, double* res2, const double* rhs2,
                         const double* target2, double* best2, int* since, int* gains, int stall_min, int stall_max,
-                        int cap, int* active, int* outer_count, int* status, int* n_active,
+                        int cap, int* active, int* outer_count, int* status, int* pending, int* n_active,
                         unsigned long long* host_word, unsigned long long* host_cnt, unsigned seq,
                         const int* tot, double* hist, int hist_len, hipStream_t st);
-// Start of a refinement round from staged[0, B) = inner targets (double) and
-// staged[B, 1.5 B) = the round mask (int): target2, mask, active, rhs2 = best2 = r2,
-// tot += count, and zero outer counts and stagnation counters.
-void launch_round_start(int B, const double* staged, const double* r2, double* rhs2, double* best2, double* target2,
-                        int* mask, int* active, int* count, int* tot, int* since, int* gains, hipStream_t st);
 void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st);
 void launch_fill_f32(float* p, float value, int64_t count, hipStream_t st);
 void launch_fill_f64(double* p, double value, int64_t count, hipStream_t st);

@@ -287,14 +287,15 @@ __global__ __launch_bounds__(WG) void k_refine_residual(PlanDev p, const double*
 __global__ __launch_bounds__(WG) void k_refine_update(PlanDev p, double* __restrict__ x,
                                                       const float* __restrict__ d0,
                                                       const float* __restrict__ d1,
-                                                      const int* __restrict__ outer_count, int flips,
-                                                      const int* __restrict__ mask) {
+                                                      const int* __restrict__ start, const int* __restrict__ outer_count,
+                                                      int flips, const int* __restrict__ mask) {
   const Tile tl = p.tiles[xcd_remap(blockIdx.x, gridDim.x)];
   if (tl.inst < 0) return;
   if (mask[tl.inst] == 0) return;
   const Inst in = p.inst[tl.inst];
   const int n = in.n;
-  const float* d = (((int64_t)outer_count[tl.inst] * flips) & 1) ? d1 : d0;
+  const int64_t iters = (int64_t)(start != nullptr ? start[tl.inst] : 0) + outer_count[tl.inst];
+  const float* d = ((iters * flips) & 1) ? d1 : d0;
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = tl.x0 + tx;
 #pragma unroll
@@ -306,6 +307,62 @@ __global__ __launch_bounds__(WG) void k_refine_update(PlanDev p, double* __restr
     }
   }
 }
+// End of one instance's refinement round, one wave per instance waiting for it
+// (pending): rho = ||b - A x|| / ||b|| from the refinement residual's tile partials
+// (summed in the order of k_reduce_partials), recorded as the round's history entry,
+// then either the instance is done (rho <= tol, zero residual, non-finite or diverged,
+// the round cap, or a second round that did not halve rho) or its next inner solve
+// starts with the target max(tol_inner, tol / (2 rho))^2 ||r||^2 at outer iteration
+// rp.start of the solve.
+__global__ __launch_bounds__(64) void k_round_decide(PlanDev p, const double* __restrict__ partial2, RoundParams rp,
+                                                     RoundState rs) {
+  const int b = blockIdx.x;
+  if (rs.pending[b] == 0) return;
+  const Inst in = p.inst[b];
+  double s0 = 0.0, s1 = 0.0;
+  for (int t = in.tile_begin + (int)threadIdx.x; t < in.tile_end; t += 64) {
+    s0 += partial2[2 * t];
+    s1 += partial2[2 * t + 1];
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if (threadIdx.x != 0) return;
+  const int j = rs.round[b];
+  const double rho = s1 > 0.0 ? sqrt(s0 / s1) : sqrt(s0);
+  rs.relres[b] = rho;
+  if (j <= rp.max_rounds) rs.history[(int64_t)j * p.B + b] = rho;
+  int fin = 0;
+  if (!isfinite(rho) || rs.status[b] == 5) {
+    fin = 5;  // RM_EDIVERGED
+  } else if (rho <= rp.tol || s0 == 0.0) {
+    fin = -1;  // converged
+  } else if (j >= rp.max_rounds) {
+    fin = 4;  // RM_ENOTCONV: round cap
+  } else if (j > 0 && rho > 0.5 * rs.prev_rho[b]) {
+    const int k = rs.strikes[b] + 1;
+    rs.strikes[b] = k;
+    if (k >= 2) fin = 4;  // two rounds without halving the residual
+  }
+  rs.prev_rho[b] = rho;
+  rs.pending[b] = 0;
+  if (fin != 0) {
+    rs.status[b] = fin > 0 ? fin : 0;
+    rs.active[b] = 0;
+    return;
+  }
+  const double tau = fmax(rp.tol_inner, 0.5 * rp.tol / rho);
+  rs.target2[b] = tau * tau * s0;
+  rs.rhs2[b] = s0;
+  rs.best2[b] = s0;
+  rs.tot[b] += rs.count[b];
+  rs.count[b] = 0;
+  rs.since[b] = 0;
+  rs.gains[b] = 0;
+  rs.start[b] = rp.start;
+  rs.round[b] = j + 1;
+  rs.active[b] = 1;
+}
+
 
 // After one outer iteration of an inner solve: stop instances whose residual
 // reached their target, hit the cap, went non-finite or grew beyond 1e6 times
@@ -326,14 +383,15 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
     double* __restrict__ res2, const double* __restrict__ rhs2, const double* __restrict__ target2,
     double* __restrict__ best2, int* __restrict__ since, int* __restrict__ gains, int stall_min, int stall_max,
     int cap, int* __restrict__ active, int* __restrict__ outer_count, int* __restrict__ status,
-    int* __restrict__ n_active, unsigned long long* __restrict__ host_word,
+    int* __restrict__ pending, int* __restrict__ n_active, unsigned long long* __restrict__ host_word,
     unsigned long long* __restrict__ host_cnt, unsigned seq,
     const int* __restrict__ tot, double* __restrict__ hist, int hist_len) {
   __shared__ int kept[16];
-  extern __shared__ int per_class[];  // [ncls] active instances per size class
+  __shared__ int waiting[16];
+  extern __shared__ int per_class[];  // [ncls] instances per size class not yet done
   for (int c = threadIdx.x; c < ncls; c += blockDim.x) per_class[c] = 0;
   __syncthreads();
-  int mine = 0;
+  int mine = 0, pend = 0;
   for (int b = threadIdx.x; b < p.B; b += blockDim.x) {
     // slot range of the configuration the instance's class ran
     const int ci = cls != nullptr ? cls[b] : 0;
@@ -342,12 +400,18 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
     const int t1 = rg != nullptr ? rg[2 * b + 1] : p.inst[b].tile_end;
     // the instance's state is read before the partial sums are waited for
     const int act = active[b], cnt = outer_count[b] + 1, sn = since[b], g = gains[b];
+    const int pd = pending != nullptr ? pending[b] : 0;
     const double rh = rhs2[b], tg = target2[b], best = best2[b];
     double r2 = 0.0;
 #pragma unroll 8
     for (int t = t0; t < t1; ++t) r2 += partial2[2 * t];
     res2[b] = r2;
-    if (act == 0) continue;
+    if (act == 0) {
+      // a round that ended earlier and waits for its refinement step
+      pend += pd;
+      if (pd && ci < ncls) atomicAdd(&per_class[ci], 1);
+      continue;
+    }
     outer_count[b] = cnt;
     if (hist != nullptr) {
       const int k = tot[b] + cnt - 1;  // outer iterations of this instance over all rounds, from 0
@@ -371,54 +435,48 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
     }
     active[b] = keep;
     mine += keep;
-    if (keep && ci < ncls) atomicAdd(&per_class[ci], 1);
+    // the inner solve of this round has ended: the refinement step takes over
+    if (!keep && pending != nullptr) {
+      pending[b] = 1;
+      ++pend;
+    }
+    if ((keep || pending != nullptr) && ci < ncls) atomicAdd(&per_class[ci], 1);
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o, 64);
-  if ((threadIdx.x & 63) == 0) kept[threadIdx.x >> 6] = mine;
+  for (int o = 32; o > 0; o >>= 1) {
+    mine += __shfl_xor(mine, o, 64);
+    pend += __shfl_xor(pend, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    kept[threadIdx.x >> 6] = mine;
+    waiting[threadIdx.x >> 6] = pend;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int total = 0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) total += kept[k];
+    int total = 0, total_pend = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      total += kept[k];
+      total_pend += waiting[k];
+    }
     *n_active = total;
     // straight to the host's pinned copies (system scope, vector stores), each one
     // 64-bit word stamped with the launch number, so the host can tell which launch
-    // wrote it without any ordering between the words: the per-class counts, then the
-    // total
+    // wrote it without any ordering between the words: the per-class counts of
+    // instances not done, the count of rounds waiting for their refinement step, then
+    // the count of instances not done (active or waiting)
     if (host_word != nullptr) {
       if (host_cnt != nullptr)
         for (int c = 0; c < ncls; ++c)
           __hip_atomic_store(host_cnt + c, ((unsigned long long)seq << 32) | (unsigned)per_class[c],
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_store(host_word, ((unsigned long long)seq << 32) | (unsigned)total, __ATOMIC_RELAXED,
+      __hip_atomic_store(host_word + 1, ((unsigned long long)seq << 32) | (unsigned)total_pend, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(host_word, ((unsigned long long)seq << 32) | (unsigned)(total + total_pend),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
 }
 
-// Start of a refinement round, one launch: from the staged host values (per instance
-// the inner target and the round mask) set target2 and the mask, activate the masked
-// instances, take the round's right-hand-side norm as the reference and the best
-// residual so far, add the last round's outer count to tot and clear the outer count
-// and the stagnation counters.
-__global__ void k_round_start(int B, const double* __restrict__ staged, const double* __restrict__ r2,
-                              double* __restrict__ rhs2, double* __restrict__ best2, double* __restrict__ target2,
-                              int* __restrict__ mask, int* __restrict__ active, int* __restrict__ count,
-                              int* __restrict__ tot, int* __restrict__ since, int* __restrict__ gains) {
-  const int* staged_mask = reinterpret_cast<const int*>(staged + B);
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
-    target2[b] = staged[b];
-    const int mk = staged_mask[b];
-    mask[b] = mk;
-    active[b] = mk;
-    rhs2[b] = r2[b];
-    best2[b] = r2[b];
-    tot[b] += count[b];
-    count[b] = 0;
-    since[b] = 0;
-    gains[b] = 0;
-  }
-}
 
 template <typename T>
 __global__ void k_fill(T* __restrict__ p, T value, int64_t count) {
@@ -779,30 +837,31 @@ void launch_refine_residual(const PlanDev& p, const double* b, const double* x, 
                      round_mask);
 }
 
-void launch_refine_update(const PlanDev& p, double* x, const float* d0, const float* d1, const int* outer_count,
-                          int m, const int* round_mask, hipStream_t st) {
-  hipLaunchKernelGGL(k_refine_update, dim3(p.ntiles), dim3(WG), 0, st, p, x, d0, d1, outer_count, m,
+void launch_refine_update(const PlanDev& p, double* x, const float* d0, const float* d1, const int* start,
+                          const int* outer_count, int flips, const int* round_mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_update, dim3(p.ntiles), dim3(WG), 0, st, p, x, d0, d1, start, outer_count, flips,
                      round_mask);
+}
+
+void launch_round_decide(const PlanDev& p, const double* partial2, const RoundParams& rp, RoundState rs,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_round_decide, dim3(p.B), dim3(64), 0, st, p, partial2, rp, rs);
 }
 
 void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ranges, const int* tranges,
                         const int* cls, unsigned long long tailmask, int ncls, double* res2, const double* rhs2,
                         const double* target2, double* best2, int* since, int* gains, int stall_min, int stall_max,
-                        int cap, int* active, int* outer_count, int* status, int* n_active,
+                        int cap, int* active, int* outer_count, int* status, int* pending, int* n_active,
                         unsigned long long* host_word, unsigned long long* host_cnt, unsigned seq,
                         const int* tot, double* hist, int hist_len, hipStream_t st) {
   const int threads = 64 * std::min(16, std::max(1, (p.B + 63) / 64));
   hipLaunchKernelGGL(k_outer_flags, dim3(1), dim3(threads), (size_t)std::max(1, ncls) * sizeof(int), st, p,
                      partial2, ranges, tranges, cls, tailmask, ncls, res2, rhs2, target2, best2, since, gains,
-                     stall_min, stall_max, cap, active, outer_count, status, n_active, host_word, host_cnt, seq, tot,
+                     stall_min, stall_max, cap, active, outer_count, status, pending, n_active, host_word, host_cnt,
+                     seq, tot,
                      hist, hist_len);
 }
 
-void launch_round_start(int B, const double* staged, const double* r2, double* rhs2, double* best2, double* target2,
-                        int* mask, int* active, int* count, int* tot, int* since, int* gains, hipStream_t st) {
-  hipLaunchKernelGGL(k_round_start, dim3((B + 255) / 256), dim3(256), 0, st, B, staged, r2, rhs2, best2, target2, mask,
-                     active, count, tot, since, gains);
-}
 void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st) {
   if (count > 0) hipLaunchKernelGGL(k_fill<int>, dim3(fill_grid(count)), dim3(256), 0, st, p, value, count);
 }
