@@ -17,10 +17,12 @@
 
 #include "../../include/rm.h"
 #include "rm_internal.h"
+#include "rm_geometry.h"
 
 using rmk::Inst;
 using rmk::PlanDev;
 using rmk::Tile;
+using namespace rmgeo;
 
 namespace {
 
@@ -249,143 +251,6 @@ size_t vec_bytes(const rm_plan_t* p) {
   return (size_t)std::max<int64_t>(p->P, 1) * sizeof(T);
 }
 
-// ---------------------------------------------------------------------------
-// temporal-blocked execution plan
-// ---------------------------------------------------------------------------
-// Boundary-aware 1D tiling of [0, n) by windows of length len: a window edge on
-// the domain boundary needs no halo (the zero border of the LDS tile and the
-// zeros published outside the interior are the Dirichlet condition); interior
-// edges overlap the neighbouring window by h.  Returns {window start, owned lo,
-// owned hi} per window, or nothing when len is too short for the halo.
-std::vector<std::array<int, 3>> partition(int n, int len, int h) {
-  std::vector<std::array<int, 3>> out;
-  int o = 0;
-  while (true) {
-    const int start = o > 0 ? o - h : 0;
-    if (start + len >= n) {
-      out.push_back({start, o, n});
-      break;
-    }
-    const int hi = start + len - h;
-    if (hi <= o) return {};
-    out.push_back({start, o, hi});
-    o = hi;
-  }
-  return out;
-}
-
-// Kernel shapes: the tiled variants 0 .. kNumBlockVariants - 1, then the row-streaming
-// kernel, whose "width" is the height of its row windows (whole rows across).
-constexpr int kStreamShape = rmk::kNumBlockVariants;
-constexpr int kNumShapes = kStreamShape + 1;
-
-// Geometry of a class (n, variant v, steps per launch T, width cw): the tiles
-// across and down.  An instance that fits in one window needs no halo; otherwise
-// the halo is T + 1 (one ring more than T steps need, so the residual of the
-// final iterate can be formed in the same launch).
-bool class_geometry(int n, int v, int T, int cw, int& tx, int& ty) {
-  if (v == kStreamShape) {
-    if (n > rmk::kStreamMaxN || T < 1 || T > rmk::kStreamMaxT || cw < 1) return false;
-    tx = 1;
-    ty = (int)partition(n, cw, T + 1).size();
-    return ty > 0;
-  }
-  if (v < 0 || v >= rmk::kNumBlockVariants || T < 1) return false;
-  const rmk::BlockVariant& bv = rmk::kBlockVariants[v];
-  if (cw < 8 || cw % 8 != 0 || cw + 2 > bv.lw) return false;
-  const int eh = 8 * bv.r;
-  const int h = T + 1;
-  tx = (int)partition(n, cw, h).size();
-  ty = (int)partition(n, eh, h).size();
-  return tx > 0 && ty > 0;
-}
-
-// Cost model used before any tuning: the larger of an arithmetic bound
-// (redundant halo work included) and an HBM bound (load u, v, f on the extended
-// tile, store u, v on the owned one, once per T steps), per inner step.
-double model_cost(int n, int v, int T, int cw, int count) {
-  int tx, ty;
-  if (!class_geometry(n, v, T, cw, tx, ty)) return 1e300;
-  if (v == kStreamShape) {
-    // whole rows in one workgroup: only the row windows overlap; a grid of fewer
-    // waves than SIMDs leaves the rest idle
-    const int nw = (n + 63) / 64;
-    const double rows = std::min<double>((double)ty * cw, (double)n + 2.0 * (ty - 1) * (T + 1));
-    const double ext = rows * 64.0 * nw;
-    const double fill = std::min(1.0, (double)count * ty * nw / 1024.0);
-    const double compute = ext / 2.4e12 / fill;
-    const double memory = (12.0 * rows * n + 8.0 * n * (double)n) / T / 5.0e12;
-    return std::max(compute, memory) + 4e-6 / T / 256.0;
-  }
-  const double ext = (double)tx * ty * cw * (double)(8 * rmk::kBlockVariants[v].r);
-  const double own = (double)n * n;
-  const double compute = ext / 1.6e12;
-  const double memory = (12.0 * ext + 8.0 * own) / T / 5.0e12;
-  // measured on MI355X: widths that are not multiples of 32 make waves straddle
-  // strips (slower LDS and global access), and workgroups wider than 64 columns
-  // fit fewer per CU
-  const double shape_penalty = (cw % 32 != 0 ? 1.3 : 1.0) * (cw > 64 ? 1.15 : 1.0);
-  return std::max(compute, memory) * shape_penalty + 4e-6 / T / 256.0;
-}
-
-// Steps per launch tried by the tuner and the cost model.
-constexpr int kTs[] = {2, 4, 8, 16, 32};
-
-// Tile widths worth trying for (n, v, T): for the few smallest tile counts k
-// across, the narrowest multiple of 8 that covers n.
-std::vector<int> candidate_widths(int n, int v, int T) {
-  std::vector<int> out;
-  if (v == kStreamShape) {
-    // windows for 1 to 10, 12 or 16 row segments per instance
-    const int h = T + 1;
-    for (int S : {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16}) {
-      const int len = S == 1 ? n : (n + 2 * (S - 1) * h + S - 1) / S;
-      int tx, ty;
-      if (class_geometry(n, v, T, len, tx, ty) && ty == S && std::find(out.begin(), out.end(), len) == out.end())
-        out.push_back(len);
-    }
-    return out;
-  }
-  const int lw = rmk::kBlockVariants[v].lw;
-  for (int cw = 8; cw + 2 <= lw && (int)out.size() < 64; cw += 8) {
-    int tx, ty;
-    if (!class_geometry(n, v, T, cw, tx, ty)) continue;
-    // keep cw only if it is the narrowest width with this tile count
-    int tx2 = -1, ty2;
-    if (cw > 8 && class_geometry(n, v, T, cw - 8, tx2, ty2) && tx2 == tx) continue;
-    out.push_back(cw);
-  }
-  // favour the widest few (fewest tiles) and widths that are multiples of 32
-  std::vector<int> keep;
-  for (auto it = out.rbegin(); it != out.rend() && (int)keep.size() < 3; ++it) keep.push_back(*it);
-  for (int w : out)
-    if (w % 32 == 0 && std::find(keep.begin(), keep.end(), w) == keep.end()) keep.push_back(w);
-  for (int w : {32, 64, 96, 128}) {
-    int tx, ty;
-    if (class_geometry(n, v, T, w, tx, ty) && std::find(keep.begin(), keep.end(), w) == keep.end())
-      keep.push_back(w);
-  }
-  return keep;
-}
-
-void default_class_config(int n, int count, int& shape, int& T, int& cw, int nshapes = kNumShapes) {
-  double best = 1e301;
-  shape = 0;
-  T = 2;
-  cw = 64;
-  for (int v = 0; v < nshapes; ++v)
-    for (int t : kTs)
-      for (int w : candidate_widths(n, v, t)) {
-        const double c = model_cost(n, v, t, w, count);
-        if (c < best * 0.999) {
-          best = c;
-          shape = v;
-          T = t;
-          cw = w;
-        }
-      }
-}
-
 // The tail is the main configuration unless that is the row-streaming kernel; then it
 // is the cost model's best tiled variant.
 void set_default_tail(rm_plan_s::ClassExec& c) {
@@ -421,39 +286,13 @@ void init_classes(rm_plan_t* pl) {
 // on and each instance's slot range goes to ranges[2b], ranges[2b + 1].
 rm_status build_table(const rm_plan_s::ClassExec& c, int shape, int T, int cw, int& slot, std::vector<int>& ranges,
                       DevBuf& tiles, int& ntiles, hipStream_t st) {
-  int tx, ty;
-  if (!class_geometry(c.n, shape, T, cw, tx, ty)) return fail(RM_EINVAL, "invalid kernel configuration");
-  const bool stream = shape == kStreamShape;
-  const int eh = stream ? cw : 8 * rmk::kBlockVariants[shape].r;
-  const auto px = stream ? std::vector<std::array<int, 3>>{{0, 0, c.n}} : partition(c.n, cw, T + 1);
-  const auto py = partition(c.n, eh, T + 1);
   std::vector<rmk::BTile> t;
-  for (int b : c.insts) {
-    ranges[2 * b] = slot;
-    for (const auto& y : py)
-      for (const auto& x : px) t.push_back(rmk::BTile{b, x[0], y[0], slot++, x[1], x[2], y[1], y[2]});
-    ranges[2 * b + 1] = slot;
-  }
-  while (t.size() % 8 != 0) t.push_back(rmk::BTile{-1, 0, 0, slot++, 0, 0, 0, 0});
+  if (!make_tiles(c.n, c.insts, shape, T, cw, slot, ranges, t)) return fail(RM_EINVAL, "invalid kernel configuration");
   ntiles = (int)t.size();
   RM_TRY(tiles.ensure(t.size() * sizeof(rmk::BTile), st));
   RM_HIP(hipStreamSynchronize(st));
   RM_HIP(hipMemcpy(tiles.ptr, t.data(), t.size() * sizeof(rmk::BTile), hipMemcpyHostToDevice));
   return RM_OK;
-}
-
-// Row-window height of the reverse-step table of a class: enough windows per instance
-// for about two waves per SIMD, each window at least four overlaps high.
-int reverse_window(int n, int count) {
-  const int h = rmk::kAdjMaxT + 1;
-  const int nw = (n + 63) / 64;
-  int want = (2048 + count * nw - 1) / std::max(1, count * nw);
-  want = std::max(1, std::min(16, want));
-  for (int S = want; S > 1; --S) {
-    const int len = (n + 2 * (S - 1) * h + S - 1) / S;
-    if (len >= 4 * h && (int)partition(n, len, h).size() == S) return len;
-  }
-  return n;
 }
 
 rm_status build_exec(rm_plan_t* pl, hipStream_t st) {

@@ -213,17 +213,6 @@ void launch_variant(int T, int cw, int method, const PlanDev& p, const BTile* ti
 
 }  // namespace
 
-const BlockVariant kBlockVariants[kNumBlockVariants] = {
-    {8, 66},    // up to 64 x 64 points
-    {16, 66},   // up to 64 x 128
-    {8, 130},   // up to 128 x 64
-    {13, 66},   // up to 64 x 104
-    {16, 130},  // up to 128 x 128
-    {12, 98},   // up to 96 x 96
-    {13, 106},  // up to 104 x 104
-    {32, 66},   // up to 64 x 256: one tile covers n <= 256 vertically (no y halo)
-    {32, 98},   // up to 96 x 256
-};
 
 bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, const BTile* tiles, int ntiles,
                   const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,

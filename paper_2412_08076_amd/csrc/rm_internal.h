@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "rm_geometry.h"
+
 namespace rmk {
 
 // Output tile of the one-step kernels: TX columns (one wave64 wide) by TY rows,
@@ -153,23 +155,7 @@ void launch_meta_backward(const PlanDev& p, int m, const float* params, const fl
                           const float* d_alpha, float* per_inst, float* d_params, hipStream_t st);
 
 // ---- temporal-blocked steps (rm_block.hip) ---------------------------------
-// Kernel variants: strips of R rows (extended tile height 8R) and an LDS row
-// stride LW (extended tile width CW <= LW - 2, CW a multiple of 8 chosen at
-// launch; 8 CW threads per workgroup).
-struct BlockVariant {
-  int r, lw;
-};
-constexpr int kNumBlockVariants = 9;
-extern const BlockVariant kBlockVariants[kNumBlockVariants];
-
-// One extended tile of a block table: origin (x0, y0) of its CW x 8R window in
-// instance coordinates, the slot of its residual partial, and the owned
-// rectangle [ox0, ox1) x [oy0, oy1) it stores.  inst < 0 marks padding.
-struct BTile {
-  int32_t inst, x0, y0, slot;
-  int32_t ox0, ox1, oy0, oy1;
-};
-
+// Variants, windows and tile tables: rm_geometry.h.
 // T fused steps (s0 .. s0 + T - 1) over a table of extended tiles.  Tiles must
 // overlap by at least T points at interior edges (T + 1 when partial2 is given,
 // which then receives ||f - A u||^2 of the final u over each tile's owned part).
@@ -189,9 +175,6 @@ bool launch_block(int variant, int T, int cw, int method, const PlanDev& p, cons
 // Same step semantics, partial2 and states layout as launch_block.  Returns false
 // when n or T is outside what is built.  The reverse steps (launch_adj_stream) are
 // built for n <= kAdjStreamMaxN.
-constexpr int kStreamMaxN = 1024;
-constexpr int kAdjStreamMaxN = 512;
-constexpr int kStreamMaxT = 8;
 bool launch_stream(int T, int wlen, int n, int method, const PlanDev& p, const BTile* tiles, int ntiles,
                    const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,
                    const float* v, float* u_out, float* v_out, const int* active, double* partial2,
@@ -204,7 +187,6 @@ bool launch_stream(int T, int wlen, int n, int method, const PlanDev& p, const B
 // and ub_out, vb_out receive them before the earliest one; fb (may be null) gets
 // w g added per step in place; part[l - 1] + 4 slot receives the window's
 // <g, r>, <g, v>, <utb, v>, 0 for level l (as launch_adj_step's partial4).
-constexpr int kAdjMaxT = 3;
 struct AdjLevels {
   const float* u[kAdjMaxT];
   const float* v[kAdjMaxT];

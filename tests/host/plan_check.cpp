@@ -1,0 +1,142 @@
+// Checks of the host planning logic of the FP32 sweeps (rm_geometry.h), built with
+// AddressSanitizer and UndefinedBehaviorSanitizer by tests/test_host_sanitized.py.
+// For many sizes, kernel shapes, steps per launch and widths:
+//   - the windows of a 1D partition own disjoint, contiguous ranges that cover [0, n), and
+//     every owned edge inside the domain lies at least the halo h inside its window;
+//   - every configuration the cost model or the tuner's candidate list proposes is valid;
+//   - a tile table owns every point of every instance exactly once, each owned rectangle
+//     lies in its tile's window with the halo, residual slots are numbered consecutively,
+//     the per-instance slot ranges partition them and the table is padded to a multiple of 8;
+//   - the reverse-step windows split n into the number of windows they promise.
+// Exit status 0 when every check holds; the first failure is printed.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "rm_geometry.h"
+
+using namespace rmgeo;
+
+static int failures = 0;
+#define CHECK(cond, ...)                                   \
+  do {                                                     \
+    if (!(cond)) {                                         \
+      std::fprintf(stderr, "check failed: %s: ", #cond);  \
+      std::fprintf(stderr, __VA_ARGS__);                   \
+      std::fprintf(stderr, "\n");                          \
+      if (++failures > 20) std::exit(1);                   \
+    }                                                      \
+  } while (0)
+
+static void check_partition(int n, int len, int h) {
+  const auto w = partition(n, len, h);
+  if (w.empty()) {
+    // only when the window is too short for the halo (or n is tiny: one window)
+    CHECK(len <= 2 * h || len < n, "n=%d len=%d h=%d: empty partition", n, len, h);
+    return;
+  }
+  int next = 0;
+  for (size_t k = 0; k < w.size(); ++k) {
+    const int start = w[k][0], lo = w[k][1], hi = w[k][2];
+    CHECK(lo == next, "n=%d len=%d h=%d: window %zu owns from %d, expected %d", n, len, h, k, lo, next);
+    CHECK(lo < hi, "n=%d len=%d h=%d: window %zu owns nothing", n, len, h, k);
+    CHECK(start >= 0 && start <= lo, "n=%d len=%d h=%d: window %zu starts at %d", n, len, h, k, start);
+    CHECK(lo == 0 || lo - start >= h, "n=%d len=%d h=%d: low halo %d", n, len, h, lo - start);
+    const int end = std::min(n, start + len);
+    CHECK(hi <= end, "n=%d len=%d h=%d: window %zu owns beyond its end", n, len, h, k);
+    CHECK(hi == n || end - hi >= h, "n=%d len=%d h=%d: high halo %d", n, len, h, end - hi);
+    next = hi;
+  }
+  CHECK(next == n, "n=%d len=%d h=%d: partition ends at %d", n, len, h, next);
+}
+
+static void check_table(int n, int count, int shape, int T, int cw) {
+  int tx = 0, ty = 0;
+  if (!class_geometry(n, shape, T, cw, tx, ty)) return;
+  std::vector<int> insts;
+  const int B = count + 2;  // the class holds every other instance of a larger batch
+  for (int b = 1; b < B; b += 2) insts.push_back(b);
+  std::vector<int> ranges(2 * (size_t)B, -7);
+  std::vector<rmk::BTile> t;
+  int slot = 5;
+  const bool ok = make_tiles(n, insts, shape, T, cw, slot, ranges, t);
+  CHECK(ok, "n=%d shape=%d T=%d cw=%d: valid geometry but no table", n, shape, T, cw);
+  if (!ok) return;
+  CHECK(t.size() % 8 == 0, "table length %zu", t.size());
+  CHECK((int)t.size() >= (int)insts.size() * tx * ty, "table too short");
+  const bool stream = shape == kStreamShape;
+  const int eh = stream ? cw : 8 * rmk::kBlockVariants[shape].r;
+  const int ew = stream ? n : cw;
+  const int h = T + 1;
+  int expect_slot = 5;
+  std::vector<int> owner((size_t)n * n);
+  for (int b : insts) {
+    CHECK(ranges[2 * b] == expect_slot, "instance %d slots start at %d", b, ranges[2 * b]);
+    std::fill(owner.begin(), owner.end(), 0);
+    for (const auto& tl : t) {
+      if (tl.inst != b) continue;
+      CHECK(tl.slot == expect_slot, "slot %d, expected %d", tl.slot, expect_slot);
+      ++expect_slot;
+      CHECK(tl.x0 >= 0 && tl.y0 >= 0, "negative origin");
+      CHECK(tl.ox0 >= tl.x0 && tl.ox1 <= std::min(n, tl.x0 + ew), "owned columns outside the window");
+      CHECK(tl.oy0 >= tl.y0 && tl.oy1 <= std::min(n, tl.y0 + eh), "owned rows outside the window");
+      CHECK(tl.ox0 == 0 || tl.ox0 - tl.x0 >= h, "column halo %d < %d", tl.ox0 - tl.x0, h);
+      CHECK(tl.oy0 == 0 || tl.oy0 - tl.y0 >= h, "row halo %d < %d", tl.oy0 - tl.y0, h);
+      CHECK(tl.ox1 == n || std::min(n, tl.x0 + ew) - tl.ox1 >= h, "east halo");
+      CHECK(tl.oy1 == n || std::min(n, tl.y0 + eh) - tl.oy1 >= h, "north halo");
+      for (int y = tl.oy0; y < tl.oy1; ++y)
+        for (int x = tl.ox0; x < tl.ox1; ++x) ++owner[(size_t)y * n + x];
+    }
+    CHECK(ranges[2 * b + 1] == expect_slot, "instance %d slots end at %d", b, ranges[2 * b + 1]);
+    for (size_t k = 0; k < owner.size(); ++k)
+      if (owner[k] != 1) {
+        CHECK(owner[k] == 1, "n=%d shape=%d T=%d cw=%d: point %zu owned %d times", n, shape, T, cw, k, owner[k]);
+        break;
+      }
+  }
+  for (int b = 0; b < B; b += 2) CHECK(ranges[2 * b] == -7, "an instance outside the class got a range");
+  for (const auto& tl : t)
+    if (tl.inst < 0) {
+      CHECK(tl.slot == expect_slot, "padding slot");
+      ++expect_slot;
+    }
+  CHECK(slot == expect_slot, "slot counter %d, expected %d", slot, expect_slot);
+}
+
+int main() {
+  // 1D partitions
+  for (int n = 1; n <= 300; ++n)
+    for (int h = 1; h <= 9; h += 2)
+      for (int len = 1; len <= n + 3; len += (len < 40 ? 1 : 7)) check_partition(n, len, h);
+  for (int n : {511, 512, 1000, 1023, 1024, 2047, 4095})
+    for (int h : {2, 5, 9, 17})
+      for (int len = 2 * h + 1; len <= n; len += 13) check_partition(n, len, h);
+  // configurations and tables
+  const int sizes[] = {1, 2, 3, 7, 8, 9, 17, 31, 63, 64, 65, 100, 127, 128, 130, 200, 255, 256, 257, 300, 511, 513,
+                       700, 1023, 1024};
+  for (int n : sizes) {
+    for (int count : {1, 3, 26}) {
+      int shape = -1, T = 0, cw = 0;
+      default_class_config(n, count, shape, T, cw);
+      int tx, ty;
+      CHECK(class_geometry(n, shape, T, cw, tx, ty), "n=%d count=%d: default configuration invalid", n, count);
+      default_class_config(n, count, shape, T, cw, rmk::kNumBlockVariants);
+      CHECK(shape < kStreamShape && class_geometry(n, shape, T, cw, tx, ty), "n=%d: default tiled config", n);
+    }
+    for (int v = 0; v < kNumShapes; ++v)
+      for (int T : {1, 2, 3, 4, 5, 6, 7, 8, 16, 32})
+        for (int w : candidate_widths(n, v, T)) {
+          int tx, ty;
+          CHECK(class_geometry(n, v, T, w, tx, ty), "n=%d v=%d T=%d: candidate width %d invalid", n, v, T, w);
+          if (n <= 300 || v == kStreamShape) check_table(n, 3, v, T, w);
+        }
+    if (n <= rmk::kAdjStreamMaxN)
+      for (int count : {1, 64, 256}) {
+        const int len = reverse_window(n, count);
+        CHECK(len >= 1 && len <= n, "reverse window %d for n=%d", len, n);
+        if (len < n) check_partition(n, len, rmk::kAdjMaxT + 1);
+      }
+  }
+  if (failures == 0) std::printf("plan checks passed\n");
+  return failures == 0 ? 0 : 1;
+}
