@@ -18,7 +18,8 @@ import numpy as np
 
 __all__ = [
     "Batch", "single_isotropic", "aniso_batch", "uneven_batch", "helmholtz_batch",
-    "random_batch", "meta_params", "pack", "unpack_vec", "offsets_of", "twogrid_symbol", "smoothing_weights",
+    "random_batch", "meta_params", "symbolnet_params", "pack", "unpack_vec", "offsets_of", "twogrid_symbol",
+    "smoothing_weights",
 ]
 
 META_HIDDEN = 64
@@ -165,4 +166,24 @@ def meta_params(m=16, seed=0, beta0=0.99, last_std=0.01):
     W3 = rng.normal(0.0, last_std, size=(m + 1, H))
     b3 = np.zeros(m + 1)
     b3[m] = np.log(beta0 / (1.0 - beta0))
+    return np.concatenate([a.ravel() for a in (W1, b1, W2, b2, W3, b3)])
+
+
+def symbolnet_params(seed=0, hidden=16, last_std=0.01):
+    """Initial parameters of the two-grid symbol network, flat, in the layout
+    W1[hidden][3][3][3], b1[hidden], W2[hidden][hidden][3][3], b2[hidden], W3[1][hidden][3][3], b3[1].
+
+    First two layers: U(-1/sqrt(fan_in), 1/sqrt(fan_in)) for weights and biases (fan_in =
+    9 x input channels); last layer: N(0, last_std^2) weights and a zero bias, so the
+    network's output starts near zero.
+    """
+    rng = np.random.default_rng(seed)
+    k1 = 1.0 / np.sqrt(9.0 * 3)
+    k2 = 1.0 / np.sqrt(9.0 * hidden)
+    W1 = rng.uniform(-k1, k1, size=(hidden, 3, 3, 3))
+    b1 = rng.uniform(-k1, k1, size=hidden)
+    W2 = rng.uniform(-k2, k2, size=(hidden, hidden, 3, 3))
+    b2 = rng.uniform(-k2, k2, size=hidden)
+    W3 = rng.normal(0.0, last_std, size=(1, hidden, 3, 3))
+    b3 = np.zeros(1)
     return np.concatenate([a.ravel() for a in (W1, b1, W2, b2, W3, b3)])
