@@ -350,6 +350,29 @@ rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
                              const float* g_uK, const float* g_loss, float* d_omega,
                              float* d_alpha, float* d_symbol, float* d_b, float* loss);
 
+/* Symbol network of the two-grid cycle (§3: the meta network that produces the diagonal
+ * Lambda~ of the spectral correction, eq. dl-him-h; §3.2 learns in log form).  The text
+ * does not give its architecture; the one built here: per coarse mode (p, q) of instance
+ * b (nc = (n - 1)/2, h = 1/(n + 1)), with lam the fine-grid eigenvalue
+ * (4/h^2)(sin^2(p pi h/2) + sin^2(q pi h/2)) - kappa^2,
+ *   features  (lam h^2 / 8, p / (nc + 1), q / (nc + 1)),
+ *   z = conv3(tanh(conv2(tanh(conv1(features))))),  3 x 3 cross-correlations with zero
+ *       padding, 3 -> 16 -> 16 -> 1 channels,
+ *   symbol = lam / (lam^2 + 1) * exp(z)   (a log-form correction of the regularised
+ *            inverse eigenvalue; layout as the symbol of rm_twogrid_solve).
+ * params: device float [rm_symbolnet_param_count() = 2913], layout
+ *   W1[16][3][3][3], b1[16], W2[16][16][3][3], b2[16], W3[1][16][3][3], b3[1].
+ * Every instance must be Helmholtz and qualify for the two-grid cycle (RM_EINVAL /
+ * RM_EUNSUPPORTED otherwise).  rm_symbolnet_forward: symbol (device float [Pc]) for every
+ * instance.  rm_symbolnet_backward: d_params (device float [2913], overwritten) = the
+ * gradient of sum(d_symbol * symbol) with respect to params, summed over the batch in a
+ * fixed order (repeated calls give identical bits); d_symbol: device float [Pc], e.g. the
+ * d_symbol of rm_twogrid_adjoint.  Both asynchronous. */
+int32_t rm_symbolnet_param_count(void);
+rm_status rm_symbolnet_forward(rm_ctx* ctx, const rm_plan_t* plan, const float* params, float* symbol);
+rm_status rm_symbolnet_backward(rm_ctx* ctx, const rm_plan_t* plan, const float* params, const float* d_symbol,
+                                float* d_params);
+
 /* Restarted flexible GMRES with a neural solver as the preconditioner (§3.2: FGMRES,
  * restart 20, preconditioned by a multilevel neural solver).  Every instance runs its
  * own FGMRES in FP64 (basis, Hessenberg, Givens rotations); the preconditioner maps

@@ -22,7 +22,8 @@ EXPORTS = [
     "rm_plan_set_tail_kernel", "rm_plan_get_tail_kernel", "rm_plan_set_tail_switch", "rm_tune",
     "rm_apply_A", "rm_residual", "rm_residual_noalloc", "rm_solve",
     "rm_solve_adjoint", "rm_plan_coarse_points", "rm_plan_coarse_offsets", "rm_twogrid_solve",
-    "rm_twogrid_adjoint", "rm_fgmres", "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count",
+    "rm_twogrid_adjoint", "rm_symbolnet_param_count", "rm_symbolnet_forward", "rm_symbolnet_backward",
+    "rm_fgmres", "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count",
     "rm_status_string", "rm_last_error",
 ]
 
@@ -89,6 +90,9 @@ def load():
         "rm_twogrid_solve": (st, [P, P, I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P, P, P]),
         "rm_twogrid_adjoint": (st, [P, P, I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P, P, P, P, P, P, P,
                                     P]),
+        "rm_symbolnet_param_count": (I32, []),
+        "rm_symbolnet_forward": (st, [P, P, P, P]),
+        "rm_symbolnet_backward": (st, [P, P, P, P, P]),
         "rm_fgmres": (st, [P, P, ctypes.POINTER(rm_fgmres_opts), I32, ctypes.POINTER(rm_solve_opts), P, P, P, P, P,
                            ctypes.POINTER(rm_report)]),
         "rm_meta_forward": (st, [P, P, I32, P, P, P]),

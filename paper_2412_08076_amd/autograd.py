@@ -9,6 +9,9 @@ UnrollLoss    (omega, alpha, b) -> per-instance ||b - A u_K||^2 / ||b||^2 after 
 TwoGridLoss   (omega, alpha, symbol, b) -> the same loss after K two-grid cycles from 0
               (rm_twogrid_solve); the backward pass runs rm_twogrid_adjoint and also
               returns the gradient of the symbol.
+SymbolNet     params -> the coarse symbol of every instance through rm_symbolnet_forward /
+              rm_symbolnet_backward; composed with TwoGridLoss it carries the loss's
+              gradient to the symbol network's parameters.
 All passes run in the HIP kernels; these classes only allocate outputs and pass
 pointers.  For RM_NAGEX, alpha has shape [2][B][m] (momentum, look-ahead).
 """
@@ -103,3 +106,21 @@ class TwoGridLoss(torch.autograd.Function):
         rm.rm_twogrid_adjoint(solver_ctx, plan, method, opts, om, al, sy, b.detach(), ckpt, d_omega, d_alpha,
                               d_symbol, g_loss=g_loss.contiguous().float(), d_b=d_b)
         return d_omega, d_alpha, d_symbol, d_b, None, None, None, None, None, None
+
+
+class SymbolNet(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, params, solver_ctx, plan):
+        symbol = torch.empty(plan.coarse_points(), dtype=torch.float32, device=params.device)
+        rm.rm_symbolnet_forward(solver_ctx, plan, params.detach(), symbol)
+        ctx.save_for_backward(params)
+        ctx.meta = (solver_ctx, plan)
+        return symbol
+
+    @staticmethod
+    def backward(ctx, d_symbol):
+        (params,) = ctx.saved_tensors
+        solver_ctx, plan = ctx.meta
+        d_params = torch.empty_like(params)
+        rm.rm_symbolnet_backward(solver_ctx, plan, params.detach(), d_symbol.contiguous(), d_params)
+        return d_params, None, None

@@ -163,6 +163,10 @@ struct rm_plan_s {
     std::vector<int64_t> coff;
     DevBuf d_inst, d_rtiles, d_groups, d_tw, c0, c1, shat, fine2, zero;
     int nrtiles = 0, ngroups = 0, mmax = 0;
+    // symbol network: 16 x 16 mode tiles, activations and gradients (16 planes each),
+    // the symbol, its log-gradient and the per-tile weight-gradient partials
+    DevBuf d_stiles, sa1, sa2, sg1, sg2, ssym, sgz, spart;
+    int nstiles = 0;
   } tg;
   // flexible GMRES: basis (FP64), preconditioned directions (FP32), work vectors and
   // per-instance state
@@ -192,7 +196,7 @@ struct rm_plan_s {
     for (DevBuf* b : {&d_tiles, &d_inst, &d_coef32, &d_coef64, &d_mu, &d_gersh, &partial, &red, &flags, &vecA,
                       &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges, &d_tranges, &d_rranges, &d_cls, &tg.d_inst,
                       &tg.d_rtiles, &tg.d_groups, &tg.d_tw, &tg.c0, &tg.c1, &tg.shat, &tg.fine2,
-                      &tg.zero, &fg.V, &fg.Z, &fg.w, &fg.t, &fg.b32, &fg.dbl, &fg.ints, &fg.partial})
+                      &tg.zero, &tg.d_stiles, &tg.sa1, &tg.sa2, &tg.sg1, &tg.sg2, &tg.ssym, &tg.sgz, &tg.spart, &fg.V, &fg.Z, &fg.w, &fg.t, &fg.b32, &fg.dbl, &fg.ints, &fg.partial})
       b->release();
     for (auto& c : classes) {
       c.tiles.release();
@@ -916,7 +920,7 @@ rm_status twogrid_setup(rm_plan_t* pl, hipStream_t st) {
   if (tg.ready) return RM_OK;
   RM_TRY(twogrid_layout(pl));
   std::vector<rmk::TgInst> ti((size_t)pl->B);
-  std::vector<Tile> rt, grp;
+  std::vector<Tile> rt, grp, stl;
   for (int b = 0; b < pl->B; ++b) {
     const int M = pl->inst[b].n + 1, nc = (M - 2) / 2;
     int lg = 0;
@@ -925,6 +929,8 @@ rm_status twogrid_setup(rm_plan_t* pl, hipStream_t st) {
     for (int y = 0; y < nc; y += 8)
       for (int x = 0; x < nc; x += 64) rt.push_back(Tile{b, x, y, 0});
     for (int y = 0; y < nc; y += 8) grp.push_back(Tile{b, 0, y, 0});
+    for (int y = 0; y < nc; y += 16)
+      for (int x = 0; x < nc; x += 16) stl.push_back(Tile{b, x, y, (int)stl.size()});
     tg.mmax = std::max(tg.mmax, M);
   }
   while (rt.size() % 8 != 0) rt.push_back(Tile{-1, 0, 0, 0});
@@ -942,6 +948,10 @@ rm_status twogrid_setup(rm_plan_t* pl, hipStream_t st) {
   RM_HIP(hipMemcpy(tg.d_rtiles.ptr, rt.data(), rt.size() * sizeof(Tile), hipMemcpyHostToDevice));
   RM_HIP(hipMemcpy(tg.d_groups.ptr, grp.data(), grp.size() * sizeof(Tile), hipMemcpyHostToDevice));
   RM_HIP(hipMemcpy(tg.d_tw.ptr, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
+  RM_TRY(tg.d_stiles.ensure(std::max<size_t>(stl.size(), 1) * sizeof(Tile), st));
+  if (!stl.empty())
+    RM_HIP(hipMemcpy(tg.d_stiles.ptr, stl.data(), stl.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  tg.nstiles = (int)stl.size();
   tg.nrtiles = (int)rt.size();
   tg.ngroups = (int)grp.size();
   const size_t cb = (size_t)std::max<int64_t>(tg.Pc, 1) * sizeof(float);
@@ -1412,6 +1422,60 @@ rm_status rm_solve_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method, c
   }
   rmk::launch_f64_to_f32(acc_w, d_omega, (int64_t)B * m, st);
   rmk::launch_f64_to_f32(acc_a, d_alpha, (int64_t)B * m * na, st);
+  return last_launch();
+}
+
+namespace {
+// Scratch of the symbol network: two activation and two gradient planes of 16 channels,
+// the symbol and its log-gradient, per-tile partials of the largest layer.
+rm_status symbolnet_prepare(rm_ctx* ctx, rm_plan_t* pl) {
+  RM_TRY(twogrid_setup(pl, ctx->stream));
+  for (int b = 0; b < pl->B; ++b)
+    if (pl->inst[b].op != RM_FD5_HELMHOLTZ) return fail(RM_EINVAL, "the symbol network needs Helmholtz instances");
+  auto& tg = pl->tg;
+  const size_t planes = (size_t)std::max<int64_t>(tg.Pc, 1) * 16 * sizeof(float);
+  const size_t one = (size_t)std::max<int64_t>(tg.Pc, 1) * sizeof(float);
+  RM_TRY(tg.sa1.ensure(planes, ctx->stream));
+  RM_TRY(tg.sa2.ensure(planes, ctx->stream));
+  RM_TRY(tg.ssym.ensure(one, ctx->stream));
+  return RM_OK;
+}
+}  // namespace
+
+int32_t rm_symbolnet_param_count(void) { return rmk::symbolnet_param_count(); }
+
+rm_status rm_symbolnet_forward(rm_ctx* ctx, const rm_plan_t* plan, const float* params, float* symbol) {
+  RM_TRY(check_ctx_plan(ctx, plan));
+  if (params == nullptr || symbol == nullptr) return fail(RM_EINVAL, "null params or symbol");
+  rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
+  RM_TRY(symbolnet_prepare(ctx, pl));
+  auto& tg = pl->tg;
+  rmk::launch_symbolnet_forward(pl->dev(), pl->tgdev(), tg.d_stiles.as<Tile>(), tg.nstiles, tg.Pc, params,
+                                tg.sa1.as<float>(), tg.sa2.as<float>(), symbol, ctx->stream);
+  return last_launch();
+}
+
+rm_status rm_symbolnet_backward(rm_ctx* ctx, const rm_plan_t* plan, const float* params, const float* d_symbol,
+                                float* d_params) {
+  RM_TRY(check_ctx_plan(ctx, plan));
+  if (params == nullptr || d_symbol == nullptr || d_params == nullptr)
+    return fail(RM_EINVAL, "null params, d_symbol or d_params");
+  rm_plan_t* pl = const_cast<rm_plan_t*>(plan);
+  RM_TRY(symbolnet_prepare(ctx, pl));
+  auto& tg = pl->tg;
+  hipStream_t st = ctx->stream;
+  const size_t planes = (size_t)std::max<int64_t>(tg.Pc, 1) * 16 * sizeof(float);
+  RM_TRY(tg.sg1.ensure(planes, st));
+  RM_TRY(tg.sg2.ensure(planes, st));
+  RM_TRY(tg.sgz.ensure((size_t)std::max<int64_t>(tg.Pc, 1) * sizeof(float), st));
+  RM_TRY(tg.spart.ensure((size_t)std::max(tg.nstiles, 1) * (16 * 16 * 9 + 16) * sizeof(float), st));
+  // the forward activations of these parameters, then the reverse pass
+  rmk::launch_symbolnet_forward(pl->dev(), pl->tgdev(), tg.d_stiles.as<Tile>(), tg.nstiles, tg.Pc, params,
+                                tg.sa1.as<float>(), tg.sa2.as<float>(), tg.ssym.as<float>(), st);
+  rmk::launch_symbolnet_backward(pl->dev(), pl->tgdev(), tg.d_stiles.as<Tile>(), tg.nstiles, tg.Pc, params,
+                                 tg.sa1.as<float>(), tg.sa2.as<float>(), tg.ssym.as<float>(), d_symbol,
+                                 tg.sgz.as<float>(), tg.sg1.as<float>(), tg.sg2.as<float>(), tg.spart.as<float>(),
+                                 d_params, st);
   return last_launch();
 }
 

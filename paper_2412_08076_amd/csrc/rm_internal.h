@@ -278,4 +278,17 @@ void launch_tg_prolong(const PlanDev& p, const TgDev& g, const float* ec, const 
 void launch_tg_adj_correct(const PlanDev& p, const TgDev& g, const float* ybar, const float* ub, float* ub_out,
                            float* fb, hipStream_t st);
 
+// ---- symbol network of the two-grid cycle (rm_symbolnet.hip) --------------------
+int symbolnet_param_count();
+// symbol = base * exp(net(features)) over 16 x 16 mode tiles (tiles[k].pad = k); a1, a2:
+// [16][Pc] activations kept for the backward pass.
+void launch_symbolnet_forward(const PlanDev& p, const TgDev& g, const Tile* tiles, int ntiles, int64_t Pc,
+                              const float* params, float* a1, float* a2, float* symbol, hipStream_t st);
+// d_params = gradient of sum(d_symbol * symbol) (a1, a2, symbol from the forward pass with
+// the same params; gz [Pc], g1, g2 [16][Pc] and part [ntiles][2320] are scratch).
+void launch_symbolnet_backward(const PlanDev& p, const TgDev& g, const Tile* tiles, int ntiles, int64_t Pc,
+                               const float* params, const float* a1, const float* a2, const float* symbol,
+                               const float* d_symbol, float* gz, float* g1, float* g2, float* part, float* d_params,
+                               hipStream_t st);
+
 }  // namespace rmk

@@ -20,6 +20,7 @@ __all__ = [
     "RMError", "Context", "Plan", "rm_tune", "rm_apply_A", "rm_residual", "rm_solve", "rm_solve_adjoint",
     "rm_twogrid_solve", "rm_twogrid_adjoint", "rm_fgmres",
     "rm_meta_forward", "rm_meta_backward", "rm_meta_param_count", "solve_opts",
+    "rm_symbolnet_param_count", "rm_symbolnet_forward", "rm_symbolnet_backward",
     "RM_Q1_ANISO", "RM_FD5_HELMHOLTZ", "RM_RICHARDSON", "RM_NAG", "RM_MOM", "RM_NAGEX", "RM_F32", "RM_F64",
     "RM_UNROLL", "RM_TO_TOL", "RM_OK", "RM_ENOTCONV", "RM_EDIVERGED",
 ]
@@ -356,3 +357,23 @@ def rm_meta_backward(ctx, plan, m, params, d_omega, d_alpha, d_params):
                                     _ptr(d_omega, torch.float32, plan.B * m, "d_omega"),
                                     _ptr(d_alpha, torch.float32, plan.B * m, "d_alpha"),
                                     _ptr(d_params, torch.float32, npar, "d_params")), "rm_meta_backward")
+
+
+def rm_symbolnet_param_count():
+    return int(_lib.load().rm_symbolnet_param_count())
+
+
+def rm_symbolnet_forward(ctx, plan, params, symbol):
+    """symbol (device float [Pc]) of every instance from the symbol network's params."""
+    _check(ctx.lib.rm_symbolnet_forward(ctx.handle, plan.handle,
+                                        _ptr(params, torch.float32, rm_symbolnet_param_count(), "params"),
+                                        _ptr(symbol, torch.float32, plan.coarse_points(), "symbol")),
+           "rm_symbolnet_forward")
+
+
+def rm_symbolnet_backward(ctx, plan, params, d_symbol, d_params):
+    npar = rm_symbolnet_param_count()
+    _check(ctx.lib.rm_symbolnet_backward(ctx.handle, plan.handle, _ptr(params, torch.float32, npar, "params"),
+                                         _ptr(d_symbol, torch.float32, plan.coarse_points(), "d_symbol"),
+                                         _ptr(d_params, torch.float32, npar, "d_params")),
+           "rm_symbolnet_backward")
