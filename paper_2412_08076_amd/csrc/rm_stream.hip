@@ -48,6 +48,9 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 constexpr int pmod(int a, int b) { return ((a % b) + b) % b; }
 
+// Kinds of iteration of the forward pipeline (see k_stream).
+constexpr int K_RUN = 0, K_STEADY = 1, K_FILL = 2;
+
 // A copy in a new register.  A prefetched row lives on in the pipeline's queues after
 // the loader consumes it; without the copy the allocator keeps it in the prefetch
 // register and moves the next (still in flight) load at the loop edge, which waits for
@@ -156,10 +159,15 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, MAXT))) void k_stream(
   // completes row y = s - 2t with the north row (its arriving row y + 1), updates it
   // and passes it on, and adds the centre row of y + 1.  Phase B: level t starts the
   // residual of row y + 2 from its f (queued by level t - 1 in phase A) with the south
-  // row.  STEADY: every level's row lies in the window, so nothing is masked.
-  auto iter = [&](auto PH_, auto STEADY_, int s) {
+  // row.  Kinds of iteration (K): K_RUN masks at run time; K_STEADY: every level's row
+  // lies in the window, nothing is masked; K_FILL (s = V, a window at least as long as
+  // the fill): the masks are constants, and a level skips phase A while its arriving row
+  // y + 1 precedes the zero row -1, and phase B while row y + 2 precedes row 0.  What is
+  // skipped would only produce values for rows before the window, which are masked,
+  // never stored and never summed; the rows in the window see the same operands.
+  auto iter = [&](auto PH_, auto K_, auto V_, int s) {
     constexpr int PH = decltype(PH_)::value;
-    constexpr bool STEADY = decltype(STEADY_)::value;
+    constexpr int K = decltype(K_)::value, V = decltype(V_)::value;
     constexpr int y2 = pmod(PH, 2);       // slot of row s - 2t (and of row s - 2t + 2)
     constexpr int y2n = pmod(PH + 1, 2);  // slot of row s - 2t + 1 (the arriving row)
     float Cv[NL + 2], Wv[NL + 2], Ev[NL + 2];
@@ -167,7 +175,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, MAXT))) void k_stream(
     // f that level t - 1 queued in its phase A
     auto phase_b = [&](auto T_) {
       constexpr int t = decltype(T_)::value;
-      if constexpr (t >= 1 && t <= NLV) {
+      if constexpr (t >= 1 && t <= NLV && !(K == K_FILL && V - 2 * t + 2 < 0)) {
         float a0 = fmadd(-c[2], Cv[t], R.qf[t][y2]);
         a0 = fmadd(-c[3], Wv[t], a0);
         R.acc[t][y2] = fmadd(-c[4], Ev[t], a0);
@@ -175,9 +183,13 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, MAXT))) void k_stream(
     };
     static_for<0, NL>([&](auto K_) {
       constexpr int t = NL - decltype(K_)::value;
-      if constexpr (t <= NLV) {
+      if constexpr (t <= NLV && K == K_FILL && V - 2 * t < -1) {
+        // the arriving row is row -2 or earlier; phase B reads these zeros as the zero
+        // row -1, the south row of row 0
+        Cv[t] = Wv[t] = Ev[t] = 0.0f;
+      } else if constexpr (t <= NLV) {
         const int y = s - 2 * t;
-        const bool rowok = STEADY || (unsigned)y < (unsigned)L;
+        const bool rowok = K == K_STEADY ? true : K == K_FILL ? V - 2 * t >= 0 : (unsigned)y < (unsigned)L;
         const bool mine = y >= own0 && y < own1 && colin;
         // row y + 1: own column from the register, neighbours from the producer's LDS slot
         const float C = R.in[t];
@@ -229,7 +241,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, MAXT))) void k_stream(
     });
     // loader: row s enters level 1
     {
-      const bool rowok = STEADY || (unsigned)s < (unsigned)L;
+      const bool rowok = K == K_STEADY || K == K_FILL || (unsigned)s < (unsigned)L;
       const float lu = fresh(R.pu[PH]), lv = fresh(R.pv[PH]), lf = fresh(R.pf[PH]);
       const float x = uses_lookahead(METHOD) ? fmadd(fat[1], lv, lu) : lu;
       const float pub = rowok ? x : 0.0f;
@@ -245,18 +257,36 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, MAXT))) void k_stream(
     __syncthreads();
   };
   // fill and drain iterations mask rows outside the window; in between none is
-  const int F = min(S, ((2 * NLV + PF - 1) / PF) * PF);
+  // With L >= FF the fill (s = 0 .. FF - 1) is unrolled with its masks known (L is the
+  // same for the whole workgroup, so every thread takes the same branch).  Only for the
+  // longest pipeline of the sweeps; the others and the recompute that stores the states
+  // keep the run-time masks.  (An unrolled drain, one copy per value of L - D, costs
+  // the kernels their registers: the compiler spills or lowers the occupancy.)
+  constexpr int FF = ((2 * NLV + PF - 1) / PF) * PF;
+  constexpr bool UNROLLED = TL == kStreamMaxT && !STORE;
+  using Run = std::integral_constant<int, K_RUN>;
+  using Steady = std::integral_constant<int, K_STEADY>;
+  using V0 = std::integral_constant<int, 0>;
+  const int F = min(S, FF);
   const int D = F + max(0, (L - F) / PF) * PF;
   int s = 0;
+  if (UNROLLED && L >= FF) {
+    static_for<0, UNROLLED ? FF : 0>([&](auto S_) {
+      constexpr int sc = decltype(S_)::value;
+      iter(std::integral_constant<int, sc % PF>{}, std::integral_constant<int, K_FILL>{}, S_, sc);
+    });
+    s = FF;
+  } else {
 #pragma unroll 1
-  for (; s < F; s += PF)
-    static_for<0, PF>([&](auto PH_) { iter(PH_, std::false_type{}, s + decltype(PH_)::value); });
+    for (; s < F; s += PF)
+      static_for<0, PF>([&](auto PH_) { iter(PH_, Run{}, V0{}, s + decltype(PH_)::value); });
+  }
 #pragma unroll 1
   for (; s < D; s += PF)
-    static_for<0, PF>([&](auto PH_) { iter(PH_, std::true_type{}, s + decltype(PH_)::value); });
+    static_for<0, PF>([&](auto PH_) { iter(PH_, Steady{}, V0{}, s + decltype(PH_)::value); });
 #pragma unroll 1
   for (; s < S; s += PF)
-    static_for<0, PF>([&](auto PH_) { iter(PH_, std::false_type{}, s + decltype(PH_)::value); });
+    static_for<0, PF>([&](auto PH_) { iter(PH_, Run{}, V0{}, s + decltype(PH_)::value); });
   if constexpr (RES) {
     r2 = wave_sum(r2);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = r2;
