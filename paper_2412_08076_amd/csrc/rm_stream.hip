@@ -128,9 +128,17 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, MAXT))) void k_stream(
   });
   for (int e = threadIdx.x; e < (NT + 5) * LS; e += NT) lds[e] = 0.0f;
   float* lb = lds + (colin ? gx : NT + 2) * LS;  // west column; own column at + LS, east at + 2 LS
-  const float* fi = f + in.off;
-  const float* ui = u + in.off;
-  const float* vi = v + in.off;
+  // Rows are read through buffer resources: the column offset is fixed per thread and
+  // the row offset is the same for the whole workgroup (a scalar), so a load needs no
+  // address arithmetic.  Every row read lies in the field.
+  const int nn4 = n * n * (int)sizeof(float);
+  const __amdgpu_buffer_rsrc_t fb_in = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(f + in.off), (short)0,
+                                                                         nn4, kBufWord3);
+  const __amdgpu_buffer_rsrc_t ub_in = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(u + in.off), (short)0,
+                                                                         nn4, kBufWord3);
+  const __amdgpu_buffer_rsrc_t vb_in = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(v + in.off), (short)0,
+                                                                         nn4, kBufWord3);
+  const int col4 = gxc * (int)sizeof(float);
   StreamRegs<TL, PF> R;
   static_for<0, NL + 1>([&](auto T_) {
     constexpr int t = decltype(T_)::value;
@@ -139,10 +147,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, MAXT))) void k_stream(
     for (int k = 0; k < 2; ++k) R.acc[t][k] = R.qu[t][k] = R.qv[t][k] = R.qf[t][k] = 0.0f;
   });
   auto load_row = [&](int r, float& lu, float& lv, float& lf) {
-    const int idx = (ys + r) * n + gxc;
-    lu = ui[idx];
-    lv = uses_momentum(METHOD) ? vi[idx] : 0.0f;
-    lf = fi[idx];
+    const int row4 = (ys + r) * n * (int)sizeof(float);
+    lu = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ub_in, col4, row4, 0));
+    lv = uses_momentum(METHOD) ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(vb_in, col4, row4, 0)) : 0.0f;
+    lf = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(fb_in, col4, row4, 0));
   };
   static_for<0, PF>([&](auto K_) {
     constexpr int k = decltype(K_)::value;
@@ -151,7 +159,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, MAXT))) void k_stream(
   __syncthreads();
   double r2 = 0.0;
   const int S = L + 2 * NLV;
-  const int nn4 = n * n * (int)sizeof(float);
+  // store offsets: the row part is the same for the whole workgroup, and a thread
+  // beyond the grid adds an offset past every field, so one addition forms the offset
+  // (at most 0x7ffffff0 + 2^30: no wrap, and always beyond the field when dropped)
+  const int colst = colin ? gx * (int)sizeof(float) : 0x40000000;
   const __amdgpu_buffer_rsrc_t ub_out = __builtin_amdgcn_make_buffer_rsrc(u_out + in.off, (short)0, nn4, kBufWord3);
   const __amdgpu_buffer_rsrc_t vb_out = __builtin_amdgcn_make_buffer_rsrc(v_out + in.off, (short)0, nn4, kBufWord3);
   // One iteration.  Phase A, levels from the last to the first (each consumes its
@@ -190,7 +201,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, MAXT))) void k_stream(
       } else if constexpr (t <= NLV) {
         const int y = s - 2 * t;
         const bool rowok = K == K_STEADY ? true : K == K_FILL ? V - 2 * t >= 0 : (unsigned)y < (unsigned)L;
-        const bool mine = y >= own0 && y < own1 && colin;
+        const bool rowmine = y >= own0 && y < own1;
+        const bool mine = rowmine && colin;
         // row y + 1: own column from the register, neighbours from the producer's LDS slot
         const float C = R.in[t];
         const float W = lb[(t - 1) * 2 + y2n];
@@ -223,7 +235,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, MAXT))) void k_stream(
               if (uses_momentum(METHOD)) su[gidx + state_stride / 2] = vn;
             }
           } else {
-            const int boff = mine ? ((ys + y) * n + gx) * (int)sizeof(float) : kDropOffset;
+            const int boff = (rowmine ? (ys + y) * n * (int)sizeof(float) : kDropOffset) + colst;
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), ub_out, boff, 0, 0);
             if (uses_momentum(METHOD))
               __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(vn), vb_out, boff, 0, 0);
