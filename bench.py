@@ -223,7 +223,7 @@ def copy_bandwidth(nbytes=1 << 30):
 class Headline:
     """The uneven batch refined to 1e-10 plus the n = 127 training step, one plan each."""
 
-    def __init__(self, tune_cache):
+    def __init__(self, tune_cache, mixed="off"):
         import torch
         from paper_2412_08076_amd import rm
         from synthetic import aniso_batch, meta_params, uneven_batch
@@ -265,6 +265,19 @@ class Headline:
         rm.rm_meta_forward(self.ctx, self.tplan, M, self.params, self.tom, self.tal)
         self.tuned_train_us = rm.rm_tune(self.ctx, self.tplan, rm.RM_NAG, M, self.tom, self.tal, self.tb32,
                                          cache_path=tune_cache)
+        # mixed-size launch: "stream" advances the classes the tuner put on the 8-step row
+        # pipeline in one launch per chunk; "all" first moves every class onto it (whole
+        # height windows where the tuner chose a tiled kernel)
+        self.mixed = mixed
+        if mixed == "all":
+            for n in sorted(set(self.ub.n)):
+                shape, T, cw = self.uplan.get_kernel(int(n))
+                if shape != rm.STREAM_SHAPE or T != 8:
+                    tail = self.uplan.get_tail_kernel(int(n))
+                    self.uplan.set_kernel(rm.STREAM_SHAPE, 8, n=int(n), cw=int(n))
+                    self.uplan.set_tail_kernel(tail[0], tail[1], n=int(n), cw=tail[2])
+        if mixed != "off":
+            self.uplan.set_mixed(True)
 
     def kernels(self):
         return {int(n): list(self.uplan.get_kernel(int(n))) for n in sorted(set(self.ub.n))}
@@ -611,6 +624,9 @@ def main():
     ap.add_argument("--no-comparator", action="store_true", help="skip the plain FP64 loop comparator")
     ap.add_argument("--kernel-only", action="store_true",
                     help="time only the dominant sweep kernel and a 1 GiB device copy (for counter runs)")
+    ap.add_argument("--mixed", default="off", choices=["off", "stream", "all"],
+                    help="mixed-size launch for the uneven batch: off (one launch per size class), stream "
+                         "(the classes on the 8-step row pipeline together), all (every class moved onto it)")
     ap.add_argument("--workload", default="headline",
                     choices=["headline", "aniso", "uneven", "train", "single", "twogrid", "ssor", "fgmres"],
                     help="headline (default) or one of the secondary shapes")
@@ -628,7 +644,7 @@ def main():
     print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
 
     import torch
-    h = Headline(cache)
+    h = Headline(cache, args.mixed)
     print(f"[bench] kernels per size class {h.kernels()}, tuned {h.tuned_us:.1f} us per inner step "
           f"(uneven), {h.tuned_train_us:.1f} (train)", file=sys.stderr, flush=True)
     if args.kernel_only:
@@ -703,7 +719,7 @@ def main():
                    "train_batch": B_TRAIN, "train_n": N_TRAIN, "K_train": K_TRAIN, "ckpt_every": CKPT},
         "time_to_tol_s": ttol,
         "solve": {"status": int(rep["status"]), "rounds_max": int(rep["rounds"].max()),
-                  "relres_max": float(rep["relres"].max()), "per_size": per, "kernels": h.kernels(),
+                  "relres_max": float(rep["relres"].max()), "per_size": per, "kernels": h.kernels(), "mixed": h.mixed,
                   "glups": h.solve_lups(rep) / ttol / 1e9},
         "train": {"ms_per_step": t_train * 1e3, "glups_fwd_adjoint": h.train_lups() / t_train / 1e9,
                   "loss_mean": float(h.loss.mean())},

@@ -177,7 +177,7 @@ rm_status rm_plan_coefficients(const rm_plan_t* plan, double* coef, double* gers
  * 3: R = 13, cw <= 64; 4: R = 16, cw <= 128; 5: R = 12, cw <= 96;
  * 6: R = 13, cw <= 104; 7: R = 32, cw <= 64; 8: R = 32, cw <= 96 (a 256-row tile
  * covers n <= 256 without a vertical halo).  Shape 9 is the row-streaming kernel
- * (n <= 512, T <= 8): one workgroup of 64 ceil(n / 64) threads holds whole rows and
+ * (n <= 1024, T <= 8): one workgroup of 64 ceil(n / 64) threads holds whole rows and
  * pipelines the T steps down a window of cw rows (cw >= n: the whole height, no
  * halo; otherwise windows overlap by T + 1 rows).  rm_plan picks a configuration
  * per class from a cost model; rm_tune measures.  All shapes reproduce one launch
@@ -207,6 +207,19 @@ rm_status rm_plan_set_tail_kernel(rm_plan_t* plan, int32_t n, int32_t shape, int
 rm_status rm_plan_get_tail_kernel(const rm_plan_t* plan, int32_t n, int32_t* shape, int32_t* T,
                                   int32_t* cw);
 rm_status rm_plan_set_tail_switch(rm_plan_t* plan, double frac);
+
+/* Mixed-size launch (the batch of instances of different sizes of Algorithm 1 and
+ * §2.3, advanced together).  on != 0: every size class whose main configuration is
+ * the row pipeline with 8 steps per launch (rm_plan_set_kernel shape 9, T = 8) is
+ * advanced, in that configuration, by one launch per chunk of steps shared by all
+ * such classes: 1024-thread workgroups, each holding 1024 / (64 ceil(n / 64)) row
+ * windows of equal height of one class.  Classes with another main configuration,
+ * classes in their tail configuration and classes from the 65th on keep launches of
+ * their own.  on = 0 (the default): one launch per class.  Iterates, residuals and
+ * reports are bit for bit the same either way.  rm_plan_get_mixed returns the
+ * setting.  RM_EINVAL for a null plan or pointer. */
+rm_status rm_plan_set_mixed(rm_plan_t* plan, int32_t on);
+rm_status rm_plan_get_mixed(const rm_plan_t* plan, int32_t* on);
 
 /* Autotuner: for every size class, time each valid (shape, T, cw) on this plan's
  * data (16 inner steps of `method` with the given device weights and right-hand

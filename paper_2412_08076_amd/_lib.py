@@ -19,7 +19,8 @@ RM_FLAG_SSOR = 4
 EXPORTS = [
     "rm_create", "rm_destroy", "rm_plan", "rm_plan_free", "rm_plan_batch", "rm_plan_points",
     "rm_plan_offsets", "rm_plan_coefficients", "rm_plan_set_kernel", "rm_plan_get_kernel",
-    "rm_plan_set_tail_kernel", "rm_plan_get_tail_kernel", "rm_plan_set_tail_switch", "rm_tune",
+    "rm_plan_set_tail_kernel", "rm_plan_get_tail_kernel", "rm_plan_set_tail_switch", "rm_plan_set_mixed",
+    "rm_plan_get_mixed", "rm_tune",
     "rm_apply_A", "rm_residual", "rm_residual_noalloc", "rm_solve",
     "rm_solve_adjoint", "rm_plan_coarse_points", "rm_plan_coarse_offsets", "rm_twogrid_solve",
     "rm_twogrid_adjoint", "rm_symbolnet_param_count", "rm_symbolnet_forward", "rm_symbolnet_backward",
@@ -78,6 +79,8 @@ def load():
         "rm_plan_set_tail_kernel": (st, [P, I32, I32, I32, I32]),
         "rm_plan_get_tail_kernel": (st, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "rm_plan_set_tail_switch": (st, [P, D]),
+        "rm_plan_set_mixed": (st, [P, I32]),
+        "rm_plan_get_mixed": (st, [P, ctypes.POINTER(I32)]),
         "rm_tune": (st, [P, P, I32, I32, P, P, P, ctypes.c_char_p, ctypes.POINTER(D)]),
         "rm_apply_A": (st, [P, P, I32, P, P]),
         "rm_residual": (st, [P, P, I32, P, P, P, P, P, P]),

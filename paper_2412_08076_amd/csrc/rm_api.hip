@@ -154,6 +154,12 @@ struct rm_plan_s {
   DevBuf d_cls;     // int [B]: size class of each instance
   DevBuf d_rranges; // the same over the reverse-step tables
   int nslots = 0;
+  // mixed-size launch (rm_plan_set_mixed): the main tiles of the classes in it, grouped,
+  // and those classes as a bit mask
+  bool mixed = false;
+  DevBuf d_mtiles, d_mgroups;
+  int nmgroups = 0;
+  unsigned long long mixed_classes = 0;
   double tail_frac = -1.0;  // active fraction below which the refined solve uses the tails (< 0: measured)
   // two-grid correction: coarse layout, tile and row-group tables, twiddles and
   // coarse scratch, built on first use
@@ -194,7 +200,7 @@ struct rm_plan_s {
   }
   ~rm_plan_s() {
     for (DevBuf* b : {&d_tiles, &d_inst, &d_coef32, &d_coef64, &d_mu, &d_gersh, &partial, &red, &flags, &vecA,
-                      &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges, &d_tranges, &d_rranges, &d_cls, &tg.d_inst,
+                      &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges, &d_tranges, &d_rranges, &d_cls, &d_mtiles, &d_mgroups, &tg.d_inst,
                       &tg.d_rtiles, &tg.d_groups, &tg.d_tw, &tg.c0, &tg.c1, &tg.shat, &tg.fine2,
                       &tg.zero, &tg.d_stiles, &tg.sa1, &tg.sa2, &tg.sg1, &tg.sg2, &tg.ssym, &tg.sgz, &tg.spart, &fg.V, &fg.Z, &fg.w, &fg.t, &fg.b32, &fg.dbl, &fg.ints, &fg.partial})
       b->release();
@@ -289,8 +295,9 @@ void init_classes(rm_plan_t* pl) {
 // Tile table of one configuration of a class; residual slots are numbered from `slot`
 // on and each instance's slot range goes to ranges[2b], ranges[2b + 1].
 rm_status build_table(const rm_plan_s::ClassExec& c, int shape, int T, int cw, int& slot, std::vector<int>& ranges,
-                      DevBuf& tiles, int& ntiles, hipStream_t st) {
-  std::vector<rmk::BTile> t;
+                      DevBuf& tiles, int& ntiles, hipStream_t st, std::vector<rmk::BTile>* keep = nullptr) {
+  std::vector<rmk::BTile> local;
+  std::vector<rmk::BTile>& t = keep != nullptr ? *keep : local;
   if (!make_tiles(c.n, c.insts, shape, T, cw, slot, ranges, t)) return fail(RM_EINVAL, "invalid kernel configuration");
   ntiles = (int)t.size();
   RM_TRY(tiles.ensure(t.size() * sizeof(rmk::BTile), st));
@@ -305,7 +312,35 @@ rm_status build_exec(rm_plan_t* pl, hipStream_t st) {
   // main and tail tables number their residual slots in one sequence, so that one outer
   // iteration may run some classes in their main and others in their tail configuration
   int slot = 0, rslot = 0;
-  for (auto& c : pl->classes) RM_TRY(build_table(c, c.shape, c.T, c.cw, slot, ranges, c.tiles, c.ntiles, st));
+  std::vector<std::vector<rmk::BTile>> main_tabs(pl->classes.size());
+  for (size_t ci = 0; ci < pl->classes.size(); ++ci) {
+    auto& c = pl->classes[ci];
+    RM_TRY(build_table(c, c.shape, c.T, c.cw, slot, ranges, c.tiles, c.ntiles, st, &main_tabs[ci]));
+  }
+  // the mixed-size launch takes the classes whose main configuration is the 8-step row
+  // pipeline, over their main tiles (so the same residual slots and ranges)
+  pl->mixed_classes = 0;
+  pl->nmgroups = 0;
+  if (pl->mixed) {
+    std::vector<rmgeo::MixedClass> mc;
+    for (size_t ci = 0; ci < pl->classes.size() && ci < 64; ++ci) {
+      const auto& c = pl->classes[ci];
+      if (c.shape != kStreamShape || c.T != rmk::kStreamMaxT) continue;
+      mc.push_back(rmgeo::MixedClass{(int)ci, c.n, c.cw, &main_tabs[ci]});
+      pl->mixed_classes |= 1ull << ci;
+    }
+    if (!mc.empty()) {
+      std::vector<rmk::BTile> all;
+      std::vector<rmk::MGroup> groups;
+      if (!make_groups(mc, all, groups)) return fail(RM_EINVAL, "mixed-size launch: invalid windows");
+      RM_TRY(pl->d_mtiles.ensure(all.size() * sizeof(rmk::BTile), st));
+      RM_TRY(pl->d_mgroups.ensure(groups.size() * sizeof(rmk::MGroup), st));
+      RM_HIP(hipStreamSynchronize(st));
+      RM_HIP(hipMemcpy(pl->d_mtiles.ptr, all.data(), all.size() * sizeof(rmk::BTile), hipMemcpyHostToDevice));
+      RM_HIP(hipMemcpy(pl->d_mgroups.ptr, groups.data(), groups.size() * sizeof(rmk::MGroup), hipMemcpyHostToDevice));
+      pl->nmgroups = (int)groups.size();
+    }
+  }
   int tslot = slot;
   std::vector<int> cls((size_t)pl->B, 0);
   for (size_t ci = 0; ci < pl->classes.size(); ++ci) {
@@ -489,10 +524,30 @@ rm_status sweep(rm_plan_t* pl, hipStream_t st, int method, int m, int s0, int ns
     for (int j = 0; j < lc; ++j) chunks[ci].push_back(nsteps / lc + (j < nsteps % lc ? 1 : 0));
     L = std::max(L, lc);
   }
+  // the classes the mixed-size launch advances in this sweep: in the launch's table, in
+  // their main configuration and not left out; they share one chunk plan (T = 8)
+  unsigned long long in_mixed = 0;
+  int mc0 = -1;
+  if (pl->mixed && pl->nmgroups > 0 && only_class < 0)
+    for (size_t ci = 0; ci < pl->classes.size() && ci < 64; ++ci)
+      if (((pl->mixed_classes >> ci) & 1ull) != 0 && !uses_tail(skip, ci) && !uses_tail(tail, ci)) {
+        in_mixed |= 1ull << ci;
+        if (mc0 < 0) mc0 = (int)ci;
+      }
   for (int j = 0; j < L; ++j) {
     const int rd = (cur + j) & 1;
+    if (mc0 >= 0 && j < (int)chunks[mc0].size()) {
+      int s = s0;
+      for (int q = 0; q < j; ++q) s += chunks[mc0][q];
+      const bool last = j + 1 == (int)chunks[mc0].size();
+      if (!rmk::launch_stream_mixed(chunks[mc0][j], method, p, pl->d_mtiles.as<rmk::BTile>(),
+                                    pl->d_mgroups.as<rmk::MGroup>(), pl->nmgroups, ~in_mixed, omega, alpha, m, s, f,
+                                    us[rd], vs[rd], us[rd ^ 1], vs[rd ^ 1], active, last ? res_partial : nullptr, st))
+        return fail(RM_EUNSUPPORTED, "mixed-size launch not built for this step count");
+    }
     for (size_t ci = 0; ci < pl->classes.size(); ++ci) {
       if (j >= (int)chunks[ci].size()) continue;
+      if (ci < 64 && ((in_mixed >> ci) & 1ull) != 0) continue;
       auto& c = pl->classes[ci];
       int s = s0;
       for (int q = 0; q < j; ++q) s += chunks[ci][q];
@@ -1839,6 +1894,21 @@ rm_status rm_plan_get_tail_kernel(const rm_plan_t* plan, int32_t n, int32_t* sha
       return RM_OK;
     }
   return fail(RM_EINVAL, "no instance of that size in the plan");
+}
+
+rm_status rm_plan_set_mixed(rm_plan_t* plan, int32_t on) {
+  if (plan == nullptr) return fail(RM_EINVAL, "null plan");
+  if (plan->mixed != (on != 0)) {
+    plan->mixed = on != 0;
+    plan->exec_dirty = true;
+  }
+  return RM_OK;
+}
+
+rm_status rm_plan_get_mixed(const rm_plan_t* plan, int32_t* on) {
+  if (plan == nullptr || on == nullptr) return fail(RM_EINVAL, "null plan or pointer");
+  *on = plan->mixed ? 1 : 0;
+  return RM_OK;
 }
 
 rm_status rm_plan_set_tail_switch(rm_plan_t* plan, double frac) {

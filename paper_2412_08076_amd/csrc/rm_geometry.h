@@ -46,6 +46,17 @@ struct BTile {
   int32_t ox0, ox1, oy0, oy1;
 };
 
+// One workgroup of the mixed-size row-pipeline launch: `count` row windows of one size
+// class (tiles first .. first + count - 1 of the launch's tile list, each window L rows
+// high), in 1024 / nt sub-groups of nt = 64 ceil(n / 64) threads; sub-groups from
+// `count` on have no window and only keep the workgroup's barriers.  cls < 0 marks
+// padding.
+struct MGroup {
+  int32_t first, count, cls, L;
+  int32_t nt, pad0, pad1, pad2;
+};
+constexpr int kMixedThreads = 1024;
+
 }  // namespace rmk
 
 namespace rmgeo {
@@ -219,6 +230,69 @@ inline bool make_tiles(int n, const std::vector<int>& insts, int shape, int T, i
     ranges[2 * b + 1] = slot;
   }
   while (out.size() % 8 != 0) out.push_back(rmk::BTile{-1, 0, 0, slot++, 0, 0, 0, 0});
+  return true;
+}
+
+// Groups of the mixed-size launch over the row windows of several size classes.  Each
+// class contributes its tile table `tiles` (padding entries skipped), whose windows
+// are `wlen` rows high (the last of an instance may be lower); the tiles go to `all`
+// class by class, and within a class height by height.  Windows of one class with the
+// same height share a workgroup, up to kMixedThreads / (64 ceil(n / 64)) of them.
+// The list is eight equal parts, one per XCD, each with an eighth of every class's
+// groups (padding groups, cls = -1, even them out), the largest n first.
+struct MixedClass {
+  int cls, n, wlen;
+  const std::vector<rmk::BTile>* tiles;
+};
+
+inline int window_rows(int n, int wlen, const rmk::BTile& t) { return std::min(n, t.y0 + wlen) - t.y0; }
+
+inline bool make_groups(const std::vector<MixedClass>& classes, std::vector<rmk::BTile>& all,
+                        std::vector<rmk::MGroup>& groups) {
+  all.clear();
+  groups.clear();
+  std::vector<std::vector<rmk::MGroup>> per(classes.size());
+  for (size_t k = 0; k < classes.size(); ++k) {
+    const MixedClass& c = classes[k];
+    if (c.n < 1 || c.n > rmk::kStreamMaxN || c.wlen < 1 || c.tiles == nullptr) return false;
+    const int nt = 64 * ((c.n + 63) / 64), G = rmk::kMixedThreads / nt;
+    // windows of this class by height (heights in order of first appearance)
+    std::vector<std::pair<int, std::vector<rmk::BTile>>> byL;
+    for (const rmk::BTile& t : *c.tiles) {
+      if (t.inst < 0) continue;
+      if (t.y0 < 0 || t.y0 >= c.n) return false;
+      const int L = window_rows(c.n, c.wlen, t);
+      auto it = std::find_if(byL.begin(), byL.end(), [&](const auto& e) { return e.first == L; });
+      if (it == byL.end()) {
+        byL.push_back({L, {}});
+        it = byL.end() - 1;
+      }
+      it->second.push_back(t);
+    }
+    // appended height by height, so that the windows of a group are consecutive
+    for (const auto& e : byL)
+      for (size_t i = 0; i < e.second.size(); i += G) {
+        const int cnt = (int)std::min<size_t>(G, e.second.size() - i);
+        per[k].push_back(rmk::MGroup{(int32_t)all.size(), cnt, c.cls, e.first, nt, 0, 0, 0});
+        all.insert(all.end(), e.second.begin() + i, e.second.begin() + i + cnt);
+      }
+  }
+  // The launch hands XCD k the k-th eighth of the list (xcd_remap): each eighth takes
+  // every eighth group of every class (groups k, k + 8, ... of it, padded to the same
+  // count), larger classes first, so each XCD gets an equal share of every class and
+  // starts its longest workgroups first.
+  std::vector<size_t> order(classes.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return classes[a].n > classes[b].n; });
+  const rmk::MGroup pad{0, 0, -1, 0, 64, 0, 0, 0};
+  for (int x = 0; x < 8; ++x)
+    for (size_t k : order) {
+      const size_t q = (per[k].size() + 7) / 8;
+      for (size_t j = 0; j < q; ++j) {
+        const size_t i = (size_t)x + 8 * j;
+        groups.push_back(i < per[k].size() ? per[k][i] : pad);
+      }
+    }
   return true;
 }
 

@@ -180,6 +180,15 @@ bool launch_stream(int T, int wlen, int n, int method, const PlanDev& p, const B
                    const float* v, float* u_out, float* v_out, const int* active, double* partial2,
                    hipStream_t st, float* states = nullptr, int64_t state_stride = 0);
 
+// T (1..kStreamMaxT) forward steps of every size class in one launch of kMixedThreads-
+// thread workgroups over a group table (rmgeo::make_groups) whose tiles are the
+// classes' row-pipeline tables; the groups of a class with bit c set in leave_out do
+// nothing (c < 64).  Results, residual partials and slots as with launch_stream.
+bool launch_stream_mixed(int T, int method, const PlanDev& p, const BTile* tiles, const MGroup* groups, int ngroups,
+                         unsigned long long leave_out, const float* omega, const float* alpha, int m, int s0,
+                         const float* f, const float* u, const float* v, float* u_out, float* v_out,
+                         const int* active, double* partial2, hipStream_t st);
+
 // Up to kAdjMaxT reverse steps per launch over a row-streaming tile table (windows
 // overlapping by at least T + 1 rows).  Level l = 1..T reverses the forward step whose
 // state (before the step) is u[l - 1], v[l - 1] and whose weight index is i[l - 1]

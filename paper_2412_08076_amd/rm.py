@@ -147,6 +147,16 @@ class Plan:
         """rm_plan_set_tail_switch: active fraction below which the tails run (< 0: measured)."""
         _check(self.lib.rm_plan_set_tail_switch(self.handle, float(frac)), "rm_plan_set_tail_switch")
 
+    def set_mixed(self, on):
+        """rm_plan_set_mixed: advance every class that runs the 8-step row pipeline in one
+        launch per chunk of steps (same results as one launch per class)."""
+        _check(self.lib.rm_plan_set_mixed(self.handle, 1 if on else 0), "rm_plan_set_mixed")
+
+    def get_mixed(self):
+        on = ctypes.c_int32()
+        _check(self.lib.rm_plan_get_mixed(self.handle, ctypes.byref(on)), "rm_plan_get_mixed")
+        return bool(on.value)
+
     def coarse_points(self):
         """rm_plan_coarse_points: total coarse points of the two-grid cycle (-1 if the
         plan's sizes do not qualify)."""

@@ -7,9 +7,14 @@
 //   - a tile table owns every point of every instance exactly once, each owned rectangle
 //     lies in its tile's window with the halo, residual slots are numbered consecutively,
 //     the per-instance slot ranges partition them and the table is padded to a multiple of 8;
-//   - the reverse-step windows split n into the number of windows they promise.
+//   - the reverse-step windows split n into the number of windows they promise;
+//   - the groups of the mixed-size launch hold every window of every class exactly once,
+//     each group windows of one class and one height, no more than its workgroup holds;
+//     the list is eight equal parts (one per XCD), each with its class's groups larger
+//     classes first and every class's groups spread over the parts within one.
 // Exit status 0 when every check holds; the first failure is printed.
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
 #include <vector>
 
@@ -103,6 +108,75 @@ static void check_table(int n, int count, int shape, int T, int cw) {
   CHECK(slot == expect_slot, "slot counter %d, expected %d", slot, expect_slot);
 }
 
+static void check_groups(const std::vector<int>& ns, const std::vector<int>& counts, int pick) {
+  std::vector<std::vector<rmk::BTile>> tabs(ns.size());
+  std::vector<MixedClass> mc;
+  std::vector<int> wl(ns.size());
+  int slot = 0, B = 0;
+  for (int c : counts) B += c;
+  std::vector<int> ranges(2 * (size_t)B, 0), ninst((size_t)B, 0);
+  int b0 = 0;
+  for (size_t k = 0; k < ns.size(); ++k) {
+    const int n = ns[k];
+    const auto ws = candidate_widths(n, kStreamShape, rmk::kStreamMaxT);
+    if (ws.empty()) return;
+    wl[k] = ws[(size_t)pick % ws.size()];
+    std::vector<int> insts;
+    for (int j = 0; j < counts[k]; ++j) {
+      insts.push_back(b0 + j);
+      ninst[(size_t)b0 + j] = n;
+    }
+    b0 += counts[k];
+    CHECK(make_tiles(n, insts, kStreamShape, rmk::kStreamMaxT, wl[k], slot, ranges, tabs[k]), "mixed table n=%d", n);
+    mc.push_back(MixedClass{(int)k, n, wl[k], &tabs[k]});
+  }
+  std::vector<rmk::BTile> all;
+  std::vector<rmk::MGroup> g;
+  CHECK(make_groups(mc, all, g), "make_groups refused valid classes");
+  CHECK(g.size() % 8 == 0, "group list length %zu", g.size());
+  std::vector<int> seen((size_t)slot, 0);
+  std::vector<std::vector<int>> per_part(ns.size(), std::vector<int>(8, 0));
+  const size_t part = g.size() / 8;
+  int prev_n = 1 << 30;
+  size_t covered = 0;
+  for (size_t gi = 0; gi < g.size(); ++gi) {
+    const auto& e = g[gi];
+    if (gi % part == 0) prev_n = 1 << 30;  // a new XCD part
+    if (e.cls < 0) continue;
+    CHECK(e.cls < (int)ns.size(), "group class %d", e.cls);
+    if (e.cls >= (int)ns.size()) continue;
+    ++per_part[(size_t)e.cls][gi / part];
+    const int n = ns[(size_t)e.cls];
+    CHECK(n <= prev_n, "groups of a part not ordered by size: %d after %d", n, prev_n);
+    prev_n = n;
+    CHECK(e.nt == 64 * ((n + 63) / 64), "n=%d: sub-group of %d threads", n, e.nt);
+    CHECK(e.count >= 1 && e.count * e.nt <= rmk::kMixedThreads, "n=%d: %d windows of %d threads", n, e.count, e.nt);
+    CHECK(e.first >= 0 && (size_t)e.first + (size_t)e.count <= all.size(), "group tiles out of range");
+    for (int j = 0; j < e.count && (size_t)(e.first + j) < all.size(); ++j) {
+      const rmk::BTile& t = all[(size_t)e.first + j];
+      CHECK(t.inst >= 0 && t.inst < B && ninst[(size_t)t.inst] == n, "tile of another class in a group of n=%d", n);
+      CHECK(window_rows(n, wl[(size_t)e.cls], t) == e.L, "n=%d: window of %d rows in a group of %d", n,
+            window_rows(n, wl[(size_t)e.cls], t), e.L);
+      CHECK(e.L >= 1 && t.y0 + e.L <= n, "n=%d: window rows [%d, %d)", n, t.y0, t.y0 + e.L);
+      if (t.slot >= 0 && t.slot < slot) ++seen[(size_t)t.slot];
+      ++covered;
+    }
+  }
+  CHECK(covered == all.size(), "groups cover %zu of %zu windows", covered, all.size());
+  for (size_t k = 0; k < ns.size(); ++k) {
+    const auto mm = std::minmax_element(per_part[k].begin(), per_part[k].end());
+    CHECK(*mm.second - *mm.first <= 1, "n=%d: %d to %d groups per XCD part", ns[k], *mm.first, *mm.second);
+  }
+  size_t windows = 0;
+  for (const auto& tab : tabs)
+    for (const auto& t : tab)
+      if (t.inst >= 0) {
+        ++windows;
+        CHECK(seen[(size_t)t.slot] == 1, "window with slot %d grouped %d times", t.slot, seen[(size_t)t.slot]);
+      }
+  CHECK(windows == all.size(), "%zu windows, %zu in the launch list", windows, all.size());
+}
+
 int main() {
   // 1D partitions
   for (int n = 1; n <= 300; ++n)
@@ -136,6 +210,12 @@ int main() {
         CHECK(len >= 1 && len <= n, "reverse window %d for n=%d", len, n);
         if (len < n) check_partition(n, len, rmk::kAdjMaxT + 1);
       }
+  }
+  // mixed-size launch groups
+  for (int pick = 0; pick < 5; ++pick) {
+    check_groups({63, 127, 255, 511, 1023}, {205, 128, 102, 51, 26}, pick);
+    check_groups({1, 2, 65, 300, 700, 1024}, {3, 1, 17, 5, 2, 1}, pick);
+    check_groups({1023, 64, 513}, {1, 40, 3}, pick);
   }
   if (failures == 0) std::printf("plan checks passed\n");
   return failures == 0 ? 0 : 1;
