@@ -17,6 +17,7 @@ train.glups_fwd_adjoint is (2) alone.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -169,6 +170,19 @@ def kernel_name(kcfg, n, count):
     return f"k_block variant {sh} T={T} width={cw} n={n} B={count}"
 
 
+# the sources of the dominant kernel: a committed traffic profile counts only while they
+# are byte for byte the ones it was measured on
+KERNEL_SOURCES = ["rm_stream_run.h", "rm_stream.hip", "rm_device.h", "rm_internal.h", "rm_geometry.h"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2412_08076_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def roofline(kstr, T, units, t_launch, copy_gbs):
     """Roofline entry of the dominant kernel (the temporal-blocked NAG sweep of the size
     class that sets the time to tolerance).
@@ -179,15 +193,16 @@ def roofline(kstr, T, units, t_launch, copy_gbs):
     the published FP32 peak.  The same rate against the FP32 peak without packed
     instructions (which this build disables) is kept as a separate field.  traffic: DRAM
     bytes per launch from the FETCH_SIZE / WRITE_SIZE counters scaled by a copy-kernel
-    calibration, when a committed profile exists for this exact kernel configuration,
-    else null; dram_frac is that traffic over the launch time against 8 TB/s."""
+    calibration, when a committed profile exists for this exact kernel configuration and
+    kernel source (KERNEL_SOURCES), else null; dram_frac is that traffic over the launch
+    time against 8 TB/s."""
     flops = FLOPS_PER_LUP * units * T
     traffic = None
     for name in sorted(os.listdir(os.path.join(ROOT, "profiles"))):
         if name.endswith("_traffic.json"):
             with open(os.path.join(ROOT, "profiles", name)) as fh:
                 prof = json.load(fh)
-            if prof.get("kernel") == kstr:
+            if prof.get("kernel") == kstr and prof.get("source_sha256") == kernel_source_hash():
                 traffic = prof["dram_bytes_per_launch"]
     achieved = flops / t_launch / 1e12
     dram = (traffic / t_launch / 1e9) if traffic else None
