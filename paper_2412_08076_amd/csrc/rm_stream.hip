@@ -36,20 +36,22 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, MAXT))) void k_stream(
                                                v_out, partial2, states, state_stride);
 }
 
-template <int TL, int MAXT, int PF>
+// PFP: prefetch depth of the plain sweep; PFR: of the launches that also form the residual
+// or store the states (more registers).
+template <int TL, int MAXT, int PFP, int PFR>
 bool launch_stream_tl(int nw, int wlen, int method, const PlanDev& p, const BTile* tiles, int ntiles,
                       const float* omega, const float* alpha, int m, int s0, const float* f, const float* u,
                       const float* v, float* u_out, float* v_out, const int* active, double* partial2,
                       float* states, int64_t state_stride, hipStream_t st) {
   const dim3 grid(ntiles), block(64 * nw);
   const size_t lds = (size_t)(64 * nw + 5) * (2 * (TL + 1) + 1) * sizeof(float);
-#define RM_LAUNCH(MM, SS, RR)                                                                                       \
+#define RM_LAUNCH(MM, SS, RR, PF)                                                                                   \
   hipLaunchKernelGGL((k_stream<TL, MM, SS, RR, MAXT, PF>), grid, block, lds, st, p, tiles, ntiles, wlen, omega,   \
                      alpha, m, s0, f, u, v, u_out, v_out, active, partial2, states, state_stride)
 #define RM_METHOD(MM)                          \
-  if (states != nullptr) RM_LAUNCH(MM, true, false);  \
-  else if (partial2 != nullptr) RM_LAUNCH(MM, false, true); \
-  else RM_LAUNCH(MM, false, false);
+  if (states != nullptr) RM_LAUNCH(MM, true, false, PFR);  \
+  else if (partial2 != nullptr) RM_LAUNCH(MM, false, true, PFR); \
+  else RM_LAUNCH(MM, false, false, PFP);
   // the forward recompute that stores every state never asks for the residual
   if (states != nullptr && partial2 != nullptr) return false;
   switch (method) {
@@ -309,10 +311,10 @@ bool launch_stream(int T, int wlen, int n, int method, const PlanDev& p, const B
   const int nw = (n + 63) / 64;
 #define RM_T_CASE(TT)                                                                                              \
   case TT:                                                                                                         \
-    return nw > 8 ? launch_stream_tl<TT, 1024, 2>(nw, wlen, method, p, tiles, ntiles, omega, alpha, m, s0, f, u, v, \
-                                                  u_out, v_out, active, partial2, states, state_stride, st)        \
-                  : launch_stream_tl<TT, 512, 4>(nw, wlen, method, p, tiles, ntiles, omega, alpha, m, s0, f, u, v,  \
-                                                 u_out, v_out, active, partial2, states, state_stride, st);
+    return nw > 8 ? launch_stream_tl<TT, 1024, 4, 2>(nw, wlen, method, p, tiles, ntiles, omega, alpha, m, s0, f, u, \
+                                                     v, u_out, v_out, active, partial2, states, state_stride, st)     \
+                  : launch_stream_tl<TT, 512, 4, 4>(nw, wlen, method, p, tiles, ntiles, omega, alpha, m, s0, f, u, v,  \
+                                                    u_out, v_out, active, partial2, states, state_stride, st);
   switch (T) {
     RM_T_CASE(1)
     RM_T_CASE(2)
