@@ -34,6 +34,7 @@ M, K_TRAIN, CKPT, TOL = 16, 64, 16, 1e-10
 # drifts from the FP64 trajectory a little below that at n >= 511), at most 16 rounds
 TOL_INNER, MAX_ROUNDS = 0.05, 16
 B_TRAIN, N_TRAIN = 64, 127
+B_ANISO, N_ANISO = 256, 255  # the single-size anisotropic batch (and the SSOR line's)
 HBM_PEAK_GBS = 8000.0
 # published MI355X vector FP32 peak (counts packed FP32 FMAs)
 FP32_PEAK_TFLOPS = 157.3
@@ -426,7 +427,7 @@ def secondary_workload(name, tune_cache):
     if name == "train":
         batch = aniso_batch(B_TRAIN, N_TRAIN, seed=3)
     elif name == "aniso":
-        batch = aniso_batch(256, 255, seed=2)
+        batch = aniso_batch(B_ANISO, N_ANISO, seed=2)
     else:
         batch = uneven_batch(seed=4)
     plan = rm.Plan(ctx, batch.n, eps=batch.eps, theta=batch.theta)
@@ -497,7 +498,7 @@ def ssor_workload(ctx, m=3, relax=1.0, w=1.2, a=0.96):
     import torch
     from paper_2412_08076_amd import rm
     from synthetic import aniso_batch
-    batch = aniso_batch(B, N, seed=2)
+    batch = aniso_batch(B_ANISO, N_ANISO, seed=2)
     plan = rm.Plan(ctx, batch.n, eps=batch.eps, theta=batch.theta)
     Bn, P = plan.B, plan.P
     om = torch.full((Bn * m,), w, dtype=torch.float32, device="cuda")
@@ -523,7 +524,7 @@ def ssor_workload(ctx, m=3, relax=1.0, w=1.2, a=0.96):
             "glups_per_step": P / t_step / 1e9, "to_tol_s": tt, "status": int(rep["status"]),
             "outer_median": float(np.median(rep["outer_iters"])), "outer_max": int(rep["outer_iters"].max()),
             "rounds_max": int(rep["rounds"].max()), "relres_max": float(rep["relres"].max()),
-            "to_tol_glups": float(np.sum(steps) * N * N) / tt / 1e9}
+            "to_tol_glups": float(np.sum(steps) * N_ANISO * N_ANISO) / tt / 1e9}
 
 
 def _helmholtz_setup(ctx, m):
@@ -574,10 +575,13 @@ def twogrid_workload(ctx, tune_cache, K=4, m=8, reps=5):
     """Two-grid Helmholtz: 32 problems, n = 511, kappa ~ U(20, 80), Gaussian point
     sources; K cycles of NAG-Richardson(8) smoothing (Chebyshev weights on the upper
     quarter of the spectrum, alpha = 0.1) plus the sine-transform coarse correction
-    with a fine-grid spectral symbol; then the adjoint of the K cycles."""
+    with a fine-grid spectral symbol; then the adjoint of the K cycles.  Then the training
+    step of the multilevel variant: the symbol from the symbol network (seeded parameters,
+    last layer near zero, so close to the fixed symbol), the K cycles with it, their
+    adjoint, and the network's backward pass to its parameter gradient."""
     import torch
     from paper_2412_08076_amd import rm
-    from synthetic import helmholtz_batch, smoothing_weights, twogrid_symbol
+    from synthetic import helmholtz_batch, smoothing_weights, symbolnet_params, twogrid_symbol
     batch = helmholtz_batch(32, 511, seed=5)
     plan = rm.Plan(ctx, batch.n, kappa=batch.kappa, op=rm.RM_FD5_HELMHOLTZ)
     P, Bn, Pc = plan.P, plan.B, plan.coarse_points()
@@ -619,6 +623,40 @@ def twogrid_workload(ctx, tune_cache, K=4, m=8, reps=5):
     e[2].record(); torch.cuda.synchronize()
     tf = e[0].elapsed_time(e[1]) / reps / 1e3
     ta = e[1].elapsed_time(e[2]) / reps / 1e3
+    # the symbol network's step
+    params = torch.tensor(symbolnet_params(seed=7), dtype=torch.float32, device="cuda")
+    sym_net = torch.empty_like(sym)
+    dparams = torch.empty_like(params)
+
+    def net_fwd():
+        rm.rm_symbolnet_forward(ctx, plan, params, sym_net)
+
+    def net_bwd():
+        rm.rm_symbolnet_backward(ctx, plan, params, ds, dparams)
+
+    def net_step():
+        net_fwd()
+        x.zero_()
+        rm.rm_twogrid_solve(ctx, plan, rm.RM_NAG, opts, om, al, sym_net, b32, x, ckpt=ck)
+        rm.rm_twogrid_adjoint(ctx, plan, rm.RM_NAG, opts, om, al, sym_net, b32, ck, dw, da, ds, d_b=db, loss=loss)
+        net_bwd()
+
+    net_step(); torch.cuda.synchronize()
+    net_loss = float(loss.mean())
+    e = [ev() for _ in range(4)]
+    e[0].record()
+    for _ in range(reps):
+        net_fwd()
+    e[1].record()
+    for _ in range(reps):
+        net_bwd()
+    e[2].record()
+    for _ in range(reps):
+        net_step()
+    e[3].record(); torch.cuda.synchronize()
+    tnf = e[0].elapsed_time(e[1]) / reps / 1e3
+    tnb = e[1].elapsed_time(e[2]) / reps / 1e3
+    tns = e[2].elapsed_time(e[3]) / reps / 1e3
     b2 = torch.as_tensor(np.array([np.sum(f * f) for f in batch.f])).cuda()
     rel = (hist.view(K, Bn) / b2).sqrt().cpu().numpy()
     lups = K * m * P
@@ -627,7 +665,10 @@ def twogrid_workload(ctx, tune_cache, K=4, m=8, reps=5):
             "tuned_us_per_step": us, "ms_forward": tf * 1e3, "ms_per_cycle": tf / K * 1e3, "ms_adjoint": ta * 1e3,
             "glups_forward": lups / tf / 1e9, "glups_fwd_adjoint": 2 * lups / (tf + ta) / 1e9,
             "relres_median_per_cycle": [float(np.median(r)) for r in rel],
-            "relres_max_after_K": float(rel[-1].max()), "loss_mean": float(loss.mean())}
+            "relres_max_after_K": float(rel[-1].max()), "loss_mean": float(loss.mean()),
+            "symbolnet": {"params": int(params.numel()), "ms_forward": tnf * 1e3, "ms_backward": tnb * 1e3,
+                          "ms_train_step": tns * 1e3, "loss_mean": net_loss,
+                          "grad_norm": float(dparams.double().norm())}}
 
 
 def main():

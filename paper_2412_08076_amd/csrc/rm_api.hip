@@ -171,7 +171,7 @@ struct rm_plan_s {
     int nrtiles = 0, ngroups = 0, mmax = 0;
     // symbol network: 16 x 16 mode tiles, activations and gradients (16 planes each),
     // the symbol, its log-gradient and the per-tile weight-gradient partials
-    DevBuf d_stiles, sa1, sa2, sg1, sg2, ssym, sgz, spart;
+    DevBuf d_stiles, sa1, sa2, sg1, sg2, ssym, sgz, spart, sgsum;
     int nstiles = 0;
   } tg;
   // flexible GMRES: basis (FP64), preconditioned directions (FP32), work vectors and
@@ -202,7 +202,7 @@ struct rm_plan_s {
     for (DevBuf* b : {&d_tiles, &d_inst, &d_coef32, &d_coef64, &d_mu, &d_gersh, &partial, &red, &flags, &vecA,
                       &vecB, &vecC, &vecD, &vecE, &vecF, &states, &acc, &meta, &d_ranges, &d_tranges, &d_rranges, &d_cls, &d_mtiles, &d_mgroups, &tg.d_inst,
                       &tg.d_rtiles, &tg.d_groups, &tg.d_tw, &tg.c0, &tg.c1, &tg.shat, &tg.fine2,
-                      &tg.zero, &tg.d_stiles, &tg.sa1, &tg.sa2, &tg.sg1, &tg.sg2, &tg.ssym, &tg.sgz, &tg.spart, &fg.V, &fg.Z, &fg.w, &fg.t, &fg.b32, &fg.dbl, &fg.ints, &fg.partial})
+                      &tg.zero, &tg.d_stiles, &tg.sa1, &tg.sa2, &tg.sg1, &tg.sg2, &tg.ssym, &tg.sgz, &tg.spart, &tg.sgsum, &fg.V, &fg.Z, &fg.w, &fg.t, &fg.b32, &fg.dbl, &fg.ints, &fg.partial})
       b->release();
     for (auto& c : classes) {
       c.tiles.release();
@@ -1524,13 +1524,15 @@ rm_status rm_symbolnet_backward(rm_ctx* ctx, const rm_plan_t* plan, const float*
   RM_TRY(tg.sg2.ensure(planes, st));
   RM_TRY(tg.sgz.ensure((size_t)std::max<int64_t>(tg.Pc, 1) * sizeof(float), st));
   RM_TRY(tg.spart.ensure((size_t)std::max(tg.nstiles, 1) * (16 * 16 * 9 + 16) * sizeof(float), st));
+  // FP64 sums of the partials over groups of 64 tiles
+  RM_TRY(tg.sgsum.ensure((size_t)std::max((tg.nstiles + 63) / 64, 1) * (16 * 16 * 9 + 16) * sizeof(double), st));
   // the forward activations of these parameters, then the reverse pass
   rmk::launch_symbolnet_forward(pl->dev(), pl->tgdev(), tg.d_stiles.as<Tile>(), tg.nstiles, tg.Pc, params,
                                 tg.sa1.as<float>(), tg.sa2.as<float>(), tg.ssym.as<float>(), st);
   rmk::launch_symbolnet_backward(pl->dev(), pl->tgdev(), tg.d_stiles.as<Tile>(), tg.nstiles, tg.Pc, params,
                                  tg.sa1.as<float>(), tg.sa2.as<float>(), tg.ssym.as<float>(), d_symbol,
                                  tg.sgz.as<float>(), tg.sg1.as<float>(), tg.sg2.as<float>(), tg.spart.as<float>(),
-                                 d_params, st);
+                                 tg.sgsum.as<double>(), d_params, st);
   return last_launch();
 }
 

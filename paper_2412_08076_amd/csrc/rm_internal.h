@@ -294,10 +294,11 @@ int symbolnet_param_count();
 void launch_symbolnet_forward(const PlanDev& p, const TgDev& g, const Tile* tiles, int ntiles, int64_t Pc,
                               const float* params, float* a1, float* a2, float* symbol, hipStream_t st);
 // d_params = gradient of sum(d_symbol * symbol) (a1, a2, symbol from the forward pass with
-// the same params; gz [Pc], g1, g2 [16][Pc] and part [ntiles][2320] are scratch).
+// the same params; gz [Pc], g1, g2 [16][Pc], part [ntiles][2320] and gsum
+// [ceil(ntiles / 64)][2320] doubles are scratch).
 void launch_symbolnet_backward(const PlanDev& p, const TgDev& g, const Tile* tiles, int ntiles, int64_t Pc,
                                const float* params, const float* a1, const float* a2, const float* symbol,
-                               const float* d_symbol, float* gz, float* g1, float* g2, float* part, float* d_params,
-                               hipStream_t st);
+                               const float* d_symbol, float* gz, float* g1, float* g2, float* part, double* gsum,
+                               float* d_params, hipStream_t st);
 
 }  // namespace rmk

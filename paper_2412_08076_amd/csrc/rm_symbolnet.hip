@@ -16,8 +16,9 @@
 // gradient through the transposed convolution and the tanh derivative, and per tile the
 // partial sums of every weight's gradient (thread = (output, input) channel pair, the nine
 // kernel offsets in registers); the weights themselves are staged in LDS, transposed so
-// that the weights one staged value multiplies are consecutive words; the partials are summed over the tiles in FP64 in tile
-// order, so the gradient is the same on every run.
+// that the weights one staged value multiplies are consecutive words.  The partials are
+// summed in FP64 in a fixed order (each group of SN_TG consecutive tiles in tile order,
+// then the groups in order), so the gradient is the same on every run.
 #include "rm_device.h"
 
 #pragma clang fp contract(off)
@@ -30,6 +31,7 @@ constexpr int SN_T = 16;            // tile edge (coarse modes)
 constexpr int SN_H = SN_T + 2;      // with the halo
 constexpr int SN_PL = SN_H * SN_H + 1;  // LDS plane stride (odd: channel planes on distinct banks)
 constexpr int SN_C = 16;            // hidden channels
+constexpr int SN_TG = 64;           // tiles per group of the weight-gradient reduction
 constexpr int SN_W1 = 0, SN_B1 = SN_W1 + SN_C * 3 * 9, SN_W2 = SN_B1 + SN_C, SN_B2 = SN_W2 + SN_C * SN_C * 9,
               SN_W3 = SN_B2 + SN_C, SN_B3 = SN_W3 + SN_C * 9, SN_NP = SN_B3 + 1;
 
@@ -203,13 +205,32 @@ __global__ __launch_bounds__(SN_T* SN_T) void k_sn_backward(PlanDev p, TgDev g, 
   }
 }
 
-// d[k] = sum over tiles t (in order) of part[t][k], k < npl, in FP64.
-__global__ void k_sn_reduce(const float* __restrict__ part, int ntiles, int npl, float* __restrict__ d) {
+// gsum[g][k] = sum over the tiles t of group g (t = g SN_TG .. , in order) of part[t][k],
+// k < npl, in FP64 (grid: parameter blocks x groups).
+__global__ void k_sn_reduce_groups(const float* __restrict__ part, int ntiles, int npl, double* __restrict__ gsum) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x, g = blockIdx.y;
+  if (k >= npl) return;
+  const int t0 = g * SN_TG, t1 = min(ntiles, t0 + SN_TG);
+  double s = 0.0;
+  for (int t = t0; t < t1; ++t) s += (double)part[(int64_t)t * npl + k];
+  gsum[(int64_t)g * npl + k] = s;
+}
+
+// d[k] = sum over the groups g (in order) of gsum[g][k], rounded to FP32 (zero without tiles).
+__global__ void k_sn_reduce(const double* __restrict__ gsum, int ngroups, int npl, float* __restrict__ d) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= npl) return;
   double s = 0.0;
-  for (int t = 0; t < ntiles; ++t) s += (double)part[(int64_t)t * npl + k];
+  for (int g = 0; g < ngroups; ++g) s += gsum[(int64_t)g * npl + k];
   d[k] = (float)s;
+}
+
+// The sum over the tiles of part[t][k] into d[k] (two kernels, see above).
+void sn_reduce(const float* part, double* gsum, int ntiles, int npl, float* d, hipStream_t st) {
+  const int ng = (ntiles + SN_TG - 1) / SN_TG;
+  if (ng > 0)
+    hipLaunchKernelGGL(k_sn_reduce_groups, dim3((npl + 255) / 256, ng), dim3(256), 0, st, part, ntiles, npl, gsum);
+  hipLaunchKernelGGL(k_sn_reduce, dim3((npl + 255) / 256), dim3(256), 0, st, (const double*)gsum, ng, npl, d);
 }
 
 }  // namespace
@@ -229,12 +250,11 @@ void launch_symbolnet_forward(const PlanDev& p, const TgDev& g, const Tile* tile
 
 void launch_symbolnet_backward(const PlanDev& p, const TgDev& g, const Tile* tiles, int ntiles, int64_t Pc,
                                const float* params, const float* a1, const float* a2, const float* symbol,
-                               const float* d_symbol, float* gz, float* g1, float* g2, float* part, float* d_params,
-                               hipStream_t st) {
+                               const float* d_symbol, float* gz, float* g1, float* g2, float* part, double* gsum,
+                               float* d_params, hipStream_t st) {
   constexpr int N3 = 1 * SN_C * 9 + 1, N2 = SN_C * SN_C * 9 + SN_C, N1 = SN_C * 3 * 9 + SN_C;
   if (ntiles == 0) {  // no coarse grid: the reductions over zero tiles write zero gradients
-    hipLaunchKernelGGL(k_sn_reduce, dim3((SN_NP + 255) / 256), dim3(256), 0, st, (const float*)part, 0, SN_NP,
-                       d_params);
+    sn_reduce(part, gsum, 0, SN_NP, d_params, st);
     return;
   }
   const int fill = (int)std::min<int64_t>((Pc + 255) / 256, 4096);
@@ -242,16 +262,13 @@ void launch_symbolnet_backward(const PlanDev& p, const TgDev& g, const Tile* til
   // layer 3: weights W3, b3 and the gradient at layer 2's pre-activation
   hipLaunchKernelGGL((k_sn_backward<SN_C, 1, false, true>), dim3(ntiles), dim3(SN_T * SN_T), 0, st, p, g, tiles, Pc,
                      params, SN_W3, a2, (const float*)gz, g2, part);
-  hipLaunchKernelGGL(k_sn_reduce, dim3((N3 + 255) / 256), dim3(256), 0, st, (const float*)part, ntiles, N3,
-                     d_params + SN_W3);
+  sn_reduce(part, gsum, ntiles, N3, d_params + SN_W3, st);
   hipLaunchKernelGGL((k_sn_backward<SN_C, SN_C, false, true>), dim3(ntiles), dim3(SN_T * SN_T), 0, st, p, g, tiles,
                      Pc, params, SN_W2, a1, (const float*)g2, g1, part);
-  hipLaunchKernelGGL(k_sn_reduce, dim3((N2 + 255) / 256), dim3(256), 0, st, (const float*)part, ntiles, N2,
-                     d_params + SN_W2);
+  sn_reduce(part, gsum, ntiles, N2, d_params + SN_W2, st);
   hipLaunchKernelGGL((k_sn_backward<3, SN_C, true, false>), dim3(ntiles), dim3(SN_T * SN_T), 0, st, p, g, tiles, Pc,
                      params, SN_W1, (const float*)nullptr, (const float*)g1, (float*)nullptr, part);
-  hipLaunchKernelGGL(k_sn_reduce, dim3((N1 + 255) / 256), dim3(256), 0, st, (const float*)part, ntiles, N1,
-                     d_params + SN_W1);
+  sn_reduce(part, gsum, ntiles, N1, d_params + SN_W1, st);
 }
 
 }  // namespace rmk
