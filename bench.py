@@ -342,12 +342,13 @@ class Headline:
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3 / reps
 
-    def dominant_kernel(self, K=128, reps=3):
+    def dominant_kernel(self, K=256, reps=5):
         """Per-launch time of the sweep kernel of the largest size class, all its instances
-        active: a plan of that class alone, its tuned configuration, unrolled solves of K
-        and 2K steps (K / T and 2K / T back-to-back launches), HIP events on the library's
-        stream; the launch time is their difference over K / T launches, so the unroll's
-        fixed work (clearing v, the final copy) cancels."""
+        active: a plan of that class alone, its tuned configuration, unrolled solves of 2K
+        and K steps (2K / T and K / T back-to-back launches) timed one after the other with
+        HIP events on the library's stream; the launch time is their difference over K / T
+        launches, so the unroll's fixed work (clearing v, the final copy) cancels, and the
+        median over `reps` such pairs is reported."""
         rm, torch = self.rm, self.torch
         n = int(self.ns.max())
         idx = [b for b in range(len(self.ns)) if self.ns[b] == n]
@@ -359,24 +360,21 @@ class Headline:
         al = self.ual[sel].contiguous()
         f = torch.cat([self.ub32[self.uplan.offsets[b]:self.uplan.offsets[b + 1]] for b in idx]).contiguous()
         x = torch.zeros(plan.P, dtype=torch.float32, device="cuda")
+        opts = {k: rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=M, K=k) for k in (K, 2 * K)}
 
         def timed(steps):
-            opts = rm.solve_opts(mode=rm.RM_UNROLL, dtype=rm.RM_F32, m=M, K=steps)
-            rm.rm_solve(self.ctx, plan, rm.RM_NAG, opts, om, al, f, x)
-            best = None
-            for _ in range(reps):
-                x.zero_()
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-                rm.rm_solve(self.ctx, plan, rm.RM_NAG, opts, om, al, f, x)
-                e1.record()
-                torch.cuda.synchronize()
-                t = e0.elapsed_time(e1) / 1e3
-                best = t if best is None else min(best, t)
-            return best
+            x.zero_()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rm.rm_solve(self.ctx, plan, rm.RM_NAG, opts[steps], om, al, f, x)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / 1e3
 
-        t_launch = (timed(2 * K) - timed(K)) / (K / kc[1])
+        timed(K)  # warm
+        diffs = [timed(2 * K) - timed(K) for _ in range(reps)]
+        t_launch = float(np.median(diffs)) / (K / kc[1])
         return kernel_name(kc, n, len(idx)), kc[1], plan.P, t_launch
 
 

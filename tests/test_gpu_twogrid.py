@@ -93,10 +93,14 @@ def test_twogrid_forward_matches_oracle(ctx, name, jacobi, resonant):
         u, hist_o = twogrid.run(name, c, fs[b], om[b], syms[b], K, binv=binv, history=True, **kw)
         fn = np.linalg.norm(fs[b])
         err = np.linalg.norm(xs[b] - u) / np.linalg.norm(u)
+        # element by element as well, relative to the largest entry
+        sup = np.max(np.abs(xs[b] - u)) / np.max(np.abs(u))
         rr_gpu = problem.relres(c, fs[b], xs[b])
         tol = 1e-5
-        say("  n", batch.n[b], "kappa", round(batch.kappa[b], 3), "relres", hist_o[-1], rr_gpu, "err", err)
+        say("  n", batch.n[b], "kappa", round(batch.kappa[b], 3), "relres", hist_o[-1], rr_gpu, "err", err,
+            "sup err", sup)
         assert err <= tol, (b, err, tol)
+        assert sup <= tol, (b, sup, tol)
         assert abs(rr_gpu - hist_o[-1]) <= tol * max(1.0, hist_o[-1])
         np.testing.assert_allclose(np.sqrt(hs[:, b]) / fn, hist_o, rtol=1e-3, atol=1e-5)
         assert np.array_equal(cks[0][b], np.zeros_like(cks[0][b]))
