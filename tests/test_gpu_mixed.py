@@ -5,7 +5,8 @@ schemes, Jacobi) and chunks of fewer than 8 steps; sizes whose sub-groups leave 
 over (n = 300: three windows of 320 threads and a rest of 64; n = 700: one window of
 704 threads and a rest of 320); several windows per instance, including a shorter last
 window; a class outside the launch (a tiled main configuration); inactive instances;
-and the refined solve to 1e-10 with its reports and iteration counts."""
+the refined solve to 1e-10 with its reports and iteration counts, eager and with captured
+outer iterations; plans with no class, or a single class, on the row pipeline."""
 import numpy as np
 import pytest
 import torch
@@ -134,6 +135,55 @@ def test_mixed_refined_solve_equals_per_class(ctx):
     for key in ("outer_iters", "rounds", "relres"):
         assert np.array_equal(np.asarray(r0[key]), np.asarray(r1[key])), key
     assert np.all(np.asarray(r1["relres"]) <= 1e-10)
+
+
+def test_mixed_refined_solve_with_graphs(ctx):
+    """The refined solve with captured outer iterations (one graph per combination of
+    class configurations, the mixed launch inside): the same iterate and reports as the
+    eager per-class solve, on two calls in a row."""
+    from paper_2412_08076_amd import rm
+    ns = [63, 127, 255, 511, 1023, 63]
+    batch = random_batch(ns, seed=41, eps_range=(0.1, 1.0))
+    plan = plan_for(ctx, batch)
+    _configure(plan, rm)
+    m = 16
+    om, al = _weights(batch, m, 6, lo=0.9, mom=(0.985, 0.99))
+    omd, ald, bd = dev(om, torch.float32), dev(al, torch.float32), dev(batch.f_packed())
+    base = dict(mode=rm.RM_TO_TOL, m=m, tol=1e-10, tol_inner=0.05, max_outer=40000, max_rounds=16)
+    runs = []
+    for mixed, graph in ((False, False), (True, True), (True, True)):
+        plan.set_mixed(mixed)
+        x = torch.zeros(plan.P, dtype=torch.float64, device="cuda")
+        rep = rm.rm_solve(ctx, plan, rm.RM_NAG, rm.solve_opts(graph=graph, **base), omd, ald, bd, x)
+        say("refined", "mixed" if mixed else "per class", "graph" if graph else "eager", "outer",
+            rep["outer_iters"])
+        assert rep["status"] == rm.RM_OK
+        runs.append((host(x), rep))
+    for x1, r1 in runs[1:]:
+        assert np.array_equal(x1, runs[0][0])
+        for key in ("outer_iters", "rounds", "relres"):
+            assert np.array_equal(np.asarray(r1[key]), np.asarray(runs[0][1][key])), key
+
+
+def test_mixed_without_row_pipeline_classes(ctx):
+    """A plan whose classes all run tiled kernels (nothing for the mixed launch) and a plan
+    of a single row-pipeline class: the setting changes nothing in the results."""
+    from paper_2412_08076_amd import rm
+    for ns, cfg in (([40, 63, 100], lambda plan: plan.set_kernel(0, 4)),
+                    ([511, 511, 511], lambda plan: plan.set_kernel(rm.STREAM_SHAPE, 8, cw=117))):
+        batch = random_batch(ns, seed=43)
+        plan = plan_for(ctx, batch)
+        cfg(plan)
+        m, K = 8, 24
+        om, al = _weights(batch, m, 7)
+        omd, ald = dev(om, torch.float32), dev(al, torch.float32)
+        f = dev(batch.f_packed(), torch.float32)
+        say("mixed setting on", ns)
+        a, ah = _unroll(ctx, plan, rm.RM_NAG, omd, ald, f, m, K)
+        plan.set_mixed(True)
+        b, bh = _unroll(ctx, plan, rm.RM_NAG, omd, ald, f, m, K)
+        assert np.array_equal(a, b)
+        assert np.array_equal(ah, bh)
 
 
 def test_mixed_setting_round_trip(ctx):
