@@ -38,7 +38,7 @@ B_ANISO, N_ANISO = 256, 255  # the single-size anisotropic batch (and the SSOR l
 HBM_PEAK_GBS = 8000.0
 # published MI355X vector FP32 peak (counts packed FP32 FMAs)
 FP32_PEAK_TFLOPS = 157.3
-# the FP32 rate without packed FP32 instructions, which this build disables:
+# the FP32 rate without packed FP32 instructions, which the kernels are compiled without:
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flop per FMA x 2.4 GHz
 FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # algorithmic flops of one point update: the 9-point stencil (9 multiply-adds), the
@@ -192,7 +192,7 @@ def roofline(kstr, T, units, t_launch, copy_gbs):
     between, so it moves one sweep's data per launch and is bound by FP32 arithmetic:
     achieved = 24 algorithmic flops per point update x units x T / launch time, against
     the published FP32 peak.  The same rate against the FP32 peak without packed
-    instructions (which this build disables) is kept as a separate field.  traffic: DRAM
+    instructions (which the kernels are compiled without) is kept as a separate field.  traffic: DRAM
     bytes per launch from the FETCH_SIZE / WRITE_SIZE counters scaled by a copy-kernel
     calibration, when a committed profile exists for this exact kernel configuration and
     kernel source (KERNEL_SOURCES), else null; dram_frac is that traffic over the launch

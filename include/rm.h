@@ -53,7 +53,7 @@ typedef enum {
   RM_EHIP = 3,         /* a HIP runtime call failed                            */
   RM_ENOTCONV = 4,     /* an instance hit its iteration or round cap           */
   RM_EDIVERGED = 5,    /* an instance produced a non-finite or growing residual */
-  RM_EUNSUPPORTED = 6  /* valid request this build does not implement          */
+  RM_EUNSUPPORTED = 6  /* valid request the library does not implement         */
 } rm_status;
 
 typedef enum { RM_Q1_ANISO = 0, RM_FD5_HELMHOLTZ = 1 } rm_op;
@@ -364,8 +364,9 @@ rm_status rm_twogrid_adjoint(rm_ctx* ctx, const rm_plan_t* plan, int32_t method,
                              float* d_alpha, float* d_symbol, float* d_b, float* loss);
 
 /* Symbol network of the two-grid cycle (§3: the meta network that produces the diagonal
- * Lambda~ of the spectral correction, eq. dl-him-h; §3.2 learns in log form).  The text
- * does not give its architecture; the one built here: per coarse mode (p, q) of instance
+ * Lambda~ of the spectral correction, eq. dl-him-h, there an FNO whose architecture the
+ * text does not give; §3.2 learns the smoother weight in log form, and the exponential
+ * below does the same for the symbol).  The one built here: per coarse mode (p, q) of instance
  * b (nc = (n - 1)/2, h = 1/(n + 1)), with lam the fine-grid eigenvalue
  * (4/h^2)(sin^2(p pi h/2) + sin^2(q pi h/2)) - kappa^2,
  *   features  (lam h^2 / 8, p / (nc + 1), q / (nc + 1)),

@@ -1,5 +1,6 @@
-// Symbol network of the two-grid Helmholtz cycle (§3: Meta-Lambda~ of the spectral
-// correction, eq. dl-him-h; §3.2 learns in log form), forward and backward, FP32.
+// Symbol network of the two-grid Helmholtz cycle (§3: the meta network behind Lambda~ of
+// the spectral correction, eq. dl-him-h; the exponential takes the log form that §3.2 uses
+// for the smoother weight), forward and backward, FP32.
 //
 // Per instance, on the coarse mode grid (nc x nc, mode (p, q) at [q-1][p-1]):
 //   features  X = (lam h^2 / 8, p / (nc + 1), q / (nc + 1)), lam the fine-grid eigenvalue
