@@ -184,6 +184,33 @@ def test_symbolnet_full_size_sampled(ctx):
     assert err <= GRAD_RTOL
 
 
+def test_symbolnet_largest_size(ctx):
+    """n = 1023 (the largest two-grid size: 511 x 511 modes, 32 x 32 tiles) beside n = 7:
+    the symbol of both and the gradient against the oracle."""
+    from paper_2412_08076_amd import rm
+    ns = [1023, 7]
+    batch = _batch(ns, seed=9, kappa_range=(20.0, 80.0))
+    plan = plan_for(ctx, batch)
+    th, thd = _params(19)
+    say("symbol network largest size", ns)
+    sym = torch.empty(plan.coarse_points(), dtype=torch.float32, device="cuda")
+    rm.rm_symbolnet_forward(ctx, plan, thd, sym)
+    got = _coarse(plan, host(sym), ns)
+    for b, n in enumerate(ns):
+        want = symbolnet.forward(th, batch.kappa[b], n)
+        err = np.max(np.abs(got[b] - want) / np.abs(want))
+        say("  n", n, "max rel err %.2e" % err)
+        assert err <= SYM_RTOL
+    rng = np.random.default_rng(21)
+    dsyms = [rng.standard_normal(((n - 1) // 2,) * 2).astype(np.float32).astype(np.float64) for n in ns]
+    d = torch.empty(thd.numel(), dtype=torch.float32, device="cuda")
+    rm.rm_symbolnet_backward(ctx, plan, thd, dev(_pack_coarse(plan, dsyms), torch.float32), d)
+    want = sum(symbolnet.backward(th, batch.kappa[b], n, dsyms[b]) for b, n in enumerate(ns))
+    err = np.max(np.abs(host(d) - want)) / np.max(np.abs(want))
+    say("  gradient rel err %.2e" % err)
+    assert err <= GRAD_RTOL
+
+
 def test_symbolnet_rejects_bad_plans(ctx):
     """Called through the C-ABI: a plan of Q1 instances and a plan whose n + 1 is not a
     power of two are refused with an error status, and nothing is written."""
