@@ -213,6 +213,11 @@ def roofline(kstr, T, units, t_launch, copy_gbs):
             "algorithmic_flops_per_launch": flops,
             "nonpacked_fp32": {"peak": FP32_NONPACKED_TFLOPS, "frac": achieved / FP32_NONPACKED_TFLOPS},
             "dram_GBs": dram, "dram_frac": (dram / HBM_PEAK_GBS) if dram else None,
+            # sweep-equivalent rate: 20 B per point update, as if no step stayed on chip
+            # between steps (the effective-bandwidth reading of the HBM target); temporal
+            # blocking takes it past the peak by design, so it is not the roofline fraction
+            "hbm_effective": {"GBs": BYTES_PER_LUP_NAG * units * T / t_launch / 1e9,
+                              "frac": BYTES_PER_LUP_NAG * units * T / t_launch / 1e9 / HBM_PEAK_GBS},
             "min_dram_bytes_per_launch": BYTES_PER_LUP_NAG * units, "measured_copy_GBs": copy_gbs}
 
 
