@@ -130,44 +130,53 @@ __device__ __forceinline__ T stencil_at(const T* q, int W, const T c[5]) {
 
 // Residual r = f - A u~ on the padded region (0 on its outer ring and outside the
 // domain), read from the look-ahead field s (row-major, UW wide), then written over s
-// as colour planes Q.  Thread t forms the residual of plane elements q = t + j WG, so
-// the write after the barrier goes to s[q] with no index arithmetic.  Ends with a
-// barrier.
+// as colour planes Q.  Plane by plane (the plane's parities are constants), thread t
+// forms the residual of plane elements e = t + j WG, so the write after the barrier goes
+// to s[plane * QS + e] with no index arithmetic, and an element's padded point needs one
+// division by the plane width.  Ends with a barrier.
 template <typename T, typename Q>
 __device__ __forceinline__ void residual_to_planes(T* s, const Field<T>& fi, int ox, int oy, int n, const T c[5]) {
-  static_assert(Q::SIZE == PH * PW, "one plane element per padded point");
-  constexpr int NR = (PH * PW + WG - 1) / WG;
-  T fv[NR], rr[NR];
-  int kk[NR];  // row-major index of element q's point, or -1 where the residual is 0
+  static_assert(Q::SIZE == PH * PW && 2 * Q::QW == PW && 2 * Q::QH == PH, "one plane element per padded point");
+  constexpr int NE = (Q::QS + WG - 1) / WG;  // elements per thread and plane
+  T rr[4][NE];
   const int t0 = opaque_tid();
 #pragma unroll
-  for (int j = 0; j < NR; ++j) {   // points not formed read f at 0
-    const int q = t0 + j * WG;
-    const int pl = q / Q::QS, e = q - pl * Q::QS;
-    const int jj = e / Q::QW, i = e - jj * Q::QW;
-    const int px = 2 * i + (pl & 1), py = 2 * jj + (pl >> 1);
-    const int gx = ox + px, gy = oy + py;
-    const bool ring = q >= PH * PW || px == 0 || py == 0 || px == PW - 1 || py == PH - 1;
-    const bool ok = !ring && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
-    kk[j] = ok ? py * PW + px : -1;
-    fv[j] = fi[ok ? (unsigned)(gy * n + gx) : 0u];
-  }
+  for (int pl = 0; pl < 4; ++pl) {
+    const int a = pl & 1, b = pl >> 1;  // x and y parity of the plane's padded points
+    T fv[NE];
+    int kk[NE];  // row-major index of the element's point, or -1 where the residual is 0
 #pragma unroll
-  for (int j = 0; j < NR; ++j) {
-    // points not formed read the stencil at an interior point
-    T st = stencil_at(s + (kk[j] >= 0 ? kk[j] : PW + 1), UW, c);
-    // the stencil is complete before the next one's LDS reads are issued, so the
-    // reads of one stencil at a time occupy registers
-    asm volatile("" : "+v"(st)::"memory");
-    rr[j] = kk[j] >= 0 ? fv[j] - st : T(0);
+    for (int j = 0; j < NE; ++j) {  // points not formed read f at 0
+      const int e = t0 + j * WG;
+      const int jj = e / Q::QW, i = e - jj * Q::QW;
+      const int px = 2 * i + a, py = 2 * jj + b;
+      const int gx = ox + px, gy = oy + py;
+      // the outer ring: x = 0 (i = 0 of an even plane) or PW - 1 (the last i of an odd
+      // one), likewise in y; and elements past the plane
+      const bool ring = e >= Q::QS || i == (a ? Q::QW - 1 : 0) || jj == (b ? Q::QH - 1 : 0);
+      const bool ok = !ring && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
+      kk[j] = ok ? py * PW + px : -1;
+      fv[j] = fi[ok ? (unsigned)(gy * n + gx) : 0u];
+    }
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+      // points not formed read the stencil at an interior point
+      T st = stencil_at(s + (kk[j] >= 0 ? kk[j] : PW + 1), UW, c);
+      // the stencil is complete before the next one's LDS reads are issued, so the
+      // reads of one stencil at a time occupy registers
+      asm volatile("" : "+v"(st)::"memory");
+      rr[pl][j] = kk[j] >= 0 ? fv[j] - st : T(0);
+    }
   }
   __syncthreads();
   const int t1 = opaque_tid();
 #pragma unroll
-  for (int j = 0; j < NR; ++j) {
-    const int q = t1 + j * WG;
-    if (q < PH * PW) s[q] = rr[j];
-  }
+  for (int pl = 0; pl < 4; ++pl)
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+      const int e = t1 + j * WG;
+      if (e < Q::QS) s[pl * Q::QS + e] = rr[pl][j];
+    }
   __syncthreads();
 }
 
