@@ -150,10 +150,6 @@ __device__ __forceinline__ void stream_run(const PlanDev& p, const BTile& tl, in
     lv = uses_momentum(METHOD) ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(vb_in, col4, row4, 0)) : 0.0f;
     lf = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(fb_in, col4, row4, 0));
   };
-  static_for<0, PF>([&](auto K_) {
-    constexpr int k = decltype(K_)::value;
-    load_row(min(k, L - 1), R.pu[k], R.pv[k], R.pf[k]);
-  });
   __syncthreads();
   double r2 = 0.0;
   const int S = L + 2 * NLV;
@@ -280,16 +276,31 @@ __device__ __forceinline__ void stream_run(const PlanDev& p, const BTile& tl, in
   const int F = min(S, FF);
   const int D = F + max(0, (L - F) / PF) * PF;
   int s = 0;
+  // The first PF rows are requested inside each branch: on every path to the steady loop
+  // they have been consumed, so its loads are waited for only where they are used.
   if (UNROLLED && L >= FF) {
+    static_for<0, PF>([&](auto K_) {
+      constexpr int k = decltype(K_)::value;
+      load_row(k, R.pu[k], R.pv[k], R.pf[k]);
+    });
     static_for<0, UNROLLED ? FF : 0>([&](auto S_) {
       constexpr int sc = decltype(S_)::value;
       iter(std::integral_constant<int, sc % PF>{}, std::integral_constant<int, K_FILL>{}, S_, sc);
     });
     s = FF;
   } else {
+    // at least one pass (F >= 2 NLV > 0): no path reaches the steady loop with the first
+    // prefetched rows still in flight, which would make the compiler wait for every load
+    // at the top of each steady pass
+    static_for<0, PF>([&](auto K_) {
+      constexpr int k = decltype(K_)::value;
+      load_row(min(k, L - 1), R.pu[k], R.pv[k], R.pf[k]);
+    });
 #pragma unroll 1
-    for (; s < F; s += PF)
+    do {
       static_for<0, PF>([&](auto PH_) { iter(PH_, Run{}, V0{}, s + decltype(PH_)::value); });
+      s += PF;
+    } while (s < F);
   }
 #pragma unroll 1
   for (; s < D; s += PF)
