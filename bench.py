@@ -35,9 +35,9 @@ M, K_TRAIN, CKPT, TOL = 16, 64, 16, 1e-10
 TOL_INNER, MAX_ROUNDS = 0.05, 16
 # a class of the uneven batch runs its tail (tiled) configuration once fewer than this
 # fraction of its instances are still iterating: measured on this batch, the time to
-# 1e-10 is flat for 0.3 .. 0.5 and 2 % longer at the tuner's estimate (0.72 for n = 1023,
-# the main configuration's one-instance time over the tail's whole-class time), which
-# leaves out the tail launch's fixed cost and its longer bookkeeping launch
+# 1e-10 is lowest for 0.3 .. 0.4 and up to 1 % longer at the tuner's estimate (0.72 for
+# n = 1023, the main configuration's one-instance time over the tail's whole-class time),
+# which leaves out the tail launch's fixed cost (it launches every tile of the class)
 TAIL_SWITCH = 0.4
 B_TRAIN, N_TRAIN = 64, 127
 B_ANISO, N_ANISO = 256, 255  # the single-size anisotropic batch (and the SSOR line's)

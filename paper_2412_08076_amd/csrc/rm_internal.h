@@ -106,8 +106,9 @@ struct RoundParams {
 // start its next inner solve at outer iteration rp.start.
 void launch_round_decide(const PlanDev& p, const double* partial2, const RoundParams& rp, RoundState rs,
                          hipStream_t st);
-// Inner-solve bookkeeping after one outer iteration, one launch: res2[b] = the sum of the
-// instance's residual partials in slot order, then for active
+// Inner-solve bookkeeping after one outer iteration, two launches: res2[b] = the sum of the
+// instance's residual partials (one wave per instance, the order of
+// launch_reduce_partials), then for active
 // instances the outer count, divergence / target / cap / stagnation tests and the new
 // active flag, and *n_active = the number still active.  The partial slots of instance b
 // are [r[2b], r[2b+1]) with r = tranges when bit cls[b] of tailmask is set (its class ran

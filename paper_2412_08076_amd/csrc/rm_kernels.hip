@@ -372,15 +372,34 @@ __global__ __launch_bounds__(64) void k_round_decide(PlanDev p, const double* __
 // clamped to [stall_min, stall_max] (stall_max before the first reduction):
 // an instance at its FP32 floor stops quickly, a slowly converging large one is
 // given time.
+// The residual of the inner iterate after one outer iteration: res2[b] = the sum of
+// instance b's residual partials over the slot range of the configuration its class ran,
+// one wave per instance in the order of k_reduce_partials (lane j adds slots t0 + j,
+// t0 + j + 64, ..., then a fixed tree over the lanes).  Spread over the whole chip, its
+// loads are coalesced; one workgroup summing thousands of scattered slots was bound by
+// its single CU's load path.
+__global__ __launch_bounds__(64) void k_outer_sums(PlanDev p, const double* __restrict__ partial2,
+                                                   const int* __restrict__ ranges, const int* __restrict__ tranges,
+                                                   const int* __restrict__ cls, unsigned long long tailmask,
+                                                   double* __restrict__ res2) {
+  const int b = blockIdx.x;
+  const int ci = cls != nullptr ? cls[b] : 0;
+  const int* rg = (tranges != nullptr && ci < 64 && ((tailmask >> ci) & 1ull)) ? tranges : ranges;
+  const int t0 = rg != nullptr ? rg[2 * b] : p.inst[b].tile_begin;
+  const int t1 = rg != nullptr ? rg[2 * b + 1] : p.inst[b].tile_end;
+  double s = 0.0;
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += 64) s += partial2[2 * t];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) res2[b] = s;
+}
+
 // Bookkeeping after one outer iteration of the refined solve, in one workgroup with a
-// thread per instance: the residual of the inner iterate (the instance's residual
-// partials summed in slot order), then for active instances the count, divergence,
-// target, cap and stagnation tests; finally the number still active, summed over the
-// threads in a fixed order (no atomics and no counter to clear beforehand).
+// thread per instance: for active instances the count, divergence, target, cap and
+// stagnation tests on res2 (formed by k_outer_sums); finally the number still active,
+// summed over the threads in a fixed order (no atomics and no counter to clear beforehand).
 __global__ __launch_bounds__(1024) void k_outer_flags(
-    PlanDev p, const double* __restrict__ partial2, const int* __restrict__ ranges,
-    const int* __restrict__ tranges, const int* __restrict__ cls, unsigned long long tailmask, int ncls,
-    double* __restrict__ res2, const double* __restrict__ rhs2, const double* __restrict__ target2,
+    PlanDev p, const int* __restrict__ cls, int ncls,
+    const double* __restrict__ res2, const double* __restrict__ rhs2, const double* __restrict__ target2,
     double* __restrict__ best2, int* __restrict__ since, int* __restrict__ gains, int stall_min, int stall_max,
     int cap, int* __restrict__ active, int* __restrict__ outer_count, int* __restrict__ status,
     int* __restrict__ pending, int* __restrict__ n_active, unsigned long long* __restrict__ host_word,
@@ -393,19 +412,11 @@ __global__ __launch_bounds__(1024) void k_outer_flags(
   __syncthreads();
   int mine = 0, pend = 0;
   for (int b = threadIdx.x; b < p.B; b += blockDim.x) {
-    // slot range of the configuration the instance's class ran
     const int ci = cls != nullptr ? cls[b] : 0;
-    const int* rg = (tranges != nullptr && ci < 64 && ((tailmask >> ci) & 1ull)) ? tranges : ranges;
-    const int t0 = rg != nullptr ? rg[2 * b] : p.inst[b].tile_begin;
-    const int t1 = rg != nullptr ? rg[2 * b + 1] : p.inst[b].tile_end;
-    // the instance's state is read before the partial sums are waited for
     const int act = active[b], cnt = outer_count[b] + 1, sn = since[b], g = gains[b];
     const int pd = pending != nullptr ? pending[b] : 0;
     const double rh = rhs2[b], tg = target2[b], best = best2[b];
-    double r2 = 0.0;
-#pragma unroll 8
-    for (int t = t0; t < t1; ++t) r2 += partial2[2 * t];
-    res2[b] = r2;
+    const double r2 = res2[b];
     if (act == 0) {
       // a round that ended earlier and waits for its refinement step
       pend += pd;
@@ -854,12 +865,12 @@ void launch_outer_flags(const PlanDev& p, const double* partial2, const int* ran
                         int cap, int* active, int* outer_count, int* status, int* pending, int* n_active,
                         unsigned long long* host_word, unsigned long long* host_cnt, unsigned seq,
                         const int* tot, double* hist, int hist_len, hipStream_t st) {
+  if (p.B > 0)
+    hipLaunchKernelGGL(k_outer_sums, dim3(p.B), dim3(64), 0, st, p, partial2, ranges, tranges, cls, tailmask, res2);
   const int threads = 64 * std::min(16, std::max(1, (p.B + 63) / 64));
-  hipLaunchKernelGGL(k_outer_flags, dim3(1), dim3(threads), (size_t)std::max(1, ncls) * sizeof(int), st, p,
-                     partial2, ranges, tranges, cls, tailmask, ncls, res2, rhs2, target2, best2, since, gains,
-                     stall_min, stall_max, cap, active, outer_count, status, pending, n_active, host_word, host_cnt,
-                     seq, tot,
-                     hist, hist_len);
+  hipLaunchKernelGGL(k_outer_flags, dim3(1), dim3(threads), (size_t)std::max(1, ncls) * sizeof(int), st, p, cls,
+                     ncls, res2, rhs2, target2, best2, since, gains, stall_min, stall_max, cap, active, outer_count,
+                     status, pending, n_active, host_word, host_cnt, seq, tot, hist, hist_len);
 }
 
 void launch_fill_i32(int* p, int value, int64_t count, hipStream_t st) {
