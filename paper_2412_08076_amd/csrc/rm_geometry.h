@@ -209,11 +209,16 @@ inline int reverse_window(int n, int count) {
   return n;
 }
 
-// Tile table of one configuration of a size class (instances `insts` of size n): for
-// every instance its tiles in row-major order of the windows, residual slots numbered
-// from `slot` on (advanced), the instance's slot range in ranges[2b], ranges[2b + 1],
-// and padding tiles (inst = -1) up to a multiple of 8.  False for an invalid
-// configuration.
+// Tile table of one configuration of a size class (instances `insts` of size n): every
+// tile of every instance, the residual slots of an instance numbered in row-major order
+// of its tiles from `slot` on (advanced), its slot range in ranges[2b], ranges[2b + 1],
+// and padding tiles (inst = -1, slots after all others).  Row windows are listed
+// instance by instance, padded to a multiple of 8.  A tiled table is eight parts of
+// equal length, one per XCD under the block remap: the tile rows of the class's k-th
+// instance are cut into eight bands of consecutive rows, band j going to part
+// (j + k) mod 8.  Any few instances still iterating then keep all eight XCDs busy (an
+// instance-major table put a lone instance's tiles on one or two of them), and vertical
+// neighbours mostly share an L2.  False for an invalid configuration.
 inline bool make_tiles(int n, const std::vector<int>& insts, int shape, int T, int cw, int& slot,
                        std::vector<int>& ranges, std::vector<rmk::BTile>& out) {
   int tx, ty;
@@ -223,13 +228,39 @@ inline bool make_tiles(int n, const std::vector<int>& insts, int shape, int T, i
   const auto px = stream ? std::vector<std::array<int, 3>>{{0, 0, n}} : partition(n, cw, T + 1);
   const auto py = partition(n, eh, T + 1);
   out.clear();
-  for (int b : insts) {
+  if (stream) {
+    for (int b : insts) {
+      ranges[2 * b] = slot;
+      for (const auto& y : py)
+        for (const auto& x : px) out.push_back(rmk::BTile{b, x[0], y[0], slot++, x[1], x[2], y[1], y[2]});
+      ranges[2 * b + 1] = slot;
+    }
+    while (out.size() % 8 != 0) out.push_back(rmk::BTile{-1, 0, 0, slot++, 0, 0, 0, 0});
+    return true;
+  }
+  const int rows = (int)py.size(), cols = (int)px.size();
+  std::vector<std::vector<rmk::BTile>> part(8);
+  for (size_t k = 0; k < insts.size(); ++k) {
+    const int b = insts[k];
     ranges[2 * b] = slot;
-    for (const auto& y : py)
-      for (const auto& x : px) out.push_back(rmk::BTile{b, x[0], y[0], slot++, x[1], x[2], y[1], y[2]});
+    for (int j = 0; j < 8; ++j) {
+      auto& dst = part[(j + k) % 8];
+      for (int r = j * rows / 8; r < (j + 1) * rows / 8; ++r)
+        for (int c = 0; c < cols; ++c) {
+          const auto& x = px[c];
+          const auto& y = py[r];
+          dst.push_back(rmk::BTile{b, x[0], y[0], slot + r * cols + c, x[1], x[2], y[1], y[2]});
+        }
+    }
+    slot += rows * cols;
     ranges[2 * b + 1] = slot;
   }
-  while (out.size() % 8 != 0) out.push_back(rmk::BTile{-1, 0, 0, slot++, 0, 0, 0, 0});
+  size_t per = 0;
+  for (const auto& q : part) per = std::max(per, q.size());
+  for (auto& q : part) {
+    while (q.size() < per) q.push_back(rmk::BTile{-1, 0, 0, slot++, 0, 0, 0, 0});
+    out.insert(out.end(), q.begin(), q.end());
+  }
   return true;
 }
 

@@ -15,6 +15,7 @@
 // Exit status 0 when every check holds; the first failure is printed.
 #include <cstdio>
 #include <algorithm>
+#include <array>
 #include <cstdlib>
 #include <vector>
 
@@ -78,9 +79,19 @@ static void check_table(int n, int count, int shape, int T, int cw) {
   for (int b : insts) {
     CHECK(ranges[2 * b] == expect_slot, "instance %d slots start at %d", b, ranges[2 * b]);
     std::fill(owner.begin(), owner.end(), 0);
+    // the instance's slots are its range, each once, in row-major order of its tiles
+    std::vector<std::array<int, 3>> mine;  // (slot, y0, x0)
+    for (const auto& tl : t)
+      if (tl.inst == b) mine.push_back({tl.slot, tl.y0, tl.x0});
+    std::sort(mine.begin(), mine.end());
+    for (size_t k = 0; k < mine.size(); ++k) {
+      CHECK(mine[k][0] == expect_slot + (int)k, "slot %d, expected %d", mine[k][0], expect_slot + (int)k);
+      if (k > 0)
+        CHECK(mine[k][1] > mine[k - 1][1] || (mine[k][1] == mine[k - 1][1] && mine[k][2] > mine[k - 1][2]),
+              "instance %d: slots not in row-major order of its tiles", b);
+    }
     for (const auto& tl : t) {
       if (tl.inst != b) continue;
-      CHECK(tl.slot == expect_slot, "slot %d, expected %d", tl.slot, expect_slot);
       ++expect_slot;
       CHECK(tl.x0 >= 0 && tl.y0 >= 0, "negative origin");
       CHECK(tl.ox0 >= tl.x0 && tl.ox1 <= std::min(n, tl.x0 + ew), "owned columns outside the window");
@@ -100,12 +111,26 @@ static void check_table(int n, int count, int shape, int T, int cw) {
       }
   }
   for (int b = 0; b < B; b += 2) CHECK(ranges[2 * b] == -7, "an instance outside the class got a range");
+  std::vector<int> pad;
   for (const auto& tl : t)
-    if (tl.inst < 0) {
-      CHECK(tl.slot == expect_slot, "padding slot");
-      ++expect_slot;
-    }
+    if (tl.inst < 0) pad.push_back(tl.slot);
+  std::sort(pad.begin(), pad.end());
+  for (int s : pad) CHECK(s == expect_slot++, "padding slot %d", s);
   CHECK(slot == expect_slot, "slot counter %d, expected %d", slot, expect_slot);
+  if (!stream) {
+    // eight parts of equal length (one per XCD under the block remap); an instance with
+    // at least eight rows of tiles has tiles in every part
+    const size_t per = t.size() / 8;
+    for (int b : insts) {
+      int parts = 0;
+      for (int x = 0; x < 8; ++x) {
+        bool any = false;
+        for (size_t i = x * per; i < (x + 1) * per; ++i) any = any || t[i].inst == b;
+        parts += any ? 1 : 0;
+      }
+      CHECK(parts == std::min(8, ty), "n=%d shape=%d: instance %d in %d of 8 parts (%d tile rows)", n, shape, b, parts, ty);
+    }
+  }
 }
 
 static void check_groups(const std::vector<int>& ns, const std::vector<int>& counts, int pick) {
