@@ -33,12 +33,6 @@ M, K_TRAIN, CKPT, TOL = 16, 64, 16, 1e-10
 # refined solve: each round's FP32 inner solve stops at 5 % of its right-hand side (it
 # drifts from the FP64 trajectory a little below that at n >= 511), at most 16 rounds
 TOL_INNER, MAX_ROUNDS = 0.05, 16
-# a class of the uneven batch runs its tail (tiled) configuration once fewer than this
-# fraction of its instances are still iterating: measured on this batch, the time to
-# 1e-10 is lowest for 0.3 .. 0.4 and up to 1 % longer at the tuner's estimate (0.72 for
-# n = 1023, the main configuration's one-instance time over the tail's whole-class time),
-# which leaves out the tail launch's fixed cost (it launches every tile of the class)
-TAIL_SWITCH = 0.4
 B_TRAIN, N_TRAIN = 64, 127
 B_ANISO, N_ANISO = 256, 255  # the single-size anisotropic batch (and the SSOR line's)
 HBM_PEAK_GBS = 8000.0
@@ -292,7 +286,6 @@ class Headline:
         rm.rm_meta_forward(self.ctx, self.tplan, M, self.params, self.tom, self.tal)
         self.tuned_train_us = rm.rm_tune(self.ctx, self.tplan, rm.RM_NAG, M, self.tom, self.tal, self.tb32,
                                          cache_path=tune_cache)
-        self.uplan.set_tail_switch(TAIL_SWITCH)
         # mixed-size launch: "stream" advances the classes the tuner put on the 8-step row
         # pipeline in one launch per chunk; "all" first moves every class onto it (whole
         # height windows where the tuner chose a tiled kernel)
@@ -782,8 +775,7 @@ def main():
                                "+ training step B=64 n=127 (K=64 unroll, ckpt 16, hand-written adjoint, "
                                "meta backward)",
                    "batch": int(h.uplan.B), "points": int(h.uplan.P), "m": M, "tol": TOL,
-                   "tail_switch": TAIL_SWITCH, "train_batch": B_TRAIN, "train_n": N_TRAIN, "K_train": K_TRAIN,
-                   "ckpt_every": CKPT},
+                   "train_batch": B_TRAIN, "train_n": N_TRAIN, "K_train": K_TRAIN, "ckpt_every": CKPT},
         "time_to_tol_s": ttol,
         "solve": {"status": int(rep["status"]), "rounds_max": int(rep["rounds"].max()),
                   "relres_max": float(rep["relres"].max()), "per_size": per, "kernels": h.kernels(), "mixed": h.mixed,
