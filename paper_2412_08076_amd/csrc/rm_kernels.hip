@@ -363,15 +363,6 @@ __global__ __launch_bounds__(64) void k_round_decide(PlanDev p, const double* __
   rs.active[b] = 1;
 }
 
-
-// After one outer iteration of an inner solve: stop instances whose residual
-// reached their target, hit the cap, went non-finite or grew beyond 1e6 times
-// the right-hand side, or stagnated; count the rest.  Stagnation: no 10 %
-// reduction of the best residual for W outer iterations, where W is six times
-// the instance's own average spacing of such reductions so far in this round,
-// clamped to [stall_min, stall_max] (stall_max before the first reduction):
-// an instance at its FP32 floor stops quickly, a slowly converging large one is
-// given time.
 // The residual of the inner iterate after one outer iteration: res2[b] = the sum of
 // instance b's residual partials over the slot range of the configuration its class ran,
 // one wave per instance in the order of k_reduce_partials (lane j adds slots t0 + j,
@@ -393,6 +384,14 @@ __global__ __launch_bounds__(64) void k_outer_sums(PlanDev p, const double* __re
   if (threadIdx.x == 0) res2[b] = s;
 }
 
+// After one outer iteration of an inner solve: stop instances whose residual
+// reached their target, hit the cap, went non-finite or grew beyond 1e6 times
+// the right-hand side, or stagnated; count the rest.  Stagnation: no 10 %
+// reduction of the best residual for W outer iterations, where W is six times
+// the instance's own average spacing of such reductions so far in this round,
+// clamped to [stall_min, stall_max] (stall_max before the first reduction):
+// an instance at its FP32 floor stops quickly, a slowly converging large one is
+// given time.
 // Bookkeeping after one outer iteration of the refined solve, in one workgroup with a
 // thread per instance: for active instances the count, divergence, target, cap and
 // stagnation tests on res2 (formed by k_outer_sums); finally the number still active,
